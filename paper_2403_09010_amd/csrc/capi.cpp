@@ -1,0 +1,307 @@
+// C entry points of the symdel library, the context and its device memory
+// pool. Every entry point converts exceptions into SD_E_* codes, so no call
+// aborts the process and the context stays usable after an error.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "sd_internal.h"
+
+namespace sd {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{SD_E_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+  }
+}
+
+static size_t size_class(size_t bytes) {
+  if (bytes < 256) bytes = 256;
+  if (bytes <= (1u << 20)) {
+    size_t p = 256;
+    while (p < bytes) p <<= 1;
+    return p;
+  }
+  const size_t g = 2u << 20;
+  return (bytes + g - 1) / g * g;
+}
+
+static void release_cache(sd_ctx* c) {
+  for (auto& kv : c->cache) {
+    (void)hipFree(kv.second);
+    c->held -= kv.first;
+  }
+  c->cache.clear();
+}
+
+void* dalloc(sd_ctx* c, size_t bytes) {
+  const size_t sz = size_class(bytes);
+  auto it = c->cache.lower_bound(sz);
+  if (it != c->cache.end() && it->first <= 2 * sz) {
+    void* p = it->second;
+    c->live[p] = it->first;
+    c->cache.erase(it);
+    return p;
+  }
+  if (c->budget && c->held + sz > c->budget) release_cache(c);
+  if (c->budget && c->held + sz > c->budget)
+    throw Error{SD_E_NOMEM, "device memory budget exceeded: need " + std::to_string(sz) +
+                                " more bytes, holding " + std::to_string(c->held) + " of " +
+                                std::to_string(c->budget)};
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release_cache(c);
+    e = hipMalloc(&p, sz);
+  }
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error{SD_E_NOMEM, "hipMalloc of " + std::to_string(sz) + " bytes failed"};
+  }
+  c->held += sz;
+  c->live[p] = sz;
+  return p;
+}
+
+void dfree(sd_ctx* c, void* p) {
+  if (!p) return;
+  auto it = c->live.find(p);
+  if (it == c->live.end()) return;
+  c->cache.insert({it->second, p});
+  c->live.erase(it);
+}
+
+uint32_t next_epoch(sd_ctx* c, uint64_t words, hipStream_t s) {
+  if (words > c->status_words) {
+    if (c->status) dfree(c, c->status);
+    uint64_t w = words + words / 4 + 4096;
+    c->status = dalloc_t<uint64_t>(c, w);
+    c->status_words = w;
+    launch_fill_u64(c->status, 0, w, s);
+    c->epoch = 0;
+  }
+  if (++c->epoch >= 0xFFFFu) {
+    launch_fill_u64(c->status, 0, c->status_words, s);
+    c->epoch = 1;
+  }
+  return c->epoch;
+}
+
+uint32_t* fresh_counters(sd_ctx* c, size_t n, hipStream_t s) {
+  if (n > c->counters_n) {
+    if (c->counters) dfree(c, c->counters);
+    c->counters = dalloc_t<uint32_t>(c, n);
+    c->counters_n = n;
+  }
+  launch_fill_u32(c->counters, 0, n, s);
+  return c->counters;
+}
+
+void* readback(sd_ctx* c, const void* dptr, size_t bytes, hipStream_t s) {
+  if (bytes > c->pinned_bytes) {
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    size_t want = bytes < 65536 ? 65536 : bytes;
+    hip_check(hipHostMalloc(&c->pinned, want, hipHostMallocDefault), "hipHostMalloc");
+    c->pinned_bytes = want;
+  }
+  hip_check(hipMemcpyAsync(c->pinned, dptr, bytes, hipMemcpyDeviceToHost, s), "read-back copy");
+  hip_check(hipStreamSynchronize(s), "read-back synchronise");
+  return c->pinned;
+}
+
+StageTimer::StageTimer(sd_ctx* ctx, hipStream_t st) : c(ctx), s(st), on(ctx->timing != 0) {
+  if (!on) return;
+  if (c->events.empty()) c->events.resize(SD_MAX_STAGES + 1, nullptr);
+  for (auto& e : c->events)
+    if (!e) hip_check(hipEventCreate(&e), "hipEventCreate");
+  hip_check(hipEventRecord(c->events[0], s), "hipEventRecord");
+}
+
+void StageTimer::mark(const char* name, double bytes, int nl) {
+  if (!on || names.size() >= SD_MAX_STAGES) return;
+  names.push_back({name, bytes});
+  launches.push_back(nl);
+  hip_check(hipEventRecord(c->events[names.size()], s), "hipEventRecord");
+}
+
+void StageTimer::finish() {
+  c->stats.n_stages = 0;
+  if (!on) return;
+  hip_check(hipEventSynchronize(c->events[names.size()]), "hipEventSynchronize");
+  for (size_t x = 0; x < names.size(); ++x) {
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, c->events[x], c->events[x + 1]), "hipEventElapsedTime");
+    std::snprintf(c->stats.stage_name[x], sizeof(c->stats.stage_name[x]), "%s",
+                  names[x].first.c_str());
+    c->stats.stage_ms[x] = ms;
+    c->stats.stage_bytes[x] = names[x].second;
+    c->stats.stage_launches[x] = launches[x];
+  }
+  c->stats.n_stages = (int32_t)names.size();
+}
+
+}  // namespace sd
+
+using sd::Error;
+
+template <typename F>
+static int guarded(sd_ctx* c, F&& f) {
+  if (c) c->last_error.clear();
+  try {
+    f();
+    return SD_OK;
+  } catch (const Error& e) {
+    if (c) c->last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->last_error = "host allocation failed";
+    return SD_E_NOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->last_error = e.what();
+    return SD_E_INVAL;
+  }
+}
+
+extern "C" {
+
+int sd_create(sd_ctx** out, int device, uint64_t hbm_budget_bytes) {
+  if (!out) return SD_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return SD_E_HIP;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return SD_E_HIP;
+  }
+  sd_ctx* c = new (std::nothrow) sd_ctx();
+  if (!c) return SD_E_NOMEM;
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return SD_OK;
+}
+
+void sd_destroy(sd_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->live) (void)hipFree(kv.first);
+  c->live.clear();
+  sd::release_cache(c);
+  for (auto& kv : c->host_live) (void)hipHostFree(kv.first);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto& e : c->events)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int sd_set_option(sd_ctx* c, int option, int64_t value) {
+  if (!c) return SD_E_INVAL;
+  switch (option) {
+    case SD_OPT_TIMING:
+      c->timing = value ? 1 : 0;
+      return SD_OK;
+    case SD_OPT_PATH:
+      if (value < 0 || value > 2) return SD_E_INVAL;
+      c->path = (int)value;
+      return SD_OK;
+    default:
+      c->last_error = "unknown option";
+      return SD_E_INVAL;
+  }
+}
+
+int sd_self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, void* stream) {
+  if (!c || !seqs || !out) return SD_E_INVAL;
+  const int32_t want_device = out->on_device;
+  std::memset(out, 0, sizeof(*out));
+  out->on_device = want_device;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::self_search(c, seqs, k, out, static_cast<hipStream_t>(stream));
+  });
+}
+
+int sd_pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32_t* ia,
+                     const uint32_t* ib, int64_t n, uint8_t* d_out, void* stream) {
+  if (!c) return SD_E_INVAL;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::pair_distance(c, a, b, ia, ib, n, d_out, static_cast<hipStream_t>(stream));
+  });
+}
+
+int sd_get_stats(const sd_ctx* c, sd_stats* out) {
+  if (!c || !out) return SD_E_INVAL;
+  *out = c->stats;
+  return SD_OK;
+}
+
+int sd_pairs_copy(sd_ctx* c, const sd_pairs* p, uint32_t* i, uint32_t* j, uint8_t* d,
+                  int dst_on_device, void* stream) {
+  if (!c || !p) return SD_E_INVAL;
+  if (p->n == 0) return SD_OK;
+  if (!i || !j || !d || !p->i || !p->j || !p->d) return SD_E_INVAL;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipMemcpyKind kind;
+    if (p->on_device)
+      kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    else
+      kind = dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+    const size_t n = (size_t)p->n;
+    sd::hip_check(hipMemcpyAsync(i, p->i, n * 4, kind, s), "copy i");
+    sd::hip_check(hipMemcpyAsync(j, p->j, n * 4, kind, s), "copy j");
+    sd::hip_check(hipMemcpyAsync(d, p->d, n, kind, s), "copy d");
+    sd::hip_check(hipStreamSynchronize(s), "copy synchronise");
+  });
+}
+
+void sd_pairs_free(sd_ctx* c, sd_pairs* p) {
+  if (!c || !p) return;
+  void* arrays[3] = {p->i, p->j, p->d};
+  for (void* a : arrays) {
+    if (!a) continue;
+    auto h = c->host_live.find(a);
+    if (h != c->host_live.end()) {
+      (void)hipHostFree(a);
+      c->host_live.erase(h);
+    } else {
+      sd::dfree(c, a);
+    }
+  }
+  p->i = nullptr;
+  p->j = nullptr;
+  p->d = nullptr;
+  p->n = 0;
+}
+
+const char* sd_strerror(int code) {
+  switch (code) {
+    case SD_OK: return "ok";
+    case SD_E_INVAL: return "invalid argument";
+    case SD_E_ALPHABET: return "residue code outside 0..19";
+    case SD_E_LENGTH: return "sequence length outside [1, 24]";
+    case SD_E_TOO_MANY: return "too many sequences or variants for 32-bit ids";
+    case SD_E_NOMEM: return "out of device memory or over the HBM budget";
+    case SD_E_HIP: return "HIP runtime error";
+    case SD_E_CANCELLED: return "cancelled";
+    case SD_E_STATE: return "wrong state for this call";
+    default: return "unknown error";
+  }
+}
+
+const char* sd_last_error(const sd_ctx* c) { return c ? c->last_error.c_str() : ""; }
+
+}  // extern "C"

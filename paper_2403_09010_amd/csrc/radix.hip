@@ -1,0 +1,289 @@
+// LSD radix sort primitives for gfx950 (wave64, 160 KB LDS per CU).
+//
+// Records are one or two 64-bit key words (structure of arrays: word 0 is
+// the least significant) with an optional 32-bit payload. A pass sorts
+// stably by one 8-bit digit:
+//   * the digit histograms of every pass come from one read of the keys
+//     (k_radix_hist), so each pass knows its global bucket bases;
+//   * each pass is a single kernel (k_onesweep): a tile ranks its elements
+//     with wave64 ballots (match-any over the 8 digit bits, mbcnt for the
+//     rank below the lane), keeps per-wave digit counters in LDS, publishes
+//     its per-digit counts and finds its global offsets by decoupled
+//     look-back, then writes through LDS so that each digit's elements leave
+//     the tile as one contiguous run.
+// This is the paper's sortKeyValues / sort primitive (Section II B; Appendix A
+// steps 4 and 6) written for CDNA4 instead of taken from a library.
+#include "sd_device.h"
+#include "sd_internal.h"
+
+namespace sdk {
+
+constexpr int RADIX = 256;
+constexpr int NT = 256;  // threads per block: four wave64s
+constexpr int NWAVE = NT / 64;
+
+// ------------------------------------------------------------------ histogram
+
+template <int NW>
+__global__ __launch_bounds__(NT) void k_radix_hist(const uint64_t* __restrict__ w0,
+                                                   const uint64_t* __restrict__ w1, uint64_t n,
+                                                   uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[NW * 8 * RADIX];
+  for (int x = threadIdx.x; x < NW * 8 * RADIX; x += NT) s_h[x] = 0;
+  __syncthreads();
+  for (uint64_t e = (uint64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (uint64_t)gridDim.x * NT) {
+    const uint64_t a = w0[e];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) atomicAdd(&s_h[q * RADIX + ((a >> (8 * q)) & 255u)], 1u);
+    if (NW == 2) {
+      const uint64_t b = w1[e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) atomicAdd(&s_h[(8 + q) * RADIX + ((b >> (8 * q)) & 255u)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < NW * 8 * RADIX; x += NT)
+    if (s_h[x]) atomicAdd(&hist[x], s_h[x]);
+}
+
+// ------------------------------------------------------------------ one pass
+
+template <int NW, bool HAS_VAL, int ITEMS>
+__global__ __launch_bounds__(NT) void k_onesweep(
+    const uint64_t* __restrict__ in0, const uint64_t* __restrict__ in1,
+    const uint32_t* __restrict__ vin, uint64_t* __restrict__ out0, uint64_t* __restrict__ out1,
+    uint32_t* __restrict__ vout, uint32_t n, int word, int shift,
+    const uint32_t* __restrict__ hist256, uint64_t* __restrict__ status,
+    uint32_t* __restrict__ tile_counter, uint32_t epoch, uint32_t* __restrict__ err) {
+  constexpr int TILE = NT * ITEMS;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_wh[NWAVE][RADIX];  // per-wave digit counts, then per-wave offsets
+  __shared__ uint32_t s_lstart[RADIX];     // digit start inside the tile
+  __shared__ uint32_t s_gstart[RADIX];     // digit start in the output for this tile
+  __shared__ uint32_t s_tmp[NWAVE];
+  __shared__ uint32_t s_gidx[TILE];        // output index of each staged slot
+  __shared__ uint64_t s_stage[TILE];
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
+  const uint32_t w = tid >> 6;
+  if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+  for (int x = tid; x < NWAVE * RADIX; x += NT) (&s_wh[0][0])[x] = 0;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  if (tile >= gridDim.x) return;  // counters are zeroed per pass; never taken
+  const uint64_t base = (uint64_t)tile * TILE;
+  const uint32_t nvalid = (uint32_t)min<uint64_t>((uint64_t)TILE, (uint64_t)n - base);
+
+  uint64_t k0[ITEMS], k1[ITEMS];
+  uint32_t val[ITEMS], dig[ITEMS], rnk[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const uint64_t e = base + (uint64_t)w * 64 * ITEMS + (uint64_t)r * 64 + lane;
+    const bool valid = e < n;
+    k0[r] = valid ? in0[e] : 0;
+    if (NW == 2) k1[r] = valid ? in1[e] : 0;
+    if (HAS_VAL) val[r] = valid ? vin[e] : 0;
+  }
+  // rank: elements are ordered (wave, item, lane), which is memory order
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const uint64_t e = base + (uint64_t)w * 64 * ITEMS + (uint64_t)r * 64 + lane;
+    const bool valid = e < n;
+    const uint64_t kw = (NW == 2 && word == 1) ? k1[r] : k0[r];
+    const uint32_t d = (uint32_t)(kw >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bb = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t below = mask_rank(peers);
+    uint32_t prev = 0;
+    if (valid) prev = s_wh[w][d];
+    if (valid && below == 0) s_wh[w][d] = prev + (uint32_t)__popcll(peers);
+    dig[r] = valid ? d : RADIX;
+    rnk[r] = prev + below;
+  }
+  __syncthreads();
+
+  // per-digit tile counts, per-wave offsets, bucket bases, look-back
+  {
+    const uint32_t t = tid;
+    const uint32_t c0 = s_wh[0][t], c1 = s_wh[1][t], c2 = s_wh[2][t], c3 = s_wh[3][t];
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    uint32_t sum;
+    const uint32_t bbase = block_excl_scan<NT>(hist256[t], s_tmp, &sum);
+    const uint32_t lstart = block_excl_scan<NT>(tot, s_tmp, &sum);
+    const uint64_t excl = lb_exclusive(status + t, tile, RADIX, epoch, tot, err);
+    s_wh[0][t] = 0;
+    s_wh[1][t] = c0;
+    s_wh[2][t] = c0 + c1;
+    s_wh[3][t] = c0 + c1 + c2;
+    s_lstart[t] = lstart;
+    s_gstart[t] = bbase + (uint32_t)excl;
+  }
+  __syncthreads();
+
+  uint32_t lpos[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const uint32_t d = dig[r];
+    if (d < RADIX) {
+      const uint32_t off = s_wh[w][d] + rnk[r];
+      lpos[r] = s_lstart[d] + off;
+      s_gidx[lpos[r]] = s_gstart[d] + off;
+    }
+  }
+  // word 0
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r)
+    if (dig[r] < RADIX) s_stage[lpos[r]] = k0[r];
+  __syncthreads();
+  for (uint32_t s = tid; s < nvalid; s += NT) out0[s_gidx[s]] = s_stage[s];
+  if (NW == 2) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+      if (dig[r] < RADIX) s_stage[lpos[r]] = k1[r];
+    __syncthreads();
+    for (uint32_t s = tid; s < nvalid; s += NT) out1[s_gidx[s]] = s_stage[s];
+  }
+  if (HAS_VAL) {
+    uint32_t* s_v = reinterpret_cast<uint32_t*>(s_stage);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+      if (dig[r] < RADIX) s_v[lpos[r]] = val[r];
+    __syncthreads();
+    for (uint32_t s = tid; s < nvalid; s += NT) vout[s_gidx[s]] = s_v[s];
+  }
+}
+
+// ------------------------------------------------------------------ scan
+
+// Exclusive scan of n 32-bit counts into n + 1 64-bit offsets (out[n] is the
+// total) in one pass with decoupled look-back.
+constexpr int SCAN_ITEMS = 16;
+__global__ __launch_bounds__(NT) void k_scan_excl(const uint32_t* __restrict__ in,
+                                                  uint64_t* __restrict__ out, uint64_t n,
+                                                  uint64_t* __restrict__ status,
+                                                  uint32_t* __restrict__ tile_counter,
+                                                  uint32_t epoch, uint32_t* __restrict__ err) {
+  constexpr int TILE = NT * SCAN_ITEMS;
+  __shared__ uint32_t s_tile;
+  __shared__ uint64_t s_tmp[NWAVE];
+  __shared__ uint64_t s_excl;
+  if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+  __syncthreads();
+  const uint64_t tile = s_tile;
+  if (tile >= gridDim.x) return;
+  const uint64_t first = tile * TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS];
+  uint64_t tsum = 0;
+#pragma unroll
+  for (int x = 0; x < SCAN_ITEMS; ++x) {
+    v[x] = (first + x < n) ? in[first + x] : 0u;
+    tsum += v[x];
+  }
+  uint64_t total;
+  const uint64_t texcl = block_excl_scan<NT>(tsum, s_tmp, &total);
+  if (threadIdx.x == 0) s_excl = lb_exclusive(status, tile, 1, epoch, total, err);
+  __syncthreads();
+  uint64_t run = s_excl + texcl;
+#pragma unroll
+  for (int x = 0; x < SCAN_ITEMS; ++x) {
+    if (first + x < n) out[first + x] = run;
+    run += v[x];
+    if (first + x + 1 == n) out[n] = run;
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, uint64_t n) {
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+}  // namespace sdk
+
+// ------------------------------------------------------------------ launchers
+
+namespace sd {
+
+static unsigned grid_for(uint64_t n, unsigned per_block, unsigned cap) {
+  uint64_t g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(sdk::k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(sdk::k_fill_u64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_radix_hist(const uint64_t* w0, const uint64_t* w1, int nwords, uint64_t n,
+                       uint32_t* hist, hipStream_t s) {
+  if (!n) return;
+  const unsigned g = grid_for(n, sdk::NT * 16, 2048);
+  if (nwords == 2)
+    hipLaunchKernelGGL(sdk::k_radix_hist<2>, dim3(g), dim3(sdk::NT), 0, s, w0, w1, n, hist);
+  else
+    hipLaunchKernelGGL(sdk::k_radix_hist<1>, dim3(g), dim3(sdk::NT), 0, s, w0, w1, n, hist);
+}
+
+uint64_t onesweep_tile(int nwords, bool has_val) {
+  (void)nwords;
+  (void)has_val;
+  return (uint64_t)sdk::NT * 16;
+}
+
+void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* vin,
+                     uint64_t* out0, uint64_t* out1, uint32_t* vout, int nwords, bool has_val,
+                     uint32_t n, int digit_pos, const uint32_t* hist256, uint64_t* status,
+                     uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s) {
+  if (!n) return;
+  const int word = digit_pos / 8;
+  const int shift = (digit_pos % 8) * 8;
+  const uint64_t tiles = (n + onesweep_tile(nwords, has_val) - 1) / onesweep_tile(nwords, has_val);
+  dim3 g((unsigned)tiles), b(sdk::NT);
+  if (nwords == 2 && has_val)
+    hipLaunchKernelGGL((sdk::k_onesweep<2, true, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
+                       vout, n, word, shift, hist256, status, tile_counter, epoch, err);
+  else if (nwords == 2)
+    hipLaunchKernelGGL((sdk::k_onesweep<2, false, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
+                       vout, n, word, shift, hist256, status, tile_counter, epoch, err);
+  else if (has_val)
+    hipLaunchKernelGGL((sdk::k_onesweep<1, true, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
+                       vout, n, word, shift, hist256, status, tile_counter, epoch, err);
+  else
+    hipLaunchKernelGGL((sdk::k_onesweep<1, false, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
+                       vout, n, word, shift, hist256, status, tile_counter, epoch, err);
+}
+
+uint64_t scan_tile() { return (uint64_t)sdk::NT * sdk::SCAN_ITEMS; }
+
+void launch_scan_excl(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* status,
+                      uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s) {
+  const uint64_t tiles = n ? (n + scan_tile() - 1) / scan_tile() : 0;
+  if (!tiles) {
+    launch_fill_u64(out, 0, 1, s);
+    return;
+  }
+  hipLaunchKernelGGL(sdk::k_scan_excl, dim3((unsigned)tiles), dim3(sdk::NT), 0, s, in, out, n,
+                     status, tile_counter, epoch, err);
+}
+
+}  // namespace sd

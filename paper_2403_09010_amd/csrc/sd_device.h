@@ -1,0 +1,172 @@
+// Device-side helpers shared by the HIP kernels of the symdel library:
+// the exact 128-bit variant key, wave64 primitives and the decoupled
+// look-back status words.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned __int128 u128;
+
+// ------------------------------------------------------------------ keys
+//
+// A sequence or deletion variant of length L <= 24 is one 128-bit integer:
+// bits 127..120 hold L, residue t occupies bits [115 - 5t, 119 - 5t]
+// (residues most significant first), unused low bits are zero. The packing
+// is injective, so equal keys are equal strings (the paper's compression of
+// a CDR3 into 12 bytes at 5 bits per residue, Appendix A, widened to 24
+// residues and a length field so that no two strings share a key).
+constexpr int KEY_FIELD_BITS = 120;
+constexpr int KEY_MAX_LEN = 24;
+
+__device__ __forceinline__ u128 u128_one() { return (u128)1; }
+
+__device__ __forceinline__ uint32_t key_len(u128 key) { return (uint32_t)(key >> 120); }
+
+__device__ __forceinline__ uint32_t key_residue(u128 key, int t) {
+  return (uint32_t)(key >> (115 - 5 * t)) & 31u;
+}
+
+// The key of the string with position p removed (0 <= p < L).
+__device__ __forceinline__ u128 key_delete(u128 key, int p) {
+  const uint32_t L = key_len(key);
+  const u128 field = key & ((u128_one() << KEY_FIELD_BITS) - 1);
+  const u128 above = field & ~((u128_one() << (120 - 5 * p)) - 1);
+  const u128 below = field & ((u128_one() << (115 - 5 * p)) - 1);
+  return ((u128)(L - 1) << 120) | above | (below << 5);
+}
+
+// Number of deletion variants with at most k deleted positions, counted
+// with multiplicity: sum_{m <= min(k, L)} C(L, m) (Section II A).
+__host__ __device__ __forceinline__ uint32_t num_variants(uint32_t L, int k) {
+  uint32_t v = 1;
+  if (k >= 1 && L >= 1) v += L;
+  if (k >= 2 && L >= 2) v += L * (L - 1) / 2;
+  return v;
+}
+
+// Variant number v of a key in the enumeration order: v = 0 keeps the
+// string, v = 1..L deletes position v-1, larger v delete a position pair
+// (p1 < p2) in lexicographic order.
+__device__ __forceinline__ u128 key_variant(u128 key, uint32_t v) {
+  const uint32_t L = key_len(key);
+  if (v == 0) return key;
+  if (v <= L) return key_delete(key, (int)v - 1);
+  uint32_t u = v - 1 - L;
+  uint32_t p1 = 0;
+  while (u >= L - 1 - p1) {
+    u -= L - 1 - p1;
+    ++p1;
+  }
+  const uint32_t p2 = p1 + 1 + u;
+  return key_delete(key_delete(key, (int)p2), (int)p1);
+}
+
+// ------------------------------------------------------------------ wave64
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// number of set bits of mask in lanes below this lane
+__device__ __forceinline__ uint32_t mask_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T t = __shfl_up(v, o, 64);
+    if (lane >= (uint32_t)o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread over a block of NT threads (NT a
+// multiple of 64, at most 1024). s_tmp holds NT/64 entries. Returns the
+// exclusive prefix; *total receives the block sum. Contains barriers.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* s_tmp, T* total) {
+  constexpr int NW = NT / 64;
+  const uint32_t lane = lane_id();
+  const uint32_t w = threadIdx.x / 64;
+  T incl = wave_incl_scan(v);
+  if (lane == 63) s_tmp[w] = incl;
+  __syncthreads();
+  T before = 0, sum = 0;
+#pragma unroll
+  for (int x = 0; x < NW; ++x) {
+    T t = s_tmp[x];
+    if ((uint32_t)x < w) before += t;
+    sum += t;
+  }
+  __syncthreads();
+  *total = sum;
+  return before + incl - v;
+}
+
+// ------------------------------------------------------------------ look-back
+//
+// Decoupled look-back (Merrill & Garland, "Single-pass parallel prefix scan
+// with decoupled look-back", 2016). One 64-bit status word per (tile, lane of
+// the scan): bits 63..48 an epoch that tags the pass, bits 47..46 a flag
+// (1 = tile aggregate only, 2 = inclusive prefix), bits 45..0 the value.
+// Words from an older epoch read as "not ready", so the status array never
+// needs clearing between passes.
+constexpr uint64_t LB_AGG = 1, LB_PREFIX = 2;
+constexpr uint64_t LB_VALUE_MASK = (1ull << 46) - 1;
+
+__device__ __forceinline__ uint64_t lb_pack(uint64_t epoch, uint64_t flag, uint64_t value) {
+  return (epoch << 48) | (flag << 46) | (value & LB_VALUE_MASK);
+}
+
+__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish this tile's aggregate, walk back over earlier tiles until an
+// inclusive prefix is found, publish this tile's inclusive prefix and return
+// the exclusive prefix. `stride` is the distance between consecutive tiles'
+// words for this lane. Tiles must be numbered in the order they started
+// (dynamic tile ids), so every earlier tile is resident or finished.
+// The wait is bounded: after LB_SPIN_LIMIT polls of one word the tile sets
+// SD_ERRBIT_LOOKBACK in *err and stops waiting (the host then reports an
+// error), so every wave exits even if an earlier tile never publishes.
+constexpr uint32_t LB_SPIN_LIMIT = 1u << 22;
+__device__ __forceinline__ uint64_t lb_exclusive(uint64_t* status, uint64_t tile, uint64_t stride,
+                                                 uint64_t epoch, uint64_t aggregate,
+                                                 uint32_t* err) {
+  uint64_t* mine = status + tile * stride;
+  if (tile == 0) {
+    lb_store(mine, lb_pack(epoch, LB_PREFIX, aggregate));
+    return 0;
+  }
+  lb_store(mine, lb_pack(epoch, LB_AGG, aggregate));
+  uint64_t excl = 0;
+  int64_t j = (int64_t)tile - 1;
+  uint32_t spins = 0;
+  while (true) {
+    const uint64_t s = lb_load(status + (uint64_t)j * stride);
+    const uint64_t flag = (s >> 46) & 3u;
+    if ((s >> 48) != epoch || flag == 0) {
+      if (++spins >= LB_SPIN_LIMIT) {
+        atomicOr(err, 8u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    spins = 0;
+    excl += s & LB_VALUE_MASK;
+    if (flag == LB_PREFIX) break;
+    --j;
+  }
+  lb_store(mine, lb_pack(epoch, LB_PREFIX, excl + aggregate));
+  return excl;
+}

@@ -1,0 +1,139 @@
+// Host-side internals of the symdel library: the context, its device memory
+// pool and the kernel launchers each translation unit provides.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/symdel.h"
+
+typedef unsigned __int128 u128;
+
+// device-side validation flags
+#define SD_ERRBIT_LENGTH 1u
+#define SD_ERRBIT_ALPHABET 2u
+#define SD_ERRBIT_INDEX 4u
+#define SD_ERRBIT_LOOKBACK 8u  // a look-back wait hit its bound (internal error)
+
+namespace sd {
+
+// ------------------------------------------------------------------ launchers
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+void launch_radix_hist(const uint64_t* w0, const uint64_t* w1, int nwords, uint64_t n,
+                       uint32_t* hist, hipStream_t s);
+uint64_t onesweep_tile(int nwords, bool has_val);
+void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* vin,
+                     uint64_t* out0, uint64_t* out1, uint32_t* vout, int nwords, bool has_val,
+                     uint32_t n, int digit_pos, const uint32_t* hist256, uint64_t* status,
+                     uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s);
+uint64_t scan_tile();
+void launch_scan_excl(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* status,
+                      uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s);
+
+void launch_pack(const uint8_t* codes, const int64_t* offs, uint64_t n, int k, u128* seq,
+                 uint32_t* vcnt, uint32_t* err, hipStream_t s);
+void launch_vargen(const u128* seq, const uint64_t* voff, uint64_t nseq, int k,
+                   uint64_t* key_lo, uint64_t* key_hi, uint32_t* id, hipStream_t s);
+void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint32_t* id,
+                      uint64_t n, uint64_t* cand, uint64_t cap,
+                      unsigned long long* counter, hipStream_t s);
+uint64_t compact_tile();
+void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* seq_a,
+                           const u128* seq_b, int k, uint32_t* out_i, uint32_t* out_j,
+                           uint8_t* out_d, uint64_t* status, uint32_t* tile_counter,
+                           uint32_t epoch, unsigned long long* out_count, uint32_t* err,
+                           hipStream_t s);
+void launch_pair_distance(const u128* seq_a, uint64_t na, const u128* seq_b, uint64_t nb,
+                          const uint32_t* ia, const uint32_t* ib, uint64_t n, uint8_t* d,
+                          uint32_t* err, hipStream_t s);
+
+// ------------------------------------------------------------------ errors
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+}  // namespace sd
+
+// ------------------------------------------------------------------ context
+
+struct sd_ctx {
+  int device = 0;
+  uint64_t budget = 0;  // 0 = unbounded
+  uint64_t held = 0;    // bytes of device memory held (live + cached)
+  std::string last_error;
+  std::multimap<size_t, void*> cache;      // free device blocks by size
+  std::unordered_map<void*, size_t> live;  // device blocks in use
+  std::unordered_map<void*, int> host_live;  // pinned host result arrays
+  // look-back state
+  uint64_t* status = nullptr;
+  size_t status_words = 0;
+  uint32_t epoch = 0;
+  uint32_t* counters = nullptr;  // small device counter area
+  size_t counters_n = 0;
+  void* pinned = nullptr;  // pinned host staging for small read-backs
+  size_t pinned_bytes = 0;
+  sd_stats stats{};
+  int timing = 0;
+  int path = 0;
+  std::vector<hipEvent_t> events;
+};
+
+namespace sd {
+
+// device memory pool (throws Error on failure)
+void* dalloc(sd_ctx* c, size_t bytes);
+void dfree(sd_ctx* c, void* p);
+template <typename T>
+T* dalloc_t(sd_ctx* c, uint64_t count) {
+  return static_cast<T*>(dalloc(c, (size_t)(count ? count : 1) * sizeof(T)));
+}
+// RAII list of scratch blocks released at scope exit
+struct Scratch {
+  sd_ctx* c;
+  std::vector<void*> blocks;
+  explicit Scratch(sd_ctx* ctx) : c(ctx) {}
+  template <typename T>
+  T* get(uint64_t count) {
+    T* p = dalloc_t<T>(c, count);
+    blocks.push_back(p);
+    return p;
+  }
+  ~Scratch() {
+    for (void* p : blocks) dfree(c, p);
+  }
+};
+
+void hip_check(hipError_t e, const char* what);
+// look-back status area with at least `words` words; returns a fresh epoch
+uint32_t next_epoch(sd_ctx* c, uint64_t words, hipStream_t s);
+// zeroed device counters (at least n), on stream s
+uint32_t* fresh_counters(sd_ctx* c, size_t n, hipStream_t s);
+// copy `bytes` from device to the pinned staging area and wait for stream s
+void* readback(sd_ctx* c, const void* dptr, size_t bytes, hipStream_t s);
+
+// stage timing (HIP events on the call's stream; no host synchronisation
+// until the end of the call)
+struct StageTimer {
+  sd_ctx* c;
+  hipStream_t s;
+  bool on;
+  std::vector<std::pair<std::string, double>> names;  // name, algorithmic bytes
+  std::vector<int> launches;
+  StageTimer(sd_ctx* ctx, hipStream_t st);
+  void mark(const char* name, double bytes, int launches = 1);  // ends the stage begun by the previous mark
+  void finish();  // waits for the stream and fills ctx->stats
+};
+
+// the search pipelines
+void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream_t s);
+void pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32_t* ia,
+                   const uint32_t* ib, int64_t n, uint8_t* d_out, hipStream_t s);
+
+}  // namespace sd

@@ -1,0 +1,285 @@
+// Sequence-side kernels of the symdel library for gfx950:
+//   k_pack            compress CSR residue codes into exact 128-bit keys
+//                     (Appendix A XTNeighbor step 1, "compress")
+//   k_vargen          every deletion variant with <= k deletions as a key and
+//                     its source id (steps 2-3, the one-to-many "expand")
+//   k_emit_runs       groups of equal keys in a sorted key array -> id pairs
+//                     (steps 4-5, "uniqueCount" + "expand")
+//   k_verify_compact  drop repeated candidates, keep pairs with Levenshtein
+//                     distance <= k, compact in order (steps 6-7)
+//   k_pair_distance   Levenshtein distance of given pairs
+#include "sd_device.h"
+#include "sd_internal.h"
+
+namespace sdk {
+
+constexpr int NT = 256;
+
+// ------------------------------------------------------------------ Levenshtein
+//
+// Bit-parallel edit distance (Myers 1999, in the global-distance form of
+// Hyyro 2001): the pattern a (m <= 24 residues) lives in one 32-bit word, the
+// text b is consumed one residue per step, and the score tracks the last row
+// of the dynamic programme. Bits above m-1 carry junk that never reaches the
+// low m bits (only shifts left and carries move bits, and they move upward).
+__device__ __forceinline__ uint32_t lev_keys(u128 a, u128 b) {
+  const uint32_t m = key_len(a), n = key_len(b);
+  if (m == 0) return n;
+  if (n == 0) return m;
+  uint32_t ares[KEY_MAX_LEN];
+#pragma unroll
+  for (int t = 0; t < KEY_MAX_LEN; ++t) ares[t] = (uint32_t)t < m ? key_residue(a, t) : 31u;
+  uint32_t pv = (1u << m) - 1u, mv = 0u, score = m;
+  const uint32_t top = 1u << (m - 1);
+  u128 text = b;
+  for (uint32_t j = 0; j < n; ++j) {
+    const uint32_t c = (uint32_t)(text >> 115) & 31u;
+    text <<= 5;
+    uint32_t eq = 0;
+#pragma unroll
+    for (int t = 0; t < KEY_MAX_LEN; ++t) eq |= (ares[t] == c ? 1u : 0u) << t;
+    const uint32_t xv = eq | mv;
+    const uint32_t xh = (((eq & pv) + pv) ^ pv) | eq;
+    uint32_t ph = mv | ~(xh | pv);
+    uint32_t mh = pv & xh;
+    if (ph & top)
+      ++score;
+    else if (mh & top)
+      --score;
+    ph = (ph << 1) | 1u;
+    mh = mh << 1;
+    pv = mh | ~(xv | ph);
+    mv = ph & xv;
+  }
+  return score;
+}
+
+// ------------------------------------------------------------------ pack
+
+__global__ __launch_bounds__(NT) void k_pack(const uint8_t* __restrict__ codes,
+                                             const int64_t* __restrict__ offs, uint64_t n, int k,
+                                             u128* __restrict__ seq, uint32_t* __restrict__ vcnt,
+                                             uint32_t* __restrict__ err) {
+  const uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const int64_t a = offs[i], b = offs[i + 1];
+  const int64_t L = b - a;
+  if (L < 1 || L > KEY_MAX_LEN) {
+    atomicOr(err, SD_ERRBIT_LENGTH);
+    seq[i] = 0;
+    if (vcnt) vcnt[i] = 0;
+    return;
+  }
+  u128 key = (u128)L << 120;
+  bool bad = false;
+  for (int t = 0; t < (int)L; ++t) {
+    const uint32_t c = codes[a + t];
+    bad |= c >= 20u;
+    key |= (u128)(c & 31u) << (115 - 5 * t);
+  }
+  if (bad) atomicOr(err, SD_ERRBIT_ALPHABET);
+  seq[i] = key;
+  if (vcnt) vcnt[i] = num_variants((uint32_t)L, k);
+}
+
+// ------------------------------------------------------------------ vargen
+
+constexpr int VG_SEQS = 64;  // sequences per block
+
+__global__ __launch_bounds__(NT) void k_vargen(const u128* __restrict__ seq,
+                                               const uint64_t* __restrict__ voff, uint64_t nseq,
+                                               uint64_t* __restrict__ key_lo,
+                                               uint64_t* __restrict__ key_hi,
+                                               uint32_t* __restrict__ id) {
+  __shared__ uint64_t s_off[VG_SEQS + 1];
+  __shared__ u128 s_seq[VG_SEQS];
+  const uint64_t s0 = (uint64_t)blockIdx.x * VG_SEQS;
+  const uint32_t ns = (uint32_t)min<uint64_t>(VG_SEQS, nseq - s0);
+  for (uint32_t x = threadIdx.x; x <= ns; x += NT) s_off[x] = voff[s0 + x];
+  for (uint32_t x = threadIdx.x; x < ns; x += NT) s_seq[x] = seq[s0 + x];
+  __syncthreads();
+  const uint64_t g0 = s_off[0], g1 = s_off[ns];
+  for (uint64_t g = g0 + threadIdx.x; g < g1; g += NT) {
+    uint32_t lo = 0, hi = ns - 1;  // last x with s_off[x] <= g
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= g)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const u128 key = key_variant(s_seq[lo], (uint32_t)(g - s_off[lo]));
+    key_lo[g] = (uint64_t)key;
+    key_hi[g] = (uint64_t)(key >> 64);
+    id[g] = (uint32_t)(s0 + lo);
+  }
+}
+
+// ------------------------------------------------------------------ group emission
+
+__device__ __forceinline__ bool same_key(const uint64_t* lo, const uint64_t* hi, uint64_t x,
+                                         uint64_t y) {
+  return lo[x] == lo[y] && hi[x] == hi[y];
+}
+
+// In a key-sorted array (stable, so ids ascend inside a group), the first
+// occurrence of each id pairs with every later distinct id of its group.
+// Candidates (i << 32 | j), i < j, are appended after a per-block reservation
+// on *counter; writes past cap are dropped but still counted.
+__global__ __launch_bounds__(NT) void k_emit_runs(const uint64_t* __restrict__ klo,
+                                                  const uint64_t* __restrict__ khi,
+                                                  const uint32_t* __restrict__ id, uint64_t n,
+                                                  uint64_t* __restrict__ cand, uint64_t cap,
+                                                  unsigned long long* __restrict__ counter) {
+  __shared__ uint64_t s_tmp[NT / 64];
+  __shared__ uint64_t s_base;
+  const uint64_t p = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  bool first = p < n;
+  if (first && p > 0) first = !(same_key(klo, khi, p, p - 1) && id[p] == id[p - 1]);
+  uint64_t cnt = 0;
+  if (first) {
+    for (uint64_t q = p + 1; q < n && same_key(klo, khi, q, p); ++q) cnt += id[q] != id[q - 1];
+  }
+  uint64_t total;
+  const uint64_t excl = block_excl_scan<NT>(cnt, s_tmp, &total);
+  if (threadIdx.x == 0) s_base = total ? atomicAdd(counter, (unsigned long long)total) : 0;
+  __syncthreads();
+  if (cnt) {
+    uint64_t pos = s_base + excl;
+    const uint64_t ip = (uint64_t)id[p] << 32;
+    for (uint64_t q = p + 1; q < n && same_key(klo, khi, q, p); ++q) {
+      if (id[q] != id[q - 1]) {
+        if (pos < cap) cand[pos] = ip | id[q];
+        ++pos;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ verify
+
+constexpr int CITEMS = 8;
+
+__global__ __launch_bounds__(NT) void k_verify_compact(
+    const uint64_t* __restrict__ cand, uint64_t c, const u128* __restrict__ sa,
+    const u128* __restrict__ sb, int k, uint32_t* __restrict__ oi, uint32_t* __restrict__ oj,
+    uint8_t* __restrict__ od, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter,
+    uint32_t epoch, unsigned long long* __restrict__ out_count, uint32_t* __restrict__ err) {
+  constexpr int TILE = NT * CITEMS;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_tmp[NT / 64];
+  __shared__ uint64_t s_excl;
+  if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+  __syncthreads();
+  const uint64_t tile = s_tile;
+  if (tile >= gridDim.x) return;
+  const uint64_t first = tile * TILE + (uint64_t)threadIdx.x * CITEMS;
+  uint32_t keepmask = 0, cnt = 0;
+  uint8_t dist[CITEMS];
+#pragma unroll
+  for (int x = 0; x < CITEMS; ++x) {
+    const uint64_t e = first + x;
+    dist[x] = 0;
+    if (e < c) {
+      const uint64_t v = cand[e];
+      if (e == 0 || cand[e - 1] != v) {
+        const u128 a = sa[v >> 32], b = sb[(uint32_t)v];
+        const int la = (int)key_len(a), lb = (int)key_len(b);
+        if (abs(la - lb) <= k) {
+          const uint32_t d = lev_keys(a, b);
+          if (d <= (uint32_t)k) {
+            keepmask |= 1u << x;
+            dist[x] = (uint8_t)d;
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  uint32_t total;
+  const uint32_t texcl = block_excl_scan<NT>(cnt, s_tmp, &total);
+  if (threadIdx.x == 0) s_excl = lb_exclusive(status, tile, 1, epoch, total, err);
+  __syncthreads();
+  uint64_t pos = s_excl + texcl;
+#pragma unroll
+  for (int x = 0; x < CITEMS; ++x) {
+    if (keepmask & (1u << x)) {
+      const uint64_t v = cand[first + x];
+      oi[pos] = (uint32_t)(v >> 32);
+      oj[pos] = (uint32_t)v;
+      od[pos] = dist[x];
+      ++pos;
+    }
+  }
+  if (threadIdx.x == 0 && tile == gridDim.x - 1) *out_count = s_excl + total;
+}
+
+__global__ __launch_bounds__(NT) void k_pair_distance(const u128* __restrict__ sa, uint64_t na,
+                                                      const u128* __restrict__ sb, uint64_t nb,
+                                                      const uint32_t* __restrict__ ia,
+                                                      const uint32_t* __restrict__ ib, uint64_t n,
+                                                      uint8_t* __restrict__ d,
+                                                      uint32_t* __restrict__ err) {
+  const uint64_t t = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= n) return;
+  const uint32_t x = ia[t], y = ib[t];
+  if (x >= na || y >= nb) {  // out-of-range pair: flag it, read nothing
+    atomicOr(err, SD_ERRBIT_INDEX);
+    d[t] = 255;
+    return;
+  }
+  const uint32_t v = lev_keys(sa[x], sb[y]);
+  d[t] = (uint8_t)(v > 255u ? 255u : v);
+}
+
+}  // namespace sdk
+
+namespace sd {
+
+static unsigned blocks_for(uint64_t n, uint64_t per) { return (unsigned)((n + per - 1) / per); }
+
+void launch_pack(const uint8_t* codes, const int64_t* offs, uint64_t n, int k, u128* seq,
+                 uint32_t* vcnt, uint32_t* err, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(sdk::k_pack, dim3(blocks_for(n, sdk::NT)), dim3(sdk::NT), 0, s, codes, offs,
+                     n, k, seq, vcnt, err);
+}
+
+void launch_vargen(const u128* seq, const uint64_t* voff, uint64_t nseq, int k, uint64_t* key_lo,
+                   uint64_t* key_hi, uint32_t* id, hipStream_t s) {
+  (void)k;
+  if (!nseq) return;
+  hipLaunchKernelGGL(sdk::k_vargen, dim3(blocks_for(nseq, sdk::VG_SEQS)), dim3(sdk::NT), 0, s,
+                     seq, voff, nseq, key_lo, key_hi, id);
+}
+
+void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint32_t* id,
+                      uint64_t n, uint64_t* cand, uint64_t cap, unsigned long long* counter,
+                      hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(sdk::k_emit_runs, dim3(blocks_for(n, sdk::NT)), dim3(sdk::NT), 0, s, key_lo,
+                     key_hi, id, n, cand, cap, counter);
+}
+
+uint64_t compact_tile() { return (uint64_t)sdk::NT * sdk::CITEMS; }
+
+void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* seq_a,
+                           const u128* seq_b, int k, uint32_t* out_i, uint32_t* out_j,
+                           uint8_t* out_d, uint64_t* status, uint32_t* tile_counter,
+                           uint32_t epoch, unsigned long long* out_count, uint32_t* err,
+                           hipStream_t s) {
+  if (!c) return;
+  hipLaunchKernelGGL(sdk::k_verify_compact, dim3(blocks_for(c, compact_tile())), dim3(sdk::NT), 0,
+                     s, cand, c, seq_a, seq_b, k, out_i, out_j, out_d, status, tile_counter, epoch,
+                     out_count, err);
+}
+
+void launch_pair_distance(const u128* seq_a, uint64_t na, const u128* seq_b, uint64_t nb,
+                          const uint32_t* ia, const uint32_t* ib, uint64_t n, uint8_t* d,
+                          uint32_t* err, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(sdk::k_pair_distance, dim3(blocks_for(n, sdk::NT)), dim3(sdk::NT), 0, s,
+                     seq_a, na, seq_b, nb, ia, ib, n, d, err);
+}
+
+}  // namespace sd

@@ -1,0 +1,245 @@
+"""Parity of the HIP self-search path with the CPU oracle (bit-exact: the
+output is integer triplets). Small workloads are compared element by
+element; the 1M-sequence k=2 workload is checked on sampled outputs the
+oracle computes one by one plus properties that hold at any size."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import cdr3gen
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "oracle_results.json")))
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2403_09010_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(codes, offsets):
+    import torch
+    return (torch.from_numpy(np.ascontiguousarray(codes)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(offsets)).cuda())
+
+
+def gpu_triples(ctx, codes, offsets, k, device=True):
+    if device:
+        r = ctx.self_search(*to_dev(codes, offsets), k)
+    else:
+        r = ctx.self_search(codes, offsets, k)
+    i, j, d = r.numpy()
+    return i.astype(np.uint32), j.astype(np.uint32), d.astype(np.int32)
+
+
+def oracle_triples(codes, offsets, k):
+    import oracle
+    a, b, d = oracle.self_search(codes, offsets, k)
+    return a, b, d
+
+
+def assert_same(got, want):
+    gi, gj, gd = got
+    wi, wj, wd = want
+    assert len(gi) == len(wi), (len(gi), len(wi))
+    assert np.array_equal(gi, wi)
+    assert np.array_equal(gj, wj)
+    assert np.array_equal(gd, wd)
+
+
+def csr(strings):
+    offs = np.zeros(len(strings) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(s) for s in strings])
+    return np.frombuffer(b"".join(strings), dtype=np.uint8).copy(), offs
+
+
+def sha(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+# ---------------------------------------------------------------- distances
+
+def test_pair_distance_exhaustive_small_alphabet(ctx):
+    import itertools
+    import torch
+    import oracle
+    strings = [bytes(t) for L in range(1, 7) for t in itertools.product(range(3), repeat=L)]
+    c, o = csr(strings)
+    rng = np.random.default_rng(0)
+    ia = rng.integers(0, len(strings), 200000).astype(np.int32)
+    ib = rng.integers(0, len(strings), 200000).astype(np.int32)
+    log("pair_distance: 200000 pairs over 3-letter strings of length 1..6")
+    d = ctx.pair_distance(to_dev(c, o), to_dev(c, o), torch.from_numpy(ia).cuda(),
+                          torch.from_numpy(ib).cuda()).cpu().numpy()
+    want = np.array([oracle.lev(strings[x], strings[y]) for x, y in zip(ia[:20000], ib[:20000])])
+    assert np.array_equal(d[:20000], want)
+
+
+def test_pair_distance_long_sequences(ctx):
+    import torch
+    import oracle
+    c, o = cdr3gen.generate(77, 3000)
+    rng = np.random.default_rng(1)
+    ia = rng.integers(0, 3000, 20000).astype(np.int32)
+    ib = rng.integers(0, 3000, 20000).astype(np.int32)
+    log("pair_distance: 20000 random generator pairs")
+    d = ctx.pair_distance(to_dev(c, o), to_dev(c, o), torch.from_numpy(ia).cuda(),
+                          torch.from_numpy(ib).cuda()).cpu().numpy()
+    seqs = [c[o[x]:o[x + 1]].tobytes() for x in range(3000)]
+    want = np.array([oracle.lev(seqs[x], seqs[y]) for x, y in zip(ia, ib)])
+    assert np.array_equal(d, want)
+
+
+def test_pair_distance_rejects_bad_index(ctx):
+    import torch
+    from paper_2403_09010_amd import SymdelError
+    c, o = cdr3gen.generate(3, 10)
+    ia = torch.tensor([0, 10], dtype=torch.int32, device="cuda")
+    ib = torch.tensor([1, 2], dtype=torch.int32, device="cuda")
+    with pytest.raises(SymdelError) as e:
+        ctx.pair_distance(to_dev(c, o), to_dev(c, o), ia, ib)
+    assert e.value.code == -1
+
+
+# ---------------------------------------------------------------- self search
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_plain_10k_matches_oracle(ctx, k):
+    c, o = cdr3gen.plain("plain_10k")
+    log(f"self_search plain_10k k={k}")
+    got = gpu_triples(ctx, c, o, k)
+    assert_same(got, oracle_triples(c, o, k))
+    g = GOLD[f"oracle_plain_10k_k{k}"]
+    assert len(got[0]) == g["pairs"]
+    assert sha(got[0], got[1], got[2].astype(np.uint8)) == g["sha256"]
+
+
+def test_plain_1m_prefix_20k_k2_golden(ctx):
+    c, o = cdr3gen.subset(*cdr3gen.plain("plain_1m"), 20000)
+    log("self_search first 20000 of plain_1m, k=2")
+    got = gpu_triples(ctx, c, o, 2)
+    g = GOLD["oracle_plain_1m_first20k_k2"]
+    assert len(got[0]) == g["pairs"]
+    assert sha(got[0], got[1], got[2].astype(np.uint8)) == g["sha256"]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_exhaustive_small_alphabet(ctx, k):
+    import itertools
+    strings = [bytes(t) for L in range(1, 7) for t in itertools.product(range(3), repeat=L)]
+    c, o = csr(strings)
+    log(f"self_search exhaustive 3-letter strings, k={k}")
+    assert_same(gpu_triples(ctx, c, o, k), oracle_triples(c, o, k))
+
+
+def test_host_and_device_inputs_agree_and_repeat_bitwise(ctx):
+    c, o = cdr3gen.generate(31, 30000)
+    log("self_search host vs device inputs, 30000 sequences k=2")
+    a = gpu_triples(ctx, c, o, 2, device=False)
+    b = gpu_triples(ctx, c, o, 2, device=True)
+    b2 = gpu_triples(ctx, c, o, 2, device=True)
+    assert_same(a, b)
+    assert_same(b, b2)
+
+
+def test_edge_cases(ctx):
+    log("self_search edge cases")
+    # empty input
+    r = ctx.self_search(np.zeros(0, np.uint8), np.zeros(1, np.int64), 2)
+    assert len(r) == 0
+    # one sequence
+    c, o = csr([bytes([1, 2, 3])])
+    assert len(ctx.self_search(c, o, 2)) == 0
+    # lengths 1 and 24, identical copies, tiny strings sharing only the empty variant
+    strings = [bytes([0]), bytes([5, 6]), bytes([0]), bytes(range(20)) + bytes([1, 2, 3, 4]),
+               bytes(range(20)) + bytes([1, 2, 3, 4]), bytes(range(20)) + bytes([1, 2, 3]),
+               bytes([7]), bytes([8, 9])]
+    c, o = csr(strings)
+    for k in (0, 1, 2):
+        assert_same(gpu_triples(ctx, c, o, k, device=False), oracle_triples(c, o, k))
+
+
+def test_heavy_groups(ctx):
+    # many copies of a few sequences: large groups of equal keys
+    base, bo = cdr3gen.generate(41, 40)
+    rng = np.random.default_rng(2)
+    pick = rng.integers(0, 40, 3000)
+    strings = [base[bo[x]:bo[x + 1]].tobytes() for x in pick]
+    c, o = csr(strings)
+    log("self_search heavy groups: 3000 sequences drawn from 40")
+    for k in (1, 2):
+        assert_same(gpu_triples(ctx, c, o, k), oracle_triples(c, o, k))
+
+
+def test_errors(ctx):
+    from paper_2403_09010_amd import SymdelError
+    log("self_search error paths")
+    c, o = csr([bytes([1, 2, 20])])
+    with pytest.raises(SymdelError) as e:
+        ctx.self_search(c, o, 1)
+    assert e.value.name == "SD_E_ALPHABET"
+    c, o = csr([bytes([1] * 25), bytes([1, 2])])
+    with pytest.raises(SymdelError) as e:
+        ctx.self_search(c, o, 1)
+    assert e.value.name == "SD_E_LENGTH"
+    c, o = csr([bytes([1, 2]), b""])
+    with pytest.raises(SymdelError) as e:
+        ctx.self_search(c, o, 1)
+    assert e.value.name == "SD_E_LENGTH"
+    c, o = csr([bytes([1, 2])])
+    with pytest.raises(SymdelError) as e:
+        ctx.self_search(c, o, 3)
+    assert e.value.name == "SD_E_INVAL"
+    # the context stays usable after errors
+    c, o = cdr3gen.plain("plain_10k")
+    assert_same(gpu_triples(ctx, c, o, 1), oracle_triples(c, o, 1))
+
+
+# ---------------------------------------------------------------- full size
+
+def test_plain_1m_k2_sampled(ctx):
+    import oracle
+    c, o = cdr3gen.plain("plain_1m")
+    n = len(o) - 1
+    log("self_search plain_1m k=2 (full size)")
+    i, j, d = gpu_triples(ctx, c, o, 2)
+    assert len(i) > 300000
+    # sorted, unique, i < j
+    key = (i.astype(np.uint64) << np.uint64(32)) | j.astype(np.uint64)
+    assert np.all(i < j) and np.all(np.diff(key.astype(np.int64)) > 0)
+    assert d.min() >= 0 and d.max() <= 2
+    # sampled outputs: exact distances
+    rng = np.random.default_rng(5)
+    seqs = lambda x: c[o[x]:o[x + 1]].tobytes()
+    for t in rng.choice(len(i), 3000, replace=False):
+        assert oracle.lev(seqs(i[t]), seqs(j[t])) == d[t]
+    # sampled completeness: every neighbour of 40 random sequences is reported
+    for x in rng.choice(n, 40, replace=False):
+        dist = oracle.lev_one_to_many(seqs(x), c, o)
+        truth = {(min(x, y), max(x, y), int(dist[y])) for y in np.nonzero(dist <= 2)[0] if y != x}
+        mine = set()
+        for sel in (np.nonzero(i == x)[0], np.nonzero(j == x)[0]):
+            mine |= {(int(i[t]), int(j[t]), int(d[t])) for t in sel}
+        assert mine == truth
+    # bag-of-amino-acids bound (Appendix B) on every output pair
+    bags = np.zeros((n, 20), dtype=np.int16)
+    seq_id = np.repeat(np.arange(n), np.diff(o))
+    np.add.at(bags, (seq_id, c.astype(np.int64)), 1)
+    diff = (bags[i] - bags[j]).astype(np.int64)
+    assert np.all((diff * diff).sum(1) <= 2 * d.astype(np.int64) ** 2)
