@@ -40,14 +40,15 @@ def cpu_baseline(codes, offsets, k, target_s=15.0):
     import cdr3gen
     import oracle
     n = 2000
-    while True:  # grow the sample until one run takes a few seconds
+    while True:  # grow the sample until one run takes about target_s
         c, o = cdr3gen.subset(codes, offsets, n)
         t0 = time.perf_counter()
         a, _, _ = oracle.self_search(c, o, k)
         dt = time.perf_counter() - t0
-        if dt > target_s / 4 or n * 2 > len(offsets) - 1:
+        if dt >= 0.5 * target_s or n >= len(offsets) - 1:
             break
-        n = min(len(offsets) - 1, int(n * min(8.0, max(2.0, (target_s / 4) / max(dt, 1e-3)))))
+        grow = min(8.0, max(1.5, target_s / max(dt, 1e-3)))
+        n = min(len(offsets) - 1, int(n * grow))
     return {"value": len(a) / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} sequences of the workload, k={k}, one thread: "
                       f"{len(a)} pairs in {dt:.2f} s ({n / dt:.0f} sequences/s)",
@@ -61,6 +62,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="plain_1m_k2", choices=sorted(WORKLOADS))
     ap.add_argument("--path", type=int, default=0, help="grouping path (0 auto, 1 full-key sort)")
+    ap.add_argument("--group-cap", type=int, default=0, help="hashed path LDS capacity (0 auto)")
+    ap.add_argument("--group-bits", type=int, default=0, help="hashed path hash bits (0 auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
     args = ap.parse_args()
@@ -71,7 +74,8 @@ def main():
     import torch
     import cdr3gen
     from paper_2403_09010_amd import Context
-    from paper_2403_09010_amd.symdel import OPT_PATH, OPT_TIMING, _Seqs
+    from paper_2403_09010_amd.symdel import (OPT_GROUP_BITS, OPT_GROUP_CAP, OPT_PATH, OPT_TIMING,
+                                             _Seqs)
 
     gen_name, k = WORKLOADS[args.workload]
     log(f"generating {gen_name}")
@@ -83,6 +87,8 @@ def main():
     seqs = _Seqs(codes_t.data_ptr(), offs_t.data_ptr(), n, 1)
     ctx = Context(0)
     ctx.set_option(OPT_PATH, args.path)
+    ctx.set_option(OPT_GROUP_CAP, args.group_cap)
+    ctx.set_option(OPT_GROUP_BITS, args.group_bits)
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
 
@@ -137,7 +143,8 @@ def main():
         "data": "synthetic (seeded CDR3-like generator)",
         "config": {"workload": args.workload, "n_seqs": n, "k": k, "seed": cdr3gen.PLAIN_CONFIGS[gen_name][0],
                    "pairs": int(npairs), "keys": st["n_keys"], "candidates_raw": st["n_cand_raw"],
-                   "seconds_per_search": round(dt, 6), "path": args.path},
+                   "seconds_per_search": round(dt, 6), "path": args.path,
+                   "group_cap": args.group_cap, "group_bits": args.group_bits},
         "stages_ms": {s: round(stage_ms[s] / args.steps, 4) for s in stage_ms},
         "roofline": roofline,
     }

@@ -78,6 +78,7 @@ typedef struct {
   int64_t n_pairs;        /* pairs returned */
   int32_t n_stages;       /* valid entries below (0 unless SD_OPT_TIMING is on) */
   int32_t n_sort_passes;  /* radix passes run by the grouping sort */
+  int64_t n_big_segments; /* hashed path: hash segments too large for LDS (full-key path) */
   char stage_name[SD_MAX_STAGES][24];
   double stage_ms[SD_MAX_STAGES];      /* device time between HIP events on `stream` */
   double stage_bytes[SD_MAX_STAGES];   /* algorithmic HBM bytes of the stage */
@@ -86,7 +87,9 @@ typedef struct {
 
 /* Options for sd_set_option. */
 #define SD_OPT_TIMING 1  /* 1: record per-stage HIP events (adds no host synchronisation) */
-#define SD_OPT_PATH 2    /* grouping path: 0 = automatic, 1 = full-key LSD sort, 2 = hashed buckets */
+#define SD_OPT_PATH 2       /* grouping path: 0 = automatic, 1 = full-key LSD sort, 2 = hashed segments */
+#define SD_OPT_GROUP_CAP 3  /* hashed path: LDS batch capacity, 0 (automatic), 256, 1024, 2048 or 4096 */
+#define SD_OPT_GROUP_BITS 4 /* hashed path: hash bits sorted by LSD passes, 0 (automatic) .. 23 */
 
 /*
  * Create a context on HIP device `device`. hbm_budget_bytes bounds the

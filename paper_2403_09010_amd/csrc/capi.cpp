@@ -215,6 +215,14 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
       if (value < 0 || value > 2) return SD_E_INVAL;
       c->path = (int)value;
       return SD_OK;
+    case SD_OPT_GROUP_CAP:
+      if (value != 0 && !sd::group_cap_supported((int)value)) return SD_E_INVAL;
+      c->group_cap = (int)value;
+      return SD_OK;
+    case SD_OPT_GROUP_BITS:
+      if (value < 0 || value > 23) return SD_E_INVAL;
+      c->group_bits = (int)value;
+      return SD_OK;
     default:
       c->last_error = "unknown option";
       return SD_E_INVAL;

@@ -1,0 +1,420 @@
+// Hashed grouping path for gfx950: equal deletion variants are brought
+// together without sorting the 128-bit keys themselves.
+//
+//   k_vargen_hash   every <= k-deletion variant of every sequence as one
+//                   64-bit element [hash of the exact key | sequence id],
+//                   with 24 id bits (40 hash bits) up to 2^24 sequences and
+//                   32 id bits (32 hash bits) above; also the digit
+//                   histograms of the hash passes
+//   (LSD passes)    k_onesweep_keys over the top B hash bits (radix.hip):
+//                   equal keys have equal hashes, so every group of equal
+//                   keys lies inside one "segment" of equal top-B bits
+//   k_seg_bounds    the [start, end) range of every segment
+//   k_group_seg     one workgroup per run of whole segments: an LDS hash
+//                   table groups the elements by their full stored hash and
+//                   emits the id pairs of every group (the paper's
+//                   uniqueCount + expand, Appendix A steps 4-5)
+//   k_gather_big    segments larger than the LDS capacity are copied out,
+//   k_emit_hash_runs  sorted by their full hash and emitted by runs
+//
+// Grouping by a hash instead of the exact key cannot lose a pair (equal keys
+// hash alike); a collision only adds a candidate whose exact distance the
+// verification step then rejects, so the result is the same set.
+#include "sd_device.h"
+#include "sd_internal.h"
+
+namespace sdk {
+
+// 64-bit hash of a key: two independent multiply-add forms of the four
+// 32-bit words, each through the murmur3 finaliser. Only the load balance and
+// the rate of extra candidates depend on its quality.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+__device__ __forceinline__ uint64_t key_hash64(u128 key) {
+  const uint32_t w0 = (uint32_t)key, w1 = (uint32_t)(key >> 32);
+  const uint32_t w2 = (uint32_t)(key >> 64), w3 = (uint32_t)(key >> 96);
+  const uint32_t a = w0 * 0x9E3779B1u + w1 * 0x85EBCA77u + w2 * 0xC2B2AE3Du + w3 * 0x27D4EB2Fu;
+  const uint32_t b =
+      w0 * 0x165667B1u + w1 * 0xD3A2646Du + w2 * 0xFD7046C5u + w3 * 0xB55A4F09u + 0x61C88647u;
+  return ((uint64_t)fmix32(a) << 32) | fmix32(b);
+}
+
+// a mix of a stored hash for LDS table slots
+__device__ __forceinline__ uint32_t slot_mix(uint64_t h) {
+  uint32_t x = (uint32_t)h ^ (uint32_t)(h >> 32) * 0x9E3779B1u;
+  x ^= x >> 15;
+  x *= 0x2C1B3C6Du;
+  x ^= x >> 12;
+  x *= 0x297A2D39u;
+  x ^= x >> 15;
+  return x;
+}
+
+// ------------------------------------------------------------------ vargen + hash
+
+constexpr int VG_NT = 256;
+constexpr int VG_SEQS = 64;
+
+// Digit q of the hash passes is (e >> shift[q]) & mask[q].
+struct PassDigits {
+  uint32_t shift[3];
+  uint32_t mask[3];
+};
+
+__global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ seq,
+                                                       const uint64_t* __restrict__ voff,
+                                                       uint64_t nseq, uint64_t* __restrict__ elem,
+                                                       uint32_t idbits, int npass, PassDigits pd,
+                                                       uint32_t* __restrict__ hist) {
+  __shared__ uint64_t s_off[VG_SEQS + 1];
+  __shared__ u128 s_seq[VG_SEQS];
+  __shared__ uint32_t s_h[3 * 256];
+  const uint64_t s0 = (uint64_t)blockIdx.x * VG_SEQS;
+  const uint32_t ns = (uint32_t)min<uint64_t>(VG_SEQS, nseq - s0);
+  for (uint32_t x = threadIdx.x; x <= ns; x += VG_NT) s_off[x] = voff[s0 + x];
+  for (uint32_t x = threadIdx.x; x < ns; x += VG_NT) s_seq[x] = seq[s0 + x];
+  for (uint32_t x = threadIdx.x; x < 3 * 256; x += VG_NT) s_h[x] = 0;
+  __syncthreads();
+  const uint64_t idmask = (1ull << idbits) - 1;
+  const uint64_t g0 = s_off[0], g1 = s_off[ns];
+  for (uint64_t g = g0 + threadIdx.x; g < g1; g += VG_NT) {
+    uint32_t lo = 0, hi = ns - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= g)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const uint32_t v = (uint32_t)(g - s_off[lo]);
+    const uint64_t e = (key_hash64(key_variant(s_seq[lo], v)) & ~idmask) | (s0 + lo);
+    elem[g] = e;
+    for (int q = 0; q < npass; ++q)
+      atomicAdd(&s_h[q * 256 + ((uint32_t)(e >> pd.shift[q]) & pd.mask[q])], 1u);
+  }
+  __syncthreads();
+  for (uint32_t x = threadIdx.x; x < (uint32_t)npass * 256; x += VG_NT)
+    if (s_h[x]) atomicAdd(&hist[x], s_h[x]);
+}
+
+// ------------------------------------------------------------------ segment bounds
+
+// After the LSD passes E is sorted by its top B bits (segshift = 64 - B; a
+// shift of 64 means one segment), so segment v is [seg_start[v], seg_end[v]);
+// both stay 0 when v does not occur.
+__device__ __forceinline__ uint32_t seg_of(uint64_t e, uint32_t segshift) {
+  return segshift >= 64 ? 0u : (uint32_t)(e >> segshift);
+}
+
+__global__ __launch_bounds__(256) void k_seg_bounds(const uint64_t* __restrict__ E, uint64_t n,
+                                                    uint32_t segshift,
+                                                    uint32_t* __restrict__ seg_start,
+                                                    uint32_t* __restrict__ seg_end) {
+  for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < n;
+       p += (uint64_t)gridDim.x * 256) {
+    const uint32_t s = seg_of(E[p], segshift);
+    if (p == 0 || seg_of(E[p - 1], segshift) != s) seg_start[s] = (uint32_t)p;
+    if (p + 1 == n || seg_of(E[p + 1], segshift) != s) seg_end[s] = (uint32_t)(p + 1);
+  }
+}
+
+// ------------------------------------------------------------------ local grouping
+
+// LDS layout of one batch of at most CAP elements (22 bytes per element):
+//   [0, 8 CAP)        the elements (hash | id)
+//   [8 CAP, 16 CAP)   open-addressing table, 2 CAP slots of element + 1
+//   [16 CAP, 20 CAP)  per representative: the last member pushed (or NONE)
+//   [20 CAP, 22 CAP)  per member: the member pushed before it (or NONE); a
+//                     repeated (hash, id) is marked REPEAT and never pushed
+constexpr uint32_t NONE16 = 0xFFFFu;
+constexpr uint16_t REPEAT16 = 0xFFFEu;
+constexpr int GROUP_LDS_PER_ELEM = 22;
+
+template <int CAP, int NTH>
+__device__ void group_batch(const uint64_t* __restrict__ E, uint32_t a, uint32_t m,
+                            uint32_t idbits, uint64_t* __restrict__ cand, uint64_t cap,
+                            unsigned long long* __restrict__ ccount, unsigned char* lds,
+                            uint64_t* s_tmp64, uint64_t* s_base) {
+  constexpr int PER = CAP / NTH;
+  uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* s_tab = reinterpret_cast<uint32_t*>(lds + CAP * 8);
+  uint32_t* s_chead = reinterpret_cast<uint32_t*>(lds + CAP * 16);
+  uint16_t* s_next = reinterpret_cast<uint16_t*>(lds + CAP * 20);
+  const uint64_t idmask = (1ull << idbits) - 1;
+  uint32_t ts = 64;  // table slots: a power of two >= 2m
+  while (ts < 2 * m) ts <<= 1;
+
+  for (uint32_t x = threadIdx.x; x < ts; x += NTH) s_tab[x] = 0;
+  for (uint32_t x = threadIdx.x; x < m; x += NTH) {
+    s_chead[x] = NONE16;
+    s_e[x] = E[a + x];
+  }
+  __syncthreads();
+  // Repeated (hash, id) come from one sequence yielding one variant twice
+  // (deleting either of two equal neighbours); inside a segment the stable
+  // passes keep generation order, so equal ids are adjacent. Everything else
+  // goes into the table and onto its representative's member chain.
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const uint32_t x = threadIdx.x + r * NTH;
+    if (x < m) {
+      const uint64_t e = s_e[x];
+      const uint64_t h = e >> idbits;
+      const uint64_t id = e & idmask;
+      bool repeat = false;
+      for (int y = (int)x - 1; y >= 0 && (s_e[y] & idmask) == id; --y) {
+        if ((s_e[y] >> idbits) == h) {
+          repeat = true;
+          break;
+        }
+      }
+      if (repeat) {
+        s_next[x] = REPEAT16;
+      } else {
+        uint32_t slot = slot_mix(h) & (ts - 1);
+        uint32_t rep;
+        while (true) {
+          uint32_t t = s_tab[slot];
+          if (t == 0) {
+            t = atomicCAS(&s_tab[slot], 0u, x + 1);
+            if (t == 0) {
+              rep = x;
+              break;
+            }
+          }
+          if ((s_e[t - 1] >> idbits) == h) {
+            rep = t - 1;
+            break;
+          }
+          slot = (slot + 1) & (ts - 1);
+        }
+        s_next[x] = (uint16_t)atomicExch(&s_chead[rep], x);
+      }
+    }
+  }
+  __syncthreads();
+  // each member pairs with the members pushed before it (distinct ids)
+  uint64_t mycnt = 0;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const uint32_t x = threadIdx.x + r * NTH;
+    if (x < m) {
+      uint32_t y = s_next[x];
+      if (y != REPEAT16)
+        for (; y != NONE16; y = s_next[y]) ++mycnt;
+    }
+  }
+  uint64_t total;
+  const uint64_t excl = block_excl_scan<NTH>(mycnt, s_tmp64, &total);
+  if (threadIdx.x == 0) *s_base = total ? atomicAdd(ccount, (unsigned long long)total) : 0ull;
+  __syncthreads();
+  if (mycnt) {
+    uint64_t pos = *s_base + excl;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const uint32_t x = threadIdx.x + r * NTH;
+      if (x < m) {
+        uint32_t y = s_next[x];
+        if (y == REPEAT16) continue;
+        const uint32_t id = (uint32_t)(s_e[x] & idmask);
+        for (; y != NONE16; y = s_next[y]) {
+          const uint32_t other = (uint32_t)(s_e[y] & idmask);
+          if (pos < cap) {
+            const uint32_t lo = id < other ? id : other, hi = id < other ? other : id;
+            cand[pos] = ((uint64_t)lo << 32) | hi;
+          }
+          ++pos;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// One workgroup per `spw` consecutive segment values; consecutive non-empty
+// segments are batched while they fit in CAP elements. A segment larger than
+// CAP is listed in big[] for the sort-and-runs fallback.
+template <int CAP, int NTH>
+__global__ __launch_bounds__(NTH) void k_group_seg(
+    const uint64_t* __restrict__ E, const uint32_t* __restrict__ seg_start,
+    const uint32_t* __restrict__ seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
+    uint64_t* __restrict__ cand, uint64_t cap, unsigned long long* __restrict__ ccount,
+    uint64_t* __restrict__ big, unsigned long long* __restrict__ nbig) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ uint64_t s_tmp64[NTH / 64];
+  __shared__ uint64_t s_base;
+  const uint32_t v0 = blockIdx.x * spw;
+  const uint32_t v1 = min(v0 + spw, nseg);
+  uint32_t v = v0;
+  while (v < v1) {
+    const uint32_t a = seg_start[v];
+    uint32_t b = seg_end[v];
+    if (a == b) {
+      ++v;
+      continue;
+    }
+    if (b - a > (uint32_t)CAP) {
+      if (threadIdx.x == 0) {
+        const unsigned long long x = atomicAdd(nbig, 1ull);
+        big[2 * x] = a;
+        big[2 * x + 1] = b;
+      }
+      ++v;
+      continue;
+    }
+    uint32_t w = v + 1;
+    while (w < v1) {
+      const uint32_t a2 = seg_start[w], b2 = seg_end[w];
+      if (a2 != b2) {
+        if (b2 - a > (uint32_t)CAP) break;
+        b = b2;
+      }
+      ++w;
+    }
+    group_batch<CAP, NTH>(E, a, b - a, idbits, cand, cap, ccount, lds, s_tmp64, &s_base);
+    v = w;
+  }
+}
+
+// ------------------------------------------------------------------ oversized segments
+
+// Listed segments [big[2s], big[2s+1]) are copied contiguously from
+// out_off[s].
+__global__ __launch_bounds__(256) void k_gather_big(const uint64_t* __restrict__ E,
+                                                    const uint64_t* __restrict__ big,
+                                                    const uint64_t* __restrict__ out_off,
+                                                    uint32_t nseg, uint64_t* __restrict__ out) {
+  for (uint32_t s = blockIdx.y; s < nseg; s += gridDim.y) {
+    const uint64_t a = big[2 * s], b = big[2 * s + 1], o = out_off[s];
+    for (uint64_t p = a + (uint64_t)blockIdx.x * 256 + threadIdx.x; p < b;
+         p += (uint64_t)gridDim.x * 256)
+      out[o + (p - a)] = E[p];
+  }
+}
+
+// In an array sorted stably by the full hash (ids ascend inside a run of
+// equal hashes), the first occurrence of each id pairs with every later
+// distinct id of its run. Appends after a per-block reservation on *counter;
+// writes past cap are dropped but still counted.
+__global__ __launch_bounds__(256) void k_emit_hash_runs(const uint64_t* __restrict__ E,
+                                                        uint64_t n, uint32_t idbits,
+                                                        uint64_t* __restrict__ cand, uint64_t cap,
+                                                        unsigned long long* __restrict__ counter) {
+  __shared__ uint64_t s_tmp[4];
+  __shared__ uint64_t s_base;
+  const uint64_t idmask = (1ull << idbits) - 1;
+  const uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  bool first = p < n;
+  if (first && p > 0) first = E[p] != E[p - 1];
+  uint64_t cnt = 0;
+  if (first) {
+    const uint64_t h = E[p] >> idbits;
+    for (uint64_t q = p + 1; q < n && (E[q] >> idbits) == h; ++q) cnt += E[q] != E[q - 1];
+  }
+  uint64_t total;
+  const uint64_t excl = block_excl_scan<256>(cnt, s_tmp, &total);
+  if (threadIdx.x == 0) s_base = total ? atomicAdd(counter, (unsigned long long)total) : 0;
+  __syncthreads();
+  if (cnt) {
+    uint64_t pos = s_base + excl;
+    const uint64_t h = E[p] >> idbits;
+    const uint64_t ip = (E[p] & idmask) << 32;
+    for (uint64_t q = p + 1; q < n && (E[q] >> idbits) == h; ++q) {
+      if (E[q] != E[q - 1]) {
+        if (pos < cap) cand[pos] = ip | (E[q] & idmask);
+        ++pos;
+      }
+    }
+  }
+}
+
+}  // namespace sdk
+
+namespace sd {
+
+void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, uint64_t* elem,
+                        uint32_t idbits, int npass, const uint32_t* shifts, const uint32_t* masks,
+                        uint32_t* hist, hipStream_t s) {
+  if (!nseq) return;
+  sdk::PassDigits pd;
+  for (int q = 0; q < 3; ++q) {
+    pd.shift[q] = q < npass ? shifts[q] : 0;
+    pd.mask[q] = q < npass ? masks[q] : 0;
+  }
+  const unsigned g = (unsigned)((nseq + sdk::VG_SEQS - 1) / sdk::VG_SEQS);
+  hipLaunchKernelGGL(sdk::k_vargen_hash, dim3(g), dim3(sdk::VG_NT), 0, s, seq, voff, nseq, elem,
+                     idbits, npass, pd, hist);
+}
+
+void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_t* seg_start,
+                       uint32_t* seg_end, hipStream_t s) {
+  if (!n) return;
+  uint64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(sdk::k_seg_bounds, dim3((unsigned)g), dim3(256), 0, s, E, n, segshift,
+                     seg_start, seg_end);
+}
+
+static size_t group_lds(int cap) { return (size_t)cap * sdk::GROUP_LDS_PER_ELEM; }
+
+template <int CAP, int NTH>
+static void launch_group_t(const uint64_t* E, const uint32_t* ss, const uint32_t* se,
+                           uint32_t nseg, uint32_t spw, uint32_t idbits, uint64_t* cand,
+                           uint64_t ccap, unsigned long long* ccount, uint64_t* big,
+                           unsigned long long* nbig, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    attr = true;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&sdk::k_group_seg<CAP, NTH>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)group_lds(CAP));
+  }
+  const unsigned g = (nseg + spw - 1) / spw;
+  hipLaunchKernelGGL((sdk::k_group_seg<CAP, NTH>), dim3(g), dim3(NTH), group_lds(CAP), s, E, ss,
+                     se, nseg, spw, idbits, cand, ccap, ccount, big, nbig);
+}
+
+bool group_cap_supported(int cap) { return cap == 4096 || cap == 2048 || cap == 1024 || cap == 256; }
+
+void launch_group_seg(int cap, const uint64_t* E, const uint32_t* seg_start,
+                      const uint32_t* seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
+                      uint64_t* cand, uint64_t ccap, unsigned long long* ccount, uint64_t* big,
+                      unsigned long long* nbig, hipStream_t s) {
+  if (!nseg) return;
+  switch (cap) {
+    case 4096:
+      launch_group_t<4096, 512>(E, seg_start, seg_end, nseg, spw, idbits, cand, ccap, ccount, big, nbig, s);
+      break;
+    case 2048:
+      launch_group_t<2048, 256>(E, seg_start, seg_end, nseg, spw, idbits, cand, ccap, ccount, big, nbig, s);
+      break;
+    case 1024:
+      launch_group_t<1024, 128>(E, seg_start, seg_end, nseg, spw, idbits, cand, ccap, ccount, big, nbig, s);
+      break;
+    default:
+      launch_group_t<256, 64>(E, seg_start, seg_end, nseg, spw, idbits, cand, ccap, ccount, big, nbig, s);
+      break;
+  }
+}
+
+void launch_gather_big(const uint64_t* E, const uint64_t* big, const uint64_t* out_off,
+                       uint32_t nseg, uint64_t* out, hipStream_t s) {
+  if (!nseg) return;
+  hipLaunchKernelGGL(sdk::k_gather_big, dim3(64, nseg < 4096 ? nseg : 4096), dim3(256), 0, s, E,
+                     big, out_off, nseg, out);
+}
+
+void launch_emit_hash_runs(const uint64_t* E, uint64_t n, uint32_t idbits, uint64_t* cand,
+                           uint64_t cap, unsigned long long* counter, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(sdk::k_emit_hash_runs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, E,
+                     n, idbits, cand, cap, counter);
+}
+
+}  // namespace sd

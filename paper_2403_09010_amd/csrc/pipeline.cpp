@@ -1,19 +1,25 @@
 // Host orchestration of the self-search pipeline (paper, Appendix A,
-// XTNeighbor steps 1-7), all device work on the caller's stream:
+// XTNeighbor steps 1-7). All device work runs on the caller's stream:
 //   1 pack            codes -> 128-bit keys, per-sequence variant counts
 //   2 scan            variant offsets (decoupled look-back)
-//   3 vargen          (key, id) for every <= k-deletion variant
-//   4 group           stable LSD radix sort of (key, id) by the 128-bit key
-//   5 emit            id pairs inside every run of equal keys
-//   6 pair sort       LSD radix sort of the 64-bit pairs
+//   3-5 grouping      equal deletion variants brought together and the id
+//                     pairs inside every group emitted, by one of two paths:
+//        full-key     (key, id) records, stable LSD radix sort over every
+//                     non-trivial digit of the 128-bit key, run emission
+//        hashed       64-bit elements [hash of the key | id], LSD passes over
+//                     the top hash bits, grouping of each hash segment by the
+//                     full stored hash in LDS (segments too large for LDS are
+//                     sorted by the full hash); a hash collision only adds a
+//                     candidate that step 7 rejects
+//   6 pair sort       LSD radix sort of the 64-bit candidate pairs
 //   7 verify          drop repeats, keep Levenshtein <= k, compact in order
-// The host synchronises only to read sizes that decide allocations: the key
-// total (with the validation flags), the non-trivial digits of the key sort,
-// the candidate count and the result count.
+// The host synchronises only to read sizes that decide allocations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "sd_internal.h"
 
@@ -64,31 +70,286 @@ int bits_for(uint64_t maxval) {
   return b;
 }
 
-// Sort records by the given digit positions in LSD order; returns true if
-// the result sits in the second buffer set.
-bool radix_sort(sd_ctx* c, Scratch& sc, uint64_t* a0, uint64_t* a1, uint32_t* av, uint64_t* b0,
-                uint64_t* b1, uint32_t* bv, int nwords, bool has_val, uint32_t n,
-                const std::vector<int>& digits, const uint32_t* hist, uint32_t* counters,
-                int& counter_slot, uint32_t* err, hipStream_t s) {
+// one LSD digit: word, shift inside the word, mask
+struct Digit {
+  int word, shift;
+  uint32_t mask;
+};
+
+// Counter slots of the per-call counter area (zeroed at the start of a call).
+enum : int {
+  CNT_ERR = 0,        // validation flags
+  CNT_TILE0 = 1,      // first of the per-launch tile counters
+  CNT_TILE_END = 60,
+  CNT_NKEYS = 64,     // u64 copy of the key total
+  CNT_CAND = 96,      // u64 candidate counter
+  CNT_PAIRS = 98,     // u64 result counter
+  CNT_LBERR = 100,    // look-back bound hits
+  CNT_NBIG = 102,     // u64 count of oversized segments
+  CNT_CAND2 = 104,    // u64 candidate counter of the full-key emission
+  CNT_TOTAL = 128
+};
+
+struct Call {
+  sd_ctx* c;
+  hipStream_t s;
+  Scratch& sc;
+  StageTimer& tm;
+  uint32_t* counters;
+  int slot = CNT_TILE0;
+  uint32_t* tile_counter() {
+    if (slot >= CNT_TILE_END) {  // recycle: zero a fresh block of slots
+      launch_fill_u32(counters + CNT_TILE0, 0, CNT_TILE_END - CNT_TILE0, s);
+      slot = CNT_TILE0;
+    }
+    return counters + slot++;
+  }
+  uint32_t* lb_err() { return counters + CNT_LBERR; }
+};
+
+// Sort records by the given digits in LSD order; returns true if the result
+// sits in the second buffer set.
+bool radix_sort(Call& cl, uint64_t* a0, uint64_t* a1, uint32_t* av, uint64_t* b0, uint64_t* b1,
+                uint32_t* bv, int nwords, bool has_val, uint32_t n, const std::vector<Digit>& digits,
+                const std::vector<const uint32_t*>& hists) {
   bool flip = false;
   const uint64_t tiles = (n + onesweep_tile(nwords, has_val) - 1) / onesweep_tile(nwords, has_val);
-  for (int q : digits) {
-    const uint32_t epoch = next_epoch(c, tiles * 256, s);
+  for (size_t x = 0; x < digits.size(); ++x) {
+    const uint32_t epoch = next_epoch(cl.c, tiles * 256, cl.s);
     const uint64_t* i0 = flip ? b0 : a0;
     const uint64_t* i1 = flip ? b1 : a1;
     const uint32_t* iv = flip ? bv : av;
     uint64_t* o0 = flip ? a0 : b0;
     uint64_t* o1 = flip ? a1 : b1;
     uint32_t* ov = flip ? av : bv;
-    launch_onesweep(i0, i1, iv, o0, o1, ov, nwords, has_val, n, q, hist + q * 256, c->status,
-                    counters + counter_slot++, epoch, err, s);
+    launch_onesweep(i0, i1, iv, o0, o1, ov, nwords, has_val, n, digits[x].word, digits[x].shift,
+                    digits[x].mask, hists[x], cl.c->status, cl.tile_counter(), epoch, cl.lb_err(),
+                    cl.s);
     flip = !flip;
   }
-  (void)sc;
   return flip;
 }
 
+struct Cands {
+  uint64_t* p = nullptr;  // pool block owned by the caller
+  uint64_t n = 0;
+};
+
+// Full-key grouping of nk (key, id) records: stable LSD sort over the
+// non-trivial digits of the 128-bit key, then run emission.
+Cands fullkey_group(Call& cl, uint64_t* klo, uint64_t* khi, uint32_t* kid, uint32_t nk,
+                    int& passes_out) {
+  sd_ctx* c = cl.c;
+  uint64_t* klo2 = cl.sc.get<uint64_t>(nk);
+  uint64_t* khi2 = cl.sc.get<uint64_t>(nk);
+  uint32_t* kid2 = cl.sc.get<uint32_t>(nk);
+  uint32_t* hist = cl.sc.get<uint32_t>(16 * 256);
+  launch_fill_u32(hist, 0, 16 * 256, cl.s);
+  launch_radix_hist(klo, khi, 2, nk, hist, cl.s);
+  std::vector<Digit> digits;
+  std::vector<const uint32_t*> hists;
+  {
+    const uint32_t* h = static_cast<const uint32_t*>(readback(c, hist, 16 * 256 * 4, cl.s));
+    for (int q = 0; q < 16; ++q) {
+      bool trivial = false;
+      for (int b = 0; b < 256; ++b)
+        if (h[q * 256 + b] == nk) trivial = true;
+      if (!trivial) {
+        digits.push_back(Digit{q / 8, (q % 8) * 8, 255u});
+        hists.push_back(hist + q * 256);
+      }
+    }
+  }
+  cl.tm.mark("sort_hist", (double)nk * 16, 2);
+  const bool flip = radix_sort(cl, klo, khi, kid, klo2, khi2, kid2, 2, true, nk, digits, hists);
+  passes_out = (int)digits.size();
+  cl.tm.mark("sort_passes", (double)nk * 40 * digits.size(), (int)digits.size());
+  const uint64_t* slo = flip ? klo2 : klo;
+  const uint64_t* shi = flip ? khi2 : khi;
+  const uint32_t* sid = flip ? kid2 : kid;
+
+  uint64_t cap = nk / 16 + 65536;
+  Cands out;
+  out.p = dalloc_t<uint64_t>(c, cap);
+  unsigned long long* ccount = reinterpret_cast<unsigned long long*>(cl.counters + CNT_CAND2);
+  launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, cl.s);
+  launch_emit_runs(slo, shi, sid, nk, out.p, cap, ccount, cl.s);
+  const uint64_t nc = *static_cast<const uint64_t*>(readback(c, ccount, 8, cl.s));
+  if (nc > cap) {  // the capacity guess was too small: grow and emit again
+    dfree(c, out.p);
+    out.p = nullptr;
+    out.p = dalloc_t<uint64_t>(c, nc);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, cl.s);
+    launch_emit_runs(slo, shi, sid, nk, out.p, nc, ccount, cl.s);
+  }
+  out.n = nc;
+  cl.tm.mark("emit", (double)nk * 20 + (double)nc * 8, 1);
+  return out;
+}
+
+// Sorting digits over bits [lo, 64) of a 64-bit word, least significant first.
+std::vector<Digit> top_digits(int lo) {
+  std::vector<Digit> d;
+  for (int b = lo; b < 64; b += 8) {
+    const int w = std::min(8, 64 - b);
+    d.push_back(Digit{0, b, (1u << w) - 1u});
+  }
+  return d;
+}
+
+// Elements of hash segments too large for LDS: sort them by the full hash
+// and emit pairs by runs of equal hash.
+Cands oversized_group(Call& cl, const uint64_t* E, const uint64_t* big, uint64_t nb,
+                      uint32_t idbits) {
+  sd_ctx* c = cl.c;
+  hipStream_t s = cl.s;
+  std::vector<uint64_t> hb(2 * nb), off(nb);
+  hip_check(hipMemcpyAsync(hb.data(), big, nb * 16, hipMemcpyDeviceToHost, s), "D2H big");
+  hip_check(hipStreamSynchronize(s), "synchronise");
+  uint64_t tot = 0;
+  for (uint64_t x = 0; x < nb; ++x) {
+    off[x] = tot;
+    tot += hb[2 * x + 1] - hb[2 * x];
+  }
+  uint64_t* doff = cl.sc.get<uint64_t>(nb);
+  hip_check(hipMemcpyAsync(doff, off.data(), nb * 8, hipMemcpyHostToDevice, s), "H2D offsets");
+  uint64_t* g1 = cl.sc.get<uint64_t>(tot);
+  uint64_t* g2 = cl.sc.get<uint64_t>(tot);
+  launch_gather_big(E, big, doff, (uint32_t)nb, g1, s);
+  uint32_t* hist = cl.sc.get<uint32_t>(8 * 256);
+  launch_fill_u32(hist, 0, 8 * 256, s);
+  launch_radix_hist(g1, nullptr, 1, tot, hist, s);
+  const std::vector<Digit> digits = top_digits((int)idbits);
+  std::vector<const uint32_t*> hists;
+  for (const Digit& d : digits) hists.push_back(hist + (d.shift / 8) * 256);
+  const bool flip =
+      radix_sort(cl, g1, nullptr, nullptr, g2, nullptr, nullptr, 1, false, (uint32_t)tot, digits, hists);
+  const uint64_t* sorted = flip ? g2 : g1;
+  uint64_t cap = tot / 8 + 65536;
+  Cands out;
+  out.p = dalloc_t<uint64_t>(c, cap);
+  unsigned long long* ccount = reinterpret_cast<unsigned long long*>(cl.counters + CNT_CAND2);
+  launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, s);
+  launch_emit_hash_runs(sorted, tot, idbits, out.p, cap, ccount, s);
+  const uint64_t nc = *static_cast<const uint64_t*>(readback(c, ccount, 8, s));
+  if (nc > cap) {
+    dfree(c, out.p);
+    out.p = nullptr;
+    out.p = dalloc_t<uint64_t>(c, nc);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, s);
+    launch_emit_hash_runs(sorted, tot, idbits, out.p, nc, ccount, s);
+  }
+  out.n = nc;
+  return out;
+}
+
+// Hashed grouping: elements [hash | id], LSD passes over the top `bits` hash
+// bits, grouping of each segment by its full hash in LDS.
+Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, uint32_t nk,
+                   int& passes_out) {
+  sd_ctx* c = cl.c;
+  hipStream_t s = cl.s;
+  int cap, bits;
+  hashed_plan(c, nk, &cap, &bits);
+  const uint32_t idbits = n <= (1ull << 24) ? 24u : 32u;
+  const std::vector<Digit> digits = bits ? top_digits(64 - bits) : std::vector<Digit>();
+  uint64_t* e1 = cl.sc.get<uint64_t>(nk);
+  uint64_t* e2 = cl.sc.get<uint64_t>(nk);
+  uint32_t* hist = cl.sc.get<uint32_t>(3 * 256);
+  launch_fill_u32(hist, 0, 3 * 256, s);
+  uint32_t shifts[3] = {0, 0, 0}, masks[3] = {0, 0, 0};
+  for (size_t x = 0; x < digits.size(); ++x) {
+    shifts[x] = (uint32_t)digits[x].shift;
+    masks[x] = digits[x].mask;
+  }
+  launch_vargen_hash(seq, voff, n, e1, idbits, (int)digits.size(), shifts, masks, hist, s);
+  cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 1);
+  std::vector<const uint32_t*> hists;
+  for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
+  const bool flip =
+      radix_sort(cl, e1, nullptr, nullptr, e2, nullptr, nullptr, 1, false, nk, digits, hists);
+  passes_out = (int)digits.size();
+  cl.tm.mark("hash_passes", (double)nk * 16 * digits.size(), (int)digits.size());
+  const uint64_t* E = flip ? e2 : e1;
+
+  // segment table, then one workgroup per `spw` segment values
+  const uint32_t nseg = 1u << bits;
+  const uint32_t segshift = 64u - (uint32_t)bits;
+  uint32_t* seg_start = cl.sc.get<uint32_t>(nseg);
+  uint32_t* seg_end = cl.sc.get<uint32_t>(nseg);
+  launch_fill_u32(seg_start, 0, nseg, s);
+  launch_fill_u32(seg_end, 0, nseg, s);
+  launch_seg_bounds(E, nk, segshift, seg_start, seg_end, s);
+  const double mean_seg = (double)nk / nseg;
+  const uint32_t spw =
+      (uint32_t)std::max(1.0, std::floor(0.8 * cap / std::max(mean_seg, 1.0) + 0.5));
+  uint64_t ccap = nk / 16 + 65536;
+  Cands cand;
+  cand.p = dalloc_t<uint64_t>(c, ccap);
+  const uint64_t nbig_cap = nk / cap + 2;
+  uint64_t* big = cl.sc.get<uint64_t>(2 * nbig_cap);
+  unsigned long long* ccount = reinterpret_cast<unsigned long long*>(cl.counters + CNT_CAND);
+  unsigned long long* nbig = reinterpret_cast<unsigned long long*>(cl.counters + CNT_NBIG);
+  launch_group_seg(cap, E, seg_start, seg_end, nseg, spw, idbits, cand.p, ccap, ccount, big, nbig,
+                   s);
+  uint64_t nc, nb;
+  {
+    const uint32_t* h = static_cast<const uint32_t*>(
+        readback(c, cl.counters + CNT_CAND, (CNT_NBIG + 2 - CNT_CAND) * 4, s));
+    std::memcpy(&nc, h, 8);
+    std::memcpy(&nb, h + (CNT_NBIG - CNT_CAND), 8);
+  }
+  if (nc > ccap) {  // capacity guess too small: grow and group again
+    dfree(c, cand.p);
+    cand.p = nullptr;
+    ccap = nc;
+    cand.p = dalloc_t<uint64_t>(c, ccap);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, s);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(nbig), 0, 1, s);
+    launch_group_seg(cap, E, seg_start, seg_end, nseg, spw, idbits, cand.p, ccap, ccount, big,
+                     nbig, s);
+  }
+  cand.n = nc;
+  cl.tm.mark("group_local", (double)nk * 8 + (double)nc * 8, 2);
+  c->stats.n_big_segments = (int64_t)nb;
+  if (nb) {
+    Cands extra = oversized_group(cl, E, big, nb, idbits);
+    if (extra.n) {
+      uint64_t* merged = dalloc_t<uint64_t>(c, cand.n + extra.n);
+      if (cand.n)
+        hip_check(hipMemcpyAsync(merged, cand.p, cand.n * 8, hipMemcpyDeviceToDevice, s), "merge");
+      hip_check(hipMemcpyAsync(merged + cand.n, extra.p, extra.n * 8, hipMemcpyDeviceToDevice, s),
+                "merge");
+      dfree(c, cand.p);
+      cand.p = merged;
+      cand.n += extra.n;
+    }
+    dfree(c, extra.p);
+    cl.tm.mark("oversized", 0, 0);
+  }
+  return cand;
+}
+
 }  // namespace
+
+// Tunables of the hashed path for a key count: the LDS capacity of a batch
+// and the number of hash bits the LSD passes sort by. Segment sizes are close
+// to Poisson(mean), so the bits are the fewest for which mean + 6 sqrt(mean)
+// stays under 0.9 of the capacity. Context options override either.
+void hashed_plan(const sd_ctx* c, uint64_t nk, int* cap, int* bits) {
+  const int cp = c->group_cap ? c->group_cap : 2048;
+  int b = c->group_bits;
+  if (b <= 0) {
+    b = 0;
+    while (b < 23) {
+      const double mean = (double)nk / (double)(1ull << b);
+      if (mean + 6.0 * std::sqrt(mean) <= 0.9 * cp) break;
+      ++b;
+    }
+  }
+  *cap = cp;
+  *bits = b;
+}
 
 void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream_t s) {
   check_seqs(seqs);
@@ -100,105 +361,72 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
   StageTimer tm(c, s);
   const DevSeqs in = stage_seqs(c, sc, seqs, s);
   const uint64_t n = in.n;
-  uint32_t* counters = fresh_counters(c, 128, s);
-  int slot = 0;
-  uint32_t* lb_err = counters + 100;  // look-back bound hits (checked at the end)
+  Call cl{c, s, sc, tm, fresh_counters(c, CNT_TOTAL, s)};
+  uint32_t* counters = cl.counters;
 
   // 1-2: pack and variant offsets
   u128* seq = sc.get<u128>(n);
   uint32_t* vcnt = sc.get<uint32_t>(n);
   uint64_t* voff = sc.get<uint64_t>(n + 1);
-  uint32_t* err = counters + slot++;
-  launch_pack(in.codes, in.offs, n, k, seq, vcnt, err, s);
+  launch_pack(in.codes, in.offs, n, k, seq, vcnt, counters + CNT_ERR, s);
   {
     const uint64_t tiles = (n + scan_tile() - 1) / scan_tile();
     const uint32_t epoch = next_epoch(c, tiles, s);
-    launch_scan_excl(vcnt, voff, n, c->status, counters + slot++, epoch, lb_err, s);
+    launch_scan_excl(vcnt, voff, n, c->status, cl.tile_counter(), epoch, cl.lb_err(), s);
   }
   tm.mark("pack_scan", (double)n * (16 + 16 + 8 + 4 + 4 + 8), 2);
   uint64_t nkeys;
   {
-    // one read-back: validation flags (counter 0) and the key total
-    hip_check(hipMemcpyAsync(counters + 64, voff + n, 8, hipMemcpyDeviceToDevice, s), "copy");
-    const uint32_t* h = static_cast<const uint32_t*>(readback(c, counters, 66 * 4, s));
-    raise_validation(h[0]);
-    uint64_t tot;
-    std::memcpy(&tot, h + 64, 8);
-    nkeys = tot;
+    // one read-back: validation flags and the key total
+    hip_check(hipMemcpyAsync(counters + CNT_NKEYS, voff + n, 8, hipMemcpyDeviceToDevice, s), "copy");
+    const uint32_t* h = static_cast<const uint32_t*>(readback(c, counters, (CNT_NKEYS + 2) * 4, s));
+    raise_validation(h[CNT_ERR]);
+    std::memcpy(&nkeys, h + CNT_NKEYS, 8);
   }
   if (nkeys >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "more than 2^32 - 2 deletion variants"};
   c->stats.n_keys = (int64_t)nkeys;
   const uint32_t nk = (uint32_t)nkeys;
 
-  // 3: variants
-  uint64_t* klo = sc.get<uint64_t>(nk);
-  uint64_t* khi = sc.get<uint64_t>(nk);
-  uint32_t* kid = sc.get<uint32_t>(nk);
-  uint64_t* klo2 = sc.get<uint64_t>(nk);
-  uint64_t* khi2 = sc.get<uint64_t>(nk);
-  uint32_t* kid2 = sc.get<uint32_t>(nk);
-  launch_vargen(seq, voff, n, k, klo, khi, kid, s);
-  tm.mark("vargen", (double)nk * 20 + (double)n * 24, 1);
-
-  // 4: group equal keys (stable LSD radix sort over the non-trivial digits)
-  uint32_t* hist = sc.get<uint32_t>(16 * 256);
-  launch_fill_u32(hist, 0, 16 * 256, s);
-  launch_radix_hist(klo, khi, 2, nk, hist, s);
-  std::vector<int> digits;
-  {
-    const uint32_t* h = static_cast<const uint32_t*>(readback(c, hist, 16 * 256 * 4, s));
-    for (int q = 0; q < 16; ++q) {
-      bool trivial = false;
-      for (int b = 0; b < 256; ++b)
-        if (h[q * 256 + b] == nk) trivial = true;
-      if (!trivial) digits.push_back(q);
-    }
+  // 3-5: grouping and in-group emission
+  Cands cand;
+  int passes = 0;
+  if (c->path == 1) {
+    uint64_t* klo = sc.get<uint64_t>(nk);
+    uint64_t* khi = sc.get<uint64_t>(nk);
+    uint32_t* kid = sc.get<uint32_t>(nk);
+    launch_vargen(seq, voff, n, k, klo, khi, kid, s);
+    tm.mark("vargen", (double)nk * 20 + (double)n * 24, 1);
+    cand = fullkey_group(cl, klo, khi, kid, nk, passes);
+  } else {
+    cand = hashed_group(cl, seq, voff, n, nk, passes);
   }
-  tm.mark("sort_hist", (double)nk * 16, 2);
-  const bool kflip = radix_sort(c, sc, klo, khi, kid, klo2, khi2, kid2, 2, true, nk, digits, hist,
-                                counters, slot, lb_err, s);
-  c->stats.n_sort_passes = (int32_t)digits.size();
-  tm.mark("sort_passes", (double)nk * 40 * digits.size(), (int)digits.size());
-  const uint64_t* slo = kflip ? klo2 : klo;
-  const uint64_t* shi = kflip ? khi2 : khi;
-  const uint32_t* sid = kflip ? kid2 : kid;
-
-  // 5: pairs inside groups of equal keys
-  uint64_t cap = nk / 16 + 65536;
-  uint64_t* cand = dalloc_t<uint64_t>(c, cap);
-  unsigned long long* ccount = reinterpret_cast<unsigned long long*>(counters + 96);
-  launch_emit_runs(slo, shi, sid, nk, cand, cap, ccount, s);
-  uint64_t nc;
-  {
-    const uint64_t* h = static_cast<const uint64_t*>(readback(c, ccount, 8, s));
-    nc = *h;
-  }
-  if (nc > cap) {  // capacity guess too small: grow and emit again
-    dfree(c, cand);
-    cap = nc;
-    cand = dalloc_t<uint64_t>(c, cap);
-    launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, s);
-    launch_emit_runs(slo, shi, sid, nk, cand, cap, ccount, s);
-  }
-  sc.blocks.push_back(cand);
+  sc.blocks.push_back(cand.p);
+  c->stats.n_sort_passes = passes;
+  const uint64_t nc = cand.n;
   c->stats.n_cand_raw = (int64_t)nc;
-  tm.mark("emit", (double)nk * 20 + (double)nc * 8, 1);
   if (nc >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "more than 2^32 - 2 candidate pairs"};
 
   // 6: sort candidate pairs (only the digits that can differ)
   uint64_t* cand2 = sc.get<uint64_t>(nc);
-  const uint64_t* sorted = cand;
+  const uint64_t* sorted = cand.p;
   if (nc > 1) {
     const int nb = bits_for(n - 1);
-    std::vector<int> pd;
-    for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(q);
-    for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(4 + q);
+    std::vector<Digit> pd;
+    std::vector<const uint32_t*> ph;
     uint32_t* phist = sc.get<uint32_t>(8 * 256);
     launch_fill_u32(phist, 0, 8 * 256, s);
-    launch_radix_hist(cand, nullptr, 1, nc, phist, s);
-    const bool pflip = radix_sort(c, sc, cand, nullptr, nullptr, cand2, nullptr, nullptr, 1, false,
-                                  (uint32_t)nc, pd, phist, counters, slot, lb_err, s);
-    sorted = pflip ? cand2 : cand;
+    launch_radix_hist(cand.p, nullptr, 1, nc, phist, s);
+    for (int q = 0; q < (nb + 7) / 8; ++q) {
+      pd.push_back(Digit{0, 8 * q, 255u});
+      ph.push_back(phist + q * 256);
+    }
+    for (int q = 0; q < (nb + 7) / 8; ++q) {
+      pd.push_back(Digit{0, 32 + 8 * q, 255u});
+      ph.push_back(phist + (4 + q) * 256);
+    }
+    const bool pflip = radix_sort(cl, cand.p, nullptr, nullptr, cand2, nullptr, nullptr, 1, false,
+                                  (uint32_t)nc, pd, ph);
+    sorted = pflip ? cand2 : cand.p;
     tm.mark("pair_sort", (double)nc * 8 + (double)nc * 16 * pd.size(), 2 + (int)pd.size());
   } else {
     tm.mark("pair_sort", 0, 0);
@@ -210,18 +438,17 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
   uint8_t* od = dalloc_t<uint8_t>(c, nc);
   uint64_t npairs = 0;
   try {
-    unsigned long long* pcount = reinterpret_cast<unsigned long long*>(counters + 98);
+    unsigned long long* pcount = reinterpret_cast<unsigned long long*>(counters + CNT_PAIRS);
     if (nc) {
       const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
       const uint32_t epoch = next_epoch(c, tiles, s);
-      launch_verify_compact(sorted, nc, seq, seq, k, oi, oj, od, c->status, counters + slot++,
-                            epoch, pcount, lb_err, s);
+      launch_verify_compact(sorted, nc, seq, seq, k, oi, oj, od, c->status, cl.tile_counter(),
+                            epoch, pcount, cl.lb_err(), s);
       tm.mark("verify", (double)nc * (8 + 32) + (double)nc * 9, 1);
     } else {
       tm.mark("verify", 0, 0);
     }
-    // counters 98-99: result count, 100: look-back errors
-    const uint32_t* h = static_cast<const uint32_t*>(readback(c, counters + 98, 12, s));
+    const uint32_t* h = static_cast<const uint32_t*>(readback(c, counters + CNT_PAIRS, 12, s));
     uint64_t cnt;
     std::memcpy(&cnt, h, 8);
     if (h[2] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
@@ -285,7 +512,7 @@ void pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32_t
   Scratch sc(c);
   const DevSeqs da = stage_seqs(c, sc, a, s);
   const DevSeqs db = stage_seqs(c, sc, b, s);
-  uint32_t* counters = fresh_counters(c, 128, s);
+  uint32_t* counters = fresh_counters(c, CNT_TOTAL, s);
   u128* sa = sc.get<u128>(da.n);
   u128* sb = sc.get<u128>(db.n);
   launch_pack(da.codes, da.offs, da.n, 0, sa, nullptr, counters, s);

@@ -52,7 +52,7 @@ template <int NW, bool HAS_VAL, int ITEMS>
 __global__ __launch_bounds__(NT) void k_onesweep(
     const uint64_t* __restrict__ in0, const uint64_t* __restrict__ in1,
     const uint32_t* __restrict__ vin, uint64_t* __restrict__ out0, uint64_t* __restrict__ out1,
-    uint32_t* __restrict__ vout, uint32_t n, int word, int shift,
+    uint32_t* __restrict__ vout, uint32_t n, int word, int shift, uint32_t mask,
     const uint32_t* __restrict__ hist256, uint64_t* __restrict__ status,
     uint32_t* __restrict__ tile_counter, uint32_t epoch, uint32_t* __restrict__ err) {
   constexpr int TILE = NT * ITEMS;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(
     const uint64_t e = base + (uint64_t)w * 64 * ITEMS + (uint64_t)r * 64 + lane;
     const bool valid = e < n;
     const uint64_t kw = (NW == 2 && word == 1) ? k1[r] : k0[r];
-    const uint32_t d = (uint32_t)(kw >> shift) & 255u;
+    const uint32_t d = (uint32_t)(kw >> shift) & mask;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -157,6 +157,91 @@ __global__ __launch_bounds__(NT) void k_onesweep(
       if (dig[r] < RADIX) s_v[lpos[r]] = val[r];
     __syncthreads();
     for (uint32_t s = tid; s < nvalid; s += NT) vout[s_gidx[s]] = s_v[s];
+  }
+}
+
+// Keys-only pass over one 64-bit word with larger tiles: the staged key
+// itself gives its digit, so no per-slot output index is kept in LDS and the
+// tile can hold twice as many elements in the same LDS footprint (fewer tiles
+// means fewer look-back chains, which bound the pass at small element sizes).
+template <int ITEMS>
+__global__ __launch_bounds__(NT) void k_onesweep_keys(const uint64_t* __restrict__ in,
+                                                      uint64_t* __restrict__ out, uint32_t n,
+                                                      int shift, uint32_t mask,
+                                                      const uint32_t* __restrict__ hist256,
+                                                      uint64_t* __restrict__ status,
+                                                      uint32_t* __restrict__ tile_counter,
+                                                      uint32_t epoch, uint32_t* __restrict__ err) {
+  constexpr int TILE = NT * ITEMS;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_wh[NWAVE][RADIX];
+  __shared__ uint32_t s_lstart[RADIX];
+  __shared__ uint32_t s_gstart[RADIX];
+  __shared__ uint32_t s_tmp[NWAVE];
+  __shared__ uint64_t s_stage[TILE];
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
+  const uint32_t w = tid >> 6;
+  if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+  for (int x = tid; x < NWAVE * RADIX; x += NT) (&s_wh[0][0])[x] = 0;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  if (tile >= gridDim.x) return;  // counters are zeroed per pass; never taken
+  const uint64_t base = (uint64_t)tile * TILE;
+  const uint32_t nvalid = (uint32_t)min<uint64_t>((uint64_t)TILE, (uint64_t)n - base);
+
+  uint64_t k0[ITEMS];
+  uint32_t dr[ITEMS];  // digit << 16 | rank inside the wave (digit 256: no element)
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const uint64_t e = base + (uint64_t)w * 64 * ITEMS + (uint64_t)r * 64 + lane;
+    k0[r] = e < n ? in[e] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const uint64_t e = base + (uint64_t)w * 64 * ITEMS + (uint64_t)r * 64 + lane;
+    const bool valid = e < n;
+    const uint32_t d = (uint32_t)(k0[r] >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bb = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t below = mask_rank(peers);
+    uint32_t prev = 0;
+    if (valid) prev = s_wh[w][d];
+    if (valid && below == 0) s_wh[w][d] = prev + (uint32_t)__popcll(peers);
+    dr[r] = ((valid ? d : (uint32_t)RADIX) << 16) | (prev + below);
+  }
+  __syncthreads();
+  {
+    const uint32_t t = tid;
+    const uint32_t c0 = s_wh[0][t], c1 = s_wh[1][t], c2 = s_wh[2][t], c3 = s_wh[3][t];
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    uint32_t sum;
+    const uint32_t bbase = block_excl_scan<NT>(hist256[t], s_tmp, &sum);
+    const uint32_t lstart = block_excl_scan<NT>(tot, s_tmp, &sum);
+    const uint64_t excl = lb_exclusive(status + t, tile, RADIX, epoch, tot, err);
+    s_wh[0][t] = 0;
+    s_wh[1][t] = c0;
+    s_wh[2][t] = c0 + c1;
+    s_wh[3][t] = c0 + c1 + c2;
+    s_lstart[t] = lstart;
+    s_gstart[t] = bbase + (uint32_t)excl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const uint32_t d = dr[r] >> 16;
+    if (d < RADIX) s_stage[s_lstart[d] + s_wh[w][d] + (dr[r] & 0xFFFFu)] = k0[r];
+  }
+  __syncthreads();
+  for (uint32_t s = tid; s < nvalid; s += NT) {
+    const uint64_t v = s_stage[s];
+    const uint32_t d = (uint32_t)(v >> shift) & mask;
+    out[s_gstart[d] + (s - s_lstart[d])] = v;
   }
 }
 
@@ -244,33 +329,33 @@ void launch_radix_hist(const uint64_t* w0, const uint64_t* w1, int nwords, uint6
     hipLaunchKernelGGL(sdk::k_radix_hist<1>, dim3(g), dim3(sdk::NT), 0, s, w0, w1, n, hist);
 }
 
+constexpr int KEYS_ITEMS = 32;
+
 uint64_t onesweep_tile(int nwords, bool has_val) {
-  (void)nwords;
-  (void)has_val;
+  if (nwords == 1 && !has_val) return (uint64_t)sdk::NT * KEYS_ITEMS;
   return (uint64_t)sdk::NT * 16;
 }
 
 void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* vin,
                      uint64_t* out0, uint64_t* out1, uint32_t* vout, int nwords, bool has_val,
-                     uint32_t n, int digit_pos, const uint32_t* hist256, uint64_t* status,
-                     uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s) {
+                     uint32_t n, int word, int shift, uint32_t mask, const uint32_t* hist256,
+                     uint64_t* status, uint32_t* tile_counter, uint32_t epoch, uint32_t* err,
+                     hipStream_t s) {
   if (!n) return;
-  const int word = digit_pos / 8;
-  const int shift = (digit_pos % 8) * 8;
   const uint64_t tiles = (n + onesweep_tile(nwords, has_val) - 1) / onesweep_tile(nwords, has_val);
   dim3 g((unsigned)tiles), b(sdk::NT);
   if (nwords == 2 && has_val)
     hipLaunchKernelGGL((sdk::k_onesweep<2, true, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
-                       vout, n, word, shift, hist256, status, tile_counter, epoch, err);
+                       vout, n, word, shift, mask, hist256, status, tile_counter, epoch, err);
   else if (nwords == 2)
     hipLaunchKernelGGL((sdk::k_onesweep<2, false, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
-                       vout, n, word, shift, hist256, status, tile_counter, epoch, err);
+                       vout, n, word, shift, mask, hist256, status, tile_counter, epoch, err);
   else if (has_val)
     hipLaunchKernelGGL((sdk::k_onesweep<1, true, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
-                       vout, n, word, shift, hist256, status, tile_counter, epoch, err);
+                       vout, n, word, shift, mask, hist256, status, tile_counter, epoch, err);
   else
-    hipLaunchKernelGGL((sdk::k_onesweep<1, false, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
-                       vout, n, word, shift, hist256, status, tile_counter, epoch, err);
+    hipLaunchKernelGGL((sdk::k_onesweep_keys<KEYS_ITEMS>), g, b, 0, s, word == 1 ? in1 : in0,
+                       out0, n, shift, mask, hist256, status, tile_counter, epoch, err);
 }
 
 uint64_t scan_tile() { return (uint64_t)sdk::NT * sdk::SCAN_ITEMS; }

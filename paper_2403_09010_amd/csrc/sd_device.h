@@ -46,19 +46,22 @@ __host__ __device__ __forceinline__ uint32_t num_variants(uint32_t L, int k) {
 
 // Variant number v of a key in the enumeration order: v = 0 keeps the
 // string, v = 1..L deletes position v-1, larger v delete a position pair
-// (p1 < p2) in lexicographic order.
+// (p1 < p2) in lexicographic order. The pair index u = v - 1 - L is unranked
+// in closed form: T(p) = p (2L - 1 - p) / 2 pairs start before p, so p1 is
+// the largest p with T(p) <= u, a root of a quadratic (one correction step
+// each way absorbs the rounding of sqrtf).
 __device__ __forceinline__ u128 key_variant(u128 key, uint32_t v) {
   const uint32_t L = key_len(key);
   if (v == 0) return key;
   if (v <= L) return key_delete(key, (int)v - 1);
-  uint32_t u = v - 1 - L;
-  uint32_t p1 = 0;
-  while (u >= L - 1 - p1) {
-    u -= L - 1 - p1;
-    ++p1;
-  }
-  const uint32_t p2 = p1 + 1 + u;
-  return key_delete(key_delete(key, (int)p2), (int)p1);
+  const int u = (int)(v - 1 - L);
+  const int a = 2 * (int)L - 1;
+  int p1 = (int)((a - sqrtf((float)(a * a - 8 * u))) * 0.5f);
+  p1 = p1 < 0 ? 0 : p1;
+  if ((p1 + 1) * (a - p1 - 1) / 2 <= u) ++p1;
+  if (p1 * (a - p1) / 2 > u) --p1;
+  const int p2 = p1 + 1 + (u - p1 * (a - p1) / 2);
+  return key_delete(key_delete(key, p2), p1);
 }
 
 // ------------------------------------------------------------------ wave64

@@ -27,10 +27,12 @@ void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 void launch_radix_hist(const uint64_t* w0, const uint64_t* w1, int nwords, uint64_t n,
                        uint32_t* hist, hipStream_t s);
 uint64_t onesweep_tile(int nwords, bool has_val);
+// one stable pass by the digit (word[word] >> shift) & mask, mask <= 255
 void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* vin,
                      uint64_t* out0, uint64_t* out1, uint32_t* vout, int nwords, bool has_val,
-                     uint32_t n, int digit_pos, const uint32_t* hist256, uint64_t* status,
-                     uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s);
+                     uint32_t n, int word, int shift, uint32_t mask, const uint32_t* hist256,
+                     uint64_t* status, uint32_t* tile_counter, uint32_t epoch, uint32_t* err,
+                     hipStream_t s);
 uint64_t scan_tile();
 void launch_scan_excl(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* status,
                       uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s);
@@ -48,6 +50,21 @@ void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* seq_a,
                            uint8_t* out_d, uint64_t* status, uint32_t* tile_counter,
                            uint32_t epoch, unsigned long long* out_count, uint32_t* err,
                            hipStream_t s);
+// hashed grouping (element = hash of the key in the top 64 - idbits bits, id below)
+void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, uint64_t* elem,
+                        uint32_t idbits, int npass, const uint32_t* shifts, const uint32_t* masks,
+                        uint32_t* hist, hipStream_t s);
+bool group_cap_supported(int cap);
+void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_t* seg_start,
+                       uint32_t* seg_end, hipStream_t s);
+void launch_group_seg(int cap, const uint64_t* E, const uint32_t* seg_start,
+                      const uint32_t* seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
+                      uint64_t* cand, uint64_t ccap, unsigned long long* ccount, uint64_t* big,
+                      unsigned long long* nbig, hipStream_t s);
+void launch_gather_big(const uint64_t* E, const uint64_t* big, const uint64_t* out_off,
+                       uint32_t nseg, uint64_t* out, hipStream_t s);
+void launch_emit_hash_runs(const uint64_t* E, uint64_t n, uint32_t idbits, uint64_t* cand,
+                           uint64_t cap, unsigned long long* counter, hipStream_t s);
 void launch_pair_distance(const u128* seq_a, uint64_t na, const u128* seq_b, uint64_t nb,
                           const uint32_t* ia, const uint32_t* ib, uint64_t n, uint8_t* d,
                           uint32_t* err, hipStream_t s);
@@ -81,7 +98,9 @@ struct sd_ctx {
   size_t pinned_bytes = 0;
   sd_stats stats{};
   int timing = 0;
-  int path = 0;
+  int path = 0;        // 0 automatic, 1 full-key sort, 2 hashed
+  int group_cap = 0;   // hashed path: LDS batch capacity (0 = automatic)
+  int group_bits = 0;  // hashed path: hash bits sorted by the LSD passes (0 = automatic)
   std::vector<hipEvent_t> events;
 };
 
@@ -132,6 +151,7 @@ struct StageTimer {
 };
 
 // the search pipelines
+void hashed_plan(const sd_ctx* c, uint64_t nk, int* cap, int* bits);
 void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream_t s);
 void pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32_t* ia,
                    const uint32_t* ib, int64_t n, uint8_t* d_out, hipStream_t s);

@@ -23,6 +23,8 @@ ERRORS = {
 }
 OPT_TIMING = 1
 OPT_PATH = 2
+OPT_GROUP_CAP = 3
+OPT_GROUP_BITS = 4
 MAX_STAGES = 16
 
 
@@ -48,7 +50,7 @@ class _Stats(ctypes.Structure):
     _fields_ = [("n_seqs", ctypes.c_int64), ("n_keys", ctypes.c_int64),
                 ("n_cand_raw", ctypes.c_int64), ("n_cand_unique", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("n_stages", ctypes.c_int32),
-                ("n_sort_passes", ctypes.c_int32),
+                ("n_sort_passes", ctypes.c_int32), ("n_big_segments", ctypes.c_int64),
                 ("stage_name", (ctypes.c_char * 24) * MAX_STAGES),
                 ("stage_ms", ctypes.c_double * MAX_STAGES),
                 ("stage_bytes", ctypes.c_double * MAX_STAGES),
@@ -249,4 +251,5 @@ class Context:
                                launches=st.stage_launches[x]))
         return dict(n_seqs=st.n_seqs, n_keys=st.n_keys, n_cand_raw=st.n_cand_raw,
                     n_cand_unique=st.n_cand_unique, n_pairs=st.n_pairs,
-                    n_sort_passes=st.n_sort_passes, stages=stages)
+                    n_sort_passes=st.n_sort_passes, n_big_segments=st.n_big_segments,
+                    stages=stages)

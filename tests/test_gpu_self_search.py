@@ -20,12 +20,43 @@ def log(msg):
     print(msg, flush=True)
 
 
-@pytest.fixture(scope="module")
-def ctx():
+# grouping configurations: the automatic (hashed) path, the full-key sort
+# path, and hashed runs with a small LDS capacity that send some or all hash
+# segments through the oversized-segment fallback
+CONFIGS = {
+    "auto": {},
+    "fullkey": {"path": 1},
+    "hashed_4096": {"path": 2, "cap": 4096},
+    "hashed_2048_b18": {"path": 2, "cap": 2048, "bits": 18},
+    "hashed_1024": {"path": 2, "cap": 1024},
+    "hashed_cap256": {"path": 2, "cap": 256},
+    "hashed_fallback": {"path": 2, "cap": 256, "bits": 4},
+}
+
+
+def make_ctx(cfg):
     import torch
     from paper_2403_09010_amd import Context
+    from paper_2403_09010_amd.symdel import OPT_GROUP_BITS, OPT_GROUP_CAP, OPT_PATH
     assert torch.cuda.is_available()
     c = Context(0)
+    c.set_option(OPT_PATH, cfg.get("path", 0))
+    c.set_option(OPT_GROUP_CAP, cfg.get("cap", 0))
+    c.set_option(OPT_GROUP_BITS, cfg.get("bits", 0))
+    return c
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = make_ctx({})
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module", params=sorted(CONFIGS))
+def cctx(request):
+    c = make_ctx(CONFIGS[request.param])
+    c.name = request.param
     yield c
     c.close()
 
@@ -120,32 +151,32 @@ def test_pair_distance_rejects_bad_index(ctx):
 # ---------------------------------------------------------------- self search
 
 @pytest.mark.parametrize("k", [0, 1, 2])
-def test_plain_10k_matches_oracle(ctx, k):
+def test_plain_10k_matches_oracle(cctx, k):
     c, o = cdr3gen.plain("plain_10k")
-    log(f"self_search plain_10k k={k}")
-    got = gpu_triples(ctx, c, o, k)
+    log(f"self_search plain_10k k={k} config={cctx.name}")
+    got = gpu_triples(cctx, c, o, k)
     assert_same(got, oracle_triples(c, o, k))
     g = GOLD[f"oracle_plain_10k_k{k}"]
     assert len(got[0]) == g["pairs"]
     assert sha(got[0], got[1], got[2].astype(np.uint8)) == g["sha256"]
 
 
-def test_plain_1m_prefix_20k_k2_golden(ctx):
+def test_plain_1m_prefix_20k_k2_golden(cctx):
     c, o = cdr3gen.subset(*cdr3gen.plain("plain_1m"), 20000)
-    log("self_search first 20000 of plain_1m, k=2")
-    got = gpu_triples(ctx, c, o, 2)
+    log(f"self_search first 20000 of plain_1m, k=2 config={cctx.name}")
+    got = gpu_triples(cctx, c, o, 2)
     g = GOLD["oracle_plain_1m_first20k_k2"]
     assert len(got[0]) == g["pairs"]
     assert sha(got[0], got[1], got[2].astype(np.uint8)) == g["sha256"]
 
 
 @pytest.mark.parametrize("k", [0, 1, 2])
-def test_exhaustive_small_alphabet(ctx, k):
+def test_exhaustive_small_alphabet(cctx, k):
     import itertools
     strings = [bytes(t) for L in range(1, 7) for t in itertools.product(range(3), repeat=L)]
     c, o = csr(strings)
-    log(f"self_search exhaustive 3-letter strings, k={k}")
-    assert_same(gpu_triples(ctx, c, o, k), oracle_triples(c, o, k))
+    log(f"self_search exhaustive 3-letter strings, k={k} config={cctx.name}")
+    assert_same(gpu_triples(cctx, c, o, k), oracle_triples(c, o, k))
 
 
 def test_host_and_device_inputs_agree_and_repeat_bitwise(ctx):
@@ -158,8 +189,9 @@ def test_host_and_device_inputs_agree_and_repeat_bitwise(ctx):
     assert_same(b, b2)
 
 
-def test_edge_cases(ctx):
-    log("self_search edge cases")
+def test_edge_cases(cctx):
+    ctx = cctx
+    log(f"self_search edge cases config={cctx.name}")
     # empty input
     r = ctx.self_search(np.zeros(0, np.uint8), np.zeros(1, np.int64), 2)
     assert len(r) == 0
@@ -175,16 +207,73 @@ def test_edge_cases(ctx):
         assert_same(gpu_triples(ctx, c, o, k, device=False), oracle_triples(c, o, k))
 
 
-def test_heavy_groups(ctx):
+def test_heavy_groups(cctx):
     # many copies of a few sequences: large groups of equal keys
     base, bo = cdr3gen.generate(41, 40)
     rng = np.random.default_rng(2)
     pick = rng.integers(0, 40, 3000)
     strings = [base[bo[x]:bo[x + 1]].tobytes() for x in pick]
     c, o = csr(strings)
-    log("self_search heavy groups: 3000 sequences drawn from 40")
+    log(f"self_search heavy groups: 3000 sequences drawn from 40, config={cctx.name}")
     for k in (1, 2):
-        assert_same(gpu_triples(ctx, c, o, k), oracle_triples(c, o, k))
+        assert_same(gpu_triples(cctx, c, o, k), oracle_triples(c, o, k))
+
+
+def test_group_larger_than_lds(ctx):
+    # 4500 copies of one sequence: its variants form hash segments larger
+    # than the 4096-element LDS capacity, so they take the full-key path
+    import oracle
+    x = cdr3gen.generate(51, 1)
+    xs = x[0].tobytes()
+    oc, oo = cdr3gen.generate(52, 300, fresh_frac=1.0)
+    others = [oc[oo[t]:oo[t + 1]].tobytes() for t in range(300)]
+    others = [t for t in others if t != xs]
+    strings = [xs] * 4500 + others
+    c, o = csr(strings)
+    k = 1
+    log("self_search 4500 identical sequences + 300 others, k=1")
+    got = gpu_triples(ctx, c, o, k)
+    assert ctx.stats()["n_big_segments"] > 0
+    want = []
+    nx = 4500
+    dx = [oracle.lev(xs, t) for t in others]
+    for i in range(nx):
+        for j in range(i + 1, nx):
+            want.append((i, j, 0))
+        for t, d in enumerate(dx):
+            if d <= k:
+                want.append((i, nx + t, d))
+    oi, oj, od = oracle.self_search(*csr(others), k)
+    want += [(nx + a, nx + b, d) for a, b, d in zip(oi.tolist(), oj.tolist(), od.tolist())]
+    want.sort()
+    w = np.array(want, dtype=np.int64)
+    assert len(got[0]) == len(w)
+    assert np.array_equal(got[0], w[:, 0]) and np.array_equal(got[1], w[:, 1])
+    assert np.array_equal(got[2], w[:, 2])
+
+
+def test_budget_error_keeps_context_usable():
+    from paper_2403_09010_amd import Context, SymdelError
+    log("self_search over a 4 MiB device budget")
+    c, o = cdr3gen.plain("plain_10k")
+    with Context(0, hbm_budget=4 << 20) as small:
+        with pytest.raises(SymdelError) as e:
+            small.self_search(*to_dev(c, o), 2)
+        assert e.value.name == "SD_E_NOMEM"
+        c2, o2 = cdr3gen.subset(c, o, 50)
+        assert_same(gpu_triples(small, c2, o2, 1), oracle_triples(c2, o2, 1))
+
+
+def test_paths_agree_at_full_size(ctx):
+    c, o = cdr3gen.plain("plain_1m")
+    log("self_search plain_1m k=2: hashed vs full-key path")
+    a = gpu_triples(ctx, c, o, 2)
+    full = make_ctx({"path": 1})
+    try:
+        b = gpu_triples(full, c, o, 2)
+    finally:
+        full.close()
+    assert_same(a, b)
 
 
 def test_errors(ctx):
