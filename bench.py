@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--path", type=int, default=0, help="grouping path (0 auto, 1 full-key sort)")
     ap.add_argument("--group-cap", type=int, default=0, help="hashed path LDS capacity (0 auto)")
     ap.add_argument("--group-bits", type=int, default=0, help="hashed path hash bits (0 auto)")
+    ap.add_argument("--sort-items", type=int, default=0, help="keys-only radix items/thread (0 auto)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one device copy of this size first (a known-size kernel for counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
     args = ap.parse_args()
@@ -74,8 +77,8 @@ def main():
     import torch
     import cdr3gen
     from paper_2403_09010_amd import Context
-    from paper_2403_09010_amd.symdel import (OPT_GROUP_BITS, OPT_GROUP_CAP, OPT_PATH, OPT_TIMING,
-                                             _Seqs)
+    from paper_2403_09010_amd.symdel import (OPT_GROUP_BITS, OPT_GROUP_CAP, OPT_PATH,
+                                             OPT_SORT_ITEMS, OPT_TIMING, _Seqs)
 
     gen_name, k = WORKLOADS[args.workload]
     log(f"generating {gen_name}")
@@ -89,6 +92,13 @@ def main():
     ctx.set_option(OPT_PATH, args.path)
     ctx.set_option(OPT_GROUP_CAP, args.group_cap)
     ctx.set_option(OPT_GROUP_BITS, args.group_bits)
+    ctx.set_option(OPT_SORT_ITEMS, args.sort_items)
+    if args.copy_calibration_mb:
+        src = torch.empty(args.copy_calibration_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
 
@@ -144,7 +154,8 @@ def main():
         "config": {"workload": args.workload, "n_seqs": n, "k": k, "seed": cdr3gen.PLAIN_CONFIGS[gen_name][0],
                    "pairs": int(npairs), "keys": st["n_keys"], "candidates_raw": st["n_cand_raw"],
                    "seconds_per_search": round(dt, 6), "path": args.path,
-                   "group_cap": args.group_cap, "group_bits": args.group_bits},
+                   "group_cap": args.group_cap, "group_bits": args.group_bits,
+                   "sort_items": args.sort_items},
         "stages_ms": {s: round(stage_ms[s] / args.steps, 4) for s in stage_ms},
         "roofline": roofline,
     }

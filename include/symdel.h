@@ -90,6 +90,7 @@ typedef struct {
 #define SD_OPT_PATH 2       /* grouping path: 0 = automatic, 1 = full-key LSD sort, 2 = hashed segments */
 #define SD_OPT_GROUP_CAP 3  /* hashed path: LDS batch capacity, 0 (automatic), 256, 1024, 2048 or 4096 */
 #define SD_OPT_GROUP_BITS 4 /* hashed path: hash bits sorted by LSD passes, 0 (automatic) .. 23 */
+#define SD_OPT_SORT_ITEMS 5 /* keys-only radix passes: items per thread, 0 (automatic), 16 or 32 */
 
 /*
  * Create a context on HIP device `device`. hbm_budget_bytes bounds the

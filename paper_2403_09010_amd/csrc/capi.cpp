@@ -223,6 +223,10 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
       if (value < 0 || value > 23) return SD_E_INVAL;
       c->group_bits = (int)value;
       return SD_OK;
+    case SD_OPT_SORT_ITEMS:
+      if (value != 0 && value != 16 && value != 32) return SD_E_INVAL;
+      c->sort_items = (int)value;
+      return SD_OK;
     default:
       c->last_error = "unknown option";
       return SD_E_INVAL;

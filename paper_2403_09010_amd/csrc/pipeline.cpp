@@ -113,7 +113,8 @@ bool radix_sort(Call& cl, uint64_t* a0, uint64_t* a1, uint32_t* av, uint64_t* b0
                 uint32_t* bv, int nwords, bool has_val, uint32_t n, const std::vector<Digit>& digits,
                 const std::vector<const uint32_t*>& hists) {
   bool flip = false;
-  const uint64_t tiles = (n + onesweep_tile(nwords, has_val) - 1) / onesweep_tile(nwords, has_val);
+  const uint64_t tile = onesweep_tile(nwords, has_val, cl.c->sort_items);
+  const uint64_t tiles = (n + tile - 1) / tile;
   for (size_t x = 0; x < digits.size(); ++x) {
     const uint32_t epoch = next_epoch(cl.c, tiles * 256, cl.s);
     const uint64_t* i0 = flip ? b0 : a0;
@@ -124,7 +125,7 @@ bool radix_sort(Call& cl, uint64_t* a0, uint64_t* a1, uint32_t* av, uint64_t* b0
     uint32_t* ov = flip ? av : bv;
     launch_onesweep(i0, i1, iv, o0, o1, ov, nwords, has_val, n, digits[x].word, digits[x].shift,
                     digits[x].mask, hists[x], cl.c->status, cl.tile_counter(), epoch, cl.lb_err(),
-                    cl.s);
+                    cl.c->sort_items, cl.s);
     flip = !flip;
   }
   return flip;
@@ -334,8 +335,9 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
 
 // Tunables of the hashed path for a key count: the LDS capacity of a batch
 // and the number of hash bits the LSD passes sort by. Segment sizes are close
-// to Poisson(mean), so the bits are the fewest for which mean + 6 sqrt(mean)
-// stays under 0.9 of the capacity. Context options override either.
+// to Poisson(mean), so the bits are the fewest for which mean + 3.5 sqrt(mean)
+// fits the capacity (the rare larger segment takes the sort-and-runs path).
+// Context options override either.
 void hashed_plan(const sd_ctx* c, uint64_t nk, int* cap, int* bits) {
   const int cp = c->group_cap ? c->group_cap : 2048;
   int b = c->group_bits;
@@ -343,7 +345,7 @@ void hashed_plan(const sd_ctx* c, uint64_t nk, int* cap, int* bits) {
     b = 0;
     while (b < 23) {
       const double mean = (double)nk / (double)(1ull << b);
-      if (mean + 6.0 * std::sqrt(mean) <= 0.9 * cp) break;
+      if (mean + 3.5 * std::sqrt(mean) <= cp) break;
       ++b;
     }
   }

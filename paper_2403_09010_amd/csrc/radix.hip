@@ -329,10 +329,11 @@ void launch_radix_hist(const uint64_t* w0, const uint64_t* w1, int nwords, uint6
     hipLaunchKernelGGL(sdk::k_radix_hist<1>, dim3(g), dim3(sdk::NT), 0, s, w0, w1, n, hist);
 }
 
-constexpr int KEYS_ITEMS = 32;
+// keys-only passes take 16 or 32 items per thread (the autotuner picks)
+static int keys_items(int items) { return items == 16 ? 16 : 32; }
 
-uint64_t onesweep_tile(int nwords, bool has_val) {
-  if (nwords == 1 && !has_val) return (uint64_t)sdk::NT * KEYS_ITEMS;
+uint64_t onesweep_tile(int nwords, bool has_val, int items) {
+  if (nwords == 1 && !has_val) return (uint64_t)sdk::NT * keys_items(items);
   return (uint64_t)sdk::NT * 16;
 }
 
@@ -340,9 +341,10 @@ void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* v
                      uint64_t* out0, uint64_t* out1, uint32_t* vout, int nwords, bool has_val,
                      uint32_t n, int word, int shift, uint32_t mask, const uint32_t* hist256,
                      uint64_t* status, uint32_t* tile_counter, uint32_t epoch, uint32_t* err,
-                     hipStream_t s) {
+                     int items, hipStream_t s) {
   if (!n) return;
-  const uint64_t tiles = (n + onesweep_tile(nwords, has_val) - 1) / onesweep_tile(nwords, has_val);
+  const uint64_t tile = onesweep_tile(nwords, has_val, items);
+  const uint64_t tiles = (n + tile - 1) / tile;
   dim3 g((unsigned)tiles), b(sdk::NT);
   if (nwords == 2 && has_val)
     hipLaunchKernelGGL((sdk::k_onesweep<2, true, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
@@ -353,9 +355,12 @@ void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* v
   else if (has_val)
     hipLaunchKernelGGL((sdk::k_onesweep<1, true, 16>), g, b, 0, s, in0, in1, vin, out0, out1,
                        vout, n, word, shift, mask, hist256, status, tile_counter, epoch, err);
+  else if (keys_items(items) == 16)
+    hipLaunchKernelGGL((sdk::k_onesweep_keys<16>), g, b, 0, s, word == 1 ? in1 : in0, out0, n,
+                       shift, mask, hist256, status, tile_counter, epoch, err);
   else
-    hipLaunchKernelGGL((sdk::k_onesweep_keys<KEYS_ITEMS>), g, b, 0, s, word == 1 ? in1 : in0,
-                       out0, n, shift, mask, hist256, status, tile_counter, epoch, err);
+    hipLaunchKernelGGL((sdk::k_onesweep_keys<32>), g, b, 0, s, word == 1 ? in1 : in0, out0, n,
+                       shift, mask, hist256, status, tile_counter, epoch, err);
 }
 
 uint64_t scan_tile() { return (uint64_t)sdk::NT * sdk::SCAN_ITEMS; }

@@ -26,13 +26,13 @@ void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 void launch_radix_hist(const uint64_t* w0, const uint64_t* w1, int nwords, uint64_t n,
                        uint32_t* hist, hipStream_t s);
-uint64_t onesweep_tile(int nwords, bool has_val);
+uint64_t onesweep_tile(int nwords, bool has_val, int items);
 // one stable pass by the digit (word[word] >> shift) & mask, mask <= 255
 void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* vin,
                      uint64_t* out0, uint64_t* out1, uint32_t* vout, int nwords, bool has_val,
                      uint32_t n, int word, int shift, uint32_t mask, const uint32_t* hist256,
                      uint64_t* status, uint32_t* tile_counter, uint32_t epoch, uint32_t* err,
-                     hipStream_t s);
+                     int items, hipStream_t s);
 uint64_t scan_tile();
 void launch_scan_excl(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* status,
                       uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s);
@@ -101,6 +101,7 @@ struct sd_ctx {
   int path = 0;        // 0 automatic, 1 full-key sort, 2 hashed
   int group_cap = 0;   // hashed path: LDS batch capacity (0 = automatic)
   int group_bits = 0;  // hashed path: hash bits sorted by the LSD passes (0 = automatic)
+  int sort_items = 0;  // keys-only radix passes: items per thread, 16 or 32 (0 = automatic)
   std::vector<hipEvent_t> events;
 };
 

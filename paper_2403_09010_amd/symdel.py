@@ -25,6 +25,7 @@ OPT_TIMING = 1
 OPT_PATH = 2
 OPT_GROUP_CAP = 3
 OPT_GROUP_BITS = 4
+OPT_SORT_ITEMS = 5
 MAX_STAGES = 16
 
 
