@@ -55,12 +55,213 @@ def cpu_baseline(codes, offsets, k, target_s=15.0):
             "seconds": dt, "sample_seqs": n, "sample_pairs": int(len(a))}
 
 
+def emit(out, args):
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
+def make_batched_sets(ref, nsets, scale):
+    """Query sets of log-uniform sizes in [1e3, 2e5] (seeded), 10% reference mutants."""
+    import cdr3gen
+    p = cdr3gen.BATCHED
+    sizes = cdr3gen.loguniform_sizes(p["size_seed"], nsets, p["size_lo"], p["size_hi"])
+    sizes = np.maximum(1, (sizes * scale).astype(np.int64))
+    return [cdr3gen.generate_query(p["set_seed_base"] + q, int(n), *ref,
+                                   ref_mut_frac=p["ref_mut_frac"]) for q, n in enumerate(sizes)]
+
+
+def run_batched(args):
+    """512 query sets against one 2M-sequence reference index at k=2: one set
+    per launch (sd_query) versus all sets in one batched call (sd_query_batch)."""
+    import torch
+    import cdr3gen
+    from paper_2403_09010_amd import Context
+    from paper_2403_09010_amd.symdel import _Seqs
+    p = cdr3gen.BATCHED
+    k = 2
+    nsets = args.sets
+    log(f"generating the {p['ref_n']}-sequence reference and {nsets} query sets")
+    ref = cdr3gen.generate(p["ref_seed"], p["ref_n"])
+    sets = make_batched_sets(ref, nsets, args.set_scale)
+    nq = sum(len(o) - 1 for _, o in sets)
+    dev = torch.device("cuda", 0)
+    ctx = Context(0)
+    stream = int(torch.cuda.current_stream().cuda_stream)
+    t0 = time.perf_counter()
+    idx = ctx.build_index(torch.from_numpy(ref[0]).to(dev), torch.from_numpy(ref[1]).to(dev), k)
+    torch.cuda.synchronize()
+    t_index = time.perf_counter() - t0
+    info = idx.info()
+    log(f"index: {info} in {t_index:.2f} s; {nq} query sequences")
+    dsets = [(torch.from_numpy(c).to(dev), torch.from_numpy(o).to(dev)) for c, o in sets]
+    arr = (_Seqs * nsets)()
+    for x, (c, o) in enumerate(dsets):
+        arr[x] = _Seqs(c.data_ptr() if c.numel() else None, o.data_ptr(), o.numel() - 1, 1)
+
+    def plain_once():
+        tot = 0
+        for x in range(nsets):
+            outs = ctx.query_batch_raw(idx, ctypes_pointer(arr, x), 1, k, stream)
+            tot += outs[0].n
+            ctx.free_pairs(outs[0])
+        return tot
+
+    def batched_once():
+        outs = ctx.query_batch_raw(idx, arr, nsets, k, stream)
+        tot = sum(outs[x].n for x in range(nsets))
+        for x in range(nsets):
+            ctx.free_pairs(outs[x])
+        return tot
+
+    res = {}
+    for name, fn in (("plain", plain_once), ("batched", batched_once)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pairs = fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[name] = (dt, pairs)
+        log(f"{name}: {dt * 1e3:.1f} ms per run, {pairs} pairs")
+    assert res["plain"][1] == res["batched"][1]
+    dt, pairs = res["batched"]
+    out = {
+        "metric": "Batched query: 512 repertoires vs 2M reference, k=2 (pairs/s)",
+        "value": round(pairs / dt, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic (seeded CDR3-like generator)",
+        "config": {"workload": "batched_2m_512", "ref_n": p["ref_n"], "sets": nsets,
+                   "query_seqs": nq, "k": k, "pairs": int(pairs),
+                   "index_keys": info["n_keys"], "index_build_s": round(t_index, 3)},
+        "plain_one_set_per_launch": {"seconds": round(res["plain"][0], 4),
+                                     "pairs_per_s": round(res["plain"][1] / res["plain"][0], 1)},
+        "batched": {"seconds": round(dt, 4), "pairs_per_s": round(pairs / dt, 1)},
+        "speedup_batched_vs_plain": round(res["plain"][0] / dt, 3),
+    }
+    idx.free()
+    ctx.close()
+    emit(out, args)
+
+
+def ctypes_pointer(arr, x):
+    import ctypes
+    from paper_2403_09010_amd.symdel import _Seqs
+    return ctypes.cast(ctypes.byref(arr, x * ctypes.sizeof(_Seqs)), ctypes.POINTER(_Seqs))
+
+
+def run_served(args):
+    """Poisson-arriving query sets (sizes log-uniform in [100, 5e4]) against a
+    5M-sequence reference index, weighted rescoring (costs {3, 4}, indel 8,
+    score <= 8), continuous batching versus one request at a time."""
+    import threading
+    import torch
+    import cdr3gen
+    from paper_2403_09010_amd import Context, Server
+    p = cdr3gen.SERVED
+    log(f"generating the {p['ref_n'] // args.ref_div}-sequence reference")
+    ref = cdr3gen.generate(p["ref_seed"], p["ref_n"] // args.ref_div)
+    dev = torch.device("cuda", 0)
+    ctx = Context(0)
+    t0 = time.perf_counter()
+    idx = ctx.build_index(torch.from_numpy(ref[0]).to(dev), torch.from_numpy(ref[1]).to(dev), 2)
+    torch.cuda.synchronize()
+    t_index = time.perf_counter() - t0
+    info = idx.info()
+    log(f"index: {info} in {t_index:.2f} s")
+    subst = cdr3gen.cost_matrix(p["cost_seed"], p["cost_lo"], p["cost_hi"])
+    nreq = args.requests
+    sizes = cdr3gen.loguniform_sizes(p["arrival_seed"], nreq, p["size_lo"], p["size_hi"])
+    reqs = [cdr3gen.generate_query(20000 + x, int(n), *ref, ref_mut_frac=0.1)
+            for x, n in enumerate(sizes)]
+
+    def run(server_kw, rate, count):
+        """Submit `count` requests (rate None: all at once); return latencies, wall time, pairs."""
+        with Server(idx, k=2, subst=subst, indel=p["indel"], max_score=p["max_score"],
+                    **server_kw) as sv:
+            ids = [None] * count
+            t_arr = (cdr3gen.poisson_arrivals(p["arrival_seed"], count, rate)
+                     if rate else np.zeros(count))
+            start = time.perf_counter()
+
+            def producer():
+                for x in range(count):
+                    wait = start + t_arr[x] - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                    ids[x] = sv.submit(*reqs[x % nreq])
+
+            th = threading.Thread(target=producer)
+            th.start()
+            lats, pairs = [], 0
+            for x in range(count):
+                while ids[x] is None:
+                    time.sleep(0.0002)
+                r, lat = sv.poll(ids[x], timeout_ms=600000)
+                lats.append(lat)
+                pairs += len(r)
+            th.join()
+            wall = time.perf_counter() - start
+            st = sv.stats()
+        return np.array(lats), wall, pairs, st
+
+    # saturation throughput X: everything queued at once
+    burst = min(nreq, args.burst)
+    lats, wall, pairs, st = run({"workers": 2}, None, burst)
+    X = burst / wall
+    log(f"saturation: {burst} requests in {wall:.2f} s -> X = {X:.1f} req/s, batches {st}")
+    _, wall1, _, st1 = run({"workers": 1, "max_batch_requests": 1}, None, min(burst, 200))
+    X1 = min(burst, 200) / wall1
+    log(f"serial saturation: {X1:.1f} req/s")
+    rates = {}
+    for frac in (0.5, 0.9):
+        rate = frac * X
+        lats, wall, pairs, st = run({"workers": 2}, rate, nreq)
+        rates[str(frac)] = {"rate_req_s": round(rate, 2), "p50_ms": round(np.percentile(lats, 50) * 1e3, 2),
+                            "p99_ms": round(np.percentile(lats, 99) * 1e3, 2),
+                            "throughput_req_s": round(nreq / wall, 2),
+                            "pairs_per_s": round(pairs / wall, 1), "batches": st["batches"],
+                            "max_batch": st["max_batch"]}
+        log(f"rate {rate:.1f}/s: {rates[str(frac)]}")
+        lats_s, wall_s, _, _ = run({"workers": 1, "max_batch_requests": 1}, rate,
+                                   min(nreq, args.serial_requests))
+        rates[str(frac)]["serial_p50_ms"] = round(np.percentile(lats_s, 50) * 1e3, 2)
+        rates[str(frac)]["serial_p99_ms"] = round(np.percentile(lats_s, 99) * 1e3, 2)
+        log(f"  serial at the same rate: p50 {rates[str(frac)]['serial_p50_ms']} ms, "
+            f"p99 {rates[str(frac)]['serial_p99_ms']} ms")
+    out = {
+        "metric": "Served: Poisson query sets vs 5M reference, weighted score <= 8 (requests/s)",
+        "value": round(X, 2), "unit": "requests/s", "n_gpus": 1, "steps": nreq, "warmup": 0,
+        "ms_per_step": round(1e3 / X, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic (seeded CDR3-like generator)",
+        "config": {"workload": "served_5m", "ref_n": int(len(ref[1]) - 1), "requests": nreq,
+                   "index_keys": info["n_keys"], "index_build_s": round(t_index, 3),
+                   "saturation_req_s": round(X, 2), "serial_saturation_req_s": round(X1, 2)},
+        "poisson": rates,
+    }
+    idx.free()
+    ctx.close()
+    emit(out, args)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain_1m_k2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="plain_1m_k2",
+                    choices=sorted(WORKLOADS) + ["batched_2m_512", "served_5m"])
+    ap.add_argument("--sets", type=int, default=512, help="batched: number of query sets")
+    ap.add_argument("--set-scale", type=float, default=1.0, help="batched: scale of set sizes")
+    ap.add_argument("--requests", type=int, default=2000, help="served: requests per rate")
+    ap.add_argument("--burst", type=int, default=400, help="served: requests for saturation")
+    ap.add_argument("--serial-requests", type=int, default=200, help="served: serial comparison")
+    ap.add_argument("--ref-div", type=int, default=1, help="served: reference size divisor")
     ap.add_argument("--path", type=int, default=0, help="grouping path (0 auto, 1 full-key sort)")
     ap.add_argument("--group-cap", type=int, default=0, help="hashed path LDS capacity (0 auto)")
     ap.add_argument("--group-bits", type=int, default=0, help="hashed path hash bits (0 auto)")
@@ -73,6 +274,10 @@ def main():
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched_2m_512":
+        return run_batched(args)
+    if args.workload == "served_5m":
+        return run_served(args)
 
     import torch
     import cdr3gen

@@ -79,6 +79,7 @@ typedef struct {
   int32_t n_stages;       /* valid entries below (0 unless SD_OPT_TIMING is on) */
   int32_t n_sort_passes;  /* radix passes run by the grouping sort */
   int64_t n_big_segments; /* hashed path: hash segments too large for LDS (full-key path) */
+  int64_t n_probe_steps;  /* learned indexes: comparisons made by the lookups' searches */
   char stage_name[SD_MAX_STAGES][24];
   double stage_ms[SD_MAX_STAGES];      /* device time between HIP events on `stream` */
   double stage_bytes[SD_MAX_STAGES];   /* algorithmic HBM bytes of the stage */
@@ -91,6 +92,8 @@ typedef struct {
 #define SD_OPT_GROUP_CAP 3  /* hashed path: LDS batch capacity, 0 (automatic), 256, 1024, 2048 or 4096 */
 #define SD_OPT_GROUP_BITS 4 /* hashed path: hash bits sorted by LSD passes, 0 (automatic) .. 23 */
 #define SD_OPT_SORT_ITEMS 5 /* keys-only radix passes: items per thread, 0 (automatic), 16 or 32 */
+#define SD_OPT_BATCH_TILE 6 /* query batches: at most this many query sequences per tile (0: 4Mi) */
+#define SD_OPT_PROBE 7      /* learned indexes: 0 = search the model's window, 1 = binary search over the whole index */
 
 /*
  * Create a context on HIP device `device`. hbm_budget_bytes bounds the
@@ -123,6 +126,166 @@ int sd_self_search(sd_ctx* ctx, const sd_seqs* seqs, int k, sd_pairs* out, void*
  */
 int sd_pair_distance(sd_ctx* ctx, const sd_seqs* a, const sd_seqs* b, const uint32_t* ia,
                      const uint32_t* ib, int64_t n, uint8_t* d_out, void* stream);
+
+/*
+ * Reference index for query-versus-reference search (the database lookup of
+ * the paper's Section IV, with the symmetric-deletion variant map of Section
+ * II A built once for the reference): every <= k-deletion variant of `ref`,
+ * stored on the context's device and owned by the index, read-only after the
+ * build (several contexts on the same device may query it concurrently).
+ * Release with sd_index_free (no context needed). k must be 0, 1 or 2.
+ * Errors: as sd_self_search.
+ */
+typedef struct sd_index sd_index;
+int sd_index_build(sd_ctx* ctx, const sd_seqs* ref, int k, sd_index** out, void* stream);
+void sd_index_free(sd_index* index);
+/* Size of an index; any output pointer may be NULL. */
+int sd_index_info(const sd_index* index, int64_t* n_ref, int64_t* n_keys, int32_t* k,
+                  int64_t* bytes);
+
+/*
+ * Learned reference index. The paper has no learned component; this one can
+ * change the speed of a lookup and never its result. The index holds every
+ * <= k-deletion variant of `ref` as its exact 128-bit key (the compressed
+ * form of Appendix A widened to 24 residues plus a length field), sorted by
+ * key with the reference id beside it, and a two-stage model that predicts a
+ * key's position:
+ *   stage 1  an FP32 MLP 1 -> SD_MLP_HIDDEN (tanh) -> 1 over a normalised
+ *            feature of the key's top 24 bits, trained on the device by
+ *            full-batch Adam on the mean squared error of the rank fraction
+ *            at cfg.samples evenly spaced ranks; its output picks a leaf
+ *   stage 2  per leaf, the line through the leaf's first and last key
+ * After training every leaf stores its exact worst position error eps over
+ * all indexed keys, and a lookup searches only [p - eps, p + eps]. Queries
+ * (sd_query, sd_query_batch, the weighted forms and the server) accept the
+ * index like a hashed one and return identical results; SD_OPT_PROBE = 1
+ * switches a context's lookups to a binary search over the whole key array
+ * (the same lookup without the model) and sd_stats.n_probe_steps counts the
+ * comparisons either way. Release with sd_index_free.
+ */
+#define SD_MLP_HIDDEN 32
+#define SD_MLP_PARAMS (3 * SD_MLP_HIDDEN + 1) /* w1[H], b1[H], w2[H], b2 */
+typedef struct {
+  int32_t leaves_log2; /* stage-2 leaves = 2^leaves_log2 in [4, 24] (0: about 256 keys per leaf) */
+  int32_t steps;       /* Adam steps (0 trains nothing; -1: 400) */
+  float lr;            /* Adam learning rate (0: 0.01) */
+  uint32_t samples;    /* training samples, at most 2^24 (0: 65536) */
+  int32_t use_init;    /* 1: start from init[]; 0: tanh units placed at sample quantiles */
+  float init[SD_MLP_PARAMS];
+} sd_learned_config;
+int sd_index_build_learned(sd_ctx* ctx, const sd_seqs* ref, int k, const sd_learned_config* cfg,
+                           sd_index** out, void* stream);
+
+/* Model of a learned index (SD_E_INVAL for a hashed index). */
+typedef struct {
+  int32_t leaves;
+  int32_t steps;            /* Adam steps taken */
+  uint32_t max_eps;         /* largest leaf error bound */
+  uint32_t empty_leaves;
+  double mean_eps;          /* leaf error bound averaged over the indexed keys */
+  double mean_window_log2;  /* log2(2 eps + 1) averaged over the indexed keys */
+  float loss_first, loss_last; /* training loss of the first and last step */
+  float feature_shift, feature_scale; /* x1 = ((key >> 104) - shift) * scale */
+  double train_ms, fit_ms;  /* device time of training and of the leaf fit */
+  float params[SD_MLP_PARAMS];
+} sd_learned_info;
+/* loss_curve (host, may be NULL) receives the first min(cap, steps) losses. */
+int sd_index_learned_info(const sd_index* index, sd_learned_info* out, float* loss_curve,
+                          int32_t cap);
+
+/*
+ * Gradient of the stage-1 training loss, computed by the same device kernels
+ * the training runs: loss = (1/n) sum_s (f(x_s) - y_s)^2 with
+ * f(x) = b2 + sum_j w2[j] tanh(w1[j] x + b1[j]). params (SD_MLP_PARAMS
+ * floats), x and y (n floats) are host arrays; grad (SD_MLP_PARAMS floats)
+ * and *loss are written on the host. Partial sums are reduced in a fixed
+ * order, so the result is deterministic. Errors: SD_E_INVAL (null pointer,
+ * n == 0 or n > 2^24), SD_E_NOMEM, SD_E_HIP.
+ */
+int sd_mlp_gradients(sd_ctx* ctx, const float* params, const float* x, const float* y, uint32_t n,
+                     float* grad, float* loss, void* stream);
+
+/*
+ * Query search: every (q, r) with Levenshtein(query q, reference r) <= k,
+ * returned as (i = q, j = r, d), sorted by (q, r). k must not exceed the
+ * index's k. Errors: as sd_self_search, and SD_E_INVAL for an index on
+ * another device.
+ */
+int sd_query(sd_ctx* ctx, const sd_index* index, const sd_seqs* q, int k, sd_pairs* out,
+             void* stream);
+
+/*
+ * Batched query search: nsets query sets against one index in as few
+ * pipeline runs as the tile limit allows (SD_OPT_BATCH_TILE); outs[s] is the
+ * result of set s exactly as sd_query would return it (query ids local to
+ * the set). The caller sets outs[s].on_device for every set. On error no
+ * result is returned.
+ */
+int sd_query_batch(sd_ctx* ctx, const sd_index* index, int nsets, const sd_seqs* sets, int k,
+                   sd_pairs* outs, void* stream);
+
+/*
+ * Weighted query (Section III D: a Levenshtein prefilter followed by a finer
+ * substitution-weighted metric): candidates within Levenshtein distance
+ * index.k, rescored by the minimum-cost global alignment with substitution
+ * costs subst[a * 20 + b] (host array of 400 bytes) and indel cost `indel`;
+ * pairs with score <= max_score are returned with d = score (capped at 255),
+ * sorted by (q, r).
+ */
+int sd_query_weighted(sd_ctx* ctx, const sd_index* index, const sd_seqs* q, const uint8_t* subst,
+                      int indel, int max_score, sd_pairs* out, void* stream);
+
+/* sd_query_weighted for nsets query sets at once (as sd_query_batch). */
+int sd_query_batch_weighted(sd_ctx* ctx, const sd_index* index, int nsets, const sd_seqs* sets,
+                            const uint8_t* subst, int indel, int max_score, sd_pairs* outs,
+                            void* stream);
+
+/*
+ * Continuous-batching query server over one index (serving query sets as
+ * they arrive). Worker threads each hold a context and a HIP stream; an idle
+ * worker admits the queued requests in arrival order while their estimated
+ * device working memory, together with the batches other workers have in
+ * flight, fits hbm_budget, and runs them as one batched query. Requests that
+ * arrive while batches run join the next batch, and batches of different
+ * workers overlap on the GPU. A request's result is identical to a query of
+ * that set alone (sd_query, or sd_query_weighted when `weighted`).
+ * The index must outlive the server.
+ */
+typedef struct sd_server sd_server;
+typedef struct {
+  int32_t k;                  /* lookup radius, at most the index's k */
+  int32_t workers;            /* batches in flight at once, 1..16 (0: 2) */
+  int32_t max_batch_requests; /* requests admitted into one batch (0: no limit) */
+  int32_t weighted;           /* 1: rescore as sd_query_weighted with the fields below */
+  uint64_t hbm_budget;        /* device working memory of all batches in flight (0: no bound) */
+  uint8_t subst[400];
+  int32_t indel;
+  int32_t max_score;
+  int32_t probe; /* SD_OPT_PROBE of the workers' contexts (learned indexes) */
+} sd_server_config;
+
+/* Errors: SD_E_INVAL (bad config, index on another device), SD_E_NOMEM. */
+int sd_server_create(const sd_index* index, int device, const sd_server_config* cfg,
+                     sd_server** out);
+/* Queue a query set (host memory, copied before return); returns its id. */
+int sd_server_submit(sd_server* server, const sd_seqs* q, uint64_t* request_id);
+/*
+ * Wait up to timeout_ms (-1: forever, 0: do not wait) for a request's result.
+ * On SD_OK `out` holds host arrays owned by the caller (release with
+ * sd_server_free_pairs) and *latency_s the seconds from submit to completion.
+ * SD_E_STATE: not finished within the timeout. SD_E_CANCELLED: cancelled.
+ * SD_E_NOMEM: the request alone exceeds hbm_budget. Other codes: the batch's
+ * error. A result is returned once.
+ */
+int sd_server_poll(sd_server* server, uint64_t request_id, int timeout_ms, sd_pairs* out,
+                   double* latency_s);
+/* Cancel a queued or running request (its poll then returns SD_E_CANCELLED). */
+int sd_server_cancel(sd_server* server, uint64_t request_id);
+/* Batches run, requests finished and the largest batch so far. */
+int sd_server_stats(sd_server* server, int64_t* batches, int64_t* requests, int64_t* max_batch);
+void sd_server_free_pairs(sd_pairs* pairs);
+/* Stop the workers (queued requests are cancelled) and free the server. */
+void sd_server_destroy(sd_server* server);
 
 /* Counters and stage timings of the last successful search on ctx. */
 int sd_get_stats(const sd_ctx* ctx, sd_stats* out);

@@ -3,6 +3,7 @@
 // aborts the process and the context stays usable after an error.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -227,6 +228,14 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
       if (value != 0 && value != 16 && value != 32) return SD_E_INVAL;
       c->sort_items = (int)value;
       return SD_OK;
+    case SD_OPT_BATCH_TILE:
+      if (value < 0) return SD_E_INVAL;
+      c->batch_tile_seqs = value;
+      return SD_OK;
+    case SD_OPT_PROBE:
+      if (value < 0 || value > 1) return SD_E_INVAL;
+      c->probe = (int)value;
+      return SD_OK;
     default:
       c->last_error = "unknown option";
       return SD_E_INVAL;
@@ -251,6 +260,112 @@ int sd_pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32
     sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
     sd::pair_distance(c, a, b, ia, ib, n, d_out, static_cast<hipStream_t>(stream));
   });
+}
+
+int sd_index_build(sd_ctx* c, const sd_seqs* ref, int k, sd_index** out, void* stream) {
+  if (!c || !ref || !out) return SD_E_INVAL;
+  *out = nullptr;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    *out = sd::index_build(c, ref, k, static_cast<hipStream_t>(stream));
+  });
+}
+
+void sd_index_free(sd_index* idx) { sd::index_free(idx); }
+
+int sd_index_info(const sd_index* idx, int64_t* n_ref, int64_t* n_keys, int32_t* k,
+                  int64_t* bytes) {
+  if (!idx) return SD_E_INVAL;
+  if (n_ref) *n_ref = (int64_t)idx->n_ref;
+  if (n_keys) *n_keys = (int64_t)idx->n_keys;
+  if (k) *k = idx->k;
+  if (bytes) *bytes = (int64_t)idx->bytes;
+  return SD_OK;
+}
+
+int sd_index_build_learned(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_config* cfg,
+                           sd_index** out, void* stream) {
+  if (!c || !ref || !out) return SD_E_INVAL;
+  *out = nullptr;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    *out = sd::learned_build(c, ref, k, cfg, static_cast<hipStream_t>(stream));
+  });
+}
+
+int sd_index_learned_info(const sd_index* idx, sd_learned_info* out, float* loss_curve,
+                          int32_t cap) {
+  if (!idx || !out || !idx->learned || cap < 0) return SD_E_INVAL;
+  *out = idx->info;
+  if (loss_curve) {
+    const size_t n = std::min<size_t>((size_t)cap, idx->loss_curve.size());
+    if (n) std::memcpy(loss_curve, idx->loss_curve.data(), n * sizeof(float));
+  }
+  return SD_OK;
+}
+
+int sd_mlp_gradients(sd_ctx* c, const float* params, const float* x, const float* y, uint32_t n,
+                     float* grad, float* loss, void* stream) {
+  if (!c) return SD_E_INVAL;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::mlp_gradients(c, params, x, y, n, grad, loss, static_cast<hipStream_t>(stream));
+  });
+}
+
+static void reset_pairs(sd_pairs* p) {
+  const int32_t want_device = p->on_device;
+  std::memset(p, 0, sizeof(*p));
+  p->on_device = want_device;
+}
+
+int sd_query(sd_ctx* c, const sd_index* idx, const sd_seqs* q, int k, sd_pairs* out,
+             void* stream) {
+  if (!c || !q || !out) return SD_E_INVAL;
+  reset_pairs(out);
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::query_sets(c, idx, 1, q, k, nullptr, out, static_cast<hipStream_t>(stream));
+  });
+}
+
+int sd_query_batch(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, int k,
+                   sd_pairs* outs, void* stream) {
+  if (!c || nsets < 0 || (nsets > 0 && (!sets || !outs))) return SD_E_INVAL;
+  for (int x = 0; x < nsets; ++x) reset_pairs(&outs[x]);
+  const int rc = guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::query_sets(c, idx, nsets, sets, k, nullptr, outs, static_cast<hipStream_t>(stream));
+  });
+  if (rc != SD_OK)  // all or nothing: release whatever was produced before the error
+    for (int x = 0; x < nsets; ++x) sd_pairs_free(c, &outs[x]);
+  return rc;
+}
+
+int sd_query_weighted(sd_ctx* c, const sd_index* idx, const sd_seqs* q, const uint8_t* subst,
+                      int indel, int max_score, sd_pairs* out, void* stream) {
+  if (!c || !q || !out) return SD_E_INVAL;
+  reset_pairs(out);
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::query_weighted(c, idx, 1, q, subst, indel, max_score, out,
+                       static_cast<hipStream_t>(stream));
+  });
+}
+
+int sd_query_batch_weighted(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets,
+                            const uint8_t* subst, int indel, int max_score, sd_pairs* outs,
+                            void* stream) {
+  if (!c || nsets < 0 || (nsets > 0 && (!sets || !outs))) return SD_E_INVAL;
+  for (int x = 0; x < nsets; ++x) reset_pairs(&outs[x]);
+  const int rc = guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::query_weighted(c, idx, nsets, sets, subst, indel, max_score, outs,
+                       static_cast<hipStream_t>(stream));
+  });
+  if (rc != SD_OK)
+    for (int x = 0; x < nsets; ++x) sd_pairs_free(c, &outs[x]);
+  return rc;
 }
 
 int sd_get_stats(const sd_ctx* c, sd_stats* out) {

@@ -21,125 +21,13 @@
 #include <cstring>
 #include <vector>
 
-#include "sd_internal.h"
+#include "sd_host.h"
 
 namespace sd {
 
-namespace {
-
-struct DevSeqs {
-  const uint8_t* codes;
-  const int64_t* offs;
-  uint64_t n;
-};
-
-void check_seqs(const sd_seqs* s) {
-  if (!s) throw Error{SD_E_INVAL, "null sequence set"};
-  if (s->n < 0) throw Error{SD_E_INVAL, "negative sequence count"};
-  if (s->n > 0 && (!s->codes || !s->offsets)) throw Error{SD_E_INVAL, "null codes or offsets"};
-  if ((uint64_t)s->n >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "at most 2^32 - 2 sequences"};
-}
-
-DevSeqs stage_seqs(sd_ctx* c, Scratch& sc, const sd_seqs* s, hipStream_t st) {
-  DevSeqs d{s->codes, s->offsets, (uint64_t)s->n};
-  if (s->on_device || s->n == 0) return d;
-  const int64_t total = s->offsets[s->n];
-  if (s->offsets[0] != 0) throw Error{SD_E_INVAL, "offsets must start at 0"};
-  for (int64_t x = 0; x < s->n; ++x)  // every sequence must lie inside codes[0, total)
-    if (s->offsets[x + 1] < s->offsets[x]) throw Error{SD_E_INVAL, "offsets must not decrease"};
-  uint8_t* codes = sc.get<uint8_t>((uint64_t)total + 1);
-  int64_t* offs = sc.get<int64_t>((uint64_t)s->n + 1);
-  if (total)
-    hip_check(hipMemcpyAsync(codes, s->codes, (size_t)total, hipMemcpyHostToDevice, st), "H2D codes");
-  hip_check(hipMemcpyAsync(offs, s->offsets, (size_t)(s->n + 1) * 8, hipMemcpyHostToDevice, st),
-            "H2D offsets");
-  d.codes = codes;
-  d.offs = offs;
-  return d;
-}
-
-void raise_validation(uint32_t err) {
-  if (err & SD_ERRBIT_LENGTH) throw Error{SD_E_LENGTH, "a sequence length is outside [1, 24]"};
-  if (err & SD_ERRBIT_ALPHABET) throw Error{SD_E_ALPHABET, "a residue code is >= 20"};
-  if (err & SD_ERRBIT_INDEX) throw Error{SD_E_INVAL, "an index is out of range"};
-}
-
-int bits_for(uint64_t maxval) {
-  int b = 0;
-  while (b < 64 && (maxval >> b)) ++b;
-  return b;
-}
-
-// one LSD digit: word, shift inside the word, mask
-struct Digit {
-  int word, shift;
-  uint32_t mask;
-};
-
-// Counter slots of the per-call counter area (zeroed at the start of a call).
-enum : int {
-  CNT_ERR = 0,        // validation flags
-  CNT_TILE0 = 1,      // first of the per-launch tile counters
-  CNT_TILE_END = 60,
-  CNT_NKEYS = 64,     // u64 copy of the key total
-  CNT_CAND = 96,      // u64 candidate counter
-  CNT_PAIRS = 98,     // u64 result counter
-  CNT_LBERR = 100,    // look-back bound hits
-  CNT_NBIG = 102,     // u64 count of oversized segments
-  CNT_CAND2 = 104,    // u64 candidate counter of the full-key emission
-  CNT_TOTAL = 128
-};
-
-struct Call {
-  sd_ctx* c;
-  hipStream_t s;
-  Scratch& sc;
-  StageTimer& tm;
-  uint32_t* counters;
-  int slot = CNT_TILE0;
-  uint32_t* tile_counter() {
-    if (slot >= CNT_TILE_END) {  // recycle: zero a fresh block of slots
-      launch_fill_u32(counters + CNT_TILE0, 0, CNT_TILE_END - CNT_TILE0, s);
-      slot = CNT_TILE0;
-    }
-    return counters + slot++;
-  }
-  uint32_t* lb_err() { return counters + CNT_LBERR; }
-};
-
-// Sort records by the given digits in LSD order; returns true if the result
-// sits in the second buffer set.
-bool radix_sort(Call& cl, uint64_t* a0, uint64_t* a1, uint32_t* av, uint64_t* b0, uint64_t* b1,
-                uint32_t* bv, int nwords, bool has_val, uint32_t n, const std::vector<Digit>& digits,
-                const std::vector<const uint32_t*>& hists) {
-  bool flip = false;
-  const uint64_t tile = onesweep_tile(nwords, has_val, cl.c->sort_items);
-  const uint64_t tiles = (n + tile - 1) / tile;
-  for (size_t x = 0; x < digits.size(); ++x) {
-    const uint32_t epoch = next_epoch(cl.c, tiles * 256, cl.s);
-    const uint64_t* i0 = flip ? b0 : a0;
-    const uint64_t* i1 = flip ? b1 : a1;
-    const uint32_t* iv = flip ? bv : av;
-    uint64_t* o0 = flip ? a0 : b0;
-    uint64_t* o1 = flip ? a1 : b1;
-    uint32_t* ov = flip ? av : bv;
-    launch_onesweep(i0, i1, iv, o0, o1, ov, nwords, has_val, n, digits[x].word, digits[x].shift,
-                    digits[x].mask, hists[x], cl.c->status, cl.tile_counter(), epoch, cl.lb_err(),
-                    cl.c->sort_items, cl.s);
-    flip = !flip;
-  }
-  return flip;
-}
-
-struct Cands {
-  uint64_t* p = nullptr;  // pool block owned by the caller
-  uint64_t n = 0;
-};
-
-// Full-key grouping of nk (key, id) records: stable LSD sort over the
-// non-trivial digits of the 128-bit key, then run emission.
-Cands fullkey_group(Call& cl, uint64_t* klo, uint64_t* khi, uint32_t* kid, uint32_t nk,
-                    int& passes_out) {
+// Stable LSD sort of nk (key, id) records over the non-trivial digits of the
+// 128-bit key.
+SortedKeys full_key_sort(Call& cl, uint64_t* klo, uint64_t* khi, uint32_t* kid, uint32_t nk) {
   sd_ctx* c = cl.c;
   uint64_t* klo2 = cl.sc.get<uint64_t>(nk);
   uint64_t* khi2 = cl.sc.get<uint64_t>(nk);
@@ -152,7 +40,7 @@ Cands fullkey_group(Call& cl, uint64_t* klo, uint64_t* khi, uint32_t* kid, uint3
   {
     const uint32_t* h = static_cast<const uint32_t*>(readback(c, hist, 16 * 256 * 4, cl.s));
     for (int q = 0; q < 16; ++q) {
-      bool trivial = false;
+      bool trivial = false;  // every key has the same digit: the pass would not move anything
       for (int b = 0; b < 256; ++b)
         if (h[q * 256 + b] == nk) trivial = true;
       if (!trivial) {
@@ -163,11 +51,22 @@ Cands fullkey_group(Call& cl, uint64_t* klo, uint64_t* khi, uint32_t* kid, uint3
   }
   cl.tm.mark("sort_hist", (double)nk * 16, 2);
   const bool flip = radix_sort(cl, klo, khi, kid, klo2, khi2, kid2, 2, true, nk, digits, hists);
-  passes_out = (int)digits.size();
   cl.tm.mark("sort_passes", (double)nk * 40 * digits.size(), (int)digits.size());
-  const uint64_t* slo = flip ? klo2 : klo;
-  const uint64_t* shi = flip ? khi2 : khi;
-  const uint32_t* sid = flip ? kid2 : kid;
+  return SortedKeys{flip ? klo2 : klo, flip ? khi2 : khi, flip ? kid2 : kid, (int)digits.size()};
+}
+
+namespace {
+
+// Full-key grouping: the key sort, then emission of the pairs in each run of
+// equal keys.
+Cands fullkey_group(Call& cl, uint64_t* klo, uint64_t* khi, uint32_t* kid, uint32_t nk,
+                    int& passes_out) {
+  sd_ctx* c = cl.c;
+  const SortedKeys sk = full_key_sort(cl, klo, khi, kid, nk);
+  passes_out = sk.passes;
+  const uint64_t* slo = sk.lo;
+  const uint64_t* shi = sk.hi;
+  const uint32_t* sid = sk.id;
 
   uint64_t cap = nk / 16 + 65536;
   Cands out;
@@ -186,16 +85,6 @@ Cands fullkey_group(Call& cl, uint64_t* klo, uint64_t* khi, uint32_t* kid, uint3
   out.n = nc;
   cl.tm.mark("emit", (double)nk * 20 + (double)nc * 8, 1);
   return out;
-}
-
-// Sorting digits over bits [lo, 64) of a 64-bit word, least significant first.
-std::vector<Digit> top_digits(int lo) {
-  std::vector<Digit> d;
-  for (int b = lo; b < 64; b += 8) {
-    const int w = std::min(8, 64 - b);
-    d.push_back(Digit{0, b, (1u << w) - 1u});
-  }
-  return d;
 }
 
 // Elements of hash segments too large for LDS: sort them by the full hash
@@ -463,6 +352,11 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
     throw;
   }
   c->stats.n_pairs = (int64_t)npairs;
+  finish_output(c, oi, oj, od, npairs, out, s);
+}
+
+void finish_output(sd_ctx* c, uint32_t* oi, uint32_t* oj, uint8_t* od, uint64_t npairs,
+                   sd_pairs* out, hipStream_t s) {
   out->n = (int64_t)npairs;
   if (out->on_device) {
     out->i = oi;
@@ -495,6 +389,7 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
     dfree(c, oi);
     dfree(c, oj);
     dfree(c, od);
+    out->n = 0;
     throw;
   }
   dfree(c, oi);

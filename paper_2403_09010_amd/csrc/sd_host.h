@@ -1,0 +1,185 @@
+// Host-side helpers shared by the search pipelines (self search and
+// query-versus-reference): staging of sequence sets, the per-call counter
+// area, and the LSD radix-sort driver over the onesweep kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "sd_internal.h"
+
+namespace sd {
+
+struct DevSeqs {
+  const uint8_t* codes;
+  const int64_t* offs;
+  uint64_t n;
+};
+
+inline void check_seqs(const sd_seqs* s) {
+  if (!s) throw Error{SD_E_INVAL, "null sequence set"};
+  if (s->n < 0) throw Error{SD_E_INVAL, "negative sequence count"};
+  if (s->n > 0 && (!s->codes || !s->offsets)) throw Error{SD_E_INVAL, "null codes or offsets"};
+  if ((uint64_t)s->n >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "at most 2^32 - 2 sequences"};
+}
+
+inline DevSeqs stage_seqs(sd_ctx* c, Scratch& sc, const sd_seqs* s, hipStream_t st) {
+  DevSeqs d{s->codes, s->offsets, (uint64_t)s->n};
+  if (s->on_device || s->n == 0) return d;
+  const int64_t total = s->offsets[s->n];
+  if (s->offsets[0] != 0) throw Error{SD_E_INVAL, "offsets must start at 0"};
+  for (int64_t x = 0; x < s->n; ++x)  // every sequence must lie inside codes[0, total)
+    if (s->offsets[x + 1] < s->offsets[x]) throw Error{SD_E_INVAL, "offsets must not decrease"};
+  uint8_t* codes = sc.get<uint8_t>((uint64_t)total + 1);
+  int64_t* offs = sc.get<int64_t>((uint64_t)s->n + 1);
+  if (total)
+    hip_check(hipMemcpyAsync(codes, s->codes, (size_t)total, hipMemcpyHostToDevice, st), "H2D codes");
+  hip_check(hipMemcpyAsync(offs, s->offsets, (size_t)(s->n + 1) * 8, hipMemcpyHostToDevice, st),
+            "H2D offsets");
+  d.codes = codes;
+  d.offs = offs;
+  return d;
+}
+
+inline void raise_validation(uint32_t err) {
+  if (err & SD_ERRBIT_LENGTH) throw Error{SD_E_LENGTH, "a sequence length is outside [1, 24]"};
+  if (err & SD_ERRBIT_ALPHABET) throw Error{SD_E_ALPHABET, "a residue code is >= 20"};
+  if (err & SD_ERRBIT_INDEX) throw Error{SD_E_INVAL, "an index is out of range"};
+}
+
+inline int bits_for(uint64_t maxval) {
+  int b = 0;
+  while (b < 64 && (maxval >> b)) ++b;
+  return b;
+}
+
+// one LSD digit: word, shift inside the word, mask
+struct Digit {
+  int word, shift;
+  uint32_t mask;
+};
+
+// Counter slots of the per-call counter area (zeroed at the start of a call).
+enum : int {
+  CNT_ERR = 0,        // validation flags
+  CNT_TILE0 = 1,      // first of the per-launch tile counters
+  CNT_TILE_END = 60,
+  CNT_NKEYS = 64,     // u64 copy of the key total
+  CNT_CAND = 96,      // u64 candidate counter
+  CNT_PAIRS = 98,     // u64 result counter
+  CNT_LBERR = 100,    // look-back bound hits
+  CNT_NBIG = 102,     // u64 count of oversized segments
+  CNT_CAND2 = 104,    // u64 candidate counter of the full-key emission
+  CNT_STEPS = 106,    // u64 search comparisons of learned-index lookups
+  CNT_TOTAL = 128
+};
+
+struct Call {
+  sd_ctx* c;
+  hipStream_t s;
+  Scratch& sc;
+  StageTimer& tm;
+  uint32_t* counters;
+  int slot = CNT_TILE0;
+  uint32_t* tile_counter() {
+    if (slot >= CNT_TILE_END) {  // recycle: zero a fresh block of slots
+      launch_fill_u32(counters + CNT_TILE0, 0, CNT_TILE_END - CNT_TILE0, s);
+      slot = CNT_TILE0;
+    }
+    return counters + slot++;
+  }
+  uint32_t* lb_err() { return counters + CNT_LBERR; }
+};
+
+// Sort records by the given digits in LSD order; returns true if the result
+// sits in the second buffer set.
+inline bool radix_sort(Call& cl, uint64_t* a0, uint64_t* a1, uint32_t* av, uint64_t* b0, uint64_t* b1,
+                uint32_t* bv, int nwords, bool has_val, uint32_t n, const std::vector<Digit>& digits,
+                const std::vector<const uint32_t*>& hists) {
+  bool flip = false;
+  const uint64_t tile = onesweep_tile(nwords, has_val, cl.c->sort_items);
+  const uint64_t tiles = (n + tile - 1) / tile;
+  for (size_t x = 0; x < digits.size(); ++x) {
+    const uint32_t epoch = next_epoch(cl.c, tiles * 256, cl.s);
+    const uint64_t* i0 = flip ? b0 : a0;
+    const uint64_t* i1 = flip ? b1 : a1;
+    const uint32_t* iv = flip ? bv : av;
+    uint64_t* o0 = flip ? a0 : b0;
+    uint64_t* o1 = flip ? a1 : b1;
+    uint32_t* ov = flip ? av : bv;
+    launch_onesweep(i0, i1, iv, o0, o1, ov, nwords, has_val, n, digits[x].word, digits[x].shift,
+                    digits[x].mask, hists[x], cl.c->status, cl.tile_counter(), epoch, cl.lb_err(),
+                    cl.c->sort_items, cl.s);
+    flip = !flip;
+  }
+  return flip;
+}
+
+struct Cands {
+  uint64_t* p = nullptr;  // pool block owned by the caller
+  uint64_t n = 0;
+};
+
+// Sorting digits over bits [lo, 64) of a 64-bit word, least significant first.
+inline std::vector<Digit> top_digits(int lo) {
+  std::vector<Digit> d;
+  for (int b = lo; b < 64; b += 8) {
+    const int w = std::min(8, 64 - b);
+    d.push_back(Digit{0, b, (1u << w) - 1u});
+  }
+  return d;
+}
+
+// Device cost table and threshold of the weighted rescoring.
+struct WeightedSpec {
+  const uint8_t* subst;  // device, 400 bytes
+  uint32_t indel, max_score;
+};
+
+// A query result in pool blocks: (i = query id, j = reference id, d), sorted
+// by (i, j), with the key and candidate counts that produced it.
+struct TileOut {
+  uint32_t* i = nullptr;
+  uint32_t* j = nullptr;
+  uint8_t* d = nullptr;
+  uint64_t n = 0;
+  uint64_t nkeys = 0, ncand = 0;
+};
+
+// Sort (q, r) candidates, verify (weighted when w) and compact in order.
+TileOut verify_candidates(Call& cl, const u128* qseq, uint64_t nq, const u128* rseq, uint64_t nr,
+                          uint64_t* cand, uint64_t nc, int k, const WeightedSpec* w);
+
+// A packed sequence set: 128-bit keys, exclusive variant offsets (n + 1)
+// and the variant total, in pool blocks of the call.
+struct Packed {
+  u128* seq = nullptr;
+  uint64_t* voff = nullptr;
+  uint64_t nkeys = 0;
+};
+// pack and validate a device CSR set, scan its variant counts (one read-back)
+Packed pack_and_count(Call& cl, const DevSeqs& in, int k);
+// raise if a look-back wait of the call hit its bound
+void check_lookback(Call& cl);
+
+// exact keys (lo and hi words) with their ids, sorted by key (pointers into
+// the caller's buffers or the call's scratch)
+struct SortedKeys {
+  const uint64_t* lo;
+  const uint64_t* hi;
+  const uint32_t* id;
+  int passes;
+};
+SortedKeys full_key_sort(Call& cl, uint64_t* klo, uint64_t* khi, uint32_t* kid, uint32_t nk);
+
+// one query tile against a learned index (probe lookups, then verification)
+TileOut learned_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const WeightedSpec* w);
+
+// Hand a finished result (pool blocks oi/oj/od holding n triplets) to the
+// caller: device arrays as they are, or pinned host copies.
+void finish_output(sd_ctx* c, uint32_t* oi, uint32_t* oj, uint8_t* od, uint64_t n, sd_pairs* out,
+                   hipStream_t s);
+
+}  // namespace sd

@@ -68,6 +68,44 @@ void launch_emit_hash_runs(const uint64_t* E, uint64_t n, uint32_t idbits, uint6
 void launch_pair_distance(const u128* seq_a, uint64_t na, const u128* seq_b, uint64_t nb,
                           const uint32_t* ia, const uint32_t* ib, uint64_t n, uint8_t* d,
                           uint32_t* err, hipStream_t s);
+// query-versus-reference
+uint64_t unique_tile();
+void launch_unique_compact(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* status,
+                           uint32_t* tile_counter, uint32_t epoch, unsigned long long* out_count,
+                           uint32_t* err, hipStream_t s);
+int join_cap();
+void launch_join_seg(const uint64_t* Er, const uint32_t* rseg_start, const uint32_t* rseg_end,
+                     const uint64_t* Eq, const uint32_t* qseg_start, const uint32_t* qseg_end,
+                     uint32_t nseg, uint32_t idbits, uint32_t lds_min_q, uint64_t* cand,
+                     uint64_t cap, unsigned long long* ccount, hipStream_t s);
+uint64_t weighted_tile();
+void launch_verify_weighted(const uint64_t* cand, uint64_t c, const u128* sa, const u128* sb,
+                            int k, const uint8_t* subst, uint32_t indel, uint32_t max_score,
+                            uint32_t* oi, uint32_t* oj, uint8_t* od, uint64_t* status,
+                            uint32_t* tile_counter, uint32_t epoch, unsigned long long* out_count,
+                            uint32_t* err, hipStream_t s);
+void launch_set_ranges(const uint32_t* qi, uint64_t n, const uint32_t* set_base, uint32_t nb,
+                       uint64_t* bounds, hipStream_t s);
+void launch_slice_rebase(const uint32_t* qi, const uint32_t* rj, const uint8_t* d, uint64_t lo,
+                         uint64_t n, uint32_t base, uint32_t* oi, uint32_t* oj, uint8_t* od,
+                         hipStream_t s);
+// learned index
+size_t leaf_bytes();
+void launch_interleave(const uint64_t* hi, const uint64_t* lo, uint64_t n, u128* out, hipStream_t s);
+void launch_train_sample(const u128* keys, uint64_t n, uint32_t S, float shift, float scale,
+                         float* x, float* y, hipStream_t s);
+uint32_t mlp_grad_blocks(uint32_t n);
+void launch_mlp_grad(const float* p, const float* x, const float* y, uint32_t n, float* partial,
+                     hipStream_t s);
+void launch_grad_reduce(const float* partial, uint32_t nblocks, float* out, hipStream_t s);
+void launch_adam_step(float* p, float* state, const float* partial, uint32_t nblocks, float lr,
+                      float* loss_out, uint32_t loss_cap, hipStream_t s);
+void launch_leaf_fit_all(const u128* keys, uint64_t n, const float* p, float shift, float scale,
+                         uint32_t nleaves, void* leaves, hipStream_t s);
+void launch_probe(const u128* qseq, const uint64_t* qvoff, uint64_t nq, const u128* keys,
+                  const uint32_t* kid, uint64_t n, int learned, const float* p, float shift,
+                  float scale, uint32_t nleaves, const void* leaves, uint64_t* cand, uint64_t cap,
+                  unsigned long long* ccount, unsigned long long* steps, hipStream_t s);
 
 // ------------------------------------------------------------------ errors
 
@@ -102,7 +140,35 @@ struct sd_ctx {
   int group_cap = 0;   // hashed path: LDS batch capacity (0 = automatic)
   int group_bits = 0;  // hashed path: hash bits sorted by the LSD passes (0 = automatic)
   int sort_items = 0;  // keys-only radix passes: items per thread, 16 or 32 (0 = automatic)
+  int64_t batch_tile_seqs = 0;  // query batches: sequences per tile (0 = automatic)
+  int probe = 0;                // learned indexes: 0 model window, 1 whole-array binary search
   std::vector<hipEvent_t> events;
+};
+
+// A reference deletion index. Hashed kind: every <= k-deletion variant of
+// the reference set as [hash | ref id], sorted by the full hash without
+// repeats, plus a directory of 2^bits hash segments. Learned kind: the exact
+// keys sorted, their reference ids, and the two-stage position model. Owns
+// its device memory (hipMalloc), read-only after the build.
+struct sd_index {
+  int device = 0;
+  int k = 0;
+  int learned = 0;  // 0 hashed, 1 learned
+  uint32_t idbits = 24;
+  int bits = 0;
+  uint64_t n_ref = 0, n_keys = 0, bytes = 0;
+  u128* ref_seq = nullptr;
+  uint64_t* E = nullptr;
+  uint32_t* seg_start = nullptr;
+  uint32_t* seg_end = nullptr;
+  // learned kind
+  u128* keys = nullptr;
+  uint32_t* kid = nullptr;
+  float* params = nullptr;  // device, SD_MLP_PARAMS floats
+  void* leaves = nullptr;   // device leaf records
+  uint32_t nleaves = 0;
+  sd_learned_info info{};
+  std::vector<float> loss_curve;
 };
 
 namespace sd {
@@ -156,5 +222,17 @@ void hashed_plan(const sd_ctx* c, uint64_t nk, int* cap, int* bits);
 void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream_t s);
 void pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32_t* ia,
                    const uint32_t* ib, int64_t n, uint8_t* d_out, hipStream_t s);
+struct WeightedSpec;
+sd_index* index_build(sd_ctx* c, const sd_seqs* ref, int k, hipStream_t s);
+void index_free(sd_index* idx);
+void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, int k,
+                const WeightedSpec* w, sd_pairs* outs, hipStream_t s);
+void query_weighted(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets,
+                    const uint8_t* subst, int indel, int max_score, sd_pairs* outs,
+                    hipStream_t s);
+sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_config* cfg,
+                        hipStream_t s);
+void mlp_gradients(sd_ctx* c, const float* params, const float* x, const float* y, uint32_t n,
+                   float* grad, float* loss, hipStream_t s);
 
 }  // namespace sd

@@ -26,7 +26,11 @@ OPT_PATH = 2
 OPT_GROUP_CAP = 3
 OPT_GROUP_BITS = 4
 OPT_SORT_ITEMS = 5
+OPT_BATCH_TILE = 6
+OPT_PROBE = 7
 MAX_STAGES = 16
+MLP_HIDDEN = 32
+MLP_PARAMS = 3 * MLP_HIDDEN + 1
 
 
 class SymdelError(RuntimeError):
@@ -52,10 +56,27 @@ class _Stats(ctypes.Structure):
                 ("n_cand_raw", ctypes.c_int64), ("n_cand_unique", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("n_stages", ctypes.c_int32),
                 ("n_sort_passes", ctypes.c_int32), ("n_big_segments", ctypes.c_int64),
+                ("n_probe_steps", ctypes.c_int64),
                 ("stage_name", (ctypes.c_char * 24) * MAX_STAGES),
                 ("stage_ms", ctypes.c_double * MAX_STAGES),
                 ("stage_bytes", ctypes.c_double * MAX_STAGES),
                 ("stage_launches", ctypes.c_int32 * MAX_STAGES)]
+
+
+class _LearnedConfig(ctypes.Structure):
+    _fields_ = [("leaves_log2", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("samples", ctypes.c_uint32),
+                ("use_init", ctypes.c_int32), ("init", ctypes.c_float * MLP_PARAMS)]
+
+
+class _LearnedInfo(ctypes.Structure):
+    _fields_ = [("leaves", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("max_eps", ctypes.c_uint32), ("empty_leaves", ctypes.c_uint32),
+                ("mean_eps", ctypes.c_double), ("mean_window_log2", ctypes.c_double),
+                ("loss_first", ctypes.c_float), ("loss_last", ctypes.c_float),
+                ("feature_shift", ctypes.c_float), ("feature_scale", ctypes.c_float),
+                ("train_ms", ctypes.c_double), ("fit_ms", ctypes.c_double),
+                ("params", ctypes.c_float * MLP_PARAMS)]
 
 
 _lib = None
@@ -91,8 +112,73 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sd_strerror.restype = ctypes.c_char_p
     lib.sd_last_error.argtypes = [P]
     lib.sd_last_error.restype = ctypes.c_char_p
+    lib.sd_index_build.argtypes = [P, ctypes.POINTER(_Seqs), I, ctypes.POINTER(P), P]
+    lib.sd_index_build.restype = I
+    lib.sd_index_free.argtypes = [P]
+    lib.sd_index_free.restype = None
+    lib.sd_index_info.argtypes = [P, P, P, P, P]
+    lib.sd_index_info.restype = I
+    lib.sd_query.argtypes = [P, P, ctypes.POINTER(_Seqs), I, ctypes.POINTER(_Pairs), P]
+    lib.sd_query.restype = I
+    lib.sd_query_batch.argtypes = [P, P, I, ctypes.POINTER(_Seqs), I, ctypes.POINTER(_Pairs), P]
+    lib.sd_query_batch.restype = I
+    lib.sd_query_weighted.argtypes = [P, P, ctypes.POINTER(_Seqs), P, I, I,
+                                      ctypes.POINTER(_Pairs), P]
+    lib.sd_query_weighted.restype = I
+    lib.sd_index_build_learned.argtypes = [P, ctypes.POINTER(_Seqs), I,
+                                           ctypes.POINTER(_LearnedConfig), ctypes.POINTER(P), P]
+    lib.sd_index_build_learned.restype = I
+    lib.sd_index_learned_info.argtypes = [P, ctypes.POINTER(_LearnedInfo), P, ctypes.c_int32]
+    lib.sd_index_learned_info.restype = I
+    lib.sd_mlp_gradients.argtypes = [P, P, P, P, ctypes.c_uint32, P, P, P]
+    lib.sd_mlp_gradients.restype = I
     _lib = lib
     return lib
+
+
+class Index:
+    """A device-resident reference deletion index (see sd_index_build)."""
+
+    def __init__(self, lib, handle: ctypes.c_void_p):
+        self._lib = lib
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        n_ref, n_keys, nbytes = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        k = ctypes.c_int32()
+        self._lib.sd_index_info(self._h, ctypes.byref(n_ref), ctypes.byref(n_keys),
+                                ctypes.byref(k), ctypes.byref(nbytes))
+        return dict(n_ref=n_ref.value, n_keys=n_keys.value, k=k.value, bytes=nbytes.value)
+
+    def learned_info(self) -> dict:
+        """Model of a learned index (sd_index_learned_info), with the loss curve."""
+        inf = _LearnedInfo()
+        rc = self._lib.sd_index_learned_info(self._h, ctypes.byref(inf), None, 0)
+        if rc != SD_OK:
+            raise SymdelError(rc, "sd_index_learned_info: not a learned index")
+        curve = np.zeros(max(inf.steps, 0), dtype=np.float32)
+        if inf.steps:
+            self._lib.sd_index_learned_info(self._h, ctypes.byref(inf), curve.ctypes.data,
+                                            inf.steps)
+        out = {f: getattr(inf, f) for f, _ in _LearnedInfo._fields_ if f != "params"}
+        out["params"] = np.ctypeslib.as_array(inf.params).copy()
+        out["loss_curve"] = curve
+        return out
+
+    def free(self):
+        if self._h:
+            self._lib.sd_index_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def _is_torch(x) -> bool:
@@ -225,6 +311,103 @@ class Context:
     def free_pairs(self, p: _Pairs):
         self._lib.sd_pairs_free(self._h, ctypes.byref(p))
 
+    # ------------------------------------------------------------ queries
+    def build_index(self, codes, offsets, k: int, stream=None) -> Index:
+        """Reference deletion index of a sequence set (sd_index_build)."""
+        s, keep, on_dev = self._seqs(codes, offsets)
+        st = _stream_handle(stream, on_dev)
+        h = ctypes.c_void_p()
+        self._check(self._lib.sd_index_build(self._h, ctypes.byref(s), int(k), ctypes.byref(h), st),
+                    "sd_index_build")
+        return Index(self._lib, h)
+
+    def build_learned_index(self, codes, offsets, k: int, leaves_log2: int = 0, steps: int = -1,
+                            lr: float = 0.0, samples: int = 0, init=None, stream=None) -> Index:
+        """Learned reference index (sd_index_build_learned); steps=-1 takes the default."""
+        s, keep, on_dev = self._seqs(codes, offsets)
+        st = _stream_handle(stream, on_dev)
+        cfg = _LearnedConfig()
+        cfg.leaves_log2, cfg.steps, cfg.lr, cfg.samples = leaves_log2, steps, lr, samples
+        if init is not None:
+            cfg.use_init = 1
+            v = np.ascontiguousarray(np.asarray(init, dtype=np.float32).reshape(MLP_PARAMS))
+            ctypes.memmove(cfg.init, v.ctypes.data, MLP_PARAMS * 4)
+        h = ctypes.c_void_p()
+        self._check(self._lib.sd_index_build_learned(self._h, ctypes.byref(s), int(k),
+                                                     ctypes.byref(cfg), ctypes.byref(h), st),
+                    "sd_index_build_learned")
+        return Index(self._lib, h)
+
+    def mlp_gradients(self, params, x, y):
+        """(grad, loss) of the stage-1 training loss from the device kernels."""
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(MLP_PARAMS))
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        assert x.shape == y.shape and x.ndim == 1
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        self._check(self._lib.sd_mlp_gradients(self._h, p.ctypes.data, x.ctypes.data,
+                                               y.ctypes.data, len(x), g.ctypes.data,
+                                               ctypes.byref(loss), None), "sd_mlp_gradients")
+        return g, float(loss.value)
+
+    def query(self, index: Index, codes, offsets, k: int, device_output: bool | None = None,
+              stream=None) -> Pairs:
+        """All (q, r) with Levenshtein(Q_q, R_r) <= k, sorted by (q, r)."""
+        s, keep, on_dev = self._seqs(codes, offsets)
+        st = _stream_handle(stream, on_dev)
+        if device_output is None:
+            device_output = on_dev
+        p = _Pairs(0, None, None, None, 1 if device_output else 0, 0)
+        self._check(self._lib.sd_query(self._h, index.handle, ctypes.byref(s), int(k),
+                                       ctypes.byref(p), st), "sd_query")
+        return self._take(p, device_output, st)
+
+    def query_batch(self, index: Index, sets, k: int, device_output: bool | None = None,
+                    stream=None) -> list:
+        """Results of many query sets against one index (sd_query_batch)."""
+        n = len(sets)
+        arr = (_Seqs * max(n, 1))()
+        keep = []
+        on_dev = False
+        for x, (codes, offsets) in enumerate(sets):
+            s, kp, od = self._seqs(codes, offsets)
+            arr[x] = s
+            keep.append(kp)
+            on_dev = on_dev or od
+        st = _stream_handle(stream, on_dev)
+        if device_output is None:
+            device_output = on_dev
+        outs = (_Pairs * max(n, 1))()
+        for x in range(n):
+            outs[x] = _Pairs(0, None, None, None, 1 if device_output else 0, 0)
+        self._check(self._lib.sd_query_batch(self._h, index.handle, n, arr, int(k), outs, st),
+                    "sd_query_batch")
+        return [self._take(outs[x], device_output, st) for x in range(n)]
+
+    def query_batch_raw(self, index: Index, arr, n: int, k: int, stream):
+        """Device-resident per-set results left in library memory (free with free_pairs)."""
+        outs = (_Pairs * max(n, 1))()
+        for x in range(n):
+            outs[x] = _Pairs(0, None, None, None, 1, 0)
+        self._check(self._lib.sd_query_batch(self._h, index.handle, n, arr, int(k), outs, stream),
+                    "sd_query_batch")
+        return outs
+
+    def query_weighted(self, index: Index, codes, offsets, subst, indel: int, max_score: int,
+                       device_output: bool | None = None, stream=None) -> Pairs:
+        """Weighted rescoring of the index's Levenshtein candidates (d = score)."""
+        s, keep, on_dev = self._seqs(codes, offsets)
+        st = _stream_handle(stream, on_dev)
+        if device_output is None:
+            device_output = on_dev
+        sub = np.ascontiguousarray(np.asarray(subst, dtype=np.uint8).reshape(400))
+        p = _Pairs(0, None, None, None, 1 if device_output else 0, 0)
+        self._check(self._lib.sd_query_weighted(self._h, index.handle, ctypes.byref(s),
+                                                sub.ctypes.data, int(indel), int(max_score),
+                                                ctypes.byref(p), st), "sd_query_weighted")
+        return self._take(p, device_output, st)
+
     def pair_distance(self, a, b, ia, ib):
         """Levenshtein distance of pairs (ia[t], ib[t]); ia, ib are int32 cuda tensors."""
         import torch
@@ -253,4 +436,110 @@ class Context:
         return dict(n_seqs=st.n_seqs, n_keys=st.n_keys, n_cand_raw=st.n_cand_raw,
                     n_cand_unique=st.n_cand_unique, n_pairs=st.n_pairs,
                     n_sort_passes=st.n_sort_passes, n_big_segments=st.n_big_segments,
-                    stages=stages)
+                    n_probe_steps=st.n_probe_steps, stages=stages)
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("workers", ctypes.c_int32),
+                ("max_batch_requests", ctypes.c_int32), ("weighted", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_uint64), ("subst", ctypes.c_uint8 * 400),
+                ("indel", ctypes.c_int32), ("max_score", ctypes.c_int32),
+                ("probe", ctypes.c_int32)]
+
+
+class Server:
+    """Continuous-batching query server over one index (sd_server_*).
+
+    Requests are host query sets; results are host numpy triplets equal to
+    querying each set alone.
+    """
+
+    def __init__(self, index: Index, k: int, device: int = 0, workers: int = 2,
+                 max_batch_requests: int = 0, hbm_budget: int = 0, subst=None, indel: int = 8,
+                 max_score: int = 8, probe: int = 0):
+        lib = load_library()
+        self._lib = lib
+        P, I = ctypes.c_void_p, ctypes.c_int
+        lib.sd_server_create.argtypes = [P, I, ctypes.POINTER(_ServerConfig), ctypes.POINTER(P)]
+        lib.sd_server_create.restype = I
+        lib.sd_server_submit.argtypes = [P, ctypes.POINTER(_Seqs), ctypes.POINTER(ctypes.c_uint64)]
+        lib.sd_server_submit.restype = I
+        lib.sd_server_poll.argtypes = [P, ctypes.c_uint64, I, ctypes.POINTER(_Pairs),
+                                       ctypes.POINTER(ctypes.c_double)]
+        lib.sd_server_poll.restype = I
+        lib.sd_server_cancel.argtypes = [P, ctypes.c_uint64]
+        lib.sd_server_cancel.restype = I
+        lib.sd_server_stats.argtypes = [P, P, P, P]
+        lib.sd_server_stats.restype = I
+        lib.sd_server_free_pairs.argtypes = [ctypes.POINTER(_Pairs)]
+        lib.sd_server_free_pairs.restype = None
+        lib.sd_server_destroy.argtypes = [P]
+        lib.sd_server_destroy.restype = None
+        cfg = _ServerConfig()
+        cfg.k, cfg.workers, cfg.max_batch_requests = k, workers, max_batch_requests
+        cfg.hbm_budget = hbm_budget
+        cfg.weighted = 1 if subst is not None else 0
+        if subst is not None:
+            sub = np.ascontiguousarray(np.asarray(subst, dtype=np.uint8).reshape(400))
+            ctypes.memmove(cfg.subst, sub.ctypes.data, 400)
+        cfg.indel, cfg.max_score, cfg.probe = indel, max_score, probe
+        self._index = index  # the index must outlive the server
+        self._h = ctypes.c_void_p()
+        rc = lib.sd_server_create(index.handle, device, ctypes.byref(cfg), ctypes.byref(self._h))
+        if rc != SD_OK:
+            raise SymdelError(rc, "sd_server_create failed")
+
+    def submit(self, codes, offsets) -> int:
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        s = _Seqs(codes.ctypes.data if codes.size else None, offsets.ctypes.data,
+                  len(offsets) - 1, 0)
+        rid = ctypes.c_uint64()
+        rc = self._lib.sd_server_submit(self._h, ctypes.byref(s), ctypes.byref(rid))
+        if rc != SD_OK:
+            raise SymdelError(rc, "sd_server_submit failed")
+        return rid.value
+
+    def poll(self, request_id: int, timeout_ms: int = -1):
+        """(Pairs, latency seconds); raises SymdelError on failure or timeout."""
+        p = _Pairs()
+        lat = ctypes.c_double()
+        rc = self._lib.sd_server_poll(self._h, request_id, timeout_ms, ctypes.byref(p),
+                                      ctypes.byref(lat))
+        if rc != SD_OK:
+            raise SymdelError(rc, f"request {request_id}")
+        n = p.n
+        i = np.empty(n, dtype=np.uint32)
+        j = np.empty(n, dtype=np.uint32)
+        d = np.empty(n, dtype=np.uint8)
+        if n:
+            ctypes.memmove(i.ctypes.data, p.i, n * 4)
+            ctypes.memmove(j.ctypes.data, p.j, n * 4)
+            ctypes.memmove(d.ctypes.data, p.d, n)
+        self._lib.sd_server_free_pairs(ctypes.byref(p))
+        return Pairs(i, j, d), lat.value
+
+    def cancel(self, request_id: int) -> int:
+        return self._lib.sd_server_cancel(self._h, request_id)
+
+    def stats(self) -> dict:
+        b, r, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._lib.sd_server_stats(self._h, ctypes.byref(b), ctypes.byref(r), ctypes.byref(m))
+        return dict(batches=b.value, requests=r.value, max_batch=m.value)
+
+    def close(self):
+        if self._h:
+            self._lib.sd_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,177 @@
+"""The learned reference index: gradients of the device training kernels
+against the float64 oracle, lookups identical to the symmetric-deletion
+oracle (and to the hashed index) whatever the model, and the gain of the
+trained model over a binary search of the whole key array."""
+import numpy as np
+import pytest
+
+import cdr3gen
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2403_09010_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ref():
+    return cdr3gen.generate(31, 20000)
+
+
+@pytest.fixture(scope="module")
+def lindex(ctx, ref):
+    log("learned index: 20000 reference sequences, k=2")
+    idx = ctx.build_learned_index(*ref, 2)
+    yield idx
+    idx.free()
+
+
+def triples(r):
+    i, j, d = r.numpy()
+    return list(zip(i.astype(np.int64).tolist(), j.astype(np.int64).tolist(),
+                    d.astype(np.int64).tolist()))
+
+
+def oracle_query(ref, qry, k):
+    import oracle
+    a, b, d = oracle.query_search(ref, qry, k)
+    return list(zip(a.tolist(), b.tolist(), d.tolist()))
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (37, 1), (4096, 2), (65536, 3)])
+def test_gradients_match_float64_oracle(ctx, n, seed):
+    from oracle import mlp_oracle as mo
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0.0, 1.0, mo.PARAMS).astype(np.float32)
+    x = rng.uniform(0.0, 1.0, n).astype(np.float32)
+    y = np.sort(rng.uniform(0.0, 1.0, n)).astype(np.float32)
+    log(f"mlp gradients n={n}")
+    g, loss = ctx.mlp_gradients(p, x, y)
+    want_loss, want = mo.loss_and_grad(p.astype(np.float64), x.astype(np.float64),
+                                       y.astype(np.float64))
+    # FP32 accumulation over n samples against float64
+    tol = 1e-4 * np.abs(want) + 1e-5 * np.abs(want).max()
+    assert np.all(np.abs(g - want) <= tol), np.abs(g - want).max()
+    assert loss == pytest.approx(want_loss, rel=1e-4)
+
+
+def test_gradients_are_deterministic(ctx):
+    rng = np.random.default_rng(4)
+    p = rng.normal(0.0, 1.0, 97).astype(np.float32)
+    x = rng.uniform(0.0, 1.0, 30000).astype(np.float32)
+    y = rng.uniform(0.0, 1.0, 30000).astype(np.float32)
+    a = ctx.mlp_gradients(p, x, y)
+    b = ctx.mlp_gradients(p, x, y)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_learned_lookup_matches_oracle(ctx, ref, lindex, k):
+    from paper_2403_09010_amd import OPT_PROBE
+    qry = cdr3gen.generate_query(32, 3000, *ref, ref_mut_frac=0.3)
+    want = oracle_query(ref, qry, k)
+    for probe in (0, 1):
+        ctx.set_option(OPT_PROBE, probe)
+        log(f"learned index lookups k={k} probe={probe}")
+        assert triples(ctx.query(lindex, *qry, k)) == want
+    ctx.set_option(OPT_PROBE, 0)
+    assert k == 0 or len(want) > 300
+
+
+def test_trained_model_gains_over_binary_search(ctx, ref, lindex):
+    from paper_2403_09010_amd import OPT_PROBE
+    qry = cdr3gen.generate_query(33, 5000, *ref, ref_mut_frac=0.3)
+    steps = {}
+    res = {}
+    for probe in (0, 1):
+        ctx.set_option(OPT_PROBE, probe)
+        res[probe] = triples(ctx.query(lindex, *qry, 2))
+        st = ctx.stats()
+        steps[probe] = st["n_probe_steps"] / st["n_keys"]
+    ctx.set_option(OPT_PROBE, 0)
+    info = lindex.learned_info()
+    log(f"comparisons per lookup: learned {steps[0]:.2f}, binary {steps[1]:.2f}; "
+        f"mean eps {info['mean_eps']:.1f}, max eps {info['max_eps']}, "
+        f"loss {info['loss_first']:.3g} -> {info['loss_last']:.3g}")
+    assert res[0] == res[1]
+    assert steps[0] < 0.6 * steps[1]
+    assert info["loss_last"] < info["loss_first"]
+    assert np.all(np.isfinite(info["loss_curve"]))
+
+
+def test_any_model_stays_exact(ctx, ref):
+    """Untrained, badly initialised or coarse models change only the window."""
+    from oracle import mlp_oracle as mo
+    qry = cdr3gen.generate_query(34, 1500, *ref, ref_mut_frac=0.3)
+    want = oracle_query(ref, qry, 2)
+    cases = [dict(steps=0), dict(leaves_log2=4), dict(init=np.zeros(mo.PARAMS), steps=0),
+             dict(init=np.full(mo.PARAMS, 50.0), steps=3, leaves_log2=10)]
+    for kw in cases:
+        log(f"learned index variant {sorted(kw)}")
+        idx = ctx.build_learned_index(*ref, 2, **kw)
+        try:
+            assert triples(ctx.query(idx, *qry, 2)) == want
+        finally:
+            idx.free()
+
+
+def test_learned_batch_weighted_and_hashed_agree(ctx, ref, lindex):
+    hidx = ctx.build_index(*ref, 2)
+    try:
+        sets = [cdr3gen.generate_query(40 + x, n, *ref, ref_mut_frac=0.2)
+                for x, n in enumerate([0, 1, 250, 3000, 17])]
+        log("batched queries: learned vs hashed index")
+        a = ctx.query_batch(lindex, sets, 2, device_output=False)
+        b = ctx.query_batch(hidx, sets, 2, device_output=False)
+        for x, (ra, rb) in enumerate(zip(a, b)):
+            assert triples(ra) == triples(rb), f"set {x}"
+        subst = cdr3gen.cost_matrix()
+        log("weighted queries: learned vs hashed index")
+        qa = ctx.query_weighted(lindex, *sets[3], subst, 8, 8, device_output=False)
+        qb = ctx.query_weighted(hidx, *sets[3], subst, 8, 8, device_output=False)
+        assert triples(qa) == triples(qb)
+    finally:
+        hidx.free()
+
+
+def test_learned_edge_cases(ctx):
+    one = cdr3gen.from_strings(["CASSLGF"])
+    empty = (np.zeros(0, dtype=np.uint8), np.zeros(1, dtype=np.int64))
+    log("learned index of one sequence and of none")
+    idx = ctx.build_learned_index(*one, 2)
+    try:
+        got = triples(ctx.query(idx, *cdr3gen.from_strings(["CASSLGF", "CASLGF", "CAF"]), 2))
+        assert got == [(0, 0, 0), (1, 0, 1)]
+        assert len(ctx.query(idx, *empty, 2, device_output=False)) == 0
+    finally:
+        idx.free()
+    idx = ctx.build_learned_index(*empty, 2)
+    try:
+        assert len(ctx.query(idx, *one, 2, device_output=False)) == 0
+        assert idx.info()["n_keys"] == 0
+    finally:
+        idx.free()
+
+
+def test_server_on_a_learned_index(ctx, ref, lindex):
+    from paper_2403_09010_amd import Server
+    reqs = [cdr3gen.generate_query(50 + x, n, *ref, ref_mut_frac=0.2)
+            for x, n in enumerate([120, 900, 40, 2000, 300, 5])]
+    alone = [triples(ctx.query(lindex, *r, 2, device_output=False)) for r in reqs]
+    log("server with 2 workers on the learned index")
+    with Server(lindex, k=2, workers=2) as sv:
+        ids = [sv.submit(*r) for r in reqs]
+        for x, rid in enumerate(ids):
+            got, _ = sv.poll(rid, timeout_ms=60000)
+            assert triples(got) == alone[x]
