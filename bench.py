@@ -29,6 +29,15 @@ WORKLOADS = {
     "plain_10m_k2": ("plain_10m", 2),
 }
 HBM_PEAK_GBS = 8000.0
+# stages that time exactly one kernel (launched once, or several times alike)
+KERNEL_OF_STAGE = {
+    "vargen_hash": "k_vargen_hash",
+    "hash_passes": "k_onesweep_keys",
+    "group_local": "k_group_seg",
+    "verify": "k_verify_compact",
+    "sort_passes": "k_onesweep",
+    "emit": "k_emit_runs",
+}
 
 
 def log(msg):
@@ -249,19 +258,102 @@ def run_served(args):
     emit(out, args)
 
 
+def run_learned(args):
+    """The learned reference index against its own lookup without the model:
+    one query set against the 5M-sequence reference at k=2, probe stage timed
+    with the model's window (probe 0) and with a binary search over the whole
+    sorted key array (probe 1); the hashed index is timed beside them."""
+    import torch
+    import cdr3gen
+    from paper_2403_09010_amd import Context, OPT_PROBE, OPT_TIMING
+    p = cdr3gen.SERVED
+    k = 2
+    log(f"generating the {p['ref_n'] // args.ref_div}-sequence reference")
+    ref = cdr3gen.generate(p["ref_seed"], p["ref_n"] // args.ref_div)
+    qry = cdr3gen.generate_query(30000, args.learned_queries, *ref, ref_mut_frac=0.1)
+    dev = torch.device("cuda", 0)
+    ctx = Context(0)
+    rd = (torch.from_numpy(ref[0]).to(dev), torch.from_numpy(ref[1]).to(dev))
+    qd = (torch.from_numpy(qry[0]).to(dev), torch.from_numpy(qry[1]).to(dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lidx = ctx.build_learned_index(*rd, k, leaves_log2=args.leaves_log2)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    info = lidx.learned_info()
+    log(f"learned index: {lidx.info()} in {t_learned:.2f} s; leaves {info['leaves']}, "
+        f"mean eps {info['mean_eps']:.1f}, max eps {info['max_eps']}, mean window log2 "
+        f"{info['mean_window_log2']:.2f}, loss {info['loss_first']:.3g} -> {info['loss_last']:.3g}, "
+        f"train {info['train_ms']:.1f} ms, fit {info['fit_ms']:.1f} ms")
+    t0 = time.perf_counter()
+    hidx = ctx.build_index(*rd, k)
+    torch.cuda.synchronize()
+    t_hashed = time.perf_counter() - t0
+    ctx.set_option(OPT_TIMING, 1)
+    res = {}
+    for name, idx, probe in (("learned", lidx, 0), ("binary", lidx, 1), ("hashed", hidx, 0)):
+        ctx.set_option(OPT_PROBE, probe)
+        for _ in range(args.warmup):
+            ctx.query(idx, *qd, k)
+        torch.cuda.synchronize()
+        stage, tot, steps = {}, 0.0, 0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = ctx.query(idx, *qd, k)
+            st = ctx.stats()
+            for sg in st["stages"]:
+                stage[sg["name"]] = stage.get(sg["name"], 0.0) + sg["ms"] / args.steps
+            steps = st["n_probe_steps"]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[name] = {"seconds": round(dt, 5), "pairs": len(r), "query_keys": st["n_keys"],
+                     "comparisons_per_lookup": round(steps / max(1, st["n_keys"]), 3),
+                     "stages_ms": {a: round(b, 4) for a, b in stage.items()}}
+        log(f"{name}: {res[name]}")
+    assert res["learned"]["pairs"] == res["binary"]["pairs"] == res["hashed"]["pairs"]
+    lp = res["learned"]["stages_ms"].get("probe", 0.0)
+    bp = res["binary"]["stages_ms"].get("probe", 0.0)
+    nkeys = res["learned"]["query_keys"]
+    out = {
+        "metric": "Learned index: query-key lookups/s in the probe stage, 5M reference k=2",
+        "value": round(nkeys / (lp * 1e-3), 1) if lp else None, "unit": "lookups/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(res["learned"]["seconds"] * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 model, u128 keys",
+        "data": "synthetic (seeded CDR3-like generator)",
+        "config": {"workload": "learned_5m", "ref_n": int(len(ref[1]) - 1),
+                   "query_seqs": args.learned_queries, "k": k, "index_keys": lidx.info()["n_keys"],
+                   "leaves": info["leaves"], "learned_build_s": round(t_learned, 3),
+                   "hashed_build_s": round(t_hashed, 3)},
+        "model": {"mean_eps": round(info["mean_eps"], 2), "max_eps": int(info["max_eps"]),
+                  "mean_window_log2": round(info["mean_window_log2"], 3),
+                  "empty_leaves": int(info["empty_leaves"]), "steps": int(info["steps"]),
+                  "loss_first": float(info["loss_first"]), "loss_last": float(info["loss_last"]),
+                  "train_ms": round(info["train_ms"], 2), "fit_ms": round(info["fit_ms"], 2)},
+        "learned": res["learned"], "binary_search": res["binary"], "hashed_index": res["hashed"],
+        "probe_speedup_learned_vs_binary": round(bp / lp, 3) if lp else None,
+    }
+    lidx.free()
+    hidx.free()
+    ctx.close()
+    emit(out, args)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="plain_1m_k2",
-                    choices=sorted(WORKLOADS) + ["batched_2m_512", "served_5m"])
+                    choices=sorted(WORKLOADS) + ["batched_2m_512", "served_5m", "learned_5m"])
     ap.add_argument("--sets", type=int, default=512, help="batched: number of query sets")
     ap.add_argument("--set-scale", type=float, default=1.0, help="batched: scale of set sizes")
     ap.add_argument("--requests", type=int, default=2000, help="served: requests per rate")
     ap.add_argument("--burst", type=int, default=400, help="served: requests for saturation")
     ap.add_argument("--serial-requests", type=int, default=200, help="served: serial comparison")
-    ap.add_argument("--ref-div", type=int, default=1, help="served: reference size divisor")
+    ap.add_argument("--ref-div", type=int, default=1, help="served/learned: reference size divisor")
+    ap.add_argument("--learned-queries", type=int, default=200000, help="learned: query sequences")
+    ap.add_argument("--leaves-log2", type=int, default=0, help="learned: leaves (0 automatic)")
     ap.add_argument("--path", type=int, default=0, help="grouping path (0 auto, 1 full-key sort)")
     ap.add_argument("--group-cap", type=int, default=0, help="hashed path LDS capacity (0 auto)")
     ap.add_argument("--group-bits", type=int, default=0, help="hashed path hash bits (0 auto)")
@@ -278,6 +370,8 @@ def main():
         return run_batched(args)
     if args.workload == "served_5m":
         return run_served(args)
+    if args.workload == "learned_5m":
+        return run_learned(args)
 
     import torch
     import cdr3gen
@@ -337,18 +431,38 @@ def main():
         gbs = stage_bytes[name] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         log(f"  stage {name:12s} {ms:8.3f} ms  {stage_launch[name]:3d} launches  {gbs:8.1f} GB/s algorithmic")
 
-    # dominant stage -> roofline entry (per-launch average)
-    dom = max(stage_ms, key=lambda s: stage_ms[s])
-    dom_ms = stage_ms[dom] / args.steps
-    launches = max(1, stage_launch[dom])
-    per_launch_bytes = stage_bytes[dom] / launches
-    per_launch_s = dom_ms * 1e-3 / launches
-    achieved = per_launch_bytes / per_launch_s / 1e9
-    roofline = {"bound": "hbm", "kernel_stage": dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "launches_per_step": launches,
-                "avg_launch_ms": round(per_launch_s * 1e3, 4),
+    # host-to-host: u8 codes and offsets in host memory, pairs back in host
+    # memory (H2D and D2H included); one warm-up, median of five
+    ctx.set_option(OPT_TIMING, 0)
+    ctx.self_search(codes, offsets, k, device_output=False)
+    h2h = []
+    for _ in range(5):
+        t1 = time.perf_counter()
+        r = ctx.self_search(codes, offsets, k, device_output=False)
+        h2h.append(time.perf_counter() - t1)
+    h2h_s = float(np.median(h2h))
+    assert len(r) == npairs
+    log(f"host-to-host: {h2h_s * 1e3:.2f} ms median of 5")
+
+    # roofline entries: the dominant single-kernel stage, and the LSD sort
+    # passes; per-launch algorithmic bytes over the per-launch device time
+    def roof(stage):
+        ms = stage_ms[stage] / args.steps
+        launches = max(1, stage_launch[stage])
+        per_launch_bytes = stage_bytes[stage] / launches
+        per_launch_s = ms * 1e-3 / launches
+        achieved = per_launch_bytes / per_launch_s / 1e9
+        return {"bound": "hbm", "kernel": KERNEL_OF_STAGE[stage], "stage": stage,
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "launches_per_step": launches, "avg_launch_ms": round(per_launch_s * 1e3, 4),
                 "algorithmic_bytes_per_launch": per_launch_bytes}
+
+    single = [x for x in stage_ms if x in KERNEL_OF_STAGE and stage_launch[x] > 0]
+    dom = max(single, key=lambda x: stage_ms[x])
+    roofline = roof(dom)
+    sort_stage = "hash_passes" if "hash_passes" in single else "sort_passes"
+    sort_roofline = roof(sort_stage) if sort_stage in single else None
     value = npairs / dt
     out = {
         "metric": "End-to-end s & pairs/s, 1M CDR3 self-search k<=2 (pairs/s)",
@@ -362,7 +476,10 @@ def main():
                    "group_cap": args.group_cap, "group_bits": args.group_bits,
                    "sort_items": args.sort_items},
         "stages_ms": {s: round(stage_ms[s] / args.steps, 4) for s in stage_ms},
+        "host_to_host": {"seconds_median_of_5": round(h2h_s, 6),
+                         "pairs_per_s": round(npairs / h2h_s, 1)},
         "roofline": roofline,
+        "sort_roofline": sort_roofline,
     }
     ctx.close()
     if not args.no_cpu_baseline:

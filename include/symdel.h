@@ -148,13 +148,16 @@ int sd_index_info(const sd_index* index, int64_t* n_ref, int64_t* n_keys, int32_
  * change the speed of a lookup and never its result. The index holds every
  * <= k-deletion variant of `ref` as its exact 128-bit key (the compressed
  * form of Appendix A widened to 24 residues plus a length field), sorted by
- * key with the reference id beside it, and a two-stage model that predicts a
- * key's position:
- *   stage 1  an FP32 MLP 1 -> SD_MLP_HIDDEN (tanh) -> 1 over a normalised
- *            feature of the key's top 24 bits, trained on the device by
- *            full-batch Adam on the mean squared error of the rank fraction
- *            at cfg.samples evenly spaced ranks; its output picks a leaf
- *   stage 2  per leaf, the line through the leaf's first and last key
+ * key with the reference id beside it, and a model of a key's position:
+ *   coordinate  per (length, position) residue frequencies and length shares,
+ *               counted over a sample of the keys, give each key its
+ *               arithmetic-coding coordinate in [0, 1) (monotone in key order)
+ *   stage 1     an FP32 MLP 1 -> SD_MLP_HIDDEN (tanh) -> 1 maps the
+ *               coordinate to the rank fraction; it is trained on the device
+ *               by full-batch Adam on the mean squared error at cfg.samples
+ *               evenly spaced ranks, and its output picks a leaf
+ *   stage 2     per leaf, the line through the leaf's first and last key
+ *               over the FP64 coordinate
  * After training every leaf stores its exact worst position error eps over
  * all indexed keys, and a lookup searches only [p - eps, p + eps]. Queries
  * (sd_query, sd_query_batch, the weighted forms and the server) accept the
@@ -185,7 +188,6 @@ typedef struct {
   double mean_eps;          /* leaf error bound averaged over the indexed keys */
   double mean_window_log2;  /* log2(2 eps + 1) averaged over the indexed keys */
   float loss_first, loss_last; /* training loss of the first and last step */
-  float feature_shift, feature_scale; /* x1 = ((key >> 104) - shift) * scale */
   double train_ms, fit_ms;  /* device time of training and of the leaf fit */
   float params[SD_MLP_PARAMS];
 } sd_learned_info;
@@ -286,6 +288,26 @@ int sd_server_stats(sd_server* server, int64_t* batches, int64_t* requests, int6
 void sd_server_free_pairs(sd_pairs* pairs);
 /* Stop the workers (queued requests are cancelled) and free the server. */
 void sd_server_destroy(sd_server* server);
+
+/*
+ * Autotuner: run a sample through candidate values of the context's tunables
+ * and keep the fastest in the context (results never depend on them).
+ * index == NULL tunes the self search on sets[0] (nsets must be 1): grouping
+ * path, SD_OPT_GROUP_CAP and SD_OPT_SORT_ITEMS. With an index it tunes
+ * sd_query_batch over the nsets sets: SD_OPT_BATCH_TILE and
+ * SD_OPT_SORT_ITEMS. Each candidate runs once to warm up and then `reps`
+ * times (1..100); the score is the mean wall time of the call. On error the
+ * context keeps its previous options.
+ */
+typedef struct {
+  int32_t trials;
+  int32_t path, group_cap, sort_items; /* the chosen SD_OPT_PATH, SD_OPT_GROUP_CAP, SD_OPT_SORT_ITEMS */
+  int64_t batch_tile;                  /* the chosen SD_OPT_BATCH_TILE */
+  double best_s;                       /* mean seconds per call with the chosen options */
+  double default_s;                    /* the same with the options the context had before */
+} sd_tune_result;
+int sd_autotune(sd_ctx* ctx, const sd_index* index, int nsets, const sd_seqs* sets, int k,
+                int reps, sd_tune_result* out, void* stream);
 
 /* Counters and stage timings of the last successful search on ctx. */
 int sd_get_stats(const sd_ctx* ctx, sd_stats* out);

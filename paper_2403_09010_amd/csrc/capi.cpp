@@ -304,6 +304,15 @@ int sd_index_learned_info(const sd_index* idx, sd_learned_info* out, float* loss
   return SD_OK;
 }
 
+int sd_autotune(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, int k, int reps,
+                sd_tune_result* out, void* stream) {
+  if (!c) return SD_E_INVAL;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::autotune(c, idx, nsets, sets, k, reps, out, static_cast<hipStream_t>(stream));
+  });
+}
+
 int sd_mlp_gradients(sd_ctx* c, const float* params, const float* x, const float* y, uint32_t n,
                      float* grad, float* loss, void* stream) {
   if (!c) return SD_E_INVAL;

@@ -1,5 +1,6 @@
-// Learned reference index: build (exact-key sort, device training of the
-// stage-1 MLP, leaf fit with exact error bounds) and lookups of query tiles.
+// Learned reference index: build (exact-key sort, the counted coordinate
+// model, device training of the stage-1 MLP, leaf fit with exact error
+// bounds) and lookups of query tiles.
 //
 // The model only narrows where a lookup searches. Every leaf's bound eps is
 // the exact worst distance between predicted and true position over all
@@ -124,19 +125,45 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
     info.leaves = (int32_t)idx->nleaves;
     idx->leaves = lidx_alloc((size_t)idx->nleaves * leaf_bytes());
 
-    // feature normalisation from the smallest and largest key
-    float shift = 0.0f, scale = 1.0f;
-    if (nk) {
-      u128 ends[2];
-      hip_check(hipMemcpyAsync(&ends[0], idx->keys, 16, hipMemcpyDeviceToHost, s), "D2H");
-      hip_check(hipMemcpyAsync(&ends[1], idx->keys + (nk - 1), 16, hipMemcpyDeviceToHost, s), "D2H");
+    // coordinate model: residue frequencies per (length, position) and
+    // length shares, counted over keys at evenly spaced ranks
+    idx->coord = lidx_alloc(coord_bytes());
+    {
+      const int NLn = coord_lengths();
+      const size_t ntab = (size_t)NLn * 24 * 20;
+      const uint32_t SC = (uint32_t)std::min<uint64_t>(nk, 1u << 22);
+      uint32_t* cnt = sc.get<uint32_t>(ntab + NLn);
+      launch_fill_u32(cnt, 0, ntab + NLn, s);
+      launch_coord_counts(idx->keys, nk, SC, cnt, s);
+      std::vector<uint32_t> hc(ntab + NLn);
+      hip_check(hipMemcpyAsync(hc.data(), cnt, hc.size() * 4, hipMemcpyDeviceToHost, s), "D2H counts");
       hip_check(hipStreamSynchronize(s), "synchronise");
-      const float a = (float)(uint32_t)(ends[0] >> 104), b = (float)(uint32_t)(ends[1] >> 104);
-      shift = a;
-      scale = b > a ? 1.0f / (b - a) : 1.0f;
+      std::vector<double> model(coord_bytes() / sizeof(double), 0.0);
+      if (model.size() * sizeof(double) != ntab * 16 + (size_t)(NLn + 1) * 8)
+        throw Error{SD_E_HIP, "internal error: coordinate model layout"};
+      const double alpha = 0.5;  // additive smoothing: every residue and length keeps a share
+      for (int L = 0; L < NLn; ++L)
+        for (int t = 0; t < L; ++t) {
+          const uint32_t* row = &hc[((size_t)L * 24 + t) * 20];
+          double tot = 0.0;
+          for (int c = 0; c < 20; ++c) tot += row[c];
+          double cum = 0.0;
+          for (int c = 0; c < 20; ++c) {
+            const double pr = (row[c] + alpha) / (tot + 20 * alpha);
+            model[(((size_t)L * 24 + t) * 20 + c) * 2] = cum;
+            model[(((size_t)L * 24 + t) * 20 + c) * 2 + 1] = pr;
+            cum += pr;
+          }
+        }
+      double* lencum = model.data() + ntab * 2;
+      double tot = 0.0;
+      for (int L = 0; L < NLn; ++L) tot += hc[ntab + L] + alpha;
+      lencum[0] = 0.0;
+      for (int L = 0; L < NLn; ++L) lencum[L + 1] = lencum[L] + (hc[ntab + L] + alpha) / tot;
+      hip_check(hipMemcpyAsync(idx->coord, model.data(), coord_bytes(), hipMemcpyHostToDevice, s),
+                "H2D coordinate model");
+      hip_check(hipStreamSynchronize(s), "synchronise");
     }
-    info.feature_shift = shift;
-    info.feature_scale = scale;
 
     // training samples and initial parameters
     const uint32_t S = nk ? (uint32_t)std::min<uint64_t>(conf.samples ? conf.samples : 65536u, nk) : 0;
@@ -146,7 +173,7 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
     if (conf.use_init) {
       std::memcpy(hp, conf.init, sizeof(hp));
     } else if (S) {
-      launch_train_sample(idx->keys, nk, S, shift, scale, sx, sy, s);
+      launch_train_sample(idx->keys, nk, S, idx->coord, sx, sy, s);
       std::vector<float> xs(S);
       hip_check(hipMemcpyAsync(xs.data(), sx, (size_t)S * 4, hipMemcpyDeviceToHost, s), "D2H");
       hip_check(hipStreamSynchronize(s), "synchronise");
@@ -155,7 +182,7 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
       quantile_init(std::vector<float>(1, 0.0f), hp);
     }
     hip_check(hipMemcpyAsync(idx->params, hp, sizeof(hp), hipMemcpyHostToDevice, s), "H2D params");
-    if (conf.use_init && S) launch_train_sample(idx->keys, nk, S, shift, scale, sx, sy, s);
+    if (conf.use_init && S) launch_train_sample(idx->keys, nk, S, idx->coord, sx, sy, s);
 
     for (int e = 0; e < 4; ++e) hip_check(hipEventCreate(&ev[e]), "event");
     hip_check(hipEventRecord(ev[0], s), "event");
@@ -192,7 +219,7 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
                 "D2H losses");
     }
     hip_check(hipEventRecord(ev[1], s), "event");
-    launch_leaf_fit_all(idx->keys, nk, idx->params, shift, scale, idx->nleaves, idx->leaves, s);
+    launch_leaf_fit_all(idx->keys, nk, idx->coord, idx->params, idx->nleaves, idx->leaves, s);
     hip_check(hipEventRecord(ev[3], s), "event");
 
     // leaf statistics
@@ -226,7 +253,8 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
     if (counted != nk) throw Error{SD_E_HIP, "internal error: leaf counts do not cover the keys"};
     info.mean_eps = nk ? sum_eps / (double)nk : 0.0;
     info.mean_window_log2 = nk ? sum_win / (double)nk : 0.0;
-    idx->bytes = idx->n_ref * 16 + nk * 20 + (uint64_t)idx->nleaves * leaf_bytes() + NP * 4;
+    idx->bytes = idx->n_ref * 16 + nk * 20 + (uint64_t)idx->nleaves * leaf_bytes() + NP * 4 +
+                 coord_bytes();
   } catch (...) {
     if (ts) (void)hipStreamSynchronize(ts);
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -260,9 +288,8 @@ TileOut learned_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, con
   auto probe = [&]() {
     launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, s);
     launch_fill_u64(reinterpret_cast<uint64_t*>(steps), 0, 1, s);
-    launch_probe(p.seq, p.voff, q.n, idx->keys, idx->kid, idx->n_keys, learned, idx->params,
-                 idx->info.feature_shift, idx->info.feature_scale, idx->nleaves, idx->leaves, cand,
-                 ccap, ccount, steps, s);
+    launch_probe(p.seq, p.voff, q.n, idx->keys, idx->kid, idx->n_keys, learned, idx->coord,
+                 idx->params, idx->nleaves, idx->leaves, cand, ccap, ccount, steps, s);
   };
   probe();
   auto counts = [&](uint64_t* got) {  // candidates and comparisons, one read-back

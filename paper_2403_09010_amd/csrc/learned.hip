@@ -1,26 +1,35 @@
 // Learned index over a reference deletion index sorted by the exact 128-bit
 // key: a model that can change the speed of a lookup and never its result.
 //
-// A two-stage recursive model index maps a key to a predicted position in
-// the sorted keys:
-//   stage 1  an FP32 MLP 1 -> H (tanh) -> 1 on a normalised key feature x1
-//            predicts the rank fraction; it selects one of F leaves
-//   stage 2  per leaf, a line through the leaf's first and last key over a
-//            finer feature x2 predicts the position
+// The model predicts a key's position in the sorted keys in three steps:
+//   coordinate  a factorised residue model (per length L and position t, the
+//               frequency of each residue, fitted by counting a sample of the
+//               keys) maps the key to its arithmetic-coding coordinate in
+//               [0, 1): the length's cumulative share, then for each of the
+//               first 12 residues the cumulative frequency of the smaller
+//               residues scaled by the probability of the prefix before it.
+//               The coordinate is monotone in key order and would be the
+//               rank fraction if residues were independent given (L, t).
+//   stage 1     an FP32 MLP 1 -> H (tanh) -> 1 maps the coordinate to the
+//               rank fraction (trained by gradient descent on the device);
+//               its output selects one of F leaves
+//   stage 2     per leaf, the line through the leaf's first and last key
+//               over the FP64 coordinate predicts the position
 // Each leaf stores its exact worst error eps over every indexed key that the
-// model sends to it (an integer computed after training), so an equality
-// lookup that searches [p - eps, p + eps] finds exactly what a binary search
-// over the whole array finds.
+// model sends to it, computed after training by the same device functions
+// the lookups call, so an equality lookup that searches [p - eps, p + eps]
+// finds exactly what a binary search over the whole array finds.
 //
 // Kernels
 //   k_interleave       (hi, lo) word arrays -> one 16-byte key per entry
-//   k_train_sample     (x1, rank / n) samples at evenly spaced ranks
+//   k_coord_counts     residue counts per (L, t) and length counts of a sample
+//   k_train_sample     (coordinate, rank / n) samples at evenly spaced ranks
 //   k_mlp_grad         forward and backward of the mean squared error over
 //                      the samples, one hidden unit per lane; one partial
 //                      gradient per block
 //   k_grad_reduce      partial gradients summed in block order
 //   k_adam_step        the same sum, then one Adam update (device step count,
-//                      so a captured graph of a training step can be replayed)
+//                      so a captured graph of training steps can be replayed)
 //   k_leaf_range       first and last position of the keys of each leaf
 //   k_leaf_fit         the leaf lines
 //   k_leaf_eps         exact per-leaf worst error
@@ -35,23 +44,45 @@ namespace sdk {
 constexpr int H = SD_MLP_HIDDEN;
 constexpr int NP = SD_MLP_PARAMS;  // w1[H] b1[H] w2[H] b2
 constexpr int LNT = 256;
+constexpr int NL = KEY_MAX_LEN + 1;  // key lengths 0 .. 24
+constexpr int NR = 20;               // residue codes
 
 struct Leaf {  // 32 bytes: one load per probe
-  double slope, x2min;
+  double slope, cmin;
   uint32_t lo, hi, eps, count;  // first and last position, error bound, keys sent here
 };
 static_assert(sizeof(Leaf) == 32, "leaf record size");
 
-__device__ __forceinline__ uint64_t key_hi(u128 k) { return (uint64_t)(k >> 64); }
+// The coordinate model: tab[(L * 24 + t) * 20 + c] = (cumulative frequency of
+// residues below c, frequency of c) at position t of length-L keys, and
+// lencum[L] = share of keys shorter than L (lencum[25] = 1).
+struct Coord {
+  double2 tab[NL * KEY_MAX_LEN * NR];
+  double lencum[NL + 1];
+};
 
-// x1: the top 24 bits of the key's high word (exact in FP32), mapped by
-// (x - shift) * scale onto about [0, 1]; x2: the top 53 bits (exact in FP64)
-__device__ __forceinline__ float key_x1(uint64_t hi, float shift, float scale) {
-  return ((float)(hi >> 40) - shift) * scale;
-}
-__device__ __forceinline__ double key_x2(uint64_t hi) { return (double)(hi >> 11); }
+// Residues that enter the coordinate: later ones refine it below the
+// resolution that separates the indexed keys (about 3.6 bits of entropy per
+// residue), and a fixed count lets every table load issue at once.
+constexpr int COORD_RES = 12;
 
 // Not inlined: the build and the lookups must run the same instructions.
+__device__ __noinline__ double key_coord(const Coord* __restrict__ cm, u128 key) {
+  const uint32_t L = key_len(key);
+  const double2* row = cm->tab + (size_t)L * KEY_MAX_LEN * NR;
+  double2 e[COORD_RES];
+#pragma unroll
+  for (int t = 0; t < COORD_RES; ++t)
+    e[t] = (uint32_t)t < L ? row[t * NR + key_residue(key, t)] : make_double2(0.0, 1.0);
+  double x = 0.0, w = 1.0;
+#pragma unroll
+  for (int t = 0; t < COORD_RES; ++t) {
+    x = fma(w, e[t].x, x);
+    w = w * e[t].y;
+  }
+  return fma(cm->lencum[L + 1] - cm->lencum[L], x, cm->lencum[L]);
+}
+
 __device__ __noinline__ float mlp_forward(const float* __restrict__ p, float x) {
   float y = p[3 * H];
 #pragma unroll 4
@@ -59,9 +90,8 @@ __device__ __noinline__ float mlp_forward(const float* __restrict__ p, float x) 
   return y;
 }
 
-__device__ __noinline__ uint32_t leaf_of(const float* __restrict__ p, float shift, float scale,
-                                         uint32_t nleaves, uint64_t hi) {
-  const float f = mlp_forward(p, key_x1(hi, shift, scale)) * (float)nleaves;
+__device__ __noinline__ uint32_t leaf_of(const float* __restrict__ p, uint32_t nleaves, double c) {
+  const float f = mlp_forward(p, (float)c) * (float)nleaves;
   if (!(f > 0.0f)) return 0;  // NaN included
   if (f >= (float)nleaves) return nleaves - 1;
   return (uint32_t)f;
@@ -70,8 +100,8 @@ __device__ __noinline__ uint32_t leaf_of(const float* __restrict__ p, float shif
 // For an indexed key the prediction lies in [lo, hi] of its leaf; keys that
 // are not indexed may land anywhere, so the value is clamped before the
 // integer conversion.
-__device__ __noinline__ int64_t leaf_predict(uint32_t lo, double slope, double x2min, uint64_t hi) {
-  const double p = floor((double)lo + slope * (key_x2(hi) - x2min));
+__device__ __noinline__ int64_t leaf_predict(const Leaf& f, double c) {
+  const double p = floor((double)f.lo + f.slope * (c - f.cmin));
   return (int64_t)fmin(fmax(p, -1.0e18), 1.0e18);
 }
 
@@ -84,15 +114,35 @@ __global__ __launch_bounds__(LNT) void k_interleave(const uint64_t* __restrict__
     out[i] = ((u128)hi[i] << 64) | lo[i];
 }
 
-// ------------------------------------------------------------------ training
+// ------------------------------------------------------------------ model fit
+
+// counts[(L * 24 + t) * 20 + c] and counts[NL * 24 * 20 + L] over the S keys
+// at ranks s * n / S
+__global__ __launch_bounds__(LNT) void k_coord_counts(const u128* __restrict__ keys, uint64_t n,
+                                                      uint32_t S, uint32_t* __restrict__ counts) {
+  constexpr int NT = NL * KEY_MAX_LEN * NR;
+  __shared__ uint32_t s_c[NT + NL];
+  for (int x = threadIdx.x; x < NT + NL; x += LNT) s_c[x] = 0;
+  __syncthreads();
+  for (uint32_t s = blockIdx.x * LNT + threadIdx.x; s < S; s += gridDim.x * LNT) {
+    const u128 key = keys[(uint64_t)s * n / S];
+    const uint32_t L = key_len(key);
+    atomicAdd(&s_c[NT + L], 1u);
+    for (uint32_t t = 0; t < L; ++t)
+      atomicAdd(&s_c[(L * KEY_MAX_LEN + t) * NR + key_residue(key, (int)t)], 1u);
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < NT + NL; x += LNT)
+    if (s_c[x]) atomicAdd(&counts[x], s_c[x]);
+}
 
 __global__ __launch_bounds__(LNT) void k_train_sample(const u128* __restrict__ keys, uint64_t n,
-                                                      uint32_t S, float shift, float scale,
+                                                      uint32_t S, const Coord* __restrict__ cm,
                                                       float* __restrict__ x, float* __restrict__ y) {
   const uint32_t s = blockIdx.x * LNT + threadIdx.x;
   if (s >= S) return;
   const uint64_t i = (uint64_t)s * n / S;
-  x[s] = key_x1(key_hi(keys[i]), shift, scale);
+  x[s] = (float)key_coord(cm, keys[i]);
   y[s] = (float)((double)i / (double)n);
 }
 
@@ -144,10 +194,20 @@ __global__ __launch_bounds__(LNT) void k_mlp_grad(const float* __restrict__ p,
   }
 }
 
+// Sum of the block partials of entry t in block order; the loads are issued
+// eight at a time so the serial chain is of additions, not of memory latency.
 __device__ __forceinline__ float sum_partials(const float* __restrict__ partial, uint32_t nblocks,
                                               int t) {
   float v = 0.0f;
-  for (uint32_t b = 0; b < nblocks; ++b) v += partial[(uint64_t)b * (NP + 1) + t];
+  uint32_t b = 0;
+  for (; b + 8 <= nblocks; b += 8) {
+    float q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = partial[(uint64_t)(b + u) * (NP + 1) + t];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += q[u];
+  }
+  for (; b < nblocks; ++b) v += partial[(uint64_t)b * (NP + 1) + t];
   return v;
 }
 
@@ -185,12 +245,17 @@ __global__ void k_adam_step(float* __restrict__ p, float* __restrict__ state,
 
 // ------------------------------------------------------------------ leaves
 
+__global__ void k_leaf_init(Leaf* __restrict__ leaves, uint32_t nleaves) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < nleaves) leaves[l] = Leaf{0.0, 0.0, 0xFFFFFFFFu, 0u, 0u, 0u};
+}
+
 __global__ __launch_bounds__(LNT) void k_leaf_range(const u128* __restrict__ keys, uint64_t n,
-                                                    const float* __restrict__ p, float shift,
-                                                    float scale, uint32_t nleaves,
+                                                    const Coord* __restrict__ cm,
+                                                    const float* __restrict__ p, uint32_t nleaves,
                                                     Leaf* __restrict__ leaves) {
   for (uint64_t i = (uint64_t)blockIdx.x * LNT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * LNT) {
-    const uint32_t l = leaf_of(p, shift, scale, nleaves, key_hi(keys[i]));
+    const uint32_t l = leaf_of(p, nleaves, key_coord(cm, keys[i]));
     // The active lanes of a wave are a prefix holding consecutive positions,
     // and sorted keys usually share a leaf: then the first active lane
     // records the whole run with one update of each field.
@@ -212,22 +277,17 @@ __global__ __launch_bounds__(LNT) void k_leaf_range(const u128* __restrict__ key
   }
 }
 
-__global__ void k_leaf_init(Leaf* __restrict__ leaves, uint32_t nleaves) {
-  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < nleaves) leaves[l] = Leaf{0.0, 0.0, 0xFFFFFFFFu, 0u, 0u, 0u};
-}
-
-__global__ void k_leaf_fit(const u128* __restrict__ keys, uint32_t nleaves,
-                           Leaf* __restrict__ leaves) {
+__global__ void k_leaf_fit(const u128* __restrict__ keys, const Coord* __restrict__ cm,
+                           uint32_t nleaves, Leaf* __restrict__ leaves) {
   const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nleaves) return;
   Leaf f = leaves[l];
   if (f.lo > f.hi) {  // empty leaf
     f.slope = 0.0;
-    f.x2min = 0.0;
+    f.cmin = 0.0;
   } else {
-    const double a = key_x2(key_hi(keys[f.lo])), b = key_x2(key_hi(keys[f.hi]));
-    f.x2min = a;
+    const double a = key_coord(cm, keys[f.lo]), b = key_coord(cm, keys[f.hi]);
+    f.cmin = a;
     f.slope = b > a ? (double)(f.hi - f.lo) / (b - a) : 0.0;
   }
   f.eps = 0;
@@ -235,16 +295,33 @@ __global__ void k_leaf_fit(const u128* __restrict__ keys, uint32_t nleaves,
 }
 
 __global__ __launch_bounds__(LNT) void k_leaf_eps(const u128* __restrict__ keys, uint64_t n,
-                                                  const float* __restrict__ p, float shift,
-                                                  float scale, uint32_t nleaves,
+                                                  const Coord* __restrict__ cm,
+                                                  const float* __restrict__ p, uint32_t nleaves,
                                                   Leaf* __restrict__ leaves) {
   for (uint64_t i = (uint64_t)blockIdx.x * LNT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * LNT) {
-    const uint64_t hi = key_hi(keys[i]);
-    const uint32_t l = leaf_of(p, shift, scale, nleaves, hi);
-    const Leaf f = leaves[l];
-    const int64_t d = leaf_predict(f.lo, f.slope, f.x2min, hi) - (int64_t)i;
-    const uint64_t e = (uint64_t)(d < 0 ? -d : d);
-    atomicMax(&leaves[l].eps, (uint32_t)(e > 0xFFFFFFFFull ? 0xFFFFFFFFull : e));
+    const double c = key_coord(cm, keys[i]);
+    const uint32_t l = leaf_of(p, nleaves, c);
+    const int64_t d = leaf_predict(leaves[l], c) - (int64_t)i;
+    const uint64_t e64 = (uint64_t)(d < 0 ? -d : d);
+    uint32_t e = (uint32_t)(e64 > 0xFFFFFFFFull ? 0xFFFFFFFFull : e64);
+    // The active lanes are a prefix of the wave and usually share a leaf:
+    // then a shift-down maximum leaves the wave's maximum in the first lane,
+    // which makes the only atomic.
+    const uint64_t active = __ballot(true);
+    const uint32_t leader = (uint32_t)__ffsll((long long)active) - 1u;
+    const uint32_t l0 = __shfl(l, (int)leader, 64);
+    if (__ballot(l == l0) == active) {
+      const uint32_t lane = lane_id();
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t other = __shfl_down(e, o, 64);
+        if (lane + (uint32_t)o < 64u && ((active >> (lane + (uint32_t)o)) & 1ull))
+          e = other > e ? other : e;
+      }
+      if (lane == leader) atomicMax(&leaves[l].eps, e);
+    } else {
+      atomicMax(&leaves[l].eps, e);
+    }
   }
 }
 
@@ -255,7 +332,7 @@ constexpr int PB_SEQS = 64;
 __global__ __launch_bounds__(LNT) void k_probe(
     const u128* __restrict__ qseq, const uint64_t* __restrict__ qvoff, uint64_t nq,
     const u128* __restrict__ keys, const uint32_t* __restrict__ kid, uint64_t n, int learned,
-    const float* __restrict__ p, float shift, float scale, uint32_t nleaves,
+    const Coord* __restrict__ cm, const float* __restrict__ p, uint32_t nleaves,
     const Leaf* __restrict__ leaves, uint64_t* __restrict__ cand, uint64_t cap,
     unsigned long long* __restrict__ ccount, unsigned long long* __restrict__ steps_total) {
   __shared__ uint64_t s_off[PB_SEQS + 1];
@@ -286,12 +363,12 @@ __global__ __launch_bounds__(LNT) void k_probe(
       const u128 key = key_variant(s_seq[lo], (uint32_t)(g - s_off[lo]));
       uint64_t a = 0, b = n;
       if (learned) {
-        const uint64_t khi = key_hi(key);
-        const Leaf f = leaves[leaf_of(p, shift, scale, nleaves, khi)];
+        const double c = key_coord(cm, key);
+        const Leaf f = leaves[leaf_of(p, nleaves, c)];
         if (f.lo > f.hi) {
           b = 0;  // no indexed key is sent to this leaf, so the key is absent
         } else {
-          const int64_t pr = leaf_predict(f.lo, f.slope, f.x2min, khi);
+          const int64_t pr = leaf_predict(f, c);
           const int64_t wa = pr - (int64_t)f.eps, wb = pr + (int64_t)f.eps + 1;
           a = wa < 0 ? 0 : (uint64_t)wa;
           b = wb < 0 ? 0 : ((uint64_t)wb > n ? n : (uint64_t)wb);
@@ -334,22 +411,32 @@ static unsigned grid_for(uint64_t n) {
 }
 
 size_t leaf_bytes() { return sizeof(sdk::Leaf); }
+size_t coord_bytes() { return sizeof(sdk::Coord); }
+int coord_lengths() { return sdk::NL; }
 
 void launch_interleave(const uint64_t* hi, const uint64_t* lo, uint64_t n, u128* out, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(sdk::k_interleave, dim3(grid_for(n)), dim3(sdk::LNT), 0, s, hi, lo, n, out);
 }
 
-void launch_train_sample(const u128* keys, uint64_t n, uint32_t S, float shift, float scale,
-                         float* x, float* y, hipStream_t s) {
+void launch_coord_counts(const u128* keys, uint64_t n, uint32_t S, uint32_t* counts,
+                         hipStream_t s) {
+  if (!S) return;
+  uint32_t g = (S + sdk::LNT * 32 - 1) / (sdk::LNT * 32);
+  g = g > 512 ? 512 : g;
+  hipLaunchKernelGGL(sdk::k_coord_counts, dim3(g), dim3(sdk::LNT), 0, s, keys, n, S, counts);
+}
+
+void launch_train_sample(const u128* keys, uint64_t n, uint32_t S, const void* coord, float* x,
+                         float* y, hipStream_t s) {
   if (!S) return;
   hipLaunchKernelGGL(sdk::k_train_sample, dim3((S + sdk::LNT - 1) / sdk::LNT), dim3(sdk::LNT), 0, s,
-                     keys, n, S, shift, scale, x, y);
+                     keys, n, S, static_cast<const sdk::Coord*>(coord), x, y);
 }
 
 uint32_t mlp_grad_blocks(uint32_t n) {
-  const uint32_t b = (n + sdk::GROUPS * 16 - 1) / (sdk::GROUPS * 16);
-  return b < 1 ? 1 : (b > 512 ? 512 : b);
+  const uint32_t b = (n + sdk::GROUPS * 64 - 1) / (sdk::GROUPS * 64);
+  return b < 1 ? 1 : (b > 128 ? 128 : b);
 }
 
 void launch_mlp_grad(const float* p, const float* x, const float* y, uint32_t n, float* partial,
@@ -368,26 +455,28 @@ void launch_adam_step(float* p, float* state, const float* partial, uint32_t nbl
                      loss_out, loss_cap);
 }
 
-void launch_leaf_fit_all(const u128* keys, uint64_t n, const float* p, float shift, float scale,
+void launch_leaf_fit_all(const u128* keys, uint64_t n, const void* coord, const float* p,
                          uint32_t nleaves, void* leaves, hipStream_t s) {
   sdk::Leaf* lv = static_cast<sdk::Leaf*>(leaves);
+  const sdk::Coord* cm = static_cast<const sdk::Coord*>(coord);
   hipLaunchKernelGGL(sdk::k_leaf_init, dim3((nleaves + 255) / 256), dim3(256), 0, s, lv, nleaves);
-  hipLaunchKernelGGL(sdk::k_leaf_range, dim3(grid_for(n)), dim3(sdk::LNT), 0, s, keys, n, p, shift,
-                     scale, nleaves, lv);
-  hipLaunchKernelGGL(sdk::k_leaf_fit, dim3((nleaves + 255) / 256), dim3(256), 0, s, keys, nleaves,
-                     lv);
-  hipLaunchKernelGGL(sdk::k_leaf_eps, dim3(grid_for(n)), dim3(sdk::LNT), 0, s, keys, n, p, shift,
-                     scale, nleaves, lv);
+  hipLaunchKernelGGL(sdk::k_leaf_range, dim3(grid_for(n)), dim3(sdk::LNT), 0, s, keys, n, cm, p,
+                     nleaves, lv);
+  hipLaunchKernelGGL(sdk::k_leaf_fit, dim3((nleaves + 255) / 256), dim3(256), 0, s, keys, cm,
+                     nleaves, lv);
+  hipLaunchKernelGGL(sdk::k_leaf_eps, dim3(grid_for(n)), dim3(sdk::LNT), 0, s, keys, n, cm, p,
+                     nleaves, lv);
 }
 
 void launch_probe(const u128* qseq, const uint64_t* qvoff, uint64_t nq, const u128* keys,
-                  const uint32_t* kid, uint64_t n, int learned, const float* p, float shift,
-                  float scale, uint32_t nleaves, const void* leaves, uint64_t* cand, uint64_t cap,
+                  const uint32_t* kid, uint64_t n, int learned, const void* coord, const float* p,
+                  uint32_t nleaves, const void* leaves, uint64_t* cand, uint64_t cap,
                   unsigned long long* ccount, unsigned long long* steps, hipStream_t s) {
   if (!nq) return;
   hipLaunchKernelGGL(sdk::k_probe, dim3((unsigned)((nq + sdk::PB_SEQS - 1) / sdk::PB_SEQS)),
-                     dim3(sdk::LNT), 0, s, qseq, qvoff, nq, keys, kid, n, learned, p, shift, scale,
-                     nleaves, static_cast<const sdk::Leaf*>(leaves), cand, cap, ccount, steps);
+                     dim3(sdk::LNT), 0, s, qseq, qvoff, nq, keys, kid, n, learned,
+                     static_cast<const sdk::Coord*>(coord), p, nleaves,
+                     static_cast<const sdk::Leaf*>(leaves), cand, cap, ccount, steps);
 }
 
 }  // namespace sd

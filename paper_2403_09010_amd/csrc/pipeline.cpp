@@ -170,10 +170,12 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   launch_fill_u32(seg_start, 0, nseg, s);
   launch_fill_u32(seg_end, 0, nseg, s);
   launch_seg_bounds(E, nk, segshift, seg_start, seg_end, s);
+  cl.tm.mark("seg_bounds", (double)nk * 8 + (double)nseg * 16, 3);
   const double mean_seg = (double)nk / nseg;
   const uint32_t spw =
       (uint32_t)std::max(1.0, std::floor(0.8 * cap / std::max(mean_seg, 1.0) + 0.5));
   uint64_t ccap = nk / 16 + 65536;
+  const uint64_t ccap0 = ccap;
   Cands cand;
   cand.p = dalloc_t<uint64_t>(c, ccap);
   const uint64_t nbig_cap = nk / cap + 2;
@@ -200,7 +202,7 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
                      nbig, s);
   }
   cand.n = nc;
-  cl.tm.mark("group_local", (double)nk * 8 + (double)nc * 8, 2);
+  cl.tm.mark("group_local", (double)nk * 8 + (double)nc * 8, nc > ccap0 ? 2 : 1);
   c->stats.n_big_segments = (int64_t)nb;
   if (nb) {
     Cands extra = oversized_group(cl, E, big, nb, idbits);

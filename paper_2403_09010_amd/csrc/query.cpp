@@ -204,7 +204,7 @@ void index_free(sd_index* idx) {
   if (!idx) return;
   (void)hipSetDevice(idx->device);
   for (void* p : {(void*)idx->ref_seq, (void*)idx->E, (void*)idx->seg_start, (void*)idx->seg_end,
-                  (void*)idx->keys, (void*)idx->kid, (void*)idx->params, idx->leaves})
+                  (void*)idx->keys, (void*)idx->kid, (void*)idx->params, idx->coord, idx->leaves})
     if (p) (void)hipFree(p);
   delete idx;
 }

@@ -91,20 +91,23 @@ void launch_slice_rebase(const uint32_t* qi, const uint32_t* rj, const uint8_t* 
                          hipStream_t s);
 // learned index
 size_t leaf_bytes();
+size_t coord_bytes();
+int coord_lengths();
 void launch_interleave(const uint64_t* hi, const uint64_t* lo, uint64_t n, u128* out, hipStream_t s);
-void launch_train_sample(const u128* keys, uint64_t n, uint32_t S, float shift, float scale,
-                         float* x, float* y, hipStream_t s);
+void launch_coord_counts(const u128* keys, uint64_t n, uint32_t S, uint32_t* counts, hipStream_t s);
+void launch_train_sample(const u128* keys, uint64_t n, uint32_t S, const void* coord, float* x,
+                         float* y, hipStream_t s);
 uint32_t mlp_grad_blocks(uint32_t n);
 void launch_mlp_grad(const float* p, const float* x, const float* y, uint32_t n, float* partial,
                      hipStream_t s);
 void launch_grad_reduce(const float* partial, uint32_t nblocks, float* out, hipStream_t s);
 void launch_adam_step(float* p, float* state, const float* partial, uint32_t nblocks, float lr,
                       float* loss_out, uint32_t loss_cap, hipStream_t s);
-void launch_leaf_fit_all(const u128* keys, uint64_t n, const float* p, float shift, float scale,
+void launch_leaf_fit_all(const u128* keys, uint64_t n, const void* coord, const float* p,
                          uint32_t nleaves, void* leaves, hipStream_t s);
 void launch_probe(const u128* qseq, const uint64_t* qvoff, uint64_t nq, const u128* keys,
-                  const uint32_t* kid, uint64_t n, int learned, const float* p, float shift,
-                  float scale, uint32_t nleaves, const void* leaves, uint64_t* cand, uint64_t cap,
+                  const uint32_t* kid, uint64_t n, int learned, const void* coord, const float* p,
+                  uint32_t nleaves, const void* leaves, uint64_t* cand, uint64_t cap,
                   unsigned long long* ccount, unsigned long long* steps, hipStream_t s);
 
 // ------------------------------------------------------------------ errors
@@ -165,6 +168,7 @@ struct sd_index {
   u128* keys = nullptr;
   uint32_t* kid = nullptr;
   float* params = nullptr;  // device, SD_MLP_PARAMS floats
+  void* coord = nullptr;    // device coordinate model (residue frequency tables)
   void* leaves = nullptr;   // device leaf records
   uint32_t nleaves = 0;
   sd_learned_info info{};
@@ -232,6 +236,8 @@ void query_weighted(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* se
                     hipStream_t s);
 sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_config* cfg,
                         hipStream_t s);
+void autotune(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, int k, int reps,
+              sd_tune_result* out, hipStream_t s);
 void mlp_gradients(sd_ctx* c, const float* params, const float* x, const float* y, uint32_t n,
                    float* grad, float* loss, hipStream_t s);
 

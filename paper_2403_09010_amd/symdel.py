@@ -74,9 +74,15 @@ class _LearnedInfo(ctypes.Structure):
                 ("max_eps", ctypes.c_uint32), ("empty_leaves", ctypes.c_uint32),
                 ("mean_eps", ctypes.c_double), ("mean_window_log2", ctypes.c_double),
                 ("loss_first", ctypes.c_float), ("loss_last", ctypes.c_float),
-                ("feature_shift", ctypes.c_float), ("feature_scale", ctypes.c_float),
                 ("train_ms", ctypes.c_double), ("fit_ms", ctypes.c_double),
                 ("params", ctypes.c_float * MLP_PARAMS)]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("trials", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("group_cap", ctypes.c_int32), ("sort_items", ctypes.c_int32),
+                ("batch_tile", ctypes.c_int64), ("best_s", ctypes.c_double),
+                ("default_s", ctypes.c_double)]
 
 
 _lib = None
@@ -89,6 +95,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise OSError(f"{path} is not built; run __graft_entry__.build() first")
+    # torch ships its own HIP runtime under the same soname; importing it first
+    # makes the library bind to that runtime, so torch streams and device
+    # pointers are valid in both and torch still initialises afterwards.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     lib.sd_create.argtypes = [ctypes.POINTER(P), I, ctypes.c_uint64]
@@ -132,6 +142,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sd_index_learned_info.restype = I
     lib.sd_mlp_gradients.argtypes = [P, P, P, P, ctypes.c_uint32, P, P, P]
     lib.sd_mlp_gradients.restype = I
+    lib.sd_autotune.argtypes = [P, P, I, ctypes.POINTER(_Seqs), I, I,
+                                ctypes.POINTER(_TuneResult), P]
+    lib.sd_autotune.restype = I
     _lib = lib
     return lib
 
@@ -337,6 +350,25 @@ class Context:
                                                      ctypes.byref(cfg), ctypes.byref(h), st),
                     "sd_index_build_learned")
         return Index(self._lib, h)
+
+    def autotune(self, sets, k: int, index: Index | None = None, reps: int = 2,
+                 stream=None) -> dict:
+        """Tune the context's options on sample set(s) (sd_autotune); returns the choice."""
+        n = len(sets)
+        arr = (_Seqs * max(n, 1))()
+        keep = []
+        on_dev = False
+        for x, (codes, offsets) in enumerate(sets):
+            s, kp, od = self._seqs(codes, offsets)
+            arr[x] = s
+            keep.append(kp)
+            on_dev = on_dev or od
+        st = _stream_handle(stream, on_dev)
+        res = _TuneResult()
+        self._check(self._lib.sd_autotune(self._h, index.handle if index is not None else None, n,
+                                          arr, int(k), int(reps), ctypes.byref(res), st),
+                    "sd_autotune")
+        return {f: getattr(res, f) for f, _ in _TuneResult._fields_}
 
     def mlp_gradients(self, params, x, y):
         """(grad, loss) of the stage-1 training loss from the device kernels."""

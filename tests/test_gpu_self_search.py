@@ -332,3 +332,38 @@ def test_plain_1m_k2_sampled(ctx):
     np.add.at(bags, (seq_id, c.astype(np.int64)), 1)
     diff = (bags[i] - bags[j]).astype(np.int64)
     assert np.all((diff * diff).sum(1) <= 2 * d.astype(np.int64) ** 2)
+
+
+@pytest.mark.parametrize("k,samples", [(1, 4), (2, 6)])
+def test_plain_10m_sampled(ctx, k, samples):
+    """10M sequences with 40% cluster members: properties of the whole output,
+    exact distances of sampled pairs and every neighbour of sampled sequences."""
+    import oracle
+    c, o = cdr3gen.plain("plain_10m")
+    n = len(o) - 1
+    log(f"self_search plain_10m k={k} (full size)")
+    i, j, d = gpu_triples(ctx, c, o, k)
+    log(f"  {len(i)} pairs")
+    assert len(i) > (1_000_000 if k == 2 else 500_000)
+    key = (i.astype(np.uint64) << np.uint64(32)) | j.astype(np.uint64)
+    assert np.all(i < j) and np.all(np.diff(key.astype(np.int64)) > 0)
+    assert d.max() <= k
+    rng = np.random.default_rng(10 + k)
+    seqs = lambda x: c[o[x]:o[x + 1]].tobytes()
+    for t in rng.choice(len(i), 2000, replace=False):
+        assert oracle.lev(seqs(i[t]), seqs(j[t])) == d[t]
+    # completeness: half the samples are reported sequences (they have
+    # neighbours), half are uniform
+    picks = list(rng.choice(i, samples // 2)) + list(rng.choice(n, samples - samples // 2))
+    order = np.argsort(i, kind="stable")
+    i_sorted = i[order]
+    order_j = np.argsort(j, kind="stable")
+    j_sorted = j[order_j]
+    for x in picks:
+        dist = oracle.lev_one_to_many(seqs(x), c, o)
+        truth = {(min(x, y), max(x, y), int(dist[y])) for y in np.nonzero(dist <= k)[0] if y != x}
+        a0, a1 = np.searchsorted(i_sorted, x), np.searchsorted(i_sorted, x, side="right")
+        b0, b1 = np.searchsorted(j_sorted, x), np.searchsorted(j_sorted, x, side="right")
+        sel = np.concatenate([order[a0:a1], order_j[b0:b1]])
+        mine = {(int(i[t]), int(j[t]), int(d[t])) for t in sel}
+        assert mine == truth, f"sequence {x}"
