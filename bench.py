@@ -106,6 +106,11 @@ def run_batched(args):
     info = idx.info()
     log(f"index: {info} in {t_index:.2f} s; {nq} query sequences")
     dsets = [(torch.from_numpy(c).to(dev), torch.from_numpy(o).to(dev)) for c, o in sets]
+    tune = None
+    if not args.no_autotune:
+        # tile size and radix items per thread from the autotuner, on these sets
+        tune = ctx.autotune(dsets, k, index=idx, reps=1)
+        log(f"autotune: {tune}")
     arr = (_Seqs * nsets)()
     for x, (c, o) in enumerate(dsets):
         arr[x] = _Seqs(c.data_ptr() if c.numel() else None, o.data_ptr(), o.numel() - 1, 1)
@@ -152,6 +157,7 @@ def run_batched(args):
                                      "pairs_per_s": round(res["plain"][1] / res["plain"][0], 1)},
         "batched": {"seconds": round(dt, 4), "pairs_per_s": round(pairs / dt, 1)},
         "speedup_batched_vs_plain": round(res["plain"][0] / dt, 3),
+        "autotune": tune,
     }
     idx.free()
     ctx.close()
@@ -307,6 +313,7 @@ def run_learned(args):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         res[name] = {"seconds": round(dt, 5), "pairs": len(r), "query_keys": st["n_keys"],
+                     "candidates": st["n_cand_raw"],
                      "comparisons_per_lookup": round(steps / max(1, st["n_keys"]), 3),
                      "stages_ms": {a: round(b, 4) for a, b in stage.items()}}
         log(f"{name}: {res[name]}")
@@ -361,6 +368,7 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this size first (a known-size kernel for counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="batched: keep the default options")
     ap.add_argument("--json-out", default=None)
     args = ap.parse_args()
     if args.gpus != 1:

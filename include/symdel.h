@@ -155,7 +155,8 @@ int sd_index_info(const sd_index* index, int64_t* n_ref, int64_t* n_keys, int32_
  *   stage 1     an FP32 MLP 1 -> SD_MLP_HIDDEN (tanh) -> 1 maps the
  *               coordinate to the rank fraction; it is trained on the device
  *               by full-batch Adam on the mean squared error at cfg.samples
- *               evenly spaced ranks, and its output picks a leaf
+ *               evenly spaced ranks (the parameters with the lowest loss
+ *               seen are kept), and its output picks a leaf
  *   stage 2     per leaf, the line through the leaf's first and last key
  *               over the FP64 coordinate
  * After training every leaf stores its exact worst position error eps over
@@ -171,7 +172,7 @@ int sd_index_info(const sd_index* index, int64_t* n_ref, int64_t* n_keys, int32_
 typedef struct {
   int32_t leaves_log2; /* stage-2 leaves = 2^leaves_log2 in [4, 24] (0: about 256 keys per leaf) */
   int32_t steps;       /* Adam steps (0 trains nothing; -1: 400) */
-  float lr;            /* Adam learning rate (0: 0.01) */
+  float lr;            /* Adam learning rate (0: 2e-4) */
   uint32_t samples;    /* training samples, at most 2^24 (0: 65536) */
   int32_t use_init;    /* 1: start from init[]; 0: tanh units placed at sample quantiles */
   float init[SD_MLP_PARAMS];
@@ -187,7 +188,8 @@ typedef struct {
   uint32_t empty_leaves;
   double mean_eps;          /* leaf error bound averaged over the indexed keys */
   double mean_window_log2;  /* log2(2 eps + 1) averaged over the indexed keys */
-  float loss_first, loss_last; /* training loss of the first and last step */
+  float loss_first;         /* training loss of the initial parameters */
+  float loss_last;          /* training loss of the returned parameters (the lowest seen) */
   double train_ms, fit_ms;  /* device time of training and of the leaf fit */
   float params[SD_MLP_PARAMS];
 } sd_learned_info;

@@ -126,6 +126,11 @@ StageTimer::StageTimer(sd_ctx* ctx, hipStream_t st) : c(ctx), s(st), on(ctx->tim
 }
 
 void StageTimer::mark(const char* name, double bytes, int nl) {
+  // a launch that the runtime rejected surfaces here, named by its stage
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    throw Error{SD_E_HIP, std::string("a kernel launch of stage ") + name + " failed: " +
+                              hipGetErrorString(e)};
   if (!on || names.size() >= SD_MAX_STAGES) return;
   names.push_back({name, bytes});
   launches.push_back(nl);
@@ -157,6 +162,9 @@ static int guarded(sd_ctx* c, F&& f) {
   if (c) c->last_error.clear();
   try {
     f();
+    const hipError_t e = hipGetLastError();  // a rejected launch is never left behind
+    if (e != hipSuccess)
+      throw Error{SD_E_HIP, std::string("a kernel launch failed: ") + hipGetErrorString(e)};
     return SD_OK;
   } catch (const Error& e) {
     if (c) c->last_error = e.msg;

@@ -68,6 +68,9 @@ struct PassDigits {
   uint32_t mask[3];
 };
 
+// Variants of one block's sequences: at most VG_SEQS * V(24, 2) = 64 * 301.
+constexpr int VG_MAX_VARIANTS = VG_SEQS * 301;
+
 __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ seq,
                                                        const uint64_t* __restrict__ voff,
                                                        uint64_t nseq, uint64_t* __restrict__ elem,
@@ -76,25 +79,26 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   __shared__ uint64_t s_off[VG_SEQS + 1];
   __shared__ u128 s_seq[VG_SEQS];
   __shared__ uint32_t s_h[3 * 256];
+  __shared__ uint8_t s_map[VG_MAX_VARIANTS];  // block-local variant -> sequence
   const uint64_t s0 = (uint64_t)blockIdx.x * VG_SEQS;
   const uint32_t ns = (uint32_t)min<uint64_t>(VG_SEQS, nseq - s0);
   for (uint32_t x = threadIdx.x; x <= ns; x += VG_NT) s_off[x] = voff[s0 + x];
   for (uint32_t x = threadIdx.x; x < ns; x += VG_NT) s_seq[x] = seq[s0 + x];
   for (uint32_t x = threadIdx.x; x < 3 * 256; x += VG_NT) s_h[x] = 0;
   __syncthreads();
-  const uint64_t idmask = (1ull << idbits) - 1;
   const uint64_t g0 = s_off[0], g1 = s_off[ns];
+  // each wave labels the variants of every fourth sequence
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  for (uint32_t x = w; x < ns; x += VG_NT / 64) {
+    const uint32_t a = (uint32_t)(s_off[x] - g0), b = (uint32_t)(s_off[x + 1] - g0);
+    for (uint32_t t = a + lane; t < b; t += 64) s_map[t] = (uint8_t)x;
+  }
+  __syncthreads();
+  const uint64_t idmask = (1ull << idbits) - 1;
   for (uint64_t g = g0 + threadIdx.x; g < g1; g += VG_NT) {
-    uint32_t lo = 0, hi = ns - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= g)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const uint32_t v = (uint32_t)(g - s_off[lo]);
-    const uint64_t e = (key_hash64(key_variant(s_seq[lo], v)) & ~idmask) | (s0 + lo);
+    const uint32_t x = s_map[g - g0];
+    const uint32_t v = (uint32_t)(g - s_off[x]);
+    const uint64_t e = (key_hash64(key_variant(s_seq[x], v)) & ~idmask) | (s0 + x);
     elem[g] = e;
     for (int q = 0; q < npass; ++q)
       atomicAdd(&s_h[q * 256 + ((uint32_t)(e >> pd.shift[q]) & pd.mask[q])], 1u);
@@ -137,11 +141,13 @@ constexpr uint32_t NONE16 = 0xFFFFu;
 constexpr uint16_t REPEAT16 = 0xFFFEu;
 constexpr int GROUP_LDS_PER_ELEM = 22;
 
+// One batch of m <= CAP elements whose values arrive in registers (element
+// x = threadIdx.x + r * NTH is in e[r]); the caller has already issued the
+// loads of the next batch, so their latency overlaps this batch's LDS work.
 template <int CAP, int NTH>
-__device__ void group_batch(const uint64_t* __restrict__ E, uint32_t a, uint32_t m,
-                            uint32_t idbits, uint64_t* __restrict__ cand, uint64_t cap,
-                            unsigned long long* __restrict__ ccount, unsigned char* lds,
-                            uint64_t* s_tmp64, uint64_t* s_base) {
+__device__ void group_batch(const uint64_t (&e)[CAP / NTH], uint32_t m, uint32_t idbits,
+                            const ShardOut& out, unsigned char* lds, uint64_t* s_tmp64,
+                            uint64_t* s_base) {
   constexpr int PER = CAP / NTH;
   uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
   uint32_t* s_tab = reinterpret_cast<uint32_t*>(lds + CAP * 8);
@@ -152,9 +158,13 @@ __device__ void group_batch(const uint64_t* __restrict__ E, uint32_t a, uint32_t
   while (ts < 2 * m) ts <<= 1;
 
   for (uint32_t x = threadIdx.x; x < ts; x += NTH) s_tab[x] = 0;
-  for (uint32_t x = threadIdx.x; x < m; x += NTH) {
-    s_chead[x] = NONE16;
-    s_e[x] = E[a + x];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const uint32_t x = threadIdx.x + r * NTH;
+    if (x < m) {
+      s_chead[x] = NONE16;
+      s_e[x] = e[r];
+    }
   }
   __syncthreads();
   // Repeated (hash, id) come from one sequence yielding one variant twice
@@ -165,9 +175,8 @@ __device__ void group_batch(const uint64_t* __restrict__ E, uint32_t a, uint32_t
   for (int r = 0; r < PER; ++r) {
     const uint32_t x = threadIdx.x + r * NTH;
     if (x < m) {
-      const uint64_t e = s_e[x];
-      const uint64_t h = e >> idbits;
-      const uint64_t id = e & idmask;
+      const uint64_t h = e[r] >> idbits;
+      const uint64_t id = e[r] & idmask;
       bool repeat = false;
       for (int y = (int)x - 1; y >= 0 && (s_e[y] & idmask) == id; --y) {
         if ((s_e[y] >> idbits) == h) {
@@ -211,51 +220,51 @@ __device__ void group_batch(const uint64_t* __restrict__ E, uint32_t a, uint32_t
         for (; y != NONE16; y = s_next[y]) ++mycnt;
     }
   }
+  // output slots: one reservation per batch, in the block's shard. The
+  // batch total is a property of its groups (per-thread counts depend on the
+  // order members were pushed), so every shard's count is reproducible.
   uint64_t total;
   const uint64_t excl = block_excl_scan<NTH>(mycnt, s_tmp64, &total);
-  if (threadIdx.x == 0) *s_base = total ? atomicAdd(ccount, (unsigned long long)total) : 0ull;
+  if (threadIdx.x == 0) {
+    const ShardResv r = total ? shard_reserve(out, blockIdx.x, total) : ShardResv{0, 0};
+    s_base[0] = r.pos;
+    s_base[1] = r.obase;
+  }
   __syncthreads();
   if (mycnt) {
-    uint64_t pos = *s_base + excl;
+    const ShardResv r{s_base[0], s_base[1]};
+    uint64_t j = excl;
 #pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const uint32_t x = threadIdx.x + r * NTH;
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t x = threadIdx.x + q * NTH;
       if (x < m) {
         uint32_t y = s_next[x];
         if (y == REPEAT16) continue;
-        const uint32_t id = (uint32_t)(s_e[x] & idmask);
+        const uint32_t id = (uint32_t)(e[q] & idmask);
         for (; y != NONE16; y = s_next[y]) {
           const uint32_t other = (uint32_t)(s_e[y] & idmask);
-          if (pos < cap) {
-            const uint32_t lo = id < other ? id : other, hi = id < other ? other : id;
-            cand[pos] = ((uint64_t)lo << 32) | hi;
-          }
-          ++pos;
+          const uint32_t lo = id < other ? id : other, hi = id < other ? other : id;
+          shard_put(out, blockIdx.x, r, j++, ((uint64_t)lo << 32) | hi);
         }
       }
     }
   }
-  __syncthreads();
+  __syncthreads();  // the next batch rewrites the LDS
 }
 
-// One workgroup per `spw` consecutive segment values; consecutive non-empty
-// segments are batched while they fit in CAP elements. A segment larger than
-// CAP is listed in big[] for the sort-and-runs fallback.
-template <int CAP, int NTH>
-__global__ __launch_bounds__(NTH) void k_group_seg(
-    const uint64_t* __restrict__ E, const uint32_t* __restrict__ seg_start,
-    const uint32_t* __restrict__ seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
-    uint64_t* __restrict__ cand, uint64_t cap, unsigned long long* __restrict__ ccount,
-    uint64_t* __restrict__ big, unsigned long long* __restrict__ nbig) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  __shared__ uint64_t s_tmp64[NTH / 64];
-  __shared__ uint64_t s_base;
-  const uint32_t v0 = blockIdx.x * spw;
-  const uint32_t v1 = min(v0 + spw, nseg);
-  uint32_t v = v0;
+// The next batch of a workgroup's segment range starting at segment v:
+// consecutive non-empty segments while they fit in CAP elements. A segment
+// larger than CAP is listed in big[] for the sort-and-runs fallback and
+// skipped. Returns false when the range is exhausted.
+template <int CAP>
+__device__ __forceinline__ bool next_batch(const uint32_t* __restrict__ seg_start,
+                                           const uint32_t* __restrict__ seg_end, uint32_t& v,
+                                           uint32_t v1, uint32_t& a, uint32_t& b,
+                                           uint64_t* __restrict__ big,
+                                           unsigned long long* __restrict__ nbig) {
   while (v < v1) {
-    const uint32_t a = seg_start[v];
-    uint32_t b = seg_end[v];
+    a = seg_start[v];
+    b = seg_end[v];
     if (a == b) {
       ++v;
       continue;
@@ -278,8 +287,50 @@ __global__ __launch_bounds__(NTH) void k_group_seg(
       }
       ++w;
     }
-    group_batch<CAP, NTH>(E, a, b - a, idbits, cand, cap, ccount, lds, s_tmp64, &s_base);
     v = w;
+    return true;
+  }
+  return false;
+}
+
+// One workgroup per `spw` consecutive segment values, processed as batches;
+// the elements of batch t + 1 are loaded into registers while batch t is
+// grouped.
+template <int CAP, int NTH>
+__global__ __launch_bounds__(NTH) void k_group_seg(
+    const uint64_t* __restrict__ E, const uint32_t* __restrict__ seg_start,
+    const uint32_t* __restrict__ seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
+    ShardOut out, uint64_t* __restrict__ big, unsigned long long* __restrict__ nbig) {
+  constexpr int PER = CAP / NTH;
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ uint64_t s_tmp64[NTH / 64];
+  __shared__ uint64_t s_base[2];
+  const uint32_t v0 = blockIdx.x * spw;
+  const uint32_t v1 = min(v0 + spw, nseg);
+  uint32_t v = v0, a = 0, b = 0;
+  bool have = next_batch<CAP>(seg_start, seg_end, v, v1, a, b, big, nbig);
+  uint64_t cur[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const uint32_t x = threadIdx.x + r * NTH;
+    cur[r] = (have && x < b - a) ? E[a + x] : 0;
+  }
+  while (have) {
+    const uint32_t m = b - a;
+    uint32_t na = 0, nb = 0;
+    const bool more = next_batch<CAP>(seg_start, seg_end, v, v1, na, nb, big, nbig);
+    uint64_t nxt[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const uint32_t x = threadIdx.x + r * NTH;
+      nxt[r] = (more && x < nb - na) ? E[na + x] : 0;
+    }
+    group_batch<CAP, NTH>(cur, m, idbits, out, lds, s_tmp64, s_base);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) cur[r] = nxt[r];
+    a = na;
+    b = nb;
+    have = more;
   }
 }
 
@@ -366,39 +417,41 @@ static size_t group_lds(int cap) { return (size_t)cap * sdk::GROUP_LDS_PER_ELEM;
 
 template <int CAP, int NTH>
 static void launch_group_t(const uint64_t* E, const uint32_t* ss, const uint32_t* se,
-                           uint32_t nseg, uint32_t spw, uint32_t idbits, uint64_t* cand,
-                           uint64_t ccap, unsigned long long* ccount, uint64_t* big,
-                           unsigned long long* nbig, hipStream_t s) {
+                           uint32_t nseg, uint32_t spw, uint32_t idbits, const ShardArgs& a,
+                           uint64_t* big, unsigned long long* nbig, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     attr = true;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&sdk::k_group_seg<CAP, NTH>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)group_lds(CAP));
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&sdk::k_group_seg<CAP, NTH>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)group_lds(CAP)) != hipSuccess)
+      (void)hipGetLastError();  // the launch reports any real problem
   }
   const unsigned g = (nseg + spw - 1) / spw;
+  const ShardOut out{a.base, a.region, a.over, a.over_cap, a.counter};
   hipLaunchKernelGGL((sdk::k_group_seg<CAP, NTH>), dim3(g), dim3(NTH), group_lds(CAP), s, E, ss,
-                     se, nseg, spw, idbits, cand, ccap, ccount, big, nbig);
+                     se, nseg, spw, idbits, out, big, nbig);
 }
 
 bool group_cap_supported(int cap) { return cap == 4096 || cap == 2048 || cap == 1024 || cap == 256; }
 
 void launch_group_seg(int cap, const uint64_t* E, const uint32_t* seg_start,
                       const uint32_t* seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
-                      uint64_t* cand, uint64_t ccap, unsigned long long* ccount, uint64_t* big,
-                      unsigned long long* nbig, hipStream_t s) {
+                      const ShardArgs& out, uint64_t* big, unsigned long long* nbig,
+                      hipStream_t s) {
   if (!nseg) return;
   switch (cap) {
     case 4096:
-      launch_group_t<4096, 512>(E, seg_start, seg_end, nseg, spw, idbits, cand, ccap, ccount, big, nbig, s);
+      launch_group_t<4096, 512>(E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
       break;
     case 2048:
-      launch_group_t<2048, 256>(E, seg_start, seg_end, nseg, spw, idbits, cand, ccap, ccount, big, nbig, s);
+      launch_group_t<2048, 256>(E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
       break;
     case 1024:
-      launch_group_t<1024, 128>(E, seg_start, seg_end, nseg, spw, idbits, cand, ccap, ccount, big, nbig, s);
+      launch_group_t<1024, 128>(E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
       break;
     default:
-      launch_group_t<256, 64>(E, seg_start, seg_end, nseg, spw, idbits, cand, ccap, ccount, big, nbig, s);
+      launch_group_t<256, 64>(E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
       break;
   }
 }

@@ -83,7 +83,7 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
   if (!(conf.lr >= 0.0f) || conf.lr > 1.0f) throw Error{SD_E_INVAL, "bad learning rate"};
   if (conf.samples > (1u << 24)) throw Error{SD_E_INVAL, "at most 2^24 training samples"};
   const int steps = conf.steps < 0 ? 400 : conf.steps;
-  const float lr = conf.lr > 0.0f ? conf.lr : 0.01f;
+  const float lr = conf.lr > 0.0f ? conf.lr : 2e-4f;
 
   sd_index* idx = new sd_index();
   idx->device = c->device;
@@ -138,28 +138,41 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
       std::vector<uint32_t> hc(ntab + NLn);
       hip_check(hipMemcpyAsync(hc.data(), cnt, hc.size() * 4, hipMemcpyDeviceToHost, s), "D2H counts");
       hip_check(hipStreamSynchronize(s), "synchronise");
-      std::vector<double> model(coord_bytes() / sizeof(double), 0.0);
-      if (model.size() * sizeof(double) != ntab * 16 + (size_t)(NLn + 1) * 8)
-        throw Error{SD_E_HIP, "internal error: coordinate model layout"};
-      const double alpha = 0.5;  // additive smoothing: every residue and length keeps a share
+      // layout: lencum[25 + 1] (double), lmin, lmax (u32), then FP32
+      // (cumulative, frequency) pairs for t < 12 of lengths lmin..lmax
+      const int R = coord_res();
+      size_t off_lmin = 0, off_rows = 0;
+      coord_offsets(&off_lmin, &off_rows);
+      std::vector<unsigned char> model(coord_bytes(), 0);
+      uint32_t lmin = 1, lmax = 0;
+      for (int L = NLn - 1; L >= 0; --L)
+        if (hc[ntab + L]) lmin = (uint32_t)L;
       for (int L = 0; L < NLn; ++L)
-        for (int t = 0; t < L; ++t) {
+        if (hc[ntab + L]) lmax = (uint32_t)L;
+      const double alpha = 0.5;  // additive smoothing: every residue and length keeps a share
+      float* rows = reinterpret_cast<float*>(model.data() + off_rows);
+      for (uint32_t L = lmin; L <= lmax && L < (uint32_t)NLn; ++L)
+        for (int t = 0; t < R && t < (int)L; ++t) {
           const uint32_t* row = &hc[((size_t)L * 24 + t) * 20];
           double tot = 0.0;
           for (int c = 0; c < 20; ++c) tot += row[c];
           double cum = 0.0;
           for (int c = 0; c < 20; ++c) {
             const double pr = (row[c] + alpha) / (tot + 20 * alpha);
-            model[(((size_t)L * 24 + t) * 20 + c) * 2] = cum;
-            model[(((size_t)L * 24 + t) * 20 + c) * 2 + 1] = pr;
+            const size_t e = ((size_t)(L - lmin) * R + t) * 20 + c;
+            rows[2 * e] = (float)cum;
+            rows[2 * e + 1] = (float)pr;
             cum += pr;
           }
         }
-      double* lencum = model.data() + ntab * 2;
+      double* lencum = reinterpret_cast<double*>(model.data());
       double tot = 0.0;
       for (int L = 0; L < NLn; ++L) tot += hc[ntab + L] + alpha;
       lencum[0] = 0.0;
       for (int L = 0; L < NLn; ++L) lencum[L + 1] = lencum[L] + (hc[ntab + L] + alpha) / tot;
+      std::memcpy(model.data() + off_lmin, &lmin, 4);
+      std::memcpy(model.data() + off_lmin + 4, &lmax, 4);
+      idx->coord_rows = lmax >= lmin ? lmax - lmin + 1 : 0;
       hip_check(hipMemcpyAsync(idx->coord, model.data(), coord_bytes(), hipMemcpyHostToDevice, s),
                 "H2D coordinate model");
       hip_check(hipStreamSynchronize(s), "synchronise");
@@ -187,13 +200,14 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
     for (int e = 0; e < 4; ++e) hip_check(hipEventCreate(&ev[e]), "event");
     hip_check(hipEventRecord(ev[0], s), "event");
     const int nsteps = S ? steps : 0;
+    float best_loss = 0.0f;
     idx->loss_curve.assign((size_t)nsteps, 0.0f);
     if (nsteps) {
       const uint32_t nb = mlp_grad_blocks(S);
       float* partial = sc.get<float>((uint64_t)nb * (NP + 1));
-      float* state = sc.get<float>(2 * NP + 1);
+      float* state = sc.get<float>((uint64_t)adam_state_floats());
       float* losses = sc.get<float>((uint64_t)nsteps);
-      launch_fill_u32(reinterpret_cast<uint32_t*>(state), 0, 2 * NP + 1, s);
+      launch_fill_u32(reinterpret_cast<uint32_t*>(state), 0, (uint64_t)adam_state_floats(), s);
       // one captured chunk of steps, replayed on a private stream
       hip_check(hipStreamCreateWithFlags(&ts, hipStreamNonBlocking), "stream");
       hip_check(hipEventRecord(ev[1], s), "event");
@@ -202,7 +216,7 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
       hip_check(hipStreamBeginCapture(ts, hipStreamCaptureModeThreadLocal), "capture");
       for (int x = 0; x < chunk; ++x) {
         launch_mlp_grad(idx->params, sx, sy, S, partial, ts);
-        launch_adam_step(idx->params, state, partial, nb, lr, losses, (uint32_t)nsteps, ts);
+        launch_adam_step(idx->params, state, partial, nb, lr, 1, losses, (uint32_t)nsteps, ts);
       }
       hip_check(hipStreamEndCapture(ts, &graph), "capture");
       hip_check(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "instantiate");
@@ -210,8 +224,14 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
       for (; done + chunk <= nsteps; done += chunk) hip_check(hipGraphLaunch(gexec, ts), "graph launch");
       for (; done < nsteps; ++done) {
         launch_mlp_grad(idx->params, sx, sy, S, partial, ts);
-        launch_adam_step(idx->params, state, partial, nb, lr, losses, (uint32_t)nsteps, ts);
+        launch_adam_step(idx->params, state, partial, nb, lr, 1, losses, (uint32_t)nsteps, ts);
       }
+      // evaluate the last update, then keep the best parameters seen
+      launch_mlp_grad(idx->params, sx, sy, S, partial, ts);
+      launch_adam_step(idx->params, state, partial, nb, lr, 0, losses, (uint32_t)nsteps, ts);
+      launch_adam_best(idx->params, state, ts);
+      hip_check(hipMemcpyAsync(&best_loss, state + 1 + 2 * NP, 4, hipMemcpyDeviceToHost, ts),
+                "D2H best loss");
       hip_check(hipEventRecord(ev[2], ts), "event");
       hip_check(hipStreamWaitEvent(s, ev[2], 0), "wait");
       hip_check(hipMemcpyAsync(idx->loss_curve.data(), losses, (size_t)nsteps * 4,
@@ -235,7 +255,7 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
     info.fit_ms = ms;
     info.steps = nsteps;
     info.loss_first = nsteps ? idx->loss_curve.front() : 0.0f;
-    info.loss_last = nsteps ? idx->loss_curve.back() : 0.0f;
+    info.loss_last = nsteps ? best_loss : 0.0f;
     double sum_eps = 0.0, sum_win = 0.0;
     uint64_t counted = 0;
     for (uint32_t l = 0; l < idx->nleaves; ++l) {
@@ -265,51 +285,36 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
     index_free(idx);
     throw;
   }
-  (void)hipGraphExecDestroy(gexec);
-  (void)hipGraphDestroy(graph);
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
   if (ts) (void)hipStreamDestroy(ts);
-  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
   return idx;
 }
 
 TileOut learned_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const WeightedSpec* w) {
   sd_ctx* c = cl.c;
   hipStream_t s = cl.s;
-  TileOut out;
   const Packed p = pack_and_count(cl, q, k);
   const uint64_t nk = p.nkeys;
   cl.tm.mark("q_pack_scan", (double)q.n * 56, 2);
   const int learned = c->probe == 0 ? 1 : 0;
-  uint64_t ccap = nk / 4 + 65536;
-  uint64_t* cand = dalloc_t<uint64_t>(c, ccap);
-  cl.sc.blocks.push_back(cand);
-  unsigned long long* ccount = reinterpret_cast<unsigned long long*>(cl.counters + CNT_CAND);
   unsigned long long* steps = reinterpret_cast<unsigned long long*>(cl.counters + CNT_STEPS);
-  auto probe = [&]() {
-    launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, s);
-    launch_fill_u64(reinterpret_cast<uint64_t*>(steps), 0, 1, s);
-    launch_probe(p.seq, p.voff, q.n, idx->keys, idx->kid, idx->n_keys, learned, idx->coord,
-                 idx->params, idx->nleaves, idx->leaves, cand, ccap, ccount, steps, s);
-  };
-  probe();
-  auto counts = [&](uint64_t* got) {  // candidates and comparisons, one read-back
-    const char* h = static_cast<const char*>(
-        readback(c, cl.counters + CNT_CAND, (CNT_STEPS + 2 - CNT_CAND) * 4, s));
-    std::memcpy(&got[0], h, 8);
-    std::memcpy(&got[1], h + (CNT_STEPS - CNT_CAND) * 4, 8);
-  };
-  uint64_t got[2];
-  counts(got);
-  if (got[0] > ccap) {  // the capacity guess was too small: grow and probe again
-    ccap = got[0];
-    cand = dalloc_t<uint64_t>(c, ccap);
-    cl.sc.blocks.push_back(cand);
-    probe();
-    counts(got);
-  }
-  const uint64_t nc = got[0];
-  c->stats.n_probe_steps += (int64_t)got[1];
-  cl.tm.mark("probe", (double)nk * 16 + (double)nc * 12, 1);
+  Cands cp = sharded_output(
+      cl, nk / 4, "probe",
+      [&](const ShardArgs& out) {
+        launch_fill_u64(reinterpret_cast<uint64_t*>(steps), 0, 1, s);
+        launch_probe(p.seq, p.voff, q.n, idx->keys, idx->kid, idx->n_keys, learned, idx->coord,
+                     idx->coord_rows, idx->params, idx->nleaves, idx->leaves, out, steps, s);
+      },
+      [&](uint64_t n) { return (double)nk * 16 + (double)n * 12; });
+  cl.sc.blocks.push_back(cp.p);
+  uint64_t* cand = cp.p;
+  const uint64_t nc = cp.n;
+  uint64_t nsteps;
+  std::memcpy(&nsteps, readback(c, steps, 8, s), 8);
+  c->stats.n_probe_steps += (int64_t)nsteps;
   TileOut v = verify_candidates(cl, p.seq, q.n, idx->ref_seq, idx->n_ref, cand, nc, k, w);
   v.nkeys = nk;
   v.ncand = nc;

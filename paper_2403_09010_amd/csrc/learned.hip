@@ -29,7 +29,9 @@
 //                      gradient per block
 //   k_grad_reduce      partial gradients summed in block order
 //   k_adam_step        the same sum, then one Adam update (device step count,
-//                      so a captured graph of training steps can be replayed)
+//                      so a captured graph of training steps can be replayed);
+//                      the parameters with the lowest loss seen are kept
+//   k_adam_best        those parameters become the model
 //   k_leaf_range       first and last position of the keys of each leaf
 //   k_leaf_fit         the leaf lines
 //   k_leaf_eps         exact per-leaf worst error
@@ -53,34 +55,49 @@ struct Leaf {  // 32 bytes: one load per probe
 };
 static_assert(sizeof(Leaf) == 32, "leaf record size");
 
-// The coordinate model: tab[(L * 24 + t) * 20 + c] = (cumulative frequency of
-// residues below c, frequency of c) at position t of length-L keys, and
-// lencum[L] = share of keys shorter than L (lencum[25] = 1).
-struct Coord {
-  double2 tab[NL * KEY_MAX_LEN * NR];
-  double lencum[NL + 1];
-};
-
 // Residues that enter the coordinate: later ones refine it below the
 // resolution that separates the indexed keys (about 3.6 bits of entropy per
 // residue), and a fixed count lets every table load issue at once.
 constexpr int COORD_RES = 12;
+constexpr int ROW = COORD_RES * NR;  // table entries per key length
 
-// Not inlined: the build and the lookups must run the same instructions.
-__device__ __noinline__ double key_coord(const Coord* __restrict__ cm, u128 key) {
+// The coordinate model: lencum[L] = share of keys shorter than L
+// (lencum[25] = 1); for lengths lmin..lmax that occur in the index,
+// rows[(L - lmin) * ROW + t * 20 + c] = (cumulative frequency of residues
+// below c, frequency of c) at position t < 12 of length-L keys. FP32 table
+// entries keep the rows of every length within 48 KB, so a lookup kernel
+// holds them in LDS; the coordinate itself is accumulated in FP64.
+struct Coord {
+  double lencum[NL + 1];
+  uint32_t lmin, lmax;
+  float2 rows[NL * ROW];
+};
+
+// Not inlined: the build and the lookups must run the same instructions
+// (the build reads the tables from global memory, a lookup from LDS).
+__device__ __noinline__ double key_coord(const double* __restrict__ lencum,
+                                         const float2* __restrict__ rows, uint32_t lmin,
+                                         uint32_t lmax, u128 key) {
   const uint32_t L = key_len(key);
-  const double2* row = cm->tab + (size_t)L * KEY_MAX_LEN * NR;
-  double2 e[COORD_RES];
+  double x = 0.0;
+  if (L >= lmin && L <= lmax) {
+    const float2* row = rows + (size_t)(L - lmin) * ROW;
+    float2 e[COORD_RES];
 #pragma unroll
-  for (int t = 0; t < COORD_RES; ++t)
-    e[t] = (uint32_t)t < L ? row[t * NR + key_residue(key, t)] : make_double2(0.0, 1.0);
-  double x = 0.0, w = 1.0;
+    for (int t = 0; t < COORD_RES; ++t)
+      e[t] = (uint32_t)t < L ? row[t * NR + key_residue(key, t)] : make_float2(0.0f, 1.0f);
+    double w = 1.0;
 #pragma unroll
-  for (int t = 0; t < COORD_RES; ++t) {
-    x = fma(w, e[t].x, x);
-    w = w * e[t].y;
+    for (int t = 0; t < COORD_RES; ++t) {
+      x = fma(w, (double)e[t].x, x);
+      w = w * (double)e[t].y;
+    }
   }
-  return fma(cm->lencum[L + 1] - cm->lencum[L], x, cm->lencum[L]);
+  return fma(lencum[L + 1] - lencum[L], x, lencum[L]);
+}
+
+__device__ __forceinline__ double key_coord(const Coord* __restrict__ cm, u128 key) {
+  return key_coord(cm->lencum, cm->rows, cm->lmin, cm->lmax, key);
 }
 
 __device__ __noinline__ float mlp_forward(const float* __restrict__ p, float x) {
@@ -217,20 +234,38 @@ __global__ void k_grad_reduce(const float* __restrict__ partial, uint32_t nblock
   if (t <= NP) out[t] = sum_partials(partial, nblocks, t);
 }
 
-// state[0] = steps taken, state[1 .. NP] = first moments, state[NP+1 .. 2NP]
-// = second moments; loss_out[step] = the loss of the step's gradient pass
+// Adam state: state[0] = steps taken, [1, 1 + NP) first moments,
+// [1 + NP, 1 + 2 NP) second moments, [1 + 2 NP] the lowest loss seen,
+// [2 + 2 NP, 2 + 3 NP) the parameters that had it.
+constexpr int ADAM_STATE = 3 * NP + 2;
+
+// One Adam step from the block partials. The partials hold the gradient and
+// loss of the current parameters: if that loss is the lowest so far, the
+// parameters are kept before they are updated. With update == 0 only that
+// bookkeeping runs (the evaluation after the last step). loss_out[step]
+// receives the loss of each step's gradient pass.
 __global__ void k_adam_step(float* __restrict__ p, float* __restrict__ state,
                             const float* __restrict__ partial, uint32_t nblocks, float lr,
-                            float* __restrict__ loss_out, uint32_t loss_cap) {
+                            int update, float* __restrict__ loss_out, uint32_t loss_cap) {
+  __shared__ float s_g[NP + 1];
+  __shared__ int s_better;
   const int t = threadIdx.x;
   const float step = state[0] + 1.0f;
-  if (t <= NP) {
-    const float gsum = sum_partials(partial, nblocks, t);
-    if (t == NP) {
-      const uint32_t si = (uint32_t)step - 1u;
-      if (si < loss_cap) loss_out[si] = gsum;
-    } else {
-      const float b1 = 0.9f, b2 = 0.999f;
+  if (t <= NP) s_g[t] = sum_partials(partial, nblocks, t);
+  __syncthreads();
+  if (t == 0) {
+    const float loss = s_g[NP];
+    const uint32_t si = (uint32_t)step - 1u;
+    if (update && si < loss_cap) loss_out[si] = loss;
+    const float best = state[1 + 2 * NP];
+    s_better = (state[0] == 0.0f || loss < best) ? 1 : 0;  // NaN never counts as better
+    if (s_better) state[1 + 2 * NP] = loss;
+  }
+  __syncthreads();
+  if (t < NP) {
+    if (s_better) state[2 + 2 * NP + t] = p[t];
+    if (update) {
+      const float b1 = 0.9f, b2 = 0.999f, gsum = s_g[t];
       const float m = b1 * state[1 + t] + (1.0f - b1) * gsum;
       const float v = b2 * state[1 + NP + t] + (1.0f - b2) * gsum * gsum;
       state[1 + t] = m;
@@ -240,7 +275,13 @@ __global__ void k_adam_step(float* __restrict__ p, float* __restrict__ state,
     }
   }
   __syncthreads();  // every thread has read state[0]
-  if (t == 0) state[0] = step;
+  if (t == 0 && update) state[0] = step;
+}
+
+// The parameters with the lowest loss seen become the model.
+__global__ void k_adam_best(float* __restrict__ p, const float* __restrict__ state) {
+  const int t = threadIdx.x;
+  if (t < NP) p[t] = state[2 + 2 * NP + t];
 }
 
 // ------------------------------------------------------------------ leaves
@@ -327,31 +368,76 @@ __global__ __launch_bounds__(LNT) void k_leaf_eps(const u128* __restrict__ keys,
 
 // ------------------------------------------------------------------ probe
 
+// First index in (lb, b] whose key differs from keys[lb] == key (or b):
+// galloping from lb, then a binary search of the last step, so a run of c
+// equal keys costs O(log c) reads instead of c.
+__device__ __forceinline__ uint64_t run_end(const u128* __restrict__ keys, uint64_t lb,
+                                            uint64_t b, u128 key) {
+  uint64_t eq = lb, step = 1, hi;
+  while (true) {
+    const uint64_t pr = eq + step;
+    if (pr >= b) {
+      hi = b;
+      break;
+    }
+    if (keys[pr] != key) {
+      hi = pr;
+      break;
+    }
+    eq = pr;
+    step <<= 1;
+  }
+  uint64_t lo = eq + 1;  // keys[eq] == key; the first difference is in [lo, hi]
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (keys[mid] == key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 constexpr int PB_SEQS = 64;
 
+// One workgroup per 64 query sequences; each wave walks the variants of its
+// own 16 of them, 64 at a time, with no block-wide barrier after the start:
+// a lane generates its variant, predicts its position (coordinate tables in
+// LDS) and binary-searches the model's window (or the whole array); the
+// wave reserves output slots for its matches with one atomic and writes them
+// together. Dynamic LDS: lencum (26 doubles) then the used table rows.
 __global__ __launch_bounds__(LNT) void k_probe(
     const u128* __restrict__ qseq, const uint64_t* __restrict__ qvoff, uint64_t nq,
     const u128* __restrict__ keys, const uint32_t* __restrict__ kid, uint64_t n, int learned,
     const Coord* __restrict__ cm, const float* __restrict__ p, uint32_t nleaves,
-    const Leaf* __restrict__ leaves, uint64_t* __restrict__ cand, uint64_t cap,
-    unsigned long long* __restrict__ ccount, unsigned long long* __restrict__ steps_total) {
+    const Leaf* __restrict__ leaves, ShardOut out, unsigned long long* __restrict__ steps_total) {
+  extern __shared__ __align__(16) unsigned char s_dyn[];
   __shared__ uint64_t s_off[PB_SEQS + 1];
   __shared__ u128 s_seq[PB_SEQS];
-  __shared__ uint32_t s_tmp[LNT / 64];
-  __shared__ unsigned long long s_base;
+  double* s_lencum = reinterpret_cast<double*>(s_dyn);
+  float2* s_rows = reinterpret_cast<float2*>(s_dyn + (NL + 1) * sizeof(double));
   const uint64_t s0 = (uint64_t)blockIdx.x * PB_SEQS;
   const uint32_t ns = (uint32_t)min<uint64_t>(PB_SEQS, nq - s0);
   for (uint32_t x = threadIdx.x; x <= ns; x += LNT) s_off[x] = qvoff[s0 + x];
   for (uint32_t x = threadIdx.x; x < ns; x += LNT) s_seq[x] = qseq[s0 + x];
+  const uint32_t lmin = cm->lmin, lmax = cm->lmax;
+  if (learned) {
+    for (uint32_t x = threadIdx.x; x <= (uint32_t)NL; x += LNT) s_lencum[x] = cm->lencum[x];
+    const uint32_t nrow = lmax >= lmin ? (lmax - lmin + 1) * ROW : 0;
+    for (uint32_t x = threadIdx.x; x < nrow; x += LNT) s_rows[x] = cm->rows[x];
+  }
   __syncthreads();
-  const uint64_t g0 = s_off[0], g1 = s_off[ns];
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  constexpr uint32_t PER_WAVE = PB_SEQS / (LNT / 64);
+  const uint32_t xa = min(w * PER_WAVE, ns), xb = min(xa + PER_WAVE, ns);
+  const uint64_t wa = s_off[xa], wb = s_off[xb];
   uint32_t steps = 0;
-  for (uint64_t r0 = g0; r0 < g1; r0 += LNT) {
-    const uint64_t g = r0 + threadIdx.x;
+  for (uint64_t r0 = wa; r0 < wb; r0 += 64) {
+    const uint64_t g = r0 + lane;
     uint64_t lb = 0;
     uint32_t cnt = 0, q = 0;
-    if (g < g1) {
-      uint32_t lo = 0, hi = ns - 1;  // the sequence whose variants hold g
+    if (g < wb) {
+      uint32_t lo = xa, hi = xb - 1;  // the sequence whose variants hold g
       while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
         if (s_off[mid] <= g)
@@ -361,44 +447,64 @@ __global__ __launch_bounds__(LNT) void k_probe(
       }
       q = (uint32_t)(s0 + lo);
       const u128 key = key_variant(s_seq[lo], (uint32_t)(g - s_off[lo]));
-      uint64_t a = 0, b = n;
+      uint64_t a = 0, b = n;    // the window; b also bounds the run of equal keys
+      uint64_t sa = 0, sb = n;  // the lower bound lies in [sa, sb]
       if (learned) {
-        const double c = key_coord(cm, key);
+        const double c = key_coord(s_lencum, s_rows, lmin, lmax, key);
         const Leaf f = leaves[leaf_of(p, nleaves, c)];
+        int64_t pr = 0;
         if (f.lo > f.hi) {
           b = 0;  // no indexed key is sent to this leaf, so the key is absent
         } else {
-          const int64_t pr = leaf_predict(f, c);
-          const int64_t wa = pr - (int64_t)f.eps, wb = pr + (int64_t)f.eps + 1;
-          a = wa < 0 ? 0 : (uint64_t)wa;
-          b = wb < 0 ? 0 : ((uint64_t)wb > n ? n : (uint64_t)wb);
+          pr = leaf_predict(f, c);
+          const int64_t ua = pr - (int64_t)f.eps, ub = pr + (int64_t)f.eps + 1;
+          a = ua < 0 ? 0 : (uint64_t)ua;
+          b = ub < 0 ? 0 : ((uint64_t)ub > n ? n : (uint64_t)ub);
           if (a > b) a = b;
         }
+        sa = a;
+        sb = b;
       }
-      uint64_t hi_b = b;
-      while (a < hi_b) {  // lower bound of key in [a, b)
-        const uint64_t mid = (a + hi_b) >> 1;
+      while (sa < sb) {  // lower bound of key in [sa, sb]
+        const uint64_t mid = (sa + sb) >> 1;
         ++steps;
         if (keys[mid] < key)
-          a = mid + 1;
+          sa = mid + 1;
         else
-          hi_b = mid;
+          sb = mid;
       }
-      lb = a;
-      while (lb + cnt < b && keys[lb + cnt] == key) ++cnt;
+      lb = sa;
+      if (lb < b && keys[lb] == key) cnt = (uint32_t)(run_end(keys, lb, b, key) - lb);
     }
-    uint32_t total;
-    const uint32_t excl = block_excl_scan<LNT>(cnt, s_tmp, &total);
-    if (threadIdx.x == 0) s_base = total ? atomicAdd(ccount, (unsigned long long)total) : 0ull;
-    __syncthreads();
-    uint64_t pos = s_base + excl;
-    for (uint32_t x = 0; x < cnt; ++x, ++pos)
-      if (pos < cap) cand[pos] = ((uint64_t)q << 32) | kid[lb + x];
-    __syncthreads();  // s_base is rewritten by the next round
+    // the wave's matches, written together: output slot t belongs to the
+    // lane whose inclusive count first exceeds t
+    const uint64_t incl = wave_incl_scan((uint64_t)cnt);
+    const uint64_t wtot = __shfl(incl, 63, 64);
+    if (wtot) {  // one reservation per wave with matches, in the wave's own shard
+      const uint32_t sel = blockIdx.x * (LNT / 64) + w;
+      ShardResv r{0, 0};
+      if (lane == 63) r = shard_reserve(out, sel, wtot);
+      r.pos = __shfl(r.pos, 63, 64);
+      r.obase = __shfl(r.obase, 63, 64);
+      for (uint64_t t0 = 0; t0 < wtot; t0 += 64) {
+        const uint64_t t = t0 + lane;
+        uint32_t lo = 0, hi = 63;
+        while (lo < hi) {  // the same number of steps in every lane
+          const uint32_t mid = (lo + hi) >> 1;
+          if (__shfl(incl, (int)mid, 64) <= t)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        const uint64_t olb = __shfl(lb, (int)lo, 64);
+        const uint64_t oex = __shfl(incl, (int)lo, 64) - __shfl((uint64_t)cnt, (int)lo, 64);
+        const uint32_t oq = __shfl(q, (int)lo, 64);
+        if (t < wtot) shard_put(out, sel, r, t, ((uint64_t)oq << 32) | kid[olb + (t - oex)]);
+      }
+    }
   }
-  uint32_t tot;
-  (void)block_excl_scan<LNT>(steps, s_tmp, &tot);
-  if (threadIdx.x == 0 && tot) atomicAdd(steps_total, (unsigned long long)tot);
+  const uint32_t wsteps = __shfl(wave_incl_scan(steps), 63, 64);
+  if (lane == 0 && wsteps) atomicAdd(steps_total, (unsigned long long)wsteps);
 }
 
 }  // namespace sdk
@@ -413,6 +519,11 @@ static unsigned grid_for(uint64_t n) {
 size_t leaf_bytes() { return sizeof(sdk::Leaf); }
 size_t coord_bytes() { return sizeof(sdk::Coord); }
 int coord_lengths() { return sdk::NL; }
+int coord_res() { return sdk::COORD_RES; }
+void coord_offsets(size_t* lmin_off, size_t* rows_off) {
+  *lmin_off = offsetof(sdk::Coord, lmin);
+  *rows_off = offsetof(sdk::Coord, rows);
+}
 
 void launch_interleave(const uint64_t* hi, const uint64_t* lo, uint64_t n, u128* out, hipStream_t s) {
   if (!n) return;
@@ -449,10 +560,16 @@ void launch_grad_reduce(const float* partial, uint32_t nblocks, float* out, hipS
   hipLaunchKernelGGL(sdk::k_grad_reduce, dim3(1), dim3(128), 0, s, partial, nblocks, out);
 }
 
+int adam_state_floats() { return sdk::ADAM_STATE; }
+
 void launch_adam_step(float* p, float* state, const float* partial, uint32_t nblocks, float lr,
-                      float* loss_out, uint32_t loss_cap, hipStream_t s) {
+                      int update, float* loss_out, uint32_t loss_cap, hipStream_t s) {
   hipLaunchKernelGGL(sdk::k_adam_step, dim3(1), dim3(128), 0, s, p, state, partial, nblocks, lr,
-                     loss_out, loss_cap);
+                     update, loss_out, loss_cap);
+}
+
+void launch_adam_best(float* p, const float* state, hipStream_t s) {
+  hipLaunchKernelGGL(sdk::k_adam_best, dim3(1), dim3(128), 0, s, p, state);
 }
 
 void launch_leaf_fit_all(const u128* keys, uint64_t n, const void* coord, const float* p,
@@ -469,14 +586,19 @@ void launch_leaf_fit_all(const u128* keys, uint64_t n, const void* coord, const 
 }
 
 void launch_probe(const u128* qseq, const uint64_t* qvoff, uint64_t nq, const u128* keys,
-                  const uint32_t* kid, uint64_t n, int learned, const void* coord, const float* p,
-                  uint32_t nleaves, const void* leaves, uint64_t* cand, uint64_t cap,
-                  unsigned long long* ccount, unsigned long long* steps, hipStream_t s) {
+                  const uint32_t* kid, uint64_t n, int learned, const void* coord,
+                  uint32_t coord_lengths_used, const float* p, uint32_t nleaves,
+                  const void* leaves, const ShardArgs& a, unsigned long long* steps,
+                  hipStream_t s) {
   if (!nq) return;
+  const ShardOut out{a.base, a.region, a.over, a.over_cap, a.counter};
+  // the learned lookups stage the coordinate rows of lengths lmin..lmax in LDS
+  const size_t lds = (sdk::NL + 1) * sizeof(double) +
+                     (size_t)coord_lengths_used * sdk::ROW * sizeof(float2);
   hipLaunchKernelGGL(sdk::k_probe, dim3((unsigned)((nq + sdk::PB_SEQS - 1) / sdk::PB_SEQS)),
-                     dim3(sdk::LNT), 0, s, qseq, qvoff, nq, keys, kid, n, learned,
+                     dim3(sdk::LNT), learned ? lds : 0, s, qseq, qvoff, nq, keys, kid, n, learned,
                      static_cast<const sdk::Coord*>(coord), p, nleaves,
-                     static_cast<const sdk::Leaf*>(leaves), cand, cap, ccount, steps);
+                     static_cast<const sdk::Leaf*>(leaves), out, steps);
 }
 
 }  // namespace sd

@@ -174,35 +174,18 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   const double mean_seg = (double)nk / nseg;
   const uint32_t spw =
       (uint32_t)std::max(1.0, std::floor(0.8 * cap / std::max(mean_seg, 1.0) + 0.5));
-  uint64_t ccap = nk / 16 + 65536;
-  const uint64_t ccap0 = ccap;
-  Cands cand;
-  cand.p = dalloc_t<uint64_t>(c, ccap);
   const uint64_t nbig_cap = nk / cap + 2;
   uint64_t* big = cl.sc.get<uint64_t>(2 * nbig_cap);
-  unsigned long long* ccount = reinterpret_cast<unsigned long long*>(cl.counters + CNT_CAND);
   unsigned long long* nbig = reinterpret_cast<unsigned long long*>(cl.counters + CNT_NBIG);
-  launch_group_seg(cap, E, seg_start, seg_end, nseg, spw, idbits, cand.p, ccap, ccount, big, nbig,
-                   s);
-  uint64_t nc, nb;
-  {
-    const uint32_t* h = static_cast<const uint32_t*>(
-        readback(c, cl.counters + CNT_CAND, (CNT_NBIG + 2 - CNT_CAND) * 4, s));
-    std::memcpy(&nc, h, 8);
-    std::memcpy(&nb, h + (CNT_NBIG - CNT_CAND), 8);
-  }
-  if (nc > ccap) {  // capacity guess too small: grow and group again
-    dfree(c, cand.p);
-    cand.p = nullptr;
-    ccap = nc;
-    cand.p = dalloc_t<uint64_t>(c, ccap);
-    launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, s);
-    launch_fill_u64(reinterpret_cast<uint64_t*>(nbig), 0, 1, s);
-    launch_group_seg(cap, E, seg_start, seg_end, nseg, spw, idbits, cand.p, ccap, ccount, big,
-                     nbig, s);
-  }
-  cand.n = nc;
-  cl.tm.mark("group_local", (double)nk * 8 + (double)nc * 8, nc > ccap0 ? 2 : 1);
+  Cands cand = sharded_output(
+      cl, nk / 24, "group_local",
+      [&](const ShardArgs& out) {
+        launch_fill_u64(reinterpret_cast<uint64_t*>(nbig), 0, 1, s);
+        launch_group_seg(cap, E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
+      },
+      [&](uint64_t n) { return (double)nk * 8 + (double)n * 8; });
+  uint64_t nb;
+  std::memcpy(&nb, readback(c, nbig, 8, s), 8);
   c->stats.n_big_segments = (int64_t)nb;
   if (nb) {
     Cands extra = oversized_group(cl, E, big, nb, idbits);

@@ -99,24 +99,17 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   cl.tm.mark("q_vargen_passes", (double)nk * (8 + 16 * digits.size() + 8), 2 + (int)digits.size());
 
   // join against the index
-  uint64_t ccap = nk / 8 + 65536;
-  uint64_t* cand = dalloc_t<uint64_t>(c, ccap);
-  cl.sc.blocks.push_back(cand);
-  unsigned long long* ccount = reinterpret_cast<unsigned long long*>(cl.counters + CNT_CAND);
-  launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, s);
-  launch_join_seg(idx->E, idx->seg_start, idx->seg_end, Eq, qs, qe, nseg, idx->idbits,
-                  JOIN_LDS_MIN_Q, cand, ccap, ccount, s);
-  uint64_t nc = *static_cast<const uint64_t*>(readback(c, ccount, 8, s));
-  if (nc > ccap) {
-    cand = dalloc_t<uint64_t>(c, nc);
-    cl.sc.blocks.push_back(cand);
-    ccap = nc;
-    launch_fill_u64(reinterpret_cast<uint64_t*>(ccount), 0, 1, s);
-    launch_join_seg(idx->E, idx->seg_start, idx->seg_end, Eq, qs, qe, nseg, idx->idbits,
-                    JOIN_LDS_MIN_Q, cand, ccap, ccount, s);
-  }
+  Cands cj = sharded_output(
+      cl, nk / 4, "join",
+      [&](const ShardArgs& out) {
+        launch_join_seg(idx->E, idx->seg_start, idx->seg_end, Eq, qs, qe, nseg, idx->idbits,
+                        JOIN_LDS_MIN_Q, out, s);
+      },
+      [&](uint64_t n) { return (double)nk * 8 + (double)n * 8; });
+  cl.sc.blocks.push_back(cj.p);
+  uint64_t* cand = cj.p;
+  const uint64_t nc = cj.n;
   out.ncand = nc;
-  cl.tm.mark("join", (double)nk * 8 + (double)nc * 8, 1);
   TileOut v = verify_candidates(cl, p.seq, q.n, idx->ref_seq, idx->n_ref, cand, nc, k, w);
   v.nkeys = out.nkeys;
   v.ncand = nc;

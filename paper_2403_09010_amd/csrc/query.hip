@@ -76,16 +76,42 @@ __device__ __forceinline__ uint32_t lower_bound_hash(const uint64_t* a, uint32_t
   return lo;
 }
 
+// First index in (lb, m] whose hash differs from a[lb]'s (== h), by galloping
+// then a binary search of the last step.
+__device__ __forceinline__ uint32_t run_end_hash(const uint64_t* a, uint32_t lb, uint32_t m,
+                                                 uint64_t h, uint32_t idbits) {
+  uint32_t eq = lb, step = 1, hi;
+  while (true) {
+    const uint32_t pr = eq + step;
+    if (pr >= m || pr < eq) {
+      hi = m;
+      break;
+    }
+    if ((a[pr] >> idbits) != h) {
+      hi = pr;
+      break;
+    }
+    eq = pr;
+    step <<= 1;
+  }
+  uint32_t lo = eq + 1;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if ((a[mid] >> idbits) == h)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 template <int CAP>
 __global__ __launch_bounds__(QNT) void k_join_seg(
     const uint64_t* __restrict__ Er, const uint32_t* __restrict__ rseg_start,
     const uint32_t* __restrict__ rseg_end, const uint64_t* __restrict__ Eq,
     const uint32_t* __restrict__ qseg_start, const uint32_t* __restrict__ qseg_end,
-    uint32_t idbits, uint32_t lds_min_q, uint64_t* __restrict__ cand, uint64_t cap,
-    unsigned long long* __restrict__ ccount) {
+    uint32_t idbits, uint32_t lds_min_q, ShardOut out) {
   __shared__ uint64_t s_r[CAP];
-  __shared__ uint32_t s_tmp[QNT / 64];
-  __shared__ uint64_t s_base;
   const uint32_t v = blockIdx.x;
   const uint32_t qs = qseg_start[v], qe = qseg_end[v];
   if (qs == qe) return;
@@ -98,6 +124,7 @@ __global__ __launch_bounds__(QNT) void k_join_seg(
     __syncthreads();
   }
   const uint64_t idmask = (1ull << idbits) - 1;
+  const uint32_t lane = threadIdx.x & 63u;
   for (uint32_t c0 = qs; c0 < qe; c0 += QNT) {
     const uint32_t p = c0 + threadIdx.x;
     uint32_t lb = 0, cnt = 0;
@@ -105,27 +132,41 @@ __global__ __launch_bounds__(QNT) void k_join_seg(
     if (p < qe) {
       eq = Eq[p];
       const uint64_t h = eq >> idbits;
-      if (use_lds) {
-        lb = lower_bound_hash(s_r, 0, m, h, idbits);
-        while (lb + cnt < m && (s_r[lb + cnt] >> idbits) == h) ++cnt;
-      } else {
-        lb = lower_bound_hash(Er, rs, re, h, idbits) - rs;
-        while (lb + cnt < m && (Er[rs + lb + cnt] >> idbits) == h) ++cnt;
+      const uint64_t* a = use_lds ? s_r : Er + rs;
+      lb = lower_bound_hash(a, 0, m, h, idbits);
+      if (lb < m && (a[lb] >> idbits) == h) cnt = run_end_hash(a, lb, m, h, idbits) - lb;
+    }
+    // one reservation per wave with matches, in the wave's own shard; the
+    // wave writes its matches together (slot t belongs to the lane whose
+    // inclusive count first exceeds t)
+    const uint64_t incl = wave_incl_scan((uint64_t)cnt);
+    const uint64_t wtot = __shfl(incl, 63, 64);
+    if (wtot) {
+      const uint32_t sel = blockIdx.x * (QNT / 64) + (threadIdx.x >> 6);
+      ShardResv r{0, 0};
+      if (lane == 63u) r = shard_reserve(out, sel, wtot);
+      r.pos = __shfl(r.pos, 63, 64);
+      r.obase = __shfl(r.obase, 63, 64);
+      for (uint64_t t0 = 0; t0 < wtot; t0 += 64) {
+        const uint64_t t = t0 + lane;
+        uint32_t lo = 0, hi = 63;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (__shfl(incl, (int)mid, 64) <= t)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        const uint32_t olb = __shfl(lb, (int)lo, 64);
+        const uint64_t oex = __shfl(incl, (int)lo, 64) - __shfl((uint64_t)cnt, (int)lo, 64);
+        const uint64_t oq = __shfl(eq, (int)lo, 64);
+        if (t < wtot) {
+          const uint32_t x = olb + (uint32_t)(t - oex);
+          const uint64_t er = use_lds ? s_r[x] : Er[rs + x];
+          shard_put(out, sel, r, t, ((oq & idmask) << 32) | (er & idmask));
+        }
       }
     }
-    uint32_t total;
-    const uint32_t excl = block_excl_scan<QNT>(cnt, s_tmp, &total);
-    if (threadIdx.x == 0) s_base = total ? atomicAdd(ccount, (unsigned long long)total) : 0ull;
-    __syncthreads();
-    if (cnt) {
-      const uint64_t qid = (eq & idmask) << 32;
-      uint64_t pos = s_base + excl;
-      for (uint32_t x = 0; x < cnt; ++x, ++pos) {
-        const uint64_t er = use_lds ? s_r[lb + x] : Er[rs + lb + x];
-        if (pos < cap) cand[pos] = qid | (er & idmask);
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -307,11 +348,12 @@ int join_cap() { return JOIN_CAP; }
 
 void launch_join_seg(const uint64_t* Er, const uint32_t* rseg_start, const uint32_t* rseg_end,
                      const uint64_t* Eq, const uint32_t* qseg_start, const uint32_t* qseg_end,
-                     uint32_t nseg, uint32_t idbits, uint32_t lds_min_q, uint64_t* cand,
-                     uint64_t cap, unsigned long long* ccount, hipStream_t s) {
+                     uint32_t nseg, uint32_t idbits, uint32_t lds_min_q, const ShardArgs& a,
+                     hipStream_t s) {
   if (!nseg) return;
+  const ShardOut out{a.base, a.region, a.over, a.over_cap, a.counter};
   hipLaunchKernelGGL(sdk::k_join_seg<JOIN_CAP>, dim3(nseg), dim3(sdk::QNT), 0, s, Er, rseg_start,
-                     rseg_end, Eq, qseg_start, qseg_end, idbits, lds_min_q, cand, cap, ccount);
+                     rseg_end, Eq, qseg_start, qseg_end, idbits, lds_min_q, out);
 }
 
 uint64_t weighted_tile() { return (uint64_t)sdk::QNT * sdk::WITEMS; }

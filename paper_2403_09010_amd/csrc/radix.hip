@@ -284,6 +284,41 @@ __global__ __launch_bounds__(NT) void k_scan_excl(const uint32_t* __restrict__ i
   }
 }
 
+// Exclusive prefix of the shards' written counts min(counter[s], region);
+// one block of OUT_SHARDS threads. off[OUT_SHARDS] = the overflow's start.
+__global__ __launch_bounds__(OUT_SHARDS) void k_shard_offsets(
+    const unsigned long long* __restrict__ counter, uint64_t region, uint64_t* __restrict__ off) {
+  __shared__ uint64_t s_tmp[OUT_SHARDS / 64];
+  const uint64_t c = min((uint64_t)counter[threadIdx.x], region);
+  uint64_t total;
+  off[threadIdx.x] = block_excl_scan<OUT_SHARDS>(c, s_tmp, &total);
+  if (threadIdx.x == 0) off[OUT_SHARDS] = total;
+}
+
+// Shard s's written slots go to out at off[s] (block s); blocks OUT_SHARDS
+// and up copy the overflow after them, grid-stride.
+__global__ __launch_bounds__(256) void k_gather_shards(const uint64_t* __restrict__ base,
+                                                       uint64_t region,
+                                                       const uint64_t* __restrict__ over,
+                                                       uint64_t over_cap,
+                                                       const unsigned long long* __restrict__ counter,
+                                                       const uint64_t* __restrict__ off,
+                                                       uint64_t* __restrict__ out) {
+  const uint32_t sh = blockIdx.x;
+  if (sh < OUT_SHARDS) {
+    const uint64_t cnt = min((uint64_t)counter[sh], region);
+    const uint64_t* src = base + (uint64_t)sh * region;
+    uint64_t* dst = out + off[sh];
+    for (uint64_t x = threadIdx.x; x < cnt; x += 256) dst[x] = src[x];
+  } else {
+    const uint64_t cnt = min((uint64_t)counter[OUT_SHARDS], over_cap);
+    uint64_t* dst = out + off[OUT_SHARDS];
+    const uint64_t nb = gridDim.x - OUT_SHARDS;
+    for (uint64_t x = (uint64_t)(sh - OUT_SHARDS) * 256 + threadIdx.x; x < cnt; x += nb * 256)
+      dst[x] = over[x];
+  }
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
   for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (uint64_t)gridDim.x * blockDim.x)
@@ -312,6 +347,17 @@ static unsigned grid_for(uint64_t n, unsigned per_block, unsigned cap) {
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(sdk::k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+}
+
+uint32_t out_shards() { return OUT_SHARDS; }
+
+// off: OUT_SHARDS + 1 scratch words
+void launch_gather_shards(const uint64_t* base, uint64_t region, const uint64_t* over,
+                          uint64_t over_cap, const unsigned long long* counter, uint64_t* off,
+                          uint64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(sdk::k_shard_offsets, dim3(1), dim3(OUT_SHARDS), 0, s, counter, region, off);
+  hipLaunchKernelGGL(sdk::k_gather_shards, dim3(OUT_SHARDS + 256), dim3(256), 0, s, base, region,
+                     over, over_cap, counter, off, out);
 }
 
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {

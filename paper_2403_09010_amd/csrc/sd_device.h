@@ -110,6 +110,53 @@ __device__ __forceinline__ T block_excl_scan(T v, T* s_tmp, T* total) {
   return before + incl - v;
 }
 
+// ------------------------------------------------------------------ sharded output
+//
+// Variable-length output of many writers (candidate pairs, matches). One
+// global counter would serialise every reservation on one address, so the
+// output is split into OUT_SHARDS regions of `region` slots, each with its
+// own counter; a writer reserves in shard (sel % OUT_SHARDS). The part of a
+// reservation that runs past its region's end goes to a shared overflow
+// region (counter[OUT_SHARDS]); only if that overflows too are slots dropped,
+// which the host sees in the counters and answers by running the kernel
+// again with more room. The host then gathers everything into one array.
+constexpr uint32_t OUT_SHARDS = 1024;
+
+struct ShardOut {
+  uint64_t* base;               // OUT_SHARDS * region slots
+  uint64_t region;              // slots per shard
+  uint64_t* over;               // overflow slots
+  uint64_t over_cap;
+  unsigned long long* counter;  // OUT_SHARDS + 1 counters, zeroed before the kernel
+};
+
+// A reservation of cnt slots: slot j (0 <= j < cnt) is shard[pos + j] while
+// pos + j < region, else over[obase + (pos + j - max(pos, region))].
+struct ShardResv {
+  uint64_t pos, obase;
+};
+
+// Taken by one lane for its wave or block.
+__device__ __forceinline__ ShardResv shard_reserve(const ShardOut& o, uint32_t sel, uint64_t cnt) {
+  ShardResv r;
+  r.pos = atomicAdd(&o.counter[sel % OUT_SHARDS], (unsigned long long)cnt);
+  const uint64_t end = r.pos + cnt;
+  const uint64_t spill = end > o.region ? end - (r.pos > o.region ? r.pos : o.region) : 0;
+  r.obase = spill ? atomicAdd(&o.counter[OUT_SHARDS], (unsigned long long)spill) : 0;
+  return r;
+}
+
+__device__ __forceinline__ void shard_put(const ShardOut& o, uint32_t sel, const ShardResv& r,
+                                          uint64_t j, uint64_t v) {
+  const uint64_t gi = r.pos + j;
+  if (gi < o.region) {
+    o.base[(uint64_t)(sel % OUT_SHARDS) * o.region + gi] = v;
+  } else {
+    const uint64_t oi = r.obase + (gi - (r.pos > o.region ? r.pos : o.region));
+    if (oi < o.over_cap) o.over[oi] = v;
+  }
+}
+
 // ------------------------------------------------------------------ look-back
 //
 // Decoupled look-back (Merrill & Garland, "Single-pass parallel prefix scan

@@ -122,6 +122,50 @@ struct Cands {
   uint64_t n = 0;
 };
 
+// Host side of a sharded output (sd_device.h): `launch(args)` runs the
+// producing kernel against zeroed counters; reservations past a shard's
+// region spill into the overflow region, and only if that overflows too does
+// the kernel run again with more room. The stage is timed as `stage` with
+// bytes(total) algorithmic bytes; the regions are then gathered (stage
+// "gather_out") into one dense pool block owned by the caller. `guess` is the
+// expected total.
+template <class Launch, class Bytes>
+Cands sharded_output(Call& cl, uint64_t guess, const char* stage, Launch&& launch, Bytes&& bytes) {
+  const uint32_t NS = out_shards();
+  sd_ctx* c = cl.c;
+  // the size the same stage produced last time on this context, if larger
+  auto hint = c->out_hint.find(stage);
+  if (hint != c->out_hint.end()) guess = std::max(guess, hint->second);
+  const uint64_t region = guess / NS + guess / (2 * NS) + 16;
+  uint64_t over_cap = guess / 4 + 4096;
+  unsigned long long* ctr = cl.sc.get<unsigned long long>(NS + 1);
+  std::vector<unsigned long long> h(NS + 1);
+  ShardArgs a{};
+  int runs = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    a = ShardArgs{cl.sc.get<uint64_t>(region * NS), region, cl.sc.get<uint64_t>(over_cap),
+                  over_cap, ctr};
+    launch_fill_u64(reinterpret_cast<uint64_t*>(ctr), 0, NS + 1, cl.s);
+    launch(a);
+    ++runs;
+    std::memcpy(h.data(), readback(c, ctr, (NS + 1) * 8, cl.s), (NS + 1) * 8);
+    if (h[NS] <= over_cap) break;
+    if (attempt == 1) throw Error{SD_E_HIP, "internal error: output overflow region exceeded twice"};
+    over_cap = h[NS] + h[NS] / 8 + 4096;  // the same reservations spill the same amount again
+  }
+  Cands out;
+  for (uint32_t x = 0; x < NS; ++x) out.n += std::min<uint64_t>(h[x], region);
+  out.n += h[NS];
+  c->out_hint[stage] = out.n;
+  cl.tm.mark(stage, bytes(out.n), runs);
+  out.p = dalloc_t<uint64_t>(c, out.n);
+  if (out.n)
+    launch_gather_shards(a.base, a.region, a.over, a.over_cap, ctr, cl.sc.get<uint64_t>(NS + 1),
+                         out.p, cl.s);
+  cl.tm.mark("gather_out", (double)out.n * 16, out.n ? 2 : 0);
+  return out;
+}
+
 // Sorting digits over bits [lo, 64) of a 64-bit word, least significant first.
 inline std::vector<Digit> top_digits(int lo) {
   std::vector<Digit> d;

@@ -24,6 +24,18 @@ namespace sd {
 // ------------------------------------------------------------------ launchers
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+uint32_t out_shards();
+void launch_gather_shards(const uint64_t* base, uint64_t region, const uint64_t* over,
+                          uint64_t over_cap, const unsigned long long* counter, uint64_t* off,
+                          uint64_t* out, hipStream_t s);
+// a sharded output as passed to the producing kernels (sd_device.h ShardOut)
+struct ShardArgs {
+  uint64_t* base;
+  uint64_t region;
+  uint64_t* over;
+  uint64_t over_cap;
+  unsigned long long* counter;
+};
 void launch_radix_hist(const uint64_t* w0, const uint64_t* w1, int nwords, uint64_t n,
                        uint32_t* hist, hipStream_t s);
 uint64_t onesweep_tile(int nwords, bool has_val, int items);
@@ -59,8 +71,8 @@ void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_
                        uint32_t* seg_end, hipStream_t s);
 void launch_group_seg(int cap, const uint64_t* E, const uint32_t* seg_start,
                       const uint32_t* seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
-                      uint64_t* cand, uint64_t ccap, unsigned long long* ccount, uint64_t* big,
-                      unsigned long long* nbig, hipStream_t s);
+                      const ShardArgs& out, uint64_t* big, unsigned long long* nbig,
+                      hipStream_t s);
 void launch_gather_big(const uint64_t* E, const uint64_t* big, const uint64_t* out_off,
                        uint32_t nseg, uint64_t* out, hipStream_t s);
 void launch_emit_hash_runs(const uint64_t* E, uint64_t n, uint32_t idbits, uint64_t* cand,
@@ -76,8 +88,8 @@ void launch_unique_compact(const uint64_t* in, uint64_t n, uint64_t* out, uint64
 int join_cap();
 void launch_join_seg(const uint64_t* Er, const uint32_t* rseg_start, const uint32_t* rseg_end,
                      const uint64_t* Eq, const uint32_t* qseg_start, const uint32_t* qseg_end,
-                     uint32_t nseg, uint32_t idbits, uint32_t lds_min_q, uint64_t* cand,
-                     uint64_t cap, unsigned long long* ccount, hipStream_t s);
+                     uint32_t nseg, uint32_t idbits, uint32_t lds_min_q, const ShardArgs& out,
+                     hipStream_t s);
 uint64_t weighted_tile();
 void launch_verify_weighted(const uint64_t* cand, uint64_t c, const u128* sa, const u128* sb,
                             int k, const uint8_t* subst, uint32_t indel, uint32_t max_score,
@@ -93,6 +105,8 @@ void launch_slice_rebase(const uint32_t* qi, const uint32_t* rj, const uint8_t* 
 size_t leaf_bytes();
 size_t coord_bytes();
 int coord_lengths();
+int coord_res();
+void coord_offsets(size_t* lmin_off, size_t* rows_off);
 void launch_interleave(const uint64_t* hi, const uint64_t* lo, uint64_t n, u128* out, hipStream_t s);
 void launch_coord_counts(const u128* keys, uint64_t n, uint32_t S, uint32_t* counts, hipStream_t s);
 void launch_train_sample(const u128* keys, uint64_t n, uint32_t S, const void* coord, float* x,
@@ -101,14 +115,18 @@ uint32_t mlp_grad_blocks(uint32_t n);
 void launch_mlp_grad(const float* p, const float* x, const float* y, uint32_t n, float* partial,
                      hipStream_t s);
 void launch_grad_reduce(const float* partial, uint32_t nblocks, float* out, hipStream_t s);
+int adam_state_floats();
 void launch_adam_step(float* p, float* state, const float* partial, uint32_t nblocks, float lr,
-                      float* loss_out, uint32_t loss_cap, hipStream_t s);
+                      int update, float* loss_out, uint32_t loss_cap, hipStream_t s);
+void launch_adam_best(float* p, const float* state, hipStream_t s);
 void launch_leaf_fit_all(const u128* keys, uint64_t n, const void* coord, const float* p,
                          uint32_t nleaves, void* leaves, hipStream_t s);
+// coord_lengths_used: table rows of the model (lmax - lmin + 1, or 0)
 void launch_probe(const u128* qseq, const uint64_t* qvoff, uint64_t nq, const u128* keys,
-                  const uint32_t* kid, uint64_t n, int learned, const void* coord, const float* p,
-                  uint32_t nleaves, const void* leaves, uint64_t* cand, uint64_t cap,
-                  unsigned long long* ccount, unsigned long long* steps, hipStream_t s);
+                  const uint32_t* kid, uint64_t n, int learned, const void* coord,
+                  uint32_t coord_lengths_used, const float* p, uint32_t nleaves,
+                  const void* leaves, const ShardArgs& out, unsigned long long* steps,
+                  hipStream_t s);
 
 // ------------------------------------------------------------------ errors
 
@@ -145,6 +163,7 @@ struct sd_ctx {
   int sort_items = 0;  // keys-only radix passes: items per thread, 16 or 32 (0 = automatic)
   int64_t batch_tile_seqs = 0;  // query batches: sequences per tile (0 = automatic)
   int probe = 0;                // learned indexes: 0 model window, 1 whole-array binary search
+  std::map<std::string, uint64_t> out_hint;  // last output size of each sharded stage
   std::vector<hipEvent_t> events;
 };
 
@@ -169,6 +188,7 @@ struct sd_index {
   uint32_t* kid = nullptr;
   float* params = nullptr;  // device, SD_MLP_PARAMS floats
   void* coord = nullptr;    // device coordinate model (residue frequency tables)
+  uint32_t coord_rows = 0;  // key lengths with a table row (lmax - lmin + 1)
   void* leaves = nullptr;   // device leaf records
   uint32_t nleaves = 0;
   sd_learned_info info{};
