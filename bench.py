@@ -29,6 +29,10 @@ WORKLOADS = {
     "plain_10m_k2": ("plain_10m", 2),
 }
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counters, scaled by a
+# 1 GiB copy (profiles/traffic_hashed_path_plain_1m_k2.md), for the kernels and
+# workload they were taken on; other kernels and workloads report null
+TRAFFIC_PER_LAUNCH = {("plain_1m_k2", "k_onesweep_keys"): 2.259e9}
 # stages that time exactly one kernel (launched once, or several times alike)
 KERNEL_OF_STAGE = {
     "vargen_hash": "k_vargen_hash",
@@ -460,9 +464,12 @@ def main():
         per_launch_bytes = stage_bytes[stage] / launches
         per_launch_s = ms * 1e-3 / launches
         achieved = per_launch_bytes / per_launch_s / 1e9
+        traffic = TRAFFIC_PER_LAUNCH.get((args.workload, KERNEL_OF_STAGE[stage]))
+        if args.path or args.group_cap or args.group_bits or args.sort_items:
+            traffic = None  # the counters were taken with the default configuration
         return {"bound": "hbm", "kernel": KERNEL_OF_STAGE[stage], "stage": stage,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "launches_per_step": launches, "avg_launch_ms": round(per_launch_s * 1e3, 4),
                 "algorithmic_bytes_per_launch": per_launch_bytes}
 
