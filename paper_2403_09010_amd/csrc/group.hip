@@ -95,13 +95,32 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   }
   __syncthreads();
   const uint64_t idmask = (1ull << idbits) - 1;
-  for (uint64_t g = g0 + threadIdx.x; g < g1; g += VG_NT) {
-    const uint32_t x = s_map[g - g0];
-    const uint32_t v = (uint32_t)(g - s_off[x]);
-    const uint64_t e = (key_hash64(key_variant(s_seq[x], v)) & ~idmask) | (s0 + x);
-    elem[g] = e;
-    for (int q = 0; q < npass; ++q)
-      atomicAdd(&s_h[q * 256 + ((uint32_t)(e >> pd.shift[q]) & pd.mask[q])], 1u);
+  // four independent variants per thread and iteration, so their LDS reads
+  // and key arithmetic overlap
+  constexpr int ILP = 4;
+  for (uint64_t g = g0 + threadIdx.x; g < g1; g += VG_NT * ILP) {
+    uint32_t xs[ILP];
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) {
+      const uint64_t gg = g + (uint64_t)u * VG_NT;
+      xs[u] = gg < g1 ? s_map[gg - g0] : 0u;
+    }
+    uint64_t e[ILP];
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) {
+      const uint64_t gg = g + (uint64_t)u * VG_NT;
+      const uint32_t v = gg < g1 ? (uint32_t)(gg - s_off[xs[u]]) : 0u;
+      e[u] = (key_hash64(key_variant(s_seq[xs[u]], v)) & ~idmask) | (s0 + xs[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) {
+      const uint64_t gg = g + (uint64_t)u * VG_NT;
+      if (gg < g1) {
+        elem[gg] = e[u];
+        for (int q = 0; q < npass; ++q)
+          atomicAdd(&s_h[q * 256 + ((uint32_t)(e[u] >> pd.shift[q]) & pd.mask[q])], 1u);
+      }
+    }
   }
   __syncthreads();
   for (uint32_t x = threadIdx.x; x < (uint32_t)npass * 256; x += VG_NT)
@@ -253,15 +272,17 @@ __device__ void group_batch(const uint64_t (&e)[CAP / NTH], uint32_t m, uint32_t
 }
 
 // The next batch of a workgroup's segment range starting at segment v:
-// consecutive non-empty segments while they fit in CAP elements. A segment
-// larger than CAP is listed in big[] for the sort-and-runs fallback and
-// skipped. Returns false when the range is exhausted.
+// consecutive non-empty segments while they fit in CAP elements (returns 1).
+// A segment of CAP < size <= 2 CAP is returned alone (returns 2) to be
+// grouped in two halves by one more hash bit; a larger one is listed in
+// big[] for the sort-and-runs fallback and skipped. Returns 0 when the range
+// is exhausted.
 template <int CAP>
-__device__ __forceinline__ bool next_batch(const uint32_t* __restrict__ seg_start,
-                                           const uint32_t* __restrict__ seg_end, uint32_t& v,
-                                           uint32_t v1, uint32_t& a, uint32_t& b,
-                                           uint64_t* __restrict__ big,
-                                           unsigned long long* __restrict__ nbig) {
+__device__ __forceinline__ int next_batch(const uint32_t* __restrict__ seg_start,
+                                          const uint32_t* __restrict__ seg_end, uint32_t& v,
+                                          uint32_t v1, uint32_t& a, uint32_t& b, bool can_split,
+                                          uint64_t* __restrict__ big,
+                                          unsigned long long* __restrict__ nbig) {
   while (v < v1) {
     a = seg_start[v];
     b = seg_end[v];
@@ -270,12 +291,13 @@ __device__ __forceinline__ bool next_batch(const uint32_t* __restrict__ seg_star
       continue;
     }
     if (b - a > (uint32_t)CAP) {
+      ++v;
+      if (can_split && b - a <= 2u * CAP) return 2;
       if (threadIdx.x == 0) {
         const unsigned long long x = atomicAdd(nbig, 1ull);
         big[2 * x] = a;
         big[2 * x + 1] = b;
       }
-      ++v;
       continue;
     }
     uint32_t w = v + 1;
@@ -288,9 +310,34 @@ __device__ __forceinline__ bool next_batch(const uint32_t* __restrict__ seg_star
       ++w;
     }
     v = w;
-    return true;
+    return 1;
   }
-  return false;
+  return 0;
+}
+
+// Count (part < 0) or stably compact into s_e (part 0 or 1) the elements of
+// [a, b), b - a <= 2 CAP, whose hash bit `bit` equals part; thread t takes a
+// contiguous chunk so the compaction keeps the segment's order. Returns the
+// number of elements with the bit set (count) or compacted (part).
+template <int CAP, int NTH>
+__device__ uint32_t split_part(const uint64_t* __restrict__ E, uint32_t a, uint32_t b,
+                               uint32_t bit, int part, uint64_t* s_e, uint64_t* s_tmp64) {
+  const uint32_t n = b - a;
+  const uint32_t chunk = (n + NTH - 1) / NTH;
+  const uint32_t c0 = min(threadIdx.x * chunk, n), c1 = min(c0 + chunk, n);
+  const uint32_t want = part < 0 ? 1u : (uint32_t)part;
+  uint64_t mine = 0;
+  for (uint32_t x = c0; x < c1; ++x) mine += ((E[a + x] >> bit) & 1u) == want;
+  uint64_t total;
+  uint64_t pos = block_excl_scan<NTH>(mine, s_tmp64, &total);
+  if (part >= 0) {
+    for (uint32_t x = c0; x < c1; ++x) {
+      const uint64_t e = E[a + x];
+      if (((e >> bit) & 1u) == want) s_e[pos++] = e;
+    }
+  }
+  __syncthreads();
+  return (uint32_t)total;
 }
 
 // One workgroup per `spw` consecutive segment values, processed as batches;
@@ -300,37 +347,72 @@ template <int CAP, int NTH>
 __global__ __launch_bounds__(NTH) void k_group_seg(
     const uint64_t* __restrict__ E, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
-    ShardOut out, uint64_t* __restrict__ big, unsigned long long* __restrict__ nbig) {
+    uint32_t splitbit, ShardOut out, uint64_t* __restrict__ big,
+    unsigned long long* __restrict__ nbig) {
   constexpr int PER = CAP / NTH;
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ uint64_t s_tmp64[NTH / 64];
   __shared__ uint64_t s_base[2];
+  uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
+  const bool can_split = splitbit >= idbits && splitbit < 64;
   const uint32_t v0 = blockIdx.x * spw;
   const uint32_t v1 = min(v0 + spw, nseg);
   uint32_t v = v0, a = 0, b = 0;
-  bool have = next_batch<CAP>(seg_start, seg_end, v, v1, a, b, big, nbig);
+  int kind = next_batch<CAP>(seg_start, seg_end, v, v1, a, b, can_split, big, nbig);
   uint64_t cur[PER];
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
     const uint32_t x = threadIdx.x + r * NTH;
-    cur[r] = (have && x < b - a) ? E[a + x] : 0;
+    cur[r] = (kind == 1 && x < b - a) ? E[a + x] : 0;
   }
-  while (have) {
+  while (kind) {
+    if (kind == 2) {
+      // a segment of up to 2 CAP elements: equal hashes share every bit, so
+      // the halves by the next hash bit are grouped one after the other
+      const uint32_t ones = split_part<CAP, NTH>(E, a, b, splitbit, -1, s_e, s_tmp64);
+      const uint32_t zeros = (b - a) - ones;
+      if (ones > (uint32_t)CAP || zeros > (uint32_t)CAP) {
+        if (threadIdx.x == 0) {
+          const unsigned long long x = atomicAdd(nbig, 1ull);
+          big[2 * x] = a;
+          big[2 * x + 1] = b;
+        }
+      } else {
+        for (int part = 0; part < 2; ++part) {
+          const uint32_t m = split_part<CAP, NTH>(E, a, b, splitbit, part, s_e, s_tmp64);
+          uint64_t e[PER];
+#pragma unroll
+          for (int r = 0; r < PER; ++r) {
+            const uint32_t x = threadIdx.x + r * NTH;
+            e[r] = x < m ? s_e[x] : 0;
+          }
+          __syncthreads();
+          group_batch<CAP, NTH>(e, m, idbits, out, lds, s_tmp64, s_base);
+        }
+      }
+      kind = next_batch<CAP>(seg_start, seg_end, v, v1, a, b, can_split, big, nbig);
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const uint32_t x = threadIdx.x + r * NTH;
+        cur[r] = (kind == 1 && x < b - a) ? E[a + x] : 0;
+      }
+      continue;
+    }
     const uint32_t m = b - a;
     uint32_t na = 0, nb = 0;
-    const bool more = next_batch<CAP>(seg_start, seg_end, v, v1, na, nb, big, nbig);
+    const int nkind = next_batch<CAP>(seg_start, seg_end, v, v1, na, nb, can_split, big, nbig);
     uint64_t nxt[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const uint32_t x = threadIdx.x + r * NTH;
-      nxt[r] = (more && x < nb - na) ? E[na + x] : 0;
+      nxt[r] = (nkind == 1 && x < nb - na) ? E[na + x] : 0;
     }
     group_batch<CAP, NTH>(cur, m, idbits, out, lds, s_tmp64, s_base);
 #pragma unroll
     for (int r = 0; r < PER; ++r) cur[r] = nxt[r];
     a = na;
     b = nb;
-    have = more;
+    kind = nkind;
   }
 }
 
@@ -417,8 +499,9 @@ static size_t group_lds(int cap) { return (size_t)cap * sdk::GROUP_LDS_PER_ELEM;
 
 template <int CAP, int NTH>
 static void launch_group_t(const uint64_t* E, const uint32_t* ss, const uint32_t* se,
-                           uint32_t nseg, uint32_t spw, uint32_t idbits, const ShardArgs& a,
-                           uint64_t* big, unsigned long long* nbig, hipStream_t s) {
+                           uint32_t nseg, uint32_t spw, uint32_t idbits, uint32_t splitbit,
+                           const ShardArgs& a, uint64_t* big, unsigned long long* nbig,
+                           hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     attr = true;
@@ -430,28 +513,28 @@ static void launch_group_t(const uint64_t* E, const uint32_t* ss, const uint32_t
   const unsigned g = (nseg + spw - 1) / spw;
   const ShardOut out{a.base, a.region, a.over, a.over_cap, a.counter};
   hipLaunchKernelGGL((sdk::k_group_seg<CAP, NTH>), dim3(g), dim3(NTH), group_lds(CAP), s, E, ss,
-                     se, nseg, spw, idbits, out, big, nbig);
+                     se, nseg, spw, idbits, splitbit, out, big, nbig);
 }
 
 bool group_cap_supported(int cap) { return cap == 4096 || cap == 2048 || cap == 1024 || cap == 256; }
 
 void launch_group_seg(int cap, const uint64_t* E, const uint32_t* seg_start,
                       const uint32_t* seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
-                      const ShardArgs& out, uint64_t* big, unsigned long long* nbig,
-                      hipStream_t s) {
+                      uint32_t splitbit, const ShardArgs& out, uint64_t* big,
+                      unsigned long long* nbig, hipStream_t s) {
   if (!nseg) return;
   switch (cap) {
     case 4096:
-      launch_group_t<4096, 512>(E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
+      launch_group_t<4096, 512>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big, nbig, s);
       break;
     case 2048:
-      launch_group_t<2048, 256>(E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
+      launch_group_t<2048, 256>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big, nbig, s);
       break;
     case 1024:
-      launch_group_t<1024, 128>(E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
+      launch_group_t<1024, 128>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big, nbig, s);
       break;
     default:
-      launch_group_t<256, 64>(E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
+      launch_group_t<256, 64>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big, nbig, s);
       break;
   }
 }

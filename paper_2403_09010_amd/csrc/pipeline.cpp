@@ -181,7 +181,9 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
       cl, nk / 24, "group_local",
       [&](const ShardArgs& out) {
         launch_fill_u64(reinterpret_cast<uint64_t*>(nbig), 0, 1, s);
-        launch_group_seg(cap, E, seg_start, seg_end, nseg, spw, idbits, out, big, nbig, s);
+        const uint32_t splitbit = segshift >= 1 ? segshift - 1 : 64u;
+        launch_group_seg(cap, E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
+                         nbig, s);
       },
       [&](uint64_t n) { return (double)nk * 8 + (double)n * 8; });
   uint64_t nb;

@@ -69,10 +69,12 @@ void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, ui
 bool group_cap_supported(int cap);
 void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_t* seg_start,
                        uint32_t* seg_end, hipStream_t s);
+// splitbit: the hash bit below the segment bits (segments of up to 2 cap
+// elements are grouped in two halves by it); 64 disables splitting
 void launch_group_seg(int cap, const uint64_t* E, const uint32_t* seg_start,
                       const uint32_t* seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
-                      const ShardArgs& out, uint64_t* big, unsigned long long* nbig,
-                      hipStream_t s);
+                      uint32_t splitbit, const ShardArgs& out, uint64_t* big,
+                      unsigned long long* nbig, hipStream_t s);
 void launch_gather_big(const uint64_t* E, const uint64_t* big, const uint64_t* out_off,
                        uint32_t nseg, uint64_t* out, hipStream_t s);
 void launch_emit_hash_runs(const uint64_t* E, uint64_t n, uint32_t idbits, uint64_t* cand,
