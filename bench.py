@@ -369,6 +369,7 @@ def main():
     ap.add_argument("--group-cap", type=int, default=0, help="hashed path LDS capacity (0 auto)")
     ap.add_argument("--group-bits", type=int, default=0, help="hashed path hash bits (0 auto)")
     ap.add_argument("--sort-items", type=int, default=0, help="keys-only radix items/thread (0 auto)")
+    ap.add_argument("--group-batches", type=int, default=0, help="hashed path LDS batches per workgroup (0 auto)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this size first (a known-size kernel for counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -388,8 +389,8 @@ def main():
     import torch
     import cdr3gen
     from paper_2403_09010_amd import Context
-    from paper_2403_09010_amd.symdel import (OPT_GROUP_BITS, OPT_GROUP_CAP, OPT_PATH,
-                                             OPT_SORT_ITEMS, OPT_TIMING, _Seqs)
+    from paper_2403_09010_amd.symdel import (OPT_GROUP_BATCHES, OPT_GROUP_BITS, OPT_GROUP_CAP,
+                                             OPT_PATH, OPT_SORT_ITEMS, OPT_TIMING, _Seqs)
 
     gen_name, k = WORKLOADS[args.workload]
     log(f"generating {gen_name}")
@@ -404,6 +405,7 @@ def main():
     ctx.set_option(OPT_GROUP_CAP, args.group_cap)
     ctx.set_option(OPT_GROUP_BITS, args.group_bits)
     ctx.set_option(OPT_SORT_ITEMS, args.sort_items)
+    ctx.set_option(OPT_GROUP_BATCHES, args.group_batches)
     if args.copy_calibration_mb:
         src = torch.empty(args.copy_calibration_mb << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -465,7 +467,7 @@ def main():
         per_launch_s = ms * 1e-3 / launches
         achieved = per_launch_bytes / per_launch_s / 1e9
         traffic = TRAFFIC_PER_LAUNCH.get((args.workload, KERNEL_OF_STAGE[stage]))
-        if args.path or args.group_cap or args.group_bits or args.sort_items:
+        if args.path or args.group_cap or args.group_bits or args.sort_items or args.group_batches:
             traffic = None  # the counters were taken with the default configuration
         return {"bound": "hbm", "kernel": KERNEL_OF_STAGE[stage], "stage": stage,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -489,7 +491,7 @@ def main():
                    "pairs": int(npairs), "keys": st["n_keys"], "candidates_raw": st["n_cand_raw"],
                    "seconds_per_search": round(dt, 6), "path": args.path,
                    "group_cap": args.group_cap, "group_bits": args.group_bits,
-                   "sort_items": args.sort_items},
+                   "sort_items": args.sort_items, "group_batches": args.group_batches},
         "stages_ms": {s: round(stage_ms[s] / args.steps, 4) for s in stage_ms},
         "host_to_host": {"seconds_median_of_5": round(h2h_s, 6),
                          "pairs_per_s": round(npairs / h2h_s, 1)},

@@ -94,6 +94,7 @@ typedef struct {
 #define SD_OPT_SORT_ITEMS 5 /* keys-only radix passes: items per thread, 0 (automatic), 16 or 32 */
 #define SD_OPT_BATCH_TILE 6 /* query batches: at most this many query sequences per tile (0: 4Mi) */
 #define SD_OPT_PROBE 7      /* learned indexes: 0 = search the model's window, 1 = binary search over the whole index */
+#define SD_OPT_GROUP_BATCHES 8 /* hashed path: LDS batches each workgroup groups in sequence, 0 (automatic: 4) .. 64 */
 
 /*
  * Create a context on HIP device `device`. hbm_budget_bytes bounds the

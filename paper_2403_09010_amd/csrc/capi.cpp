@@ -240,6 +240,10 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
       if (value < 0) return SD_E_INVAL;
       c->batch_tile_seqs = value;
       return SD_OK;
+    case SD_OPT_GROUP_BATCHES:
+      if (value < 0 || value > 64) return SD_E_INVAL;
+      c->group_batches = (int)value;
+      return SD_OK;
     case SD_OPT_PROBE:
       if (value < 0 || value > 1) return SD_E_INVAL;
       c->probe = (int)value;

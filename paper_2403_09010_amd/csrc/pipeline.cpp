@@ -172,8 +172,12 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   launch_seg_bounds(E, nk, segshift, seg_start, seg_end, s);
   cl.tm.mark("seg_bounds", (double)nk * 8 + (double)nseg * 16, 3);
   const double mean_seg = (double)nk / nseg;
-  const uint32_t spw =
+  // segments per workgroup: about one LDS batch's worth, times the batches a
+  // workgroup runs in sequence (the next batch's loads overlap the current
+  // batch's grouping)
+  const uint32_t per_batch =
       (uint32_t)std::max(1.0, std::floor(0.8 * cap / std::max(mean_seg, 1.0) + 0.5));
+  const uint32_t spw = per_batch * (uint32_t)(c->group_batches ? c->group_batches : 4);
   const uint64_t nbig_cap = nk / cap + 2;
   uint64_t* big = cl.sc.get<uint64_t>(2 * nbig_cap);
   unsigned long long* nbig = reinterpret_cast<unsigned long long*>(cl.counters + CNT_NBIG);

@@ -162,6 +162,7 @@ struct sd_ctx {
   int path = 0;        // 0 automatic, 1 full-key sort, 2 hashed
   int group_cap = 0;   // hashed path: LDS batch capacity (0 = automatic)
   int group_bits = 0;  // hashed path: hash bits sorted by the LSD passes (0 = automatic)
+  int group_batches = 0;  // hashed path: LDS batches per workgroup (0 = automatic)
   int sort_items = 0;  // keys-only radix passes: items per thread, 16 or 32 (0 = automatic)
   int64_t batch_tile_seqs = 0;  // query batches: sequences per tile (0 = automatic)
   int probe = 0;                // learned indexes: 0 model window, 1 whole-array binary search

@@ -28,6 +28,7 @@ OPT_GROUP_BITS = 4
 OPT_SORT_ITEMS = 5
 OPT_BATCH_TILE = 6
 OPT_PROBE = 7
+OPT_GROUP_BATCHES = 8
 MAX_STAGES = 16
 MLP_HIDDEN = 32
 MLP_PARAMS = 3 * MLP_HIDDEN + 1
