@@ -130,22 +130,35 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
 // ------------------------------------------------------------------ segment bounds
 
 // After the LSD passes E is sorted by its top B bits (segshift = 64 - B; a
-// shift of 64 means one segment), so segment v is [seg_start[v], seg_end[v]);
-// both stay 0 when v does not occur.
+// shift of 64 means one segment), so segment v is [seg_start[v], seg_end[v])
+// with seg_start[v] the first position whose top bits are >= v. One thread
+// per boundary v in [0, nseg] finds it by binary search (the upper levels of
+// all searches share cache lines), which touches a few MB instead of reading
+// the whole array; an absent segment gets an empty range.
 __device__ __forceinline__ uint32_t seg_of(uint64_t e, uint32_t segshift) {
   return segshift >= 64 ? 0u : (uint32_t)(e >> segshift);
 }
 
-__global__ __launch_bounds__(256) void k_seg_bounds(const uint64_t* __restrict__ E, uint64_t n,
-                                                    uint32_t segshift,
+__global__ __launch_bounds__(256) void k_seg_bounds(const uint64_t* __restrict__ E, uint32_t n,
+                                                    uint32_t segshift, uint32_t nseg,
                                                     uint32_t* __restrict__ seg_start,
                                                     uint32_t* __restrict__ seg_end) {
-  for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < n;
-       p += (uint64_t)gridDim.x * 256) {
-    const uint32_t s = seg_of(E[p], segshift);
-    if (p == 0 || seg_of(E[p - 1], segshift) != s) seg_start[s] = (uint32_t)p;
-    if (p + 1 == n || seg_of(E[p + 1], segshift) != s) seg_end[s] = (uint32_t)(p + 1);
+  const uint32_t v = blockIdx.x * 256 + threadIdx.x;
+  if (v > nseg) return;
+  uint32_t lo = 0, hi = n;
+  if (v == nseg) {
+    lo = n;
+  } else {
+    while (lo < hi) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      if (seg_of(E[mid], segshift) < v)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
   }
+  if (v < nseg) seg_start[v] = lo;
+  if (v > 0) seg_end[v - 1] = lo;
 }
 
 // ------------------------------------------------------------------ local grouping
@@ -488,10 +501,9 @@ void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, ui
 
 void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_t* seg_start,
                        uint32_t* seg_end, hipStream_t s) {
-  if (!n) return;
-  uint64_t g = (n + 255) / 256;
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(sdk::k_seg_bounds, dim3((unsigned)g), dim3(256), 0, s, E, n, segshift,
+  const uint32_t nseg = segshift >= 64 ? 1u : (1u << (64u - segshift));
+  const uint32_t g = (nseg + 1 + 255) / 256;
+  hipLaunchKernelGGL(sdk::k_seg_bounds, dim3(g), dim3(256), 0, s, E, (uint32_t)n, segshift, nseg,
                      seg_start, seg_end);
 }
 

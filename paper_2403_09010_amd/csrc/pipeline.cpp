@@ -167,10 +167,8 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   const uint32_t segshift = 64u - (uint32_t)bits;
   uint32_t* seg_start = cl.sc.get<uint32_t>(nseg);
   uint32_t* seg_end = cl.sc.get<uint32_t>(nseg);
-  launch_fill_u32(seg_start, 0, nseg, s);
-  launch_fill_u32(seg_end, 0, nseg, s);
   launch_seg_bounds(E, nk, segshift, seg_start, seg_end, s);
-  cl.tm.mark("seg_bounds", (double)nk * 8 + (double)nseg * 16, 3);
+  cl.tm.mark("seg_bounds", (double)nseg * 8, 1);
   const double mean_seg = (double)nk / nseg;
   // segments per workgroup: about one LDS batch's worth, times the batches a
   // workgroup runs in sequence (the next batch's loads overlap the current

@@ -93,10 +93,8 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   const uint32_t nseg = 1u << bits;
   uint32_t* qs = cl.sc.get<uint32_t>(nseg);
   uint32_t* qe = cl.sc.get<uint32_t>(nseg);
-  launch_fill_u32(qs, 0, nseg, s);
-  launch_fill_u32(qe, 0, nseg, s);
   launch_seg_bounds(Eq, nk, 64u - (uint32_t)bits, qs, qe, s);
-  cl.tm.mark("q_vargen_passes", (double)nk * (8 + 16 * digits.size() + 8), 2 + (int)digits.size());
+  cl.tm.mark("q_vargen_passes", (double)nk * (8 + 16 * digits.size()), 2 + (int)digits.size());
 
   // join against the index
   Cands cj = sharded_output(
@@ -263,8 +261,6 @@ sd_index* index_build(sd_ctx* c, const sd_seqs* ref, int k, hipStream_t s) {
     idx->seg_end = static_cast<uint32_t*>(idx_alloc((size_t)nseg * 4));
     if (nk)
       hip_check(hipMemcpyAsync(idx->E, E, nk * 8, hipMemcpyDeviceToDevice, s), "copy index");
-    launch_fill_u32(idx->seg_start, 0, nseg, s);
-    launch_fill_u32(idx->seg_end, 0, nseg, s);
     launch_seg_bounds(idx->E, nk, 64u - (uint32_t)idx->bits, idx->seg_start, idx->seg_end, s);
     hip_check(hipStreamSynchronize(s), "synchronise");
     idx->bytes = idx->n_ref * 16 + nk * 8 + (uint64_t)nseg * 8;
