@@ -2,7 +2,7 @@
 // together without sorting the 128-bit keys themselves.
 //
 //   k_vargen_hash   every <= k-deletion variant of every sequence as one
-//                   64-bit element [hash of the exact key | sequence id],
+//                   64-bit element [hash of the variant | sequence id],
 //                   with 24 id bits (40 hash bits) up to 2^24 sequences and
 //                   32 id bits (32 hash bits) above; also the digit
 //                   histograms of the hash passes
@@ -25,26 +25,39 @@
 
 namespace sdk {
 
-// 64-bit hash of a key: two independent multiply-add forms of the four
-// 32-bit words, each through the murmur3 finaliser. Only the load balance and
-// the rate of extra candidates depend on its quality.
-__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
-  h ^= h >> 16;
-  h *= 0x85EBCA6Bu;
-  h ^= h >> 13;
-  h *= 0xC2B2AE35u;
-  h ^= h >> 16;
-  return h;
+// 64-bit hash of a string y of length m: h(y) = C[m] xor the XOR over
+// positions j of rotr(B[y_j], j), with B (per residue) and C (per length)
+// fixed pseudo-random words. Rotation commutes with XOR, so a residue that
+// moves one or two places left after a deletion changes its term by a left
+// rotation of 1 or 2: with the prefix XORs P[i] of the undeleted string, the
+// variant without positions p1 < p2 hashes to
+//   C[m] ^ P[p1] ^ rotl(P[p2] ^ P[p1 + 1], 1) ^ rotl(P[L] ^ P[p2 + 1], 2),
+// five LDS reads instead of rebuilding the 128-bit key. One deletion is the
+// case p2 = L, none the case p1 = L, p2 = L + 1 (P is constant past L). Only
+// the load balance and the rate of extra candidates depend on the hash.
+struct HashTab {
+  uint64_t b[32];  // per residue code
+  uint64_t c[32];  // per string length
+};
+
+// splitmix64 (Steele, Lea and Flood, 2014) as a compile-time generator
+constexpr uint64_t splitmix_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ uint64_t key_hash64(u128 key) {
-  const uint32_t w0 = (uint32_t)key, w1 = (uint32_t)(key >> 32);
-  const uint32_t w2 = (uint32_t)(key >> 64), w3 = (uint32_t)(key >> 96);
-  const uint32_t a = w0 * 0x9E3779B1u + w1 * 0x85EBCA77u + w2 * 0xC2B2AE3Du + w3 * 0x27D4EB2Fu;
-  const uint32_t b =
-      w0 * 0x165667B1u + w1 * 0xD3A2646Du + w2 * 0xFD7046C5u + w3 * 0xB55A4F09u + 0x61C88647u;
-  return ((uint64_t)fmix32(a) << 32) | fmix32(b);
+constexpr HashTab make_hash_tab() {
+  HashTab t{};
+  uint64_t state = 0x5D3E1B7A2C4F9081ull;
+  for (int x = 0; x < 32; ++x) t.b[x] = splitmix_next(state);
+  for (int x = 0; x < 32; ++x) t.c[x] = splitmix_next(state);
+  return t;
 }
+
+__constant__ HashTab kHashTab = make_hash_tab();
 
 // a mix of a stored hash for LDS table slots
 __device__ __forceinline__ uint32_t slot_mix(uint64_t h) {
@@ -70,6 +83,31 @@ struct PassDigits {
 
 // Variants of one block's sequences: at most VG_SEQS * V(24, 2) = 64 * 301.
 constexpr int VG_MAX_VARIANTS = VG_SEQS * 301;
+// prefix XORs per sequence: indices 0..L + 2 <= 26 are read; an odd row
+// length starts consecutive rows in different LDS banks
+constexpr int VG_PRE = 27;
+
+// Deletion positions of variant v of a string of length L in the enumeration
+// order (v = 0 the string itself, v = 1..L one deletion at v - 1, then the
+// pairs p1 < p2 in lexicographic order), in the form the prefix-XOR hash
+// takes: p2 = L for one deletion, p1 = L and p2 = L + 1 for none. The pair
+// index u = v - 1 - L is unranked in closed form: T(p) = p (2L - 1 - p) / 2
+// pairs start before p, so p1 is the largest p with T(p) <= u, a root of a
+// quadratic (one correction step each way absorbs the rounding of the
+// hardware square root).
+__device__ __forceinline__ void variant_positions(uint32_t L, uint32_t v, uint32_t& p1,
+                                                  uint32_t& p2) {
+  const int u = max((int)v - 1 - (int)L, 0);
+  const int a = 2 * (int)L - 1;
+  int q1 = (int)((a - __builtin_amdgcn_sqrtf((float)max(a * a - 8 * u, 0))) * 0.5f);
+  q1 = q1 < 0 ? 0 : q1;
+  if ((q1 + 1) * (a - q1 - 1) / 2 <= u) ++q1;
+  if (q1 * (a - q1) / 2 > u) --q1;
+  const int q2 = q1 + 1 + (u - q1 * (a - q1) / 2);
+  const bool none = v == 0, one = v != 0 && v <= L;
+  p1 = none ? L : one ? v - 1 : (uint32_t)q1;
+  p2 = none ? L + 1 : one ? L : (uint32_t)q2;
+}
 
 __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ seq,
                                                        const uint64_t* __restrict__ voff,
@@ -77,48 +115,99 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
                                                        uint32_t idbits, int npass, PassDigits pd,
                                                        uint32_t* __restrict__ hist) {
   __shared__ uint64_t s_off[VG_SEQS + 1];
-  __shared__ u128 s_seq[VG_SEQS];
+  __shared__ uint64_t s_pre[VG_SEQS * VG_PRE];
+  __shared__ uint64_t s_c[32];
+  __shared__ uint32_t s_len[VG_SEQS];
+  __shared__ uint32_t s_info[VG_SEQS];
   __shared__ uint32_t s_h[3 * 256];
   __shared__ uint8_t s_map[VG_MAX_VARIANTS];  // block-local variant -> sequence
   const uint64_t s0 = (uint64_t)blockIdx.x * VG_SEQS;
   const uint32_t ns = (uint32_t)min<uint64_t>(VG_SEQS, nseq - s0);
-  for (uint32_t x = threadIdx.x; x <= ns; x += VG_NT) s_off[x] = voff[s0 + x];
-  for (uint32_t x = threadIdx.x; x < ns; x += VG_NT) s_seq[x] = seq[s0 + x];
-  for (uint32_t x = threadIdx.x; x < 3 * 256; x += VG_NT) s_h[x] = 0;
-  __syncthreads();
-  const uint64_t g0 = s_off[0], g1 = s_off[ns];
-  // each wave labels the variants of every fourth sequence
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  for (uint32_t x = threadIdx.x; x <= ns; x += VG_NT) s_off[x] = voff[s0 + x];
+  for (uint32_t x = threadIdx.x; x < 3 * 256; x += VG_NT) s_h[x] = 0;
+  if (threadIdx.x < 32) s_c[threadIdx.x] = kHashTab.c[threadIdx.x];
+  // prefix XORs: each half-wave takes one sequence, lane t its position t
+  {
+    const uint32_t half = lane >> 5, t = lane & 31u;
+    for (uint32_t x0 = 2 * w; x0 < ns; x0 += 2 * (VG_NT / 64)) {
+      const uint32_t x = x0 + half;
+      const bool live = x < ns;
+      const u128 key = live ? seq[s0 + x] : (u128)0;
+      const uint32_t L = key_len(key);
+      uint64_t term = 0;
+      if (live && t < L) {
+        const uint32_t r = (uint32_t)(key >> (115 - 5 * t)) & 31u;
+        term = __builtin_rotateright64(kHashTab.b[r], t);
+      }
+      // inclusive XOR scan over the 32 lanes of the half-wave
+      uint32_t lo = (uint32_t)term, hi = (uint32_t)(term >> 32);
+#pragma unroll
+      for (int o = 1; o < 32; o <<= 1) {
+        const uint32_t plo = __shfl_up(lo, o, 32), phi = __shfl_up(hi, o, 32);
+        if (t >= (uint32_t)o) {
+          lo ^= plo;
+          hi ^= phi;
+        }
+      }
+      if (live && t + 1 < (uint32_t)VG_PRE) {
+        s_pre[x * VG_PRE + t + 1] = ((uint64_t)hi << 32) | lo;
+        if (t == 0) {
+          s_pre[x * VG_PRE] = 0;
+          s_len[x] = L;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const uint64_t g0 = s_off[0];
+  const uint32_t nv = (uint32_t)(s_off[ns] - g0);
+  // each wave labels the variants of every fourth sequence and packs its
+  // block-local first variant (< 2^15) with its length
   for (uint32_t x = w; x < ns; x += VG_NT / 64) {
     const uint32_t a = (uint32_t)(s_off[x] - g0), b = (uint32_t)(s_off[x + 1] - g0);
     for (uint32_t t = a + lane; t < b; t += 64) s_map[t] = (uint8_t)x;
+    if (lane == 0) s_info[x] = a | (s_len[x] << 16);
   }
   __syncthreads();
   const uint64_t idmask = (1ull << idbits) - 1;
+  const uint32_t sh[3] = {pd.shift[0], pd.shift[1], pd.shift[2]};
+  const uint32_t mk[3] = {pd.mask[0], pd.mask[1], pd.mask[2]};
+  uint64_t* __restrict__ out = elem + g0;
   // four independent variants per thread and iteration, so their LDS reads
-  // and key arithmetic overlap
+  // overlap
   constexpr int ILP = 4;
-  for (uint64_t g = g0 + threadIdx.x; g < g1; g += VG_NT * ILP) {
+  for (uint32_t t = threadIdx.x; t < nv; t += VG_NT * ILP) {
     uint32_t xs[ILP];
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
-      const uint64_t gg = g + (uint64_t)u * VG_NT;
-      xs[u] = gg < g1 ? s_map[gg - g0] : 0u;
+      const uint32_t tt = t + u * VG_NT;
+      xs[u] = tt < nv ? s_map[tt] : 0u;
     }
     uint64_t e[ILP];
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
-      const uint64_t gg = g + (uint64_t)u * VG_NT;
-      const uint32_t v = gg < g1 ? (uint32_t)(gg - s_off[xs[u]]) : 0u;
-      e[u] = (key_hash64(key_variant(s_seq[xs[u]], v)) & ~idmask) | (s0 + xs[u]);
+      const uint32_t tt = t + u * VG_NT;
+      const uint32_t x = xs[u];
+      const uint32_t info = s_info[x];
+      const uint32_t v = tt < nv ? tt - (info & 0xFFFFu) : 0u;
+      const uint32_t L = info >> 16;
+      uint32_t p1, p2;
+      variant_positions(L, v, p1, p2);
+      const uint32_t m = L - (uint32_t)(v != 0) - (uint32_t)(v > L);
+      const uint64_t* P = s_pre + x * VG_PRE;
+      const uint64_t h = s_c[m] ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
+                         __builtin_rotateleft64(P[L] ^ P[p2 + 1], 2);
+      e[u] = (h & ~idmask) | (s0 + x);
     }
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
-      const uint64_t gg = g + (uint64_t)u * VG_NT;
-      if (gg < g1) {
-        elem[gg] = e[u];
-        for (int q = 0; q < npass; ++q)
-          atomicAdd(&s_h[q * 256 + ((uint32_t)(e[u] >> pd.shift[q]) & pd.mask[q])], 1u);
+      const uint32_t tt = t + u * VG_NT;
+      if (tt < nv) {
+        out[tt] = e[u];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e[u] >> sh[q]) & mk[q])], 1u);
       }
     }
   }
