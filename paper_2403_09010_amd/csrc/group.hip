@@ -262,19 +262,77 @@ constexpr uint32_t NONE16 = 0xFFFFu;
 constexpr uint16_t REPEAT16 = 0xFFFEu;
 constexpr int GROUP_LDS_PER_ELEM = 22;
 
-// One batch of m <= CAP elements whose values arrive in registers (element
-// x = threadIdx.x + r * NTH is in e[r]); the caller has already issued the
-// loads of the next batch, so their latency overlaps this batch's LDS work.
+// One batch of m_in <= CAP elements whose values arrive in registers
+// (element x = threadIdx.x + r * NTH is in e_in[r]); the caller has already
+// issued the loads of the next batch, so their latency overlaps this batch's
+// LDS work.
+//
+// Most elements have a hash no other element of the batch shares. A
+// prefilter finds the rest first: every element sets the bit of its low hash
+// bits in a bitmap of 32 CAP bits (atomicOr returns whether the bit was
+// already set; if so the bit is also set in a second bitmap), and only the
+// elements whose bit ends up in the second bitmap (every element of a group
+// of equal hashes, plus about m / (32 CAP) of the others) are compacted, in
+// order, and grouped in the table. No pair is lost: equal hashes have equal
+// bits.
 template <int CAP, int NTH>
-__device__ void group_batch(const uint64_t (&e)[CAP / NTH], uint32_t m, uint32_t idbits,
+__device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, uint32_t idbits,
                             const ShardOut& out, unsigned char* lds, uint64_t* s_tmp64,
                             uint64_t* s_base) {
   constexpr int PER = CAP / NTH;
+  constexpr int NW = NTH / 64;
+  static_assert(PER * NW <= 64, "one wave scans the compaction counts");
+  __shared__ uint32_t s_cnt[PER * NW + 1];
   uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
   uint32_t* s_tab = reinterpret_cast<uint32_t*>(lds + CAP * 8);
   uint32_t* s_chead = reinterpret_cast<uint32_t*>(lds + CAP * 16);
   uint16_t* s_next = reinterpret_cast<uint16_t*>(lds + CAP * 20);
   const uint64_t idmask = (1ull << idbits) - 1;
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+
+  // prefilter: the two bitmaps occupy the table's 2 CAP words
+  uint32_t* s_seen = s_tab;
+  uint32_t* s_twice = s_tab + CAP;
+  for (uint32_t x = threadIdx.x; x < 2 * CAP; x += NTH) s_tab[x] = 0;
+  __syncthreads();
+  uint32_t bitx[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const uint32_t x = threadIdx.x + r * NTH;
+    bitx[r] = (uint32_t)(e_in[r] >> idbits) & (32u * CAP - 1);
+    if (x < m_in) {
+      const uint32_t bit = 1u << (bitx[r] & 31u);
+      if (atomicOr(&s_seen[bitx[r] >> 5], bit) & bit) atomicOr(&s_twice[bitx[r] >> 5], bit);
+    }
+  }
+  __syncthreads();
+  uint64_t keep[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const uint32_t x = threadIdx.x + r * NTH;
+    keep[r] = __ballot(x < m_in && ((s_twice[bitx[r] >> 5] >> (bitx[r] & 31u)) & 1u));
+    if (lane == 0) s_cnt[r * NW + w] = (uint32_t)__popcll(keep[r]);
+  }
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t c = lane < (uint32_t)(PER * NW) ? s_cnt[lane] : 0u;
+    const uint32_t incl = wave_incl_scan(c);
+    if (lane < (uint32_t)(PER * NW)) s_cnt[lane] = incl - c;
+    if (lane == 63) s_cnt[PER * NW] = incl;
+  }
+  __syncthreads();
+  const uint32_t m = s_cnt[PER * NW];
+#pragma unroll
+  for (int r = 0; r < PER; ++r)
+    if ((keep[r] >> lane) & 1u) s_e[s_cnt[r * NW + w] + mask_rank(keep[r])] = e_in[r];
+  __syncthreads();
+  if (m == 0) return;
+  uint64_t e[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const uint32_t x = threadIdx.x + r * NTH;
+    e[r] = x < m ? s_e[x] : 0;
+  }
   uint32_t ts = 64;  // table slots: a power of two >= 2m
   while (ts < 2 * m) ts <<= 1;
 
@@ -282,10 +340,7 @@ __device__ void group_batch(const uint64_t (&e)[CAP / NTH], uint32_t m, uint32_t
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
     const uint32_t x = threadIdx.x + r * NTH;
-    if (x < m) {
-      s_chead[x] = NONE16;
-      s_e[x] = e[r];
-    }
+    if (x < m) s_chead[x] = NONE16;
   }
   __syncthreads();
   // Repeated (hash, id) come from one sequence yielding one variant twice
