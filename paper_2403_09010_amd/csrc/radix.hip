@@ -92,12 +92,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(
     const bool valid = e < n;
     const uint64_t kw = (NW == 2 && word == 1) ? k1[r] : k0[r];
     const uint32_t d = (uint32_t)(kw >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? bb : ~bb;
-    }
+    const uint64_t peers = match_digit8(d, __ballot(valid));
     const uint32_t below = mask_rank(peers);
     uint32_t prev = 0;
     if (valid) prev = s_wh[w][d];
@@ -191,24 +186,20 @@ __global__ __launch_bounds__(NT) void k_onesweep_keys(const uint64_t* __restrict
   const uint64_t base = (uint64_t)tile * TILE;
   const uint32_t nvalid = (uint32_t)min<uint64_t>((uint64_t)TILE, (uint64_t)n - base);
 
+  const uint64_t* __restrict__ tin = in + base;
+  const uint32_t lbase = w * 64 * ITEMS + lane;
   uint64_t k0[ITEMS];
   uint32_t dr[ITEMS];  // digit << 16 | rank inside the wave (digit 256: no element)
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
-    const uint64_t e = base + (uint64_t)w * 64 * ITEMS + (uint64_t)r * 64 + lane;
-    k0[r] = e < n ? in[e] : 0;
+    const uint32_t le = lbase + r * 64;
+    k0[r] = le < nvalid ? tin[le] : 0;
   }
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
-    const uint64_t e = base + (uint64_t)w * 64 * ITEMS + (uint64_t)r * 64 + lane;
-    const bool valid = e < n;
+    const bool valid = lbase + r * 64 < nvalid;
     const uint32_t d = (uint32_t)(k0[r] >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? bb : ~bb;
-    }
+    const uint64_t peers = match_digit8(d, __ballot(valid));
     const uint32_t below = mask_rank(peers);
     uint32_t prev = 0;
     if (valid) prev = s_wh[w][d];

@@ -76,6 +76,25 @@ __device__ __forceinline__ uint32_t mask_rank(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Lanes of `live` whose 8-bit digit equals this lane's: for each bit, keep
+// the lanes that agree with this lane on it. m is 0 or all ones (this lane's
+// bit, a signed one-bit field extract), so the agreeing lanes are
+// ~(ballot ^ m); v_bitop3 applies peers & ~(ballot ^ m) to each 32-bit half
+// in one instruction. Its table 0x84 is symmetric in the first and third
+// operands, so it does not depend on which of them indexes the high bit.
+__device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t live) {
+  uint32_t lo = (uint32_t)live, hi = (uint32_t)(live >> 32);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    uint32_t m;  // the compiler would expand a constant-offset field extract into two shifts
+    asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(m) : "v"(d), "s"(b));
+    const uint64_t bb = __ballot(m != 0);
+    lo = __builtin_amdgcn_bitop3_b32((uint32_t)bb, lo, m, 0x84);
+    hi = __builtin_amdgcn_bitop3_b32((uint32_t)(bb >> 32), hi, m, 0x84);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
   const uint32_t lane = lane_id();
