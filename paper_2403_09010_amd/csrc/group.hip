@@ -73,7 +73,7 @@ __device__ __forceinline__ uint32_t slot_mix(uint64_t h) {
 // ------------------------------------------------------------------ vargen + hash
 
 constexpr int VG_NT = 256;
-constexpr int VG_SEQS = 64;
+constexpr int VG_SEQS = sd::VG_MAX_SEQS_PER_BLOCK;
 
 // Digit q of the hash passes is (e >> shift[q]) & mask[q].
 struct PassDigits {
@@ -113,7 +113,9 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
                                                        const uint64_t* __restrict__ voff,
                                                        uint64_t nseq, uint64_t* __restrict__ elem,
                                                        uint32_t idbits, int npass, PassDigits pd,
-                                                       uint32_t* __restrict__ hist) {
+                                                       uint32_t* __restrict__ hist,
+                                                       uint32_t* __restrict__ tcounts,
+                                                       uint32_t spb) {
   __shared__ uint64_t s_off[VG_SEQS + 1];
   __shared__ uint64_t s_pre[VG_SEQS * VG_PRE];
   __shared__ uint64_t s_c[32];
@@ -121,8 +123,9 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   __shared__ uint32_t s_info[VG_SEQS];
   __shared__ uint32_t s_h[3 * 256];
   __shared__ uint8_t s_map[VG_MAX_VARIANTS];  // block-local variant -> sequence
-  const uint64_t s0 = (uint64_t)blockIdx.x * VG_SEQS;
-  const uint32_t ns = (uint32_t)min<uint64_t>(VG_SEQS, nseq - s0);
+  // spb <= VG_SEQS sequences per block
+  const uint64_t s0 = (uint64_t)blockIdx.x * spb;
+  const uint32_t ns = (uint32_t)min<uint64_t>(spb, nseq - s0);
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   for (uint32_t x = threadIdx.x; x <= ns; x += VG_NT) s_off[x] = voff[s0 + x];
   for (uint32_t x = threadIdx.x; x < 3 * 256; x += VG_NT) s_h[x] = 0;
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   const uint32_t sh[3] = {pd.shift[0], pd.shift[1], pd.shift[2]};
   const uint32_t mk[3] = {pd.mask[0], pd.mask[1], pd.mask[2]};
   uint64_t* __restrict__ out = elem + g0;
+  const bool tiled = tcounts != nullptr;
   // four independent variants per thread and iteration, so their LDS reads
   // overlap
   constexpr int ILP = 4;
@@ -212,8 +216,37 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
     }
   }
   __syncthreads();
-  for (uint32_t x = threadIdx.x; x < (uint32_t)npass * 256; x += VG_NT)
-    if (s_h[x]) atomicAdd(&hist[x], s_h[x]);
+  // With tcounts, every pass's counts are stored as this block's rows (pass
+  // q's rows start at q * gridDim.x): pass 0's are the tiles of the counted
+  // first pass, the others are summed by k_hist_rows (plain stores instead
+  // of thousands of blocks adding into the same 256 counters).
+  if (tiled) {
+    for (uint32_t x = threadIdx.x; x < (uint32_t)npass * 256; x += VG_NT)
+      tcounts[((uint64_t)(x >> 8) * gridDim.x + blockIdx.x) * 256 + (x & 255u)] = s_h[x];
+  } else {
+    for (uint32_t x = threadIdx.x; x < (uint32_t)npass * 256; x += VG_NT)
+      if (s_h[x]) atomicAdd(&hist[x], s_h[x]);
+  }
+}
+
+// hist[q * 256 + d] += the sum over rows r of rows[(q * nrows + r) * 256 + d]
+// for passes q = 1 .. npass - 1; block (x, q - 1) sums a slice of the rows.
+constexpr int HR_LOADS = 16;
+__global__ __launch_bounds__(256) void k_hist_rows(const uint32_t* __restrict__ rows,
+                                                   uint32_t nrows, uint32_t* __restrict__ hist) {
+  const uint32_t q = blockIdx.y + 1, d = threadIdx.x;
+  const uint32_t per = (nrows + gridDim.x - 1) / gridDim.x;
+  const uint32_t r0 = min(blockIdx.x * per, nrows), r1 = min(r0 + per, nrows);
+  const uint32_t* __restrict__ base = rows + (uint64_t)q * nrows * 256 + d;
+  uint32_t sum = 0;
+  for (uint32_t r = r0; r < r1; r += HR_LOADS) {
+    uint32_t c[HR_LOADS];
+#pragma unroll
+    for (int u = 0; u < HR_LOADS; ++u) c[u] = r + u < r1 ? base[(uint64_t)(r + u) * 256] : 0u;
+#pragma unroll
+    for (int u = 0; u < HR_LOADS; ++u) sum += c[u];
+  }
+  if (sum) atomicAdd(&hist[q * 256 + d], sum);
 }
 
 // ------------------------------------------------------------------ segment bounds
@@ -631,16 +664,21 @@ namespace sd {
 
 void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, uint64_t* elem,
                         uint32_t idbits, int npass, const uint32_t* shifts, const uint32_t* masks,
-                        uint32_t* hist, hipStream_t s) {
+                        uint32_t* hist, uint32_t* tcounts, uint32_t seqs_per_block, hipStream_t s) {
   if (!nseq) return;
+  if (seqs_per_block < 1 || seqs_per_block > (uint32_t)sdk::VG_SEQS)
+    throw Error{SD_E_INVAL, "internal error: sequences per generator block out of range"};
   sdk::PassDigits pd;
   for (int q = 0; q < 3; ++q) {
     pd.shift[q] = q < npass ? shifts[q] : 0;
     pd.mask[q] = q < npass ? masks[q] : 0;
   }
-  const unsigned g = (unsigned)((nseq + sdk::VG_SEQS - 1) / sdk::VG_SEQS);
+  const unsigned g = (unsigned)((nseq + seqs_per_block - 1) / seqs_per_block);
   hipLaunchKernelGGL(sdk::k_vargen_hash, dim3(g), dim3(sdk::VG_NT), 0, s, seq, voff, nseq, elem,
-                     idbits, npass, pd, hist);
+                     idbits, npass, pd, hist, npass ? tcounts : nullptr, seqs_per_block);
+  if (tcounts && npass > 1)
+    hipLaunchKernelGGL(sdk::k_hist_rows, dim3(std::min(128u, g), npass - 1), dim3(256), 0, s, tcounts,
+                       g, hist);
 }
 
 void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_t* seg_start,

@@ -152,12 +152,20 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
     shifts[x] = (uint32_t)digits[x].shift;
     masks[x] = digits[x].mask;
   }
-  launch_vargen_hash(seq, voff, n, e1, idbits, (int)digits.size(), shifts, masks, hist, s);
-  cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 1);
+  // the first pass's digits are counted per tile during generation
+  const uint32_t spt = vargen_seqs_per_tile(n, nk);
+  uint32_t* tcounts = nullptr;
+  if (!digits.empty()) {
+    tcounts = cl.sc.get<uint32_t>(((n + spt - 1) / spt) * 256 * digits.size());
+  }
+  launch_vargen_hash(seq, voff, n, e1, idbits, (int)digits.size(), shifts, masks, hist, tcounts,
+                     spt, s);
+  cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 2);
   std::vector<const uint32_t*> hists;
   for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
-  const bool flip =
-      radix_sort(cl, e1, nullptr, nullptr, e2, nullptr, nullptr, 1, false, nk, digits, hists);
+  const CountedFirst first{tcounts, (n + spt - 1) / spt, voff, spt, n};
+  const bool flip = radix_sort(cl, e1, nullptr, nullptr, e2, nullptr, nullptr, 1, false, nk, digits,
+                               hists, &first);
   passes_out = (int)digits.size();
   cl.tm.mark("hash_passes", (double)nk * 16 * digits.size(), (int)digits.size());
   const uint64_t* E = flip ? e2 : e1;
@@ -332,6 +340,7 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
     uint64_t cnt;
     std::memcpy(&cnt, h, 8);
     if (h[2] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
+    if (h[2] & SD_ERRBIT_PLACEMENT) throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
     npairs = nc ? cnt : 0;
     tm.finish();
   } catch (...) {

@@ -45,6 +45,7 @@ Packed pack_and_count(Call& cl, const DevSeqs& in, int k) {
 void check_lookback(Call& cl) {
   const uint32_t* h = static_cast<const uint32_t*>(readback(cl.c, cl.counters + CNT_LBERR, 4, cl.s));
   if (h[0] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
+  if (h[0] & SD_ERRBIT_PLACEMENT) throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
 }
 
 namespace {
@@ -84,11 +85,18 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
     shifts[x] = (uint32_t)digits[x].shift;
     masks[x] = digits[x].mask;
   }
-  launch_vargen_hash(p.seq, p.voff, q.n, e1, idx->idbits, (int)digits.size(), shifts, masks, hist, s);
+  const uint32_t spt = vargen_seqs_per_tile(q.n, nk);
+  uint32_t* tcounts = nullptr;
+  if (!digits.empty()) {
+    tcounts = cl.sc.get<uint32_t>(((q.n + spt - 1) / spt) * 256 * digits.size());
+  }
+  launch_vargen_hash(p.seq, p.voff, q.n, e1, idx->idbits, (int)digits.size(), shifts, masks, hist,
+                     tcounts, spt, s);
   std::vector<const uint32_t*> hists;
   for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
-  const bool flip =
-      radix_sort(cl, e1, nullptr, nullptr, e2, nullptr, nullptr, 1, false, nk, digits, hists);
+  const CountedFirst first{tcounts, (q.n + spt - 1) / spt, p.voff, spt, q.n};
+  const bool flip = radix_sort(cl, e1, nullptr, nullptr, e2, nullptr, nullptr, 1, false, nk, digits,
+                               hists, &first);
   const uint64_t* Eq = flip ? e2 : e1;
   const uint32_t nseg = 1u << bits;
   uint32_t* qs = cl.sc.get<uint32_t>(nseg);
@@ -180,6 +188,7 @@ TileOut verify_candidates(Call& cl, const u128* qseq, uint64_t nq, const u128* r
     uint64_t cnt;
     std::memcpy(&cnt, h, 8);
     if (h[2] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
+    if (h[2] & SD_ERRBIT_PLACEMENT) throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
     out.n = nc ? cnt : 0;
     cl.tm.mark("q_verify", (double)nc * 49, 1);
   } catch (...) {
@@ -233,7 +242,8 @@ sd_index* index_build(sd_ctx* c, const sd_seqs* ref, int k, hipStream_t s) {
       uint64_t* e2 = sc.get<uint64_t>(nk);
       uint32_t* unused = sc.get<uint32_t>(3 * 256);
       const uint32_t z[3] = {0, 0, 0};
-      launch_vargen_hash(p.seq, p.voff, in.n, e1, idx->idbits, 0, z, z, unused, s);
+      launch_vargen_hash(p.seq, p.voff, in.n, e1, idx->idbits, 0, z, z, unused, nullptr,
+                         VG_MAX_SEQS_PER_BLOCK, s);
       uint32_t* hist = sc.get<uint32_t>(8 * 256);
       launch_fill_u32(hist, 0, 8 * 256, s);
       launch_radix_hist(e1, nullptr, 1, nk, hist, s);

@@ -13,6 +13,8 @@
 //     the tile as one contiguous run.
 // This is the paper's sortKeyValues / sort primitive (Section II B; Appendix A
 // steps 4 and 6) written for CDNA4 instead of taken from a library.
+#include <algorithm>
+
 #include "sd_device.h"
 #include "sd_internal.h"
 
@@ -229,10 +231,186 @@ __global__ __launch_bounds__(NT) void k_onesweep_keys(const uint64_t* __restrict
     if (d < RADIX) s_stage[s_lstart[d] + s_wh[w][d] + (dr[r] & 0xFFFFu)] = k0[r];
   }
   __syncthreads();
+  // counts that disagree with the input would place past the end: such a
+  // write is dropped and reported
   for (uint32_t s = tid; s < nvalid; s += NT) {
     const uint64_t v = s_stage[s];
     const uint32_t d = (uint32_t)(v >> shift) & mask;
-    out[s_gstart[d] + (s - s_lstart[d])] = v;
+    const uint32_t pos = s_gstart[d] + (s - s_lstart[d]);
+    if (pos < n)
+      out[pos] = v;
+    else
+      atomicOr(err, SD_ERRBIT_PLACEMENT);
+  }
+}
+
+// ------------------------------------------------------------------ counted pass
+
+// A keys-only pass over input written by a producer in consecutive ranges
+// ("tiles") whose digits it also counted: tile t holds the elements
+// [voff[t spt], voff[min((t + 1) spt, nseq)]) and counts[t][d] of them have
+// digit d. After a scan of the counts every tile knows where its digit runs
+// go, so the pass needs no look-back chain between tiles; a tile is placed in
+// chunks of CT_CHUNK elements, each advancing per-digit cursors.
+constexpr int CT_ITEMS = 16;
+constexpr uint32_t CT_CHUNK = NT * CT_ITEMS;
+constexpr int CT_LOADS = 16;  // loads in flight per thread in the count scans
+
+// Per block of R consecutive tiles and per digit: the exclusive running sum
+// inside the block (into local) and the block total (into bsum).
+__global__ __launch_bounds__(RADIX) void k_tile_scan_local(const uint32_t* __restrict__ counts,
+                                                           uint32_t tiles, uint32_t R,
+                                                           uint32_t* __restrict__ local,
+                                                           uint32_t* __restrict__ bsum) {
+  const uint32_t d = threadIdx.x;
+  const uint32_t t0 = blockIdx.x * R, t1 = min(t0 + R, tiles);
+  uint32_t run = 0;
+  for (uint32_t t = t0; t < t1; t += CT_LOADS) {
+    uint32_t c[CT_LOADS];
+#pragma unroll
+    for (int u = 0; u < CT_LOADS; ++u)
+      c[u] = t + u < t1 ? counts[(uint64_t)(t + u) * RADIX + d] : 0u;
+#pragma unroll
+    for (int u = 0; u < CT_LOADS; ++u) {
+      if (t + u < t1) local[(uint64_t)(t + u) * RADIX + d] = run;
+      run += c[u];
+    }
+  }
+  bsum[(uint64_t)blockIdx.x * RADIX + d] = run;
+}
+
+// One block: bsum[b][d] becomes the start of block b's digit-d elements in
+// the sorted output (digit base plus the totals of earlier blocks). Thread
+// (g, d) runs digit d over a quarter g of the rows.
+constexpr int CT_SCAN_GROUPS = 4;
+__global__ __launch_bounds__(CT_SCAN_GROUPS * RADIX) void k_tile_scan_blocks(
+    uint32_t* __restrict__ bsum, uint32_t nb) {
+  constexpr int NTH = CT_SCAN_GROUPS * RADIX;
+  __shared__ uint32_t s_part[CT_SCAN_GROUPS][RADIX];
+  __shared__ uint32_t s_base[RADIX];
+  __shared__ uint32_t s_tmp[NTH / 64];
+  const uint32_t d = threadIdx.x % RADIX, g = threadIdx.x / RADIX;
+  const uint32_t per = (nb + CT_SCAN_GROUPS - 1) / CT_SCAN_GROUPS;
+  const uint32_t b0 = min(g * per, nb), b1 = min(b0 + per, nb);
+  uint32_t run = 0;
+  for (uint32_t b = b0; b < b1; b += CT_LOADS) {
+    uint32_t c[CT_LOADS];
+#pragma unroll
+    for (int u = 0; u < CT_LOADS; ++u) c[u] = b + u < b1 ? bsum[(uint64_t)(b + u) * RADIX + d] : 0u;
+#pragma unroll
+    for (int u = 0; u < CT_LOADS; ++u) {
+      if (b + u < b1) bsum[(uint64_t)(b + u) * RADIX + d] = run;
+      run += c[u];
+    }
+  }
+  s_part[g][d] = run;
+  __syncthreads();
+  uint32_t total = 0;
+  if (g == 0) {
+    for (int q = 0; q < CT_SCAN_GROUPS; ++q) {
+      const uint32_t c = s_part[q][d];
+      s_part[q][d] = total;
+      total += c;
+    }
+  }
+  // digit bases: threads 0..255 (group 0) are the digits in order
+  uint32_t all;
+  const uint32_t base = block_excl_scan<NTH>(total, s_tmp, &all);
+  if (g == 0) s_base[d] = base;
+  __syncthreads();
+  const uint32_t add = s_part[g][d] + s_base[d];
+  for (uint32_t b = b0; b < b1; ++b) bsum[(uint64_t)b * RADIX + d] += add;
+}
+
+// Workgroups are dispatched to the eight XCDs in turn; this maps them so that
+// each XCD takes one contiguous range of tiles in order. Consecutive tiles
+// write adjacent pieces of every digit's run, so the cache lines they share
+// are completed in one XCD's L2 instead of being written back partially by
+// two (a bijection of [0, G)).
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t G) {
+  const uint32_t x = b & 7u;
+  uint32_t start = 0;
+  for (uint32_t q = 0; q < x; ++q) start += (G - q + 7) / 8;
+  return start + (b >> 3);
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(NT) void k_scatter_counted(
+    const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint32_t n, int shift,
+    uint32_t mask, const uint32_t* __restrict__ local, const uint32_t* __restrict__ boff, uint32_t R,
+    const uint64_t* __restrict__ voff, uint32_t spt, uint64_t nseq, uint32_t* __restrict__ err) {
+  constexpr int CHUNK = NT * ITEMS;
+  __shared__ uint32_t s_wh[NWAVE][RADIX];
+  __shared__ uint32_t s_lstart[RADIX];
+  __shared__ uint32_t s_gstart[RADIX];
+  __shared__ uint32_t s_tmp[NWAVE];
+  __shared__ uint64_t s_stage[CHUNK];
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
+  const uint32_t w = tid >> 6;
+  const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x);
+  const uint64_t q0 = (uint64_t)tile * spt;
+  const uint64_t a = voff[q0], b = voff[min<uint64_t>(q0 + spt, nseq)];
+  // this thread's digit (tid) cursor in the output
+  uint32_t cur = boff[(uint64_t)(tile / R) * RADIX + tid] + local[(uint64_t)tile * RADIX + tid];
+  for (uint64_t c0 = a; c0 < b; c0 += CHUNK) {
+    for (int x = tid; x < NWAVE * RADIX; x += NT) (&s_wh[0][0])[x] = 0;
+    __syncthreads();
+    const uint32_t nvalid = (uint32_t)min<uint64_t>((uint64_t)CHUNK, b - c0);
+    const uint64_t* __restrict__ tin = in + c0;
+    const uint32_t lbase = w * 64 * ITEMS + lane;
+    uint64_t k0[ITEMS];
+    uint32_t dr[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const uint32_t le = lbase + r * 64;
+      k0[r] = le < nvalid ? tin[le] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const bool valid = lbase + r * 64 < nvalid;
+      const uint32_t d = (uint32_t)(k0[r] >> shift) & mask;
+      const uint64_t peers = match_digit8(d, __ballot(valid));
+      const uint32_t below = mask_rank(peers);
+      uint32_t prev = 0;
+      if (valid) prev = s_wh[w][d];
+      if (valid && below == 0) s_wh[w][d] = prev + (uint32_t)__popcll(peers);
+      dr[r] = ((valid ? d : (uint32_t)RADIX) << 16) | (prev + below);
+    }
+    __syncthreads();
+    {
+      const uint32_t t = tid;
+      const uint32_t n0 = s_wh[0][t], n1 = s_wh[1][t], n2 = s_wh[2][t], n3 = s_wh[3][t];
+      uint32_t sum;
+      const uint32_t lstart = block_excl_scan<NT>(n0 + n1 + n2 + n3, s_tmp, &sum);
+      s_wh[0][t] = 0;
+      s_wh[1][t] = n0;
+      s_wh[2][t] = n0 + n1;
+      s_wh[3][t] = n0 + n1 + n2;
+      s_lstart[t] = lstart;
+      s_gstart[t] = cur;
+      cur += n0 + n1 + n2 + n3;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const uint32_t d = dr[r] >> 16;
+      if (d < RADIX) s_stage[s_lstart[d] + s_wh[w][d] + (dr[r] & 0xFFFFu)] = k0[r];
+    }
+    __syncthreads();
+    // counts that disagree with the input would place past the end: such a
+    // write is dropped and reported
+    for (uint32_t s = tid; s < nvalid; s += NT) {
+      const uint64_t v = s_stage[s];
+      const uint32_t d = (uint32_t)(v >> shift) & mask;
+      const uint32_t pos = s_gstart[d] + (s - s_lstart[d]);
+      if (pos < n)
+        out[pos] = v;
+      else
+        atomicOr(err, SD_ERRBIT_PLACEMENT);
+    }
+    __syncthreads();  // the next chunk rewrites the LDS
   }
 }
 
@@ -398,6 +576,30 @@ void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* v
   else
     hipLaunchKernelGGL((sdk::k_onesweep_keys<32>), g, b, 0, s, word == 1 ? in1 : in0, out0, n,
                        shift, mask, hist256, status, tile_counter, epoch, err);
+}
+
+static uint32_t counted_rows_per_block(uint64_t tiles) {
+  return (uint32_t)std::max<uint64_t>(64, (tiles + 511) / 512);
+}
+
+uint32_t counted_scan_rows(uint64_t tiles) {
+  const uint32_t R = counted_rows_per_block(tiles);
+  return (uint32_t)((tiles + R - 1) / R);
+}
+
+void launch_counted_pass(const uint64_t* in, uint64_t* out, uint32_t n, int shift, uint32_t mask,
+                         const uint32_t* counts, uint64_t tiles, const uint64_t* voff,
+                         uint32_t seqs_per_tile, uint64_t nseq, uint32_t* local, uint32_t* bsum,
+                         uint32_t* err, hipStream_t s) {
+  if (!n || !tiles) return;
+  const uint32_t R = counted_rows_per_block(tiles);
+  const uint32_t nb = counted_scan_rows(tiles);
+  hipLaunchKernelGGL(sdk::k_tile_scan_local, dim3(nb), dim3(sdk::RADIX), 0, s, counts,
+                     (uint32_t)tiles, R, local, bsum);
+  hipLaunchKernelGGL(sdk::k_tile_scan_blocks, dim3(1), dim3(sdk::CT_SCAN_GROUPS * sdk::RADIX), 0, s,
+                     bsum, nb);
+  hipLaunchKernelGGL((sdk::k_scatter_counted<sdk::CT_ITEMS>), dim3((unsigned)tiles), dim3(sdk::NT),
+                     0, s, in, out, n, shift, mask, local, bsum, R, voff, seqs_per_tile, nseq, err);
 }
 
 uint64_t scan_tile() { return (uint64_t)sdk::NT * sdk::SCAN_ITEMS; }

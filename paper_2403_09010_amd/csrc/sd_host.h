@@ -95,20 +95,41 @@ struct Call {
 
 // Sort records by the given digits in LSD order; returns true if the result
 // sits in the second buffer set.
+// A first pass whose digits the input's producer counted per tile (see
+// launch_counted_pass).
+struct CountedFirst {
+  const uint32_t* counts;
+  uint64_t tiles;
+  const uint64_t* voff;
+  uint32_t seqs_per_tile;
+  uint64_t nseq;
+};
+
 inline bool radix_sort(Call& cl, uint64_t* a0, uint64_t* a1, uint32_t* av, uint64_t* b0, uint64_t* b1,
                 uint32_t* bv, int nwords, bool has_val, uint32_t n, const std::vector<Digit>& digits,
-                const std::vector<const uint32_t*>& hists) {
+                const std::vector<const uint32_t*>& hists,
+                const CountedFirst* first = nullptr) {
   bool flip = false;
   const uint64_t tile = onesweep_tile(nwords, has_val, cl.c->sort_items);
   const uint64_t tiles = (n + tile - 1) / tile;
   for (size_t x = 0; x < digits.size(); ++x) {
-    const uint32_t epoch = next_epoch(cl.c, tiles * 256, cl.s);
     const uint64_t* i0 = flip ? b0 : a0;
     const uint64_t* i1 = flip ? b1 : a1;
     const uint32_t* iv = flip ? bv : av;
     uint64_t* o0 = flip ? a0 : b0;
     uint64_t* o1 = flip ? a1 : b1;
     uint32_t* ov = flip ? av : bv;
+    if (x == 0 && first && nwords == 1 && !has_val && digits[0].word == 0) {
+      // the producer counted this pass's digits per tile: no look-back
+      uint32_t* local = cl.sc.get<uint32_t>(first->tiles * 256);
+      uint32_t* bsum = cl.sc.get<uint32_t>((uint64_t)counted_scan_rows(first->tiles) * 256);
+      launch_counted_pass(i0, o0, n, digits[0].shift, digits[0].mask, first->counts, first->tiles,
+                          first->voff, first->seqs_per_tile, first->nseq, local, bsum, cl.lb_err(),
+                          cl.s);
+      flip = !flip;
+      continue;
+    }
+    const uint32_t epoch = next_epoch(cl.c, tiles * 256, cl.s);
     launch_onesweep(i0, i1, iv, o0, o1, ov, nwords, has_val, n, digits[x].word, digits[x].shift,
                     digits[x].mask, hists[x], cl.c->status, cl.tile_counter(), epoch, cl.lb_err(),
                     cl.c->sort_items, cl.s);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <unordered_map>
@@ -18,6 +19,7 @@ typedef unsigned __int128 u128;
 #define SD_ERRBIT_ALPHABET 2u
 #define SD_ERRBIT_INDEX 4u
 #define SD_ERRBIT_LOOKBACK 8u  // a look-back wait hit its bound (internal error)
+#define SD_ERRBIT_PLACEMENT 16u  // a counted pass computed a position past the end (internal error)
 
 namespace sd {
 
@@ -45,6 +47,17 @@ void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* v
                      uint32_t n, int word, int shift, uint32_t mask, const uint32_t* hist256,
                      uint64_t* status, uint32_t* tile_counter, uint32_t epoch, uint32_t* err,
                      int items, hipStream_t s);
+// A keys-only pass over input that its producer wrote in consecutive ranges
+// ("tiles") and counted: tile t holds the elements [voff[t * seqs_per_tile],
+// voff[min((t + 1) * seqs_per_tile, nseq)]) and counts[t][d] of them have
+// digit d. local needs tiles * 256 and bsum counted_scan_rows(tiles) * 256
+// entries of scratch. A position past n (counts that disagree with the
+// input) sets SD_ERRBIT_PLACEMENT in *err and is not written.
+uint32_t counted_scan_rows(uint64_t tiles);
+void launch_counted_pass(const uint64_t* in, uint64_t* out, uint32_t n, int shift, uint32_t mask,
+                         const uint32_t* counts, uint64_t tiles, const uint64_t* voff,
+                         uint32_t seqs_per_tile, uint64_t nseq, uint32_t* local, uint32_t* bsum,
+                         uint32_t* err, hipStream_t s);
 uint64_t scan_tile();
 void launch_scan_excl(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* status,
                       uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s);
@@ -63,9 +76,25 @@ void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* seq_a,
                            uint32_t epoch, unsigned long long* out_count, uint32_t* err,
                            hipStream_t s);
 // hashed grouping (element = hash of the key in the top 64 - idbits bits, id below)
+// Every variant as [hash | id] in voff order; block b generates sequences
+// [b * seqs_per_block, ...) (1 <= seqs_per_block <= VG_MAX_SEQS_PER_BLOCK).
+// hist[q * 256 + d] receives the digit counts of pass q, except pass 0's
+// when tcounts is non-null: then tcounts holds npass * G rows of 256 (G =
+// ceil(nseq / seqs_per_block) blocks, every entry written), pass q's block
+// counts at rows q * G .. q * G + G - 1, and the first G rows are the tiles
+// of a counted first pass.
+constexpr uint32_t VG_MAX_SEQS_PER_BLOCK = 64;
+// Sequences per generator block for a counted first pass: tiles of about
+// 3584 elements, which with at most 301 variants per sequence fit the pass's
+// 4096-element chunk in one piece.
+inline uint32_t vargen_seqs_per_tile(uint64_t nseq, uint64_t nkeys) {
+  if (!nseq || !nkeys) return VG_MAX_SEQS_PER_BLOCK;
+  const uint64_t per = 3584 * nseq / nkeys;
+  return (uint32_t)std::min<uint64_t>(VG_MAX_SEQS_PER_BLOCK, std::max<uint64_t>(1, per));
+}
 void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, uint64_t* elem,
                         uint32_t idbits, int npass, const uint32_t* shifts, const uint32_t* masks,
-                        uint32_t* hist, hipStream_t s);
+                        uint32_t* hist, uint32_t* tcounts, uint32_t seqs_per_block, hipStream_t s);
 bool group_cap_supported(int cap);
 void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_t* seg_start,
                        uint32_t* seg_end, hipStream_t s);
