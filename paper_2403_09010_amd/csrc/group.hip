@@ -298,7 +298,7 @@ constexpr int GROUP_LDS_PER_ELEM = 22;
 // One batch of m_in <= CAP elements whose values arrive in registers
 // (element x = threadIdx.x + r * NTH is in e_in[r]); the caller has already
 // issued the loads of the next batch, so their latency overlaps this batch's
-// LDS work.
+// LDS work. On entry and on return the table area (2 CAP words) is zero.
 //
 // Most elements have a hash no other element of the batch shares. A
 // prefilter finds the rest first: every element sets the bit of its low hash
@@ -314,8 +314,9 @@ __device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
                             uint64_t* s_base) {
   constexpr int PER = CAP / NTH;
   constexpr int NW = NTH / 64;
-  static_assert(PER * NW <= 64, "one wave scans the compaction counts");
-  __shared__ uint32_t s_cnt[PER * NW + 1];
+  constexpr int NC = PER * NW;
+  static_assert(NC % 4 == 0, "compaction counts are read four at a time");
+  __shared__ __align__(16) uint32_t s_cnt[NC];
   uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
   uint32_t* s_tab = reinterpret_cast<uint32_t*>(lds + CAP * 8);
   uint32_t* s_chead = reinterpret_cast<uint32_t*>(lds + CAP * 16);
@@ -323,11 +324,9 @@ __device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
   const uint64_t idmask = (1ull << idbits) - 1;
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
 
-  // prefilter: the two bitmaps occupy the table's 2 CAP words
+  // prefilter: the two bitmaps occupy the (zero) table area
   uint32_t* s_seen = s_tab;
   uint32_t* s_twice = s_tab + CAP;
-  for (uint32_t x = threadIdx.x; x < 2 * CAP; x += NTH) s_tab[x] = 0;
-  __syncthreads();
   uint32_t bitx[PER];
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
@@ -347,93 +346,89 @@ __device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
     if (lane == 0) s_cnt[r * NW + w] = (uint32_t)__popcll(keep[r]);
   }
   __syncthreads();
-  if (w == 0) {
-    const uint32_t c = lane < (uint32_t)(PER * NW) ? s_cnt[lane] : 0u;
-    const uint32_t incl = wave_incl_scan(c);
-    if (lane < (uint32_t)(PER * NW)) s_cnt[lane] = incl - c;
-    if (lane == 63) s_cnt[PER * NW] = incl;
+  // every thread sums the counts before each of its (row, wave) pieces; the
+  // bitmaps are dead now and are cleared for the next batch
+  uint32_t before[PER];
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 0; i < NC; i += 4) {
+    const uint4 c4 = *reinterpret_cast<const uint4*>(&s_cnt[i]);
+    const uint32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if ((i + j) % NW == (int)w) before[(i + j) / NW] = m;
+      m += c[j];
+    }
   }
-  __syncthreads();
-  const uint32_t m = s_cnt[PER * NW];
+  for (uint32_t x = threadIdx.x; x < 2 * CAP; x += NTH) s_tab[x] = 0;
 #pragma unroll
   for (int r = 0; r < PER; ++r)
-    if ((keep[r] >> lane) & 1u) s_e[s_cnt[r * NW + w] + mask_rank(keep[r])] = e_in[r];
+    if ((keep[r] >> lane) & 1u) s_e[before[r] + mask_rank(keep[r])] = e_in[r];
+  for (uint32_t x = threadIdx.x; x < m; x += NTH) s_chead[x] = NONE16;
   __syncthreads();
   if (m == 0) return;
-  uint64_t e[PER];
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const uint32_t x = threadIdx.x + r * NTH;
-    e[r] = x < m ? s_e[x] : 0;
-  }
   uint32_t ts = 64;  // table slots: a power of two >= 2m
   while (ts < 2 * m) ts <<= 1;
 
-  for (uint32_t x = threadIdx.x; x < ts; x += NTH) s_tab[x] = 0;
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const uint32_t x = threadIdx.x + r * NTH;
-    if (x < m) s_chead[x] = NONE16;
-  }
-  __syncthreads();
   // Repeated (hash, id) come from one sequence yielding one variant twice
   // (deleting either of two equal neighbours); inside a segment the stable
   // passes keep generation order, so equal ids are adjacent. Everything else
   // goes into the table and onto its representative's member chain.
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const uint32_t x = threadIdx.x + r * NTH;
-    if (x < m) {
-      const uint64_t h = e[r] >> idbits;
-      const uint64_t id = e[r] & idmask;
-      bool repeat = false;
-      for (int y = (int)x - 1; y >= 0 && (s_e[y] & idmask) == id; --y) {
-        if ((s_e[y] >> idbits) == h) {
-          repeat = true;
-          break;
-        }
+  for (uint32_t x = threadIdx.x; x < m; x += NTH) {
+    const uint64_t ex = s_e[x];
+    const uint64_t h = ex >> idbits;
+    const uint64_t id = ex & idmask;
+    bool repeat = false;
+    for (int y = (int)x - 1; y >= 0 && (s_e[y] & idmask) == id; --y) {
+      if ((s_e[y] >> idbits) == h) {
+        repeat = true;
+        break;
       }
-      if (repeat) {
-        s_next[x] = REPEAT16;
-      } else {
-        uint32_t slot = slot_mix(h) & (ts - 1);
-        uint32_t rep;
-        while (true) {
-          uint32_t t = s_tab[slot];
+    }
+    if (repeat) {
+      s_next[x] = REPEAT16;
+    } else {
+      uint32_t slot = slot_mix(h) & (ts - 1);
+      uint32_t rep;
+      while (true) {
+        uint32_t t = s_tab[slot];
+        if (t == 0) {
+          t = atomicCAS(&s_tab[slot], 0u, x + 1);
           if (t == 0) {
-            t = atomicCAS(&s_tab[slot], 0u, x + 1);
-            if (t == 0) {
-              rep = x;
-              break;
-            }
-          }
-          if ((s_e[t - 1] >> idbits) == h) {
-            rep = t - 1;
+            rep = x;
             break;
           }
-          slot = (slot + 1) & (ts - 1);
         }
-        s_next[x] = (uint16_t)atomicExch(&s_chead[rep], x);
+        if ((s_e[t - 1] >> idbits) == h) {
+          rep = t - 1;
+          break;
+        }
+        slot = (slot + 1) & (ts - 1);
       }
+      s_next[x] = (uint16_t)atomicExch(&s_chead[rep], x);
     }
   }
   __syncthreads();
   // each member pairs with the members pushed before it (distinct ids)
-  uint64_t mycnt = 0;
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const uint32_t x = threadIdx.x + r * NTH;
-    if (x < m) {
-      uint32_t y = s_next[x];
-      if (y != REPEAT16)
-        for (; y != NONE16; y = s_next[y]) ++mycnt;
-    }
+  uint32_t mycnt = 0;
+  for (uint32_t x = threadIdx.x; x < m; x += NTH) {
+    uint32_t y = s_next[x];
+    if (y != REPEAT16)
+      for (; y != NONE16; y = s_next[y]) ++mycnt;
   }
   // output slots: one reservation per batch, in the block's shard. The
   // batch total is a property of its groups (per-thread counts depend on the
   // order members were pushed), so every shard's count is reproducible.
-  uint64_t total;
-  const uint64_t excl = block_excl_scan<NTH>(mycnt, s_tmp64, &total);
+  const uint32_t incl = wave_incl_scan(mycnt);
+  if (lane == 63) s_tmp64[w] = incl;
+  __syncthreads();
+  uint64_t excl = incl - mycnt, total = 0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const uint64_t t = s_tmp64[q];
+    if (q < (int)w) excl += t;
+    total += t;
+  }
   if (threadIdx.x == 0) {
     const ShardResv r = total ? shard_reserve(out, blockIdx.x, total) : ShardResv{0, 0};
     s_base[0] = r.pos;
@@ -443,21 +438,19 @@ __device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
   if (mycnt) {
     const ShardResv r{s_base[0], s_base[1]};
     uint64_t j = excl;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const uint32_t x = threadIdx.x + q * NTH;
-      if (x < m) {
-        uint32_t y = s_next[x];
-        if (y == REPEAT16) continue;
-        const uint32_t id = (uint32_t)(e[q] & idmask);
-        for (; y != NONE16; y = s_next[y]) {
-          const uint32_t other = (uint32_t)(s_e[y] & idmask);
-          const uint32_t lo = id < other ? id : other, hi = id < other ? other : id;
-          shard_put(out, blockIdx.x, r, j++, ((uint64_t)lo << 32) | hi);
-        }
+    for (uint32_t x = threadIdx.x; x < m; x += NTH) {
+      uint32_t y = s_next[x];
+      if (y == REPEAT16) continue;
+      const uint32_t id = (uint32_t)(s_e[x] & idmask);
+      for (; y != NONE16; y = s_next[y]) {
+        const uint32_t other = (uint32_t)(s_e[y] & idmask);
+        const uint32_t lo = id < other ? id : other, hi = id < other ? other : id;
+        shard_put(out, blockIdx.x, r, j++, ((uint64_t)lo << 32) | hi);
       }
     }
   }
+  // the table is not read by the emission: clear it for the next batch
+  for (uint32_t x = threadIdx.x; x < ts; x += NTH) s_tab[x] = 0;
   __syncthreads();  // the next batch rewrites the LDS
 }
 
@@ -544,6 +537,10 @@ __global__ __launch_bounds__(NTH) void k_group_seg(
   __shared__ uint64_t s_tmp64[NTH / 64];
   __shared__ uint64_t s_base[2];
   uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
+  // group_batch expects a zero table area
+  for (uint32_t x = threadIdx.x; x < 2 * CAP; x += NTH)
+    reinterpret_cast<uint32_t*>(lds + CAP * 8)[x] = 0;
+  __syncthreads();
   const bool can_split = splitbit >= idbits && splitbit < 64;
   const uint32_t v0 = blockIdx.x * spw;
   const uint32_t v1 = min(v0 + spw, nseg);
