@@ -308,10 +308,29 @@ constexpr int GROUP_LDS_PER_ELEM = 22;
 // of equal hashes, plus about m / (32 CAP) of the others) are compacted, in
 // order, and grouped in the table. No pair is lost: equal hashes have equal
 // bits.
+// Pairs collect in an LDS buffer of GROUP_PBUF entries (pbuf_n of them used,
+// a block-uniform count) and go out with one reservation when it fills or
+// the workgroup ends, instead of one global atomic per batch.
+constexpr uint32_t GROUP_PBUF = 896;
+
+template <int NTH>
+__device__ void flush_pairs(const ShardOut& out, const uint64_t* s_pbuf, uint32_t n,
+                            uint64_t* s_base) {
+  if (threadIdx.x == 0) {
+    const ShardResv r = shard_reserve(out, blockIdx.x, n);
+    s_base[0] = r.pos;
+    s_base[1] = r.obase;
+  }
+  __syncthreads();
+  const ShardResv r{s_base[0], s_base[1]};
+  for (uint32_t i = threadIdx.x; i < n; i += NTH) shard_put(out, blockIdx.x, r, i, s_pbuf[i]);
+  __syncthreads();
+}
+
 template <int CAP, int NTH>
 __device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, uint32_t idbits,
                             const ShardOut& out, unsigned char* lds, uint64_t* s_tmp64,
-                            uint64_t* s_base) {
+                            uint64_t* s_base, uint64_t* s_pbuf, uint32_t& pbuf_n) {
   constexpr int PER = CAP / NTH;
   constexpr int NW = NTH / 64;
   constexpr int NC = PER * NW;
@@ -416,7 +435,8 @@ __device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
     if (y != REPEAT16)
       for (; y != NONE16; y = s_next[y]) ++mycnt;
   }
-  // output slots: one reservation per batch, in the block's shard. The
+  // output slots in the pair buffer (or, for a batch with more pairs than
+  // the buffer holds, one reservation of its own in the block's shard). The
   // batch total is a property of its groups (per-thread counts depend on the
   // order members were pushed), so every shard's count is reproducible.
   const uint32_t incl = wave_incl_scan(mycnt);
@@ -429,25 +449,39 @@ __device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
     if (q < (int)w) excl += t;
     total += t;
   }
-  if (threadIdx.x == 0) {
-    const ShardResv r = total ? shard_reserve(out, blockIdx.x, total) : ShardResv{0, 0};
-    s_base[0] = r.pos;
-    s_base[1] = r.obase;
-  }
-  __syncthreads();
-  if (mycnt) {
-    const ShardResv r{s_base[0], s_base[1]};
-    uint64_t j = excl;
-    for (uint32_t x = threadIdx.x; x < m; x += NTH) {
-      uint32_t y = s_next[x];
-      if (y == REPEAT16) continue;
-      const uint32_t id = (uint32_t)(s_e[x] & idmask);
-      for (; y != NONE16; y = s_next[y]) {
-        const uint32_t other = (uint32_t)(s_e[y] & idmask);
-        const uint32_t lo = id < other ? id : other, hi = id < other ? other : id;
-        shard_put(out, blockIdx.x, r, j++, ((uint64_t)lo << 32) | hi);
+  if (total) {
+    if (pbuf_n + total > GROUP_PBUF) {
+      flush_pairs<NTH>(out, s_pbuf, pbuf_n, s_base);
+      pbuf_n = 0;
+    }
+    const bool direct = total > GROUP_PBUF;
+    if (direct) {
+      if (threadIdx.x == 0) {
+        const ShardResv r = shard_reserve(out, blockIdx.x, total);
+        s_base[0] = r.pos;
+        s_base[1] = r.obase;
+      }
+      __syncthreads();
+    }
+    if (mycnt) {
+      const ShardResv r{s_base[0], s_base[1]};
+      uint64_t j = excl;
+      for (uint32_t x = threadIdx.x; x < m; x += NTH) {
+        uint32_t y = s_next[x];
+        if (y == REPEAT16) continue;
+        const uint32_t id = (uint32_t)(s_e[x] & idmask);
+        for (; y != NONE16; y = s_next[y]) {
+          const uint32_t other = (uint32_t)(s_e[y] & idmask);
+          const uint32_t lo = id < other ? id : other, hi = id < other ? other : id;
+          const uint64_t pair = ((uint64_t)lo << 32) | hi;
+          if (direct)
+            shard_put(out, blockIdx.x, r, j++, pair);
+          else
+            s_pbuf[pbuf_n + j++] = pair;
+        }
       }
     }
+    if (!direct) pbuf_n += (uint32_t)total;
   }
   // the table is not read by the emission: clear it for the next batch
   for (uint32_t x = threadIdx.x; x < ts; x += NTH) s_tab[x] = 0;
@@ -536,6 +570,8 @@ __global__ __launch_bounds__(NTH) void k_group_seg(
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ uint64_t s_tmp64[NTH / 64];
   __shared__ uint64_t s_base[2];
+  __shared__ uint64_t s_pbuf[GROUP_PBUF];
+  uint32_t pbuf_n = 0;
   uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
   // group_batch expects a zero table area
   for (uint32_t x = threadIdx.x; x < 2 * CAP; x += NTH)
@@ -574,7 +610,7 @@ __global__ __launch_bounds__(NTH) void k_group_seg(
             e[r] = x < m ? s_e[x] : 0;
           }
           __syncthreads();
-          group_batch<CAP, NTH>(e, m, idbits, out, lds, s_tmp64, s_base);
+          group_batch<CAP, NTH>(e, m, idbits, out, lds, s_tmp64, s_base, s_pbuf, pbuf_n);
         }
       }
       kind = next_batch<CAP>(seg_start, seg_end, v, v1, a, b, can_split, big, nbig);
@@ -594,13 +630,14 @@ __global__ __launch_bounds__(NTH) void k_group_seg(
       const uint32_t x = threadIdx.x + r * NTH;
       nxt[r] = (nkind == 1 && x < nb - na) ? E[na + x] : 0;
     }
-    group_batch<CAP, NTH>(cur, m, idbits, out, lds, s_tmp64, s_base);
+    group_batch<CAP, NTH>(cur, m, idbits, out, lds, s_tmp64, s_base, s_pbuf, pbuf_n);
 #pragma unroll
     for (int r = 0; r < PER; ++r) cur[r] = nxt[r];
     a = na;
     b = nb;
     kind = nkind;
   }
+  if (pbuf_n) flush_pairs<NTH>(out, s_pbuf, pbuf_n, s_base);
 }
 
 // ------------------------------------------------------------------ oversized segments
