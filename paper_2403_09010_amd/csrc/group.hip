@@ -109,20 +109,30 @@ __device__ __forceinline__ void variant_positions(uint32_t L, uint32_t v, uint32
   p2 = none ? L + 1 : one ? L : (uint32_t)q2;
 }
 
+// DISTINCT: the variant offsets count distinct strings only
+// (num_distinct_variants); every V(L, k) deletion set is still enumerated,
+// and the canonical ones are written compactly in enumeration order.
+template <bool DISTINCT>
 __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ seq,
                                                        const uint64_t* __restrict__ voff,
-                                                       uint64_t nseq, uint64_t* __restrict__ elem,
+                                                       uint64_t nseq, int k,
+                                                       uint64_t* __restrict__ elem,
                                                        uint32_t idbits, int npass, PassDigits pd,
                                                        uint32_t* __restrict__ hist,
                                                        uint32_t* __restrict__ tcounts,
                                                        uint32_t spb) {
+  constexpr int ILP = 4;
+  constexpr int NWV = VG_NT / 64;
   __shared__ uint64_t s_off[VG_SEQS + 1];
   __shared__ uint64_t s_pre[VG_SEQS * VG_PRE];
   __shared__ uint64_t s_c[32];
   __shared__ uint32_t s_len[VG_SEQS];
   __shared__ uint32_t s_info[VG_SEQS];
+  __shared__ uint32_t s_roff[VG_SEQS + 1];  // block-local first deletion set of each sequence
   __shared__ uint32_t s_h[3 * 256];
-  __shared__ uint8_t s_map[VG_MAX_VARIANTS];  // block-local variant -> sequence
+  __shared__ uint32_t s_vc[2][ILP * NWV];   // canonical counts per (u, wave), by parity
+  __shared__ uint8_t s_res[DISTINCT ? VG_SEQS * KEY_MAX_LEN : 1];
+  __shared__ uint8_t s_map[VG_MAX_VARIANTS];  // block-local deletion set -> sequence
   // spb <= VG_SEQS sequences per block
   const uint64_t s0 = (uint64_t)blockIdx.x * spb;
   const uint32_t ns = (uint32_t)min<uint64_t>(spb, nseq - s0);
@@ -133,7 +143,7 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   // prefix XORs: each half-wave takes one sequence, lane t its position t
   {
     const uint32_t half = lane >> 5, t = lane & 31u;
-    for (uint32_t x0 = 2 * w; x0 < ns; x0 += 2 * (VG_NT / 64)) {
+    for (uint32_t x0 = 2 * w; x0 < ns; x0 += 2 * NWV) {
       const uint32_t x = x0 + half;
       const bool live = x < ns;
       const u128 key = live ? seq[s0 + x] : (u128)0;
@@ -142,6 +152,7 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
       if (live && t < L) {
         const uint32_t r = (uint32_t)(key >> (115 - 5 * t)) & 31u;
         term = __builtin_rotateright64(kHashTab.b[r], t);
+        if (DISTINCT) s_res[x * KEY_MAX_LEN + t] = (uint8_t)r;
       }
       // inclusive XOR scan over the 32 lanes of the half-wave
       uint32_t lo = (uint32_t)term, hi = (uint32_t)(term >> 32);
@@ -164,11 +175,21 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   }
   __syncthreads();
   const uint64_t g0 = s_off[0];
-  const uint32_t nv = (uint32_t)(s_off[ns] - g0);
-  // each wave labels the variants of every fourth sequence and packs its
-  // block-local first variant (< 2^15) with its length
-  for (uint32_t x = w; x < ns; x += VG_NT / 64) {
-    const uint32_t a = (uint32_t)(s_off[x] - g0), b = (uint32_t)(s_off[x + 1] - g0);
+  // the deletion sets to enumerate: all V(L, k) of every sequence
+  if (w == 0) {
+    const uint32_t c = lane < ns ? (DISTINCT ? num_variants(s_len[lane], k)
+                                             : (uint32_t)(s_off[lane + 1] - s_off[lane]))
+                                 : 0u;
+    const uint32_t incl = wave_incl_scan(c);
+    if (lane < ns) s_roff[lane + 1] = incl;
+    if (lane == 0) s_roff[0] = 0;
+  }
+  __syncthreads();
+  const uint32_t nv = s_roff[ns];
+  // each wave labels the deletion sets of every fourth sequence and packs
+  // its block-local first one (< 2^15) with its length
+  for (uint32_t x = w; x < ns; x += NWV) {
+    const uint32_t a = s_roff[x], b = s_roff[x + 1];
     for (uint32_t t = a + lane; t < b; t += 64) s_map[t] = (uint8_t)x;
     if (lane == 0) s_info[x] = a | (s_len[x] << 16);
   }
@@ -178,20 +199,23 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   const uint32_t mk[3] = {pd.mask[0], pd.mask[1], pd.mask[2]};
   uint64_t* __restrict__ out = elem + g0;
   const bool tiled = tcounts != nullptr;
-  // four independent variants per thread and iteration, so their LDS reads
-  // overlap
-  constexpr int ILP = 4;
-  for (uint32_t t = threadIdx.x; t < nv; t += VG_NT * ILP) {
+  uint32_t written = 0;  // canonical variants written by earlier iterations
+  int par = 0;
+  // four independent deletion sets per thread and iteration, so their LDS
+  // reads overlap
+  for (uint32_t t = 0; t < nv; t += VG_NT * ILP) {
     uint32_t xs[ILP];
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
-      const uint32_t tt = t + u * VG_NT;
+      const uint32_t tt = t + u * VG_NT + threadIdx.x;
       xs[u] = tt < nv ? s_map[tt] : 0u;
     }
     uint64_t e[ILP];
+    uint32_t pos[ILP];
+    bool keep[ILP];
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
-      const uint32_t tt = t + u * VG_NT;
+      const uint32_t tt = t + u * VG_NT + threadIdx.x;
       const uint32_t x = xs[u];
       const uint32_t info = s_info[x];
       const uint32_t v = tt < nv ? tt - (info & 0xFFFFu) : 0u;
@@ -203,12 +227,32 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
       const uint64_t h = s_c[m] ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
                          __builtin_rotateleft64(P[L] ^ P[p2 + 1], 2);
       e[u] = (h & ~idmask) | (s0 + x);
+      keep[u] = tt < nv && (!DISTINCT || variant_canonical(s_res + x * KEY_MAX_LEN, L, p1, p2));
+      pos[u] = tt;
+    }
+    if (DISTINCT) {
+      // compact the canonical ones in enumeration order (u, wave, lane)
+      uint64_t bal[ILP];
+#pragma unroll
+      for (int u = 0; u < ILP; ++u) {
+        bal[u] = __ballot(keep[u]);
+        if (lane == 0) s_vc[par][u * NWV + w] = (uint32_t)__popcll(bal[u]);
+      }
+      __syncthreads();
+      uint32_t run = written;
+#pragma unroll
+      for (int i = 0; i < ILP * NWV; ++i) {
+        const uint32_t c = s_vc[par][i];
+        if (i % NWV == (int)w) pos[i / NWV] = run + mask_rank(bal[i / NWV]);
+        run += c;
+      }
+      written = run;
+      par ^= 1;
     }
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
-      const uint32_t tt = t + u * VG_NT;
-      if (tt < nv) {
-        out[tt] = e[u];
+      if (keep[u]) {
+        out[pos[u]] = e[u];
 #pragma unroll
         for (int q = 0; q < 3; ++q)
           if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e[u] >> sh[q]) & mk[q])], 1u);
@@ -696,9 +740,10 @@ __global__ __launch_bounds__(256) void k_emit_hash_runs(const uint64_t* __restri
 
 namespace sd {
 
-void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, uint64_t* elem,
-                        uint32_t idbits, int npass, const uint32_t* shifts, const uint32_t* masks,
-                        uint32_t* hist, uint32_t* tcounts, uint32_t seqs_per_block, hipStream_t s) {
+void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, int k, bool distinct,
+                        uint64_t* elem, uint32_t idbits, int npass, const uint32_t* shifts,
+                        const uint32_t* masks, uint32_t* hist, uint32_t* tcounts,
+                        uint32_t seqs_per_block, hipStream_t s) {
   if (!nseq) return;
   if (seqs_per_block < 1 || seqs_per_block > (uint32_t)sdk::VG_SEQS)
     throw Error{SD_E_INVAL, "internal error: sequences per generator block out of range"};
@@ -708,8 +753,12 @@ void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, ui
     pd.mask[q] = q < npass ? masks[q] : 0;
   }
   const unsigned g = (unsigned)((nseq + seqs_per_block - 1) / seqs_per_block);
-  hipLaunchKernelGGL(sdk::k_vargen_hash, dim3(g), dim3(sdk::VG_NT), 0, s, seq, voff, nseq, elem,
-                     idbits, npass, pd, hist, npass ? tcounts : nullptr, seqs_per_block);
+  if (distinct)
+    hipLaunchKernelGGL(sdk::k_vargen_hash<true>, dim3(g), dim3(sdk::VG_NT), 0, s, seq, voff, nseq,
+                       k, elem, idbits, npass, pd, hist, npass ? tcounts : nullptr, seqs_per_block);
+  else
+    hipLaunchKernelGGL(sdk::k_vargen_hash<false>, dim3(g), dim3(sdk::VG_NT), 0, s, seq, voff, nseq,
+                       k, elem, idbits, npass, pd, hist, npass ? tcounts : nullptr, seqs_per_block);
   if (tcounts && npass > 1)
     hipLaunchKernelGGL(sdk::k_hist_rows, dim3(std::min(128u, g), npass - 1), dim3(256), 0, s, tcounts,
                        g, hist);

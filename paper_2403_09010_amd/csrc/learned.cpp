@@ -104,7 +104,7 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
     idx->params = static_cast<float*>(lidx_alloc(NP * sizeof(float)));
     uint64_t nk = 0;
     if (in.n) {
-      const Packed p = pack_and_count(cl, in, k);
+      const Packed p = pack_and_count(cl, in, k, false);
       hip_check(hipMemcpyAsync(idx->ref_seq, p.seq, in.n * 16, hipMemcpyDeviceToDevice, s), "copy");
       nk = p.nkeys;
       uint64_t* klo = sc.get<uint64_t>(nk);
@@ -296,7 +296,7 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
 TileOut learned_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const WeightedSpec* w) {
   sd_ctx* c = cl.c;
   hipStream_t s = cl.s;
-  const Packed p = pack_and_count(cl, q, k);
+  const Packed p = pack_and_count(cl, q, k, false);
   const uint64_t nk = p.nkeys;
   cl.tm.mark("q_pack_scan", (double)q.n * 56, 2);
   const int learned = c->probe == 0 ? 1 : 0;

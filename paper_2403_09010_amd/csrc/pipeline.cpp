@@ -135,7 +135,7 @@ Cands oversized_group(Call& cl, const uint64_t* E, const uint64_t* big, uint64_t
 
 // Hashed grouping: elements [hash | id], LSD passes over the top `bits` hash
 // bits, grouping of each segment by its full hash in LDS.
-Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, uint32_t nk,
+Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, int k, uint32_t nk,
                    int& passes_out) {
   sd_ctx* c = cl.c;
   hipStream_t s = cl.s;
@@ -158,8 +158,8 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   if (!digits.empty()) {
     tcounts = cl.sc.get<uint32_t>(((n + spt - 1) / spt) * 256 * digits.size());
   }
-  launch_vargen_hash(seq, voff, n, e1, idbits, (int)digits.size(), shifts, masks, hist, tcounts,
-                     spt, s);
+  launch_vargen_hash(seq, voff, n, k, true, e1, idbits, (int)digits.size(), shifts, masks, hist,
+                     tcounts, spt, s);
   cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 2);
   std::vector<const uint32_t*> hists;
   for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
@@ -256,7 +256,8 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
   u128* seq = sc.get<u128>(n);
   uint32_t* vcnt = sc.get<uint32_t>(n);
   uint64_t* voff = sc.get<uint64_t>(n + 1);
-  launch_pack(in.codes, in.offs, n, k, seq, vcnt, counters + CNT_ERR, s);
+  // the hashed path generates each distinct variant string of a sequence once
+  launch_pack(in.codes, in.offs, n, k, c->path != 1, seq, vcnt, counters + CNT_ERR, s);
   {
     const uint64_t tiles = (n + scan_tile() - 1) / scan_tile();
     const uint32_t epoch = next_epoch(c, tiles, s);
@@ -286,7 +287,7 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
     tm.mark("vargen", (double)nk * 20 + (double)n * 24, 1);
     cand = fullkey_group(cl, klo, khi, kid, nk, passes);
   } else {
-    cand = hashed_group(cl, seq, voff, n, nk, passes);
+    cand = hashed_group(cl, seq, voff, n, k, nk, passes);
   }
   sc.blocks.push_back(cand.p);
   c->stats.n_sort_passes = passes;
@@ -410,8 +411,8 @@ void pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32_t
   uint32_t* counters = fresh_counters(c, CNT_TOTAL, s);
   u128* sa = sc.get<u128>(da.n);
   u128* sb = sc.get<u128>(db.n);
-  launch_pack(da.codes, da.offs, da.n, 0, sa, nullptr, counters, s);
-  launch_pack(db.codes, db.offs, db.n, 0, sb, nullptr, counters, s);
+  launch_pack(da.codes, da.offs, da.n, 0, false, sa, nullptr, counters, s);
+  launch_pack(db.codes, db.offs, db.n, 0, false, sb, nullptr, counters, s);
   const uint32_t* h = static_cast<const uint32_t*>(readback(c, counters, 4, s));
   raise_validation(h[0]);
   launch_pair_distance(sa, da.n, sb, db.n, ia, ib, (uint64_t)n, d_out, counters + 1, s);

@@ -22,13 +22,13 @@
 
 namespace sd {
 
-Packed pack_and_count(Call& cl, const DevSeqs& in, int k) {
+Packed pack_and_count(Call& cl, const DevSeqs& in, int k, bool distinct) {
   Packed p;
   p.seq = cl.sc.get<u128>(in.n);
   uint32_t* vcnt = cl.sc.get<uint32_t>(in.n);
   p.voff = cl.sc.get<uint64_t>(in.n + 1);
   launch_fill_u32(cl.counters + CNT_ERR, 0, 1, cl.s);
-  launch_pack(in.codes, in.offs, in.n, k, p.seq, vcnt, cl.counters + CNT_ERR, cl.s);
+  launch_pack(in.codes, in.offs, in.n, k, distinct, p.seq, vcnt, cl.counters + CNT_ERR, cl.s);
   const uint64_t tiles = (in.n + scan_tile() - 1) / scan_tile();
   const uint32_t epoch = next_epoch(cl.c, tiles, cl.s);
   launch_scan_excl(vcnt, p.voff, in.n, cl.c->status, cl.tile_counter(), epoch, cl.lb_err(), cl.s);
@@ -68,7 +68,7 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   if (q.n == 0) return out;
   if (idx->learned) return learned_tile(cl, idx, q, k, w);
   if (q.n >= (1ull << idx->idbits)) throw Error{SD_E_TOO_MANY, "query tile exceeds the index id width"};
-  const Packed p = pack_and_count(cl, q, k);
+  const Packed p = pack_and_count(cl, q, k, true);
   out.nkeys = p.nkeys;
   const uint32_t nk = (uint32_t)p.nkeys;
   cl.tm.mark("q_pack_scan", (double)q.n * 56, 2);
@@ -90,8 +90,8 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   if (!digits.empty()) {
     tcounts = cl.sc.get<uint32_t>(((q.n + spt - 1) / spt) * 256 * digits.size());
   }
-  launch_vargen_hash(p.seq, p.voff, q.n, e1, idx->idbits, (int)digits.size(), shifts, masks, hist,
-                     tcounts, spt, s);
+  launch_vargen_hash(p.seq, p.voff, q.n, k, true, e1, idx->idbits, (int)digits.size(), shifts,
+                     masks, hist, tcounts, spt, s);
   std::vector<const uint32_t*> hists;
   for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
   const CountedFirst first{tcounts, (q.n + spt - 1) / spt, p.voff, spt, q.n};
@@ -235,14 +235,14 @@ sd_index* index_build(sd_ctx* c, const sd_seqs* ref, int k, hipStream_t s) {
     uint64_t nk = 0;
     const uint64_t* E = nullptr;
     if (in.n) {
-      const Packed p = pack_and_count(cl, in, k);
+      const Packed p = pack_and_count(cl, in, k, true);
       hip_check(hipMemcpyAsync(idx->ref_seq, p.seq, in.n * 16, hipMemcpyDeviceToDevice, s), "copy");
       nk = p.nkeys;
       uint64_t* e1 = sc.get<uint64_t>(nk);
       uint64_t* e2 = sc.get<uint64_t>(nk);
       uint32_t* unused = sc.get<uint32_t>(3 * 256);
       const uint32_t z[3] = {0, 0, 0};
-      launch_vargen_hash(p.seq, p.voff, in.n, e1, idx->idbits, 0, z, z, unused, nullptr,
+      launch_vargen_hash(p.seq, p.voff, in.n, k, true, e1, idx->idbits, 0, z, z, unused, nullptr,
                          VG_MAX_SEQS_PER_BLOCK, s);
       uint32_t* hist = sc.get<uint32_t>(8 * 256);
       launch_fill_u32(hist, 0, 8 * 256, s);

@@ -44,6 +44,50 @@ __host__ __device__ __forceinline__ uint32_t num_variants(uint32_t L, int k) {
   return v;
 }
 
+// Equal strings from different deletion sets. Deleting D from s gives t;
+// the greedy leftmost embedding of t in s (match each position of s to the
+// next character of t whenever they agree) deletes a unique set D*(t), so
+// keeping only the variants with D = D* keeps each distinct string once. For
+// |D| <= 2 the test is local: with t_j the j-th character of t,
+//   {p}       is D*  iff p = L - 1 or s[p] != s[p + 1]
+//   {p1 < p2} is D*  iff s[p1] != t[p1] (t[p1] = s[p1 + 1], or s[p1 + 2]
+//             when p2 = p1 + 1; vacuous when p1 = L - 2 = |t|) and
+//             (p2 = L - 1 or s[p2] != s[p2 + 1])
+// (greedy reaches p1 with every earlier position matched, and reaches p2
+// with every position between matched). Deletion variants of one string are
+// counted once each this way (Section II A defines the variant set; the
+// multiplicity only changes how often a pair is found, not which pairs).
+__device__ __forceinline__ bool variant_canonical(const uint8_t* r, uint32_t L, uint32_t p1,
+                                                  uint32_t p2) {
+  // p2 = L: one deletion at p1; p1 = L: none (the forms of variant_positions)
+  if (p1 >= L) return true;
+  if (p2 >= L) return p1 + 1 == L || r[p1] != r[p1 + 1];
+  const bool b = p2 + 1 == L || r[p2] != r[p2 + 1];
+  const bool a = p1 + 1 < p2 ? r[p1] != r[p1 + 1] : (p2 + 1 == L || r[p1] != r[p2 + 1]);
+  return a && b;
+}
+
+// Number of distinct strings among the deletion variants with at most k
+// deletions: the canonical sets above, counted in O(L).
+__device__ __forceinline__ uint32_t num_distinct_variants(u128 key, int k) {
+  const uint32_t L = key_len(key);
+  uint32_t c = 1;
+  if (k >= 1)
+    for (uint32_t p = 0; p < L; ++p)
+      c += (p + 1 == L || key_residue(key, (int)p) != key_residue(key, (int)p + 1)) ? 1u : 0u;
+  if (k >= 2) {
+    uint32_t run = 0;  // canonical first deletions p1 <= p2 - 2
+    for (uint32_t p2 = 1; p2 < L; ++p2) {
+      if (p2 >= 2 && key_residue(key, (int)p2 - 2) != key_residue(key, (int)p2 - 1)) ++run;
+      if (p2 + 1 == L || key_residue(key, (int)p2) != key_residue(key, (int)p2 + 1)) {
+        c += run;
+        if (p2 + 1 == L || key_residue(key, (int)p2 - 1) != key_residue(key, (int)p2 + 1)) ++c;
+      }
+    }
+  }
+  return c;
+}
+
 // Variant number v of a key in the enumeration order: v = 0 keeps the
 // string, v = 1..L deletes position v-1, larger v delete a position pair
 // (p1 < p2) in lexicographic order. The pair index u = v - 1 - L is unranked

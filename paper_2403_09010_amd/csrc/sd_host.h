@@ -225,7 +225,9 @@ struct Packed {
   uint64_t nkeys = 0;
 };
 // pack and validate a device CSR set, scan its variant counts (one read-back)
-Packed pack_and_count(Call& cl, const DevSeqs& in, int k);
+// distinct: count (and later generate) each distinct variant string of a
+// sequence once instead of all V(L, k) deletion sets
+Packed pack_and_count(Call& cl, const DevSeqs& in, int k, bool distinct);
 // raise if a look-back wait of the call hit its bound
 void check_lookback(Call& cl);
 

@@ -62,8 +62,10 @@ uint64_t scan_tile();
 void launch_scan_excl(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* status,
                       uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s);
 
-void launch_pack(const uint8_t* codes, const int64_t* offs, uint64_t n, int k, u128* seq,
-                 uint32_t* vcnt, uint32_t* err, hipStream_t s);
+// vcnt[i]: the variants of sequence i, all V(L, k) of them or, with
+// distinct, only the distinct strings among them (variant_canonical)
+void launch_pack(const uint8_t* codes, const int64_t* offs, uint64_t n, int k, bool distinct,
+                 u128* seq, uint32_t* vcnt, uint32_t* err, hipStream_t s);
 void launch_vargen(const u128* seq, const uint64_t* voff, uint64_t nseq, int k,
                    uint64_t* key_lo, uint64_t* key_hi, uint32_t* id, hipStream_t s);
 void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint32_t* id,
@@ -92,9 +94,12 @@ inline uint32_t vargen_seqs_per_tile(uint64_t nseq, uint64_t nkeys) {
   const uint64_t per = 3584 * nseq / nkeys;
   return (uint32_t)std::min<uint64_t>(VG_MAX_SEQS_PER_BLOCK, std::max<uint64_t>(1, per));
 }
-void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, uint64_t* elem,
-                        uint32_t idbits, int npass, const uint32_t* shifts, const uint32_t* masks,
-                        uint32_t* hist, uint32_t* tcounts, uint32_t seqs_per_block, hipStream_t s);
+// distinct: voff counts distinct variants (launch_pack with distinct) and
+// only the canonical deletion sets are written
+void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, int k, bool distinct,
+                        uint64_t* elem, uint32_t idbits, int npass, const uint32_t* shifts,
+                        const uint32_t* masks, uint32_t* hist, uint32_t* tcounts,
+                        uint32_t seqs_per_block, hipStream_t s);
 bool group_cap_supported(int cap);
 void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_t* seg_start,
                        uint32_t* seg_end, hipStream_t s);

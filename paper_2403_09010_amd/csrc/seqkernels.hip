@@ -58,7 +58,8 @@ __device__ __forceinline__ uint32_t lev_keys(u128 a, u128 b) {
 
 __global__ __launch_bounds__(NT) void k_pack(const uint8_t* __restrict__ codes,
                                              const int64_t* __restrict__ offs, uint64_t n, int k,
-                                             u128* __restrict__ seq, uint32_t* __restrict__ vcnt,
+                                             int distinct, u128* __restrict__ seq,
+                                             uint32_t* __restrict__ vcnt,
                                              uint32_t* __restrict__ err) {
   const uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(NT) void k_pack(const uint8_t* __restrict__ codes,
   }
   if (bad) atomicOr(err, SD_ERRBIT_ALPHABET);
   seq[i] = key;
-  if (vcnt) vcnt[i] = num_variants((uint32_t)L, k);
+  if (vcnt) vcnt[i] = distinct ? num_distinct_variants(key, k) : num_variants((uint32_t)L, k);
 }
 
 // ------------------------------------------------------------------ vargen
@@ -238,11 +239,11 @@ namespace sd {
 
 static unsigned blocks_for(uint64_t n, uint64_t per) { return (unsigned)((n + per - 1) / per); }
 
-void launch_pack(const uint8_t* codes, const int64_t* offs, uint64_t n, int k, u128* seq,
-                 uint32_t* vcnt, uint32_t* err, hipStream_t s) {
+void launch_pack(const uint8_t* codes, const int64_t* offs, uint64_t n, int k, bool distinct,
+                 u128* seq, uint32_t* vcnt, uint32_t* err, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(sdk::k_pack, dim3(blocks_for(n, sdk::NT)), dim3(sdk::NT), 0, s, codes, offs,
-                     n, k, seq, vcnt, err);
+                     n, k, distinct ? 1 : 0, seq, vcnt, err);
 }
 
 void launch_vargen(const u128* seq, const uint64_t* voff, uint64_t nseq, int k, uint64_t* key_lo,
