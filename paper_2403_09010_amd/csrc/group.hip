@@ -81,8 +81,6 @@ struct PassDigits {
   uint32_t mask[3];
 };
 
-// Variants of one block's sequences: at most VG_SEQS * V(24, 2) = 64 * 301.
-constexpr int VG_MAX_VARIANTS = VG_SEQS * 301;
 // prefix XORs per sequence: indices 0..L + 2 <= 26 are read; an odd row
 // length starts consecutive rows in different LDS banks
 constexpr int VG_PRE = 27;
@@ -109,9 +107,11 @@ __device__ __forceinline__ void variant_positions(uint32_t L, uint32_t v, uint32
   p2 = none ? L + 1 : one ? L : (uint32_t)q2;
 }
 
-// DISTINCT: the variant offsets count distinct strings only
-// (num_distinct_variants); every V(L, k) deletion set is still enumerated,
-// and the canonical ones are written compactly in enumeration order.
+// One block per spb sequences. Each wave takes every fourth sequence and
+// enumerates its V(L, k) deletion sets in chunks of 64 lanes, two chunks at a
+// time. DISTINCT: the variant offsets count distinct strings only
+// (num_distinct_variants), and a wave writes the canonical deletion sets of
+// the sequence compactly, in enumeration order, at its offset.
 template <bool DISTINCT>
 __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ seq,
                                                        const uint64_t* __restrict__ voff,
@@ -121,18 +121,13 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
                                                        uint32_t* __restrict__ hist,
                                                        uint32_t* __restrict__ tcounts,
                                                        uint32_t spb) {
-  constexpr int ILP = 4;
   constexpr int NWV = VG_NT / 64;
   __shared__ uint64_t s_off[VG_SEQS + 1];
   __shared__ uint64_t s_pre[VG_SEQS * VG_PRE];
   __shared__ uint64_t s_c[32];
   __shared__ uint32_t s_len[VG_SEQS];
-  __shared__ uint32_t s_info[VG_SEQS];
-  __shared__ uint32_t s_roff[VG_SEQS + 1];  // block-local first deletion set of each sequence
+  __shared__ uint32_t s_n1[VG_SEQS], s_n2[VG_SEQS];  // canonical-test masks
   __shared__ uint32_t s_h[3 * 256];
-  __shared__ uint32_t s_vc[2][ILP * NWV];   // canonical counts per (u, wave), by parity
-  __shared__ uint8_t s_res[DISTINCT ? VG_SEQS * KEY_MAX_LEN : 1];
-  __shared__ uint8_t s_map[VG_MAX_VARIANTS];  // block-local deletion set -> sequence
   // spb <= VG_SEQS sequences per block
   const uint64_t s0 = (uint64_t)blockIdx.x * spb;
   const uint32_t ns = (uint32_t)min<uint64_t>(spb, nseq - s0);
@@ -149,10 +144,19 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
       const u128 key = live ? seq[s0 + x] : (u128)0;
       const uint32_t L = key_len(key);
       uint64_t term = 0;
+      uint32_t r = 32u + t;  // distinct from every residue
       if (live && t < L) {
-        const uint32_t r = (uint32_t)(key >> (115 - 5 * t)) & 31u;
+        r = (uint32_t)(key >> (115 - 5 * t)) & 31u;
         term = __builtin_rotateright64(kHashTab.b[r], t);
-        if (DISTINCT) s_res[x * KEY_MAX_LEN + t] = (uint8_t)r;
+      }
+      if (DISTINCT) {
+        const uint32_t r1 = __shfl_down(r, 1, 32), r2 = __shfl_down(r, 2, 32);
+        const uint64_t b1 = __ballot(t < L && (t + 1 == L || r != r1));
+        const uint64_t b2 = __ballot(t + 1 < L && (t + 2 == L || r != r2));
+        if (live && t == 0) {
+          s_n1[x] = (uint32_t)(b1 >> (32 * half));
+          s_n2[x] = (uint32_t)(b2 >> (32 * half));
+        }
       }
       // inclusive XOR scan over the 32 lanes of the half-wave
       uint32_t lo = (uint32_t)term, hi = (uint32_t)(term >> 32);
@@ -175,87 +179,45 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   }
   __syncthreads();
   const uint64_t g0 = s_off[0];
-  // the deletion sets to enumerate: all V(L, k) of every sequence
-  if (w == 0) {
-    const uint32_t c = lane < ns ? (DISTINCT ? num_variants(s_len[lane], k)
-                                             : (uint32_t)(s_off[lane + 1] - s_off[lane]))
-                                 : 0u;
-    const uint32_t incl = wave_incl_scan(c);
-    if (lane < ns) s_roff[lane + 1] = incl;
-    if (lane == 0) s_roff[0] = 0;
-  }
-  __syncthreads();
-  const uint32_t nv = s_roff[ns];
-  // each wave labels the deletion sets of every fourth sequence and packs
-  // its block-local first one (< 2^15) with its length
-  for (uint32_t x = w; x < ns; x += NWV) {
-    const uint32_t a = s_roff[x], b = s_roff[x + 1];
-    for (uint32_t t = a + lane; t < b; t += 64) s_map[t] = (uint8_t)x;
-    if (lane == 0) s_info[x] = a | (s_len[x] << 16);
-  }
-  __syncthreads();
   const uint64_t idmask = (1ull << idbits) - 1;
   const uint32_t sh[3] = {pd.shift[0], pd.shift[1], pd.shift[2]};
   const uint32_t mk[3] = {pd.mask[0], pd.mask[1], pd.mask[2]};
   uint64_t* __restrict__ out = elem + g0;
   const bool tiled = tcounts != nullptr;
-  uint32_t written = 0;  // canonical variants written by earlier iterations
-  int par = 0;
-  // four independent deletion sets per thread and iteration, so their LDS
-  // reads overlap
-  for (uint32_t t = 0; t < nv; t += VG_NT * ILP) {
-    uint32_t xs[ILP];
+  for (uint32_t x = w; x < ns; x += NWV) {
+    const uint32_t L = s_len[x];
+    const uint32_t n1 = DISTINCT ? s_n1[x] : 0u, n2 = DISTINCT ? s_n2[x] : 0u;
+    const uint32_t nraw = DISTINCT ? num_variants(L, k) : (uint32_t)(s_off[x + 1] - s_off[x]);
+    const uint64_t* P = s_pre + x * VG_PRE;
+    const uint64_t id = s0 + x;
+    uint32_t at = (uint32_t)(s_off[x] - g0);  // next output slot of this sequence
+    const uint32_t end = (uint32_t)(s_off[x + 1] - g0);
+    for (uint32_t c0 = 0; c0 < nraw; c0 += 128) {
+      uint64_t e[2];
+      bool keep[2];
 #pragma unroll
-    for (int u = 0; u < ILP; ++u) {
-      const uint32_t tt = t + u * VG_NT + threadIdx.x;
-      xs[u] = tt < nv ? s_map[tt] : 0u;
-    }
-    uint64_t e[ILP];
-    uint32_t pos[ILP];
-    bool keep[ILP];
-#pragma unroll
-    for (int u = 0; u < ILP; ++u) {
-      const uint32_t tt = t + u * VG_NT + threadIdx.x;
-      const uint32_t x = xs[u];
-      const uint32_t info = s_info[x];
-      const uint32_t v = tt < nv ? tt - (info & 0xFFFFu) : 0u;
-      const uint32_t L = info >> 16;
-      uint32_t p1, p2;
-      variant_positions(L, v, p1, p2);
-      const uint32_t m = L - (uint32_t)(v != 0) - (uint32_t)(v > L);
-      const uint64_t* P = s_pre + x * VG_PRE;
-      const uint64_t h = s_c[m] ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
-                         __builtin_rotateleft64(P[L] ^ P[p2 + 1], 2);
-      e[u] = (h & ~idmask) | (s0 + x);
-      keep[u] = tt < nv && (!DISTINCT || variant_canonical(s_res + x * KEY_MAX_LEN, L, p1, p2));
-      pos[u] = tt;
-    }
-    if (DISTINCT) {
-      // compact the canonical ones in enumeration order (u, wave, lane)
-      uint64_t bal[ILP];
-#pragma unroll
-      for (int u = 0; u < ILP; ++u) {
-        bal[u] = __ballot(keep[u]);
-        if (lane == 0) s_vc[par][u * NWV + w] = (uint32_t)__popcll(bal[u]);
+      for (int u = 0; u < 2; ++u) {
+        const uint32_t v = c0 + 64 * u + lane;
+        uint32_t p1, p2;
+        variant_positions(L, v < nraw ? v : 0u, p1, p2);
+        const uint32_t m = L - (uint32_t)(p1 < L) - (uint32_t)(p2 < L);
+        const uint64_t h = s_c[m] ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
+                           __builtin_rotateleft64(P[L] ^ P[p2 + 1], 2);
+        e[u] = (h & ~idmask) | id;
+        keep[u] = v < nraw && (!DISTINCT || variant_canonical(n1, n2, L, p1, p2));
       }
-      __syncthreads();
-      uint32_t run = written;
 #pragma unroll
-      for (int i = 0; i < ILP * NWV; ++i) {
-        const uint32_t c = s_vc[par][i];
-        if (i % NWV == (int)w) pos[i / NWV] = run + mask_rank(bal[i / NWV]);
-        run += c;
-      }
-      written = run;
-      par ^= 1;
-    }
+      for (int u = 0; u < 2; ++u) {
+        const uint64_t bal = __ballot(keep[u]);
+        // (the pack kernel's count and the canonical test agree, so the
+        // bound never drops a variant; it keeps any disagreement in range)
+        if (keep[u] && at + mask_rank(bal) < end) {
+          out[at + mask_rank(bal)] = e[u];
 #pragma unroll
-    for (int u = 0; u < ILP; ++u) {
-      if (keep[u]) {
-        out[pos[u]] = e[u];
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-          if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e[u] >> sh[q]) & mk[q])], 1u);
+          for (int q = 0; q < 3; ++q)
+            if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e[u] >> sh[q]) & mk[q])], 1u);
+        }
+        at += (uint32_t)__popcll(bal);
       }
     }
   }

@@ -57,14 +57,15 @@ __host__ __device__ __forceinline__ uint32_t num_variants(uint32_t L, int k) {
 // with every position between matched). Deletion variants of one string are
 // counted once each this way (Section II A defines the variant set; the
 // multiplicity only changes how often a pair is found, not which pairs).
-__device__ __forceinline__ bool variant_canonical(const uint8_t* r, uint32_t L, uint32_t p1,
-                                                  uint32_t p2) {
-  // p2 = L: one deletion at p1; p1 = L: none (the forms of variant_positions)
+// With n1 bit p = (p = L - 1 or s[p] != s[p + 1]) and n2 bit p = (p = L - 2
+// or s[p] != s[p + 2]), in the position forms of variant_positions (p2 = L:
+// one deletion at p1; p1 = L: none).
+__device__ __forceinline__ bool variant_canonical(uint32_t n1, uint32_t n2, uint32_t L,
+                                                  uint32_t p1, uint32_t p2) {
   if (p1 >= L) return true;
-  if (p2 >= L) return p1 + 1 == L || r[p1] != r[p1 + 1];
-  const bool b = p2 + 1 == L || r[p2] != r[p2 + 1];
-  const bool a = p1 + 1 < p2 ? r[p1] != r[p1 + 1] : (p2 + 1 == L || r[p1] != r[p2 + 1]);
-  return a && b;
+  if (p2 >= L) return (n1 >> p1) & 1u;
+  const uint32_t a = p1 + 1 < p2 ? (n1 >> p1) : (n2 >> p1);
+  return (a & (n1 >> p2) & 1u) != 0;
 }
 
 // Number of distinct strings among the deletion variants with at most k
