@@ -163,11 +163,30 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 2);
   std::vector<const uint32_t*> hists;
   for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
-  const CountedFirst first{tcounts, (n + spt - 1) / spt, voff, spt, n};
-  const bool flip = radix_sort(cl, e1, nullptr, nullptr, e2, nullptr, nullptr, 1, false, nk, digits,
-                               hists, &first);
+  // pass 1 from the generator's counts (the count scans, then the scatter),
+  // then the onesweep passes
+  bool flip = false;
+  if (!digits.empty()) {
+    const uint64_t tiles = (n + spt - 1) / spt;
+    uint32_t* local = cl.sc.get<uint32_t>(tiles * 256);
+    uint32_t* bsum = cl.sc.get<uint32_t>((uint64_t)counted_scan_rows(tiles) * 256);
+    launch_counted_scan(tcounts, tiles, local, bsum, s);
+    cl.tm.mark("counted_scan", (double)tiles * 256 * 12, 2);
+    launch_counted_scatter(e1, e2, nk, digits[0].shift, digits[0].mask, tiles, local, bsum, voff,
+                           spt, n, cl.lb_err(), s);
+    cl.tm.mark("hash_counted_pass", (double)nk * 16, 1);
+    flip = true;
+  }
+  if (digits.size() > 1) {
+    uint64_t* in = flip ? e2 : e1;
+    uint64_t* other = flip ? e1 : e2;
+    const bool f2 = radix_sort(cl, in, nullptr, nullptr, other, nullptr, nullptr, 1, false, nk,
+                               std::vector<Digit>(digits.begin() + 1, digits.end()),
+                               std::vector<const uint32_t*>(hists.begin() + 1, hists.end()));
+    if (f2) flip = !flip;
+    cl.tm.mark("hash_passes", (double)nk * 16 * (digits.size() - 1), (int)digits.size() - 1);
+  }
   passes_out = (int)digits.size();
-  cl.tm.mark("hash_passes", (double)nk * 16 * digits.size(), (int)digits.size());
   const uint64_t* E = flip ? e2 : e1;
 
   // segment table, then one workgroup per `spw` segment values

@@ -587,19 +587,35 @@ uint32_t counted_scan_rows(uint64_t tiles) {
   return (uint32_t)((tiles + R - 1) / R);
 }
 
-void launch_counted_pass(const uint64_t* in, uint64_t* out, uint32_t n, int shift, uint32_t mask,
-                         const uint32_t* counts, uint64_t tiles, const uint64_t* voff,
-                         uint32_t seqs_per_tile, uint64_t nseq, uint32_t* local, uint32_t* bsum,
-                         uint32_t* err, hipStream_t s) {
-  if (!n || !tiles) return;
+void launch_counted_scan(const uint32_t* counts, uint64_t tiles, uint32_t* local, uint32_t* bsum,
+                         hipStream_t s) {
+  if (!tiles) return;
   const uint32_t R = counted_rows_per_block(tiles);
   const uint32_t nb = counted_scan_rows(tiles);
   hipLaunchKernelGGL(sdk::k_tile_scan_local, dim3(nb), dim3(sdk::RADIX), 0, s, counts,
                      (uint32_t)tiles, R, local, bsum);
   hipLaunchKernelGGL(sdk::k_tile_scan_blocks, dim3(1), dim3(sdk::CT_SCAN_GROUPS * sdk::RADIX), 0, s,
                      bsum, nb);
+}
+
+void launch_counted_scatter(const uint64_t* in, uint64_t* out, uint32_t n, int shift, uint32_t mask,
+                            uint64_t tiles, const uint32_t* local, const uint32_t* bsum,
+                            const uint64_t* voff, uint32_t seqs_per_tile, uint64_t nseq,
+                            uint32_t* err, hipStream_t s) {
+  if (!n || !tiles) return;
+  const uint32_t R = counted_rows_per_block(tiles);
   hipLaunchKernelGGL((sdk::k_scatter_counted<sdk::CT_ITEMS>), dim3((unsigned)tiles), dim3(sdk::NT),
                      0, s, in, out, n, shift, mask, local, bsum, R, voff, seqs_per_tile, nseq, err);
+}
+
+void launch_counted_pass(const uint64_t* in, uint64_t* out, uint32_t n, int shift, uint32_t mask,
+                         const uint32_t* counts, uint64_t tiles, const uint64_t* voff,
+                         uint32_t seqs_per_tile, uint64_t nseq, uint32_t* local, uint32_t* bsum,
+                         uint32_t* err, hipStream_t s) {
+  if (!n || !tiles) return;
+  launch_counted_scan(counts, tiles, local, bsum, s);
+  launch_counted_scatter(in, out, n, shift, mask, tiles, local, bsum, voff, seqs_per_tile, nseq,
+                         err, s);
 }
 
 uint64_t scan_tile() { return (uint64_t)sdk::NT * sdk::SCAN_ITEMS; }

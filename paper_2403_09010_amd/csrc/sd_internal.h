@@ -58,6 +58,13 @@ void launch_counted_pass(const uint64_t* in, uint64_t* out, uint32_t n, int shif
                          const uint32_t* counts, uint64_t tiles, const uint64_t* voff,
                          uint32_t seqs_per_tile, uint64_t nseq, uint32_t* local, uint32_t* bsum,
                          uint32_t* err, hipStream_t s);
+// the two halves of launch_counted_pass: the count scans, then the scatter
+void launch_counted_scan(const uint32_t* counts, uint64_t tiles, uint32_t* local, uint32_t* bsum,
+                         hipStream_t s);
+void launch_counted_scatter(const uint64_t* in, uint64_t* out, uint32_t n, int shift, uint32_t mask,
+                            uint64_t tiles, const uint32_t* local, const uint32_t* bsum,
+                            const uint64_t* voff, uint32_t seqs_per_tile, uint64_t nseq,
+                            uint32_t* err, hipStream_t s);
 uint64_t scan_tile();
 void launch_scan_excl(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* status,
                       uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s);

@@ -1,0 +1,118 @@
+"""The rule by which the hashed path generates each distinct deletion variant
+of a sequence once (the GPU keeps only "canonical" deletion sets; their
+count per sequence sizes the variant offsets).
+
+Deleting a set D of at most two positions from s gives a string t; the
+greedy leftmost embedding of t in s deletes a unique set D*(t). For |D| <= 2
+the test D == D* is local (see variant_canonical in the device header):
+
+  {p}       : p = L-1 or s[p] != s[p+1]
+  {p1 < p2} : (p2 = L-1 or s[p2] != s[p2+1]) and
+              (s[p1] != s[p1+1] if p2 > p1+1, else p2 = L-1 or s[p1] != s[p1+2])
+
+and the number of canonical sets has the O(L) form used by the pack kernel.
+These checks hold the rule against brute force: every distinct variant string
+has exactly one canonical deletion set, and the count matches. The variant
+set itself is the paper's (Section II A); the rule only drops repeats of the
+same string, so the pairs found are unchanged.
+"""
+import itertools
+import random
+
+import pytest
+
+
+def variants(s, k):
+    """Every deletion set with at most k positions and the string it leaves."""
+    L = len(s)
+    out = [((), s)]
+    for m in range(1, min(k, L) + 1):
+        for D in itertools.combinations(range(L), m):
+            out.append((D, "".join(c for i, c in enumerate(s) if i not in D)))
+    return out
+
+
+def greedy_deleted(s, t):
+    """Positions of s left out by the greedy leftmost embedding of t."""
+    j, dele = 0, []
+    for i, c in enumerate(s):
+        if j < len(t) and c == t[j]:
+            j += 1
+        else:
+            dele.append(i)
+    assert j == len(t)
+    return tuple(dele)
+
+
+def canonical(s, D):
+    L = len(s)
+    if len(D) == 0:
+        return True
+    if len(D) == 1:
+        p = D[0]
+        return p == L - 1 or s[p] != s[p + 1]
+    p1, p2 = D
+    b = p2 == L - 1 or s[p2] != s[p2 + 1]
+    if p1 + 1 < p2:
+        a = s[p1] != s[p1 + 1]
+    else:
+        a = p2 == L - 1 or s[p1] != s[p1 + 2]
+    return a and b
+
+
+def distinct_count(s, k):
+    """The O(L) count of canonical sets (the pack kernel's form)."""
+    L = len(s)
+    c = 1
+    if k >= 1:
+        c += sum(1 for p in range(L) if p == L - 1 or s[p] != s[p + 1])
+    if k >= 2:
+        run = 0  # canonical first deletions p1 <= p2 - 2
+        for p2 in range(1, L):
+            if p2 >= 2 and s[p2 - 2] != s[p2 - 1]:
+                run += 1
+            if p2 == L - 1 or s[p2] != s[p2 + 1]:
+                c += run
+                if p2 == L - 1 or s[p2 - 1] != s[p2 + 1]:
+                    c += 1
+    return c
+
+
+def random_strings(n, seed):
+    rng = random.Random(seed)
+    for _ in range(n):
+        L = rng.randint(1, 10)
+        alphabet = "ACDEFGHIKLMNPQRSTVWY"[: rng.choice([1, 2, 3, 20])]
+        yield "".join(rng.choice(alphabet) for _ in range(L))
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_one_canonical_set_per_distinct_string(k):
+    for s in random_strings(3000, 11 + k):
+        by_string = {}
+        for D, t in variants(s, k):
+            by_string.setdefault(t, []).append(D)
+        for t, Ds in by_string.items():
+            canon = [D for D in Ds if canonical(s, D)]
+            assert len(canon) == 1, (s, t, Ds)
+            # the canonical set is the greedy embedding's
+            assert canon[0] == greedy_deleted(s, t), (s, t)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_distinct_count_formula(k):
+    for s in random_strings(3000, 23 + k):
+        assert distinct_count(s, k) == len({t for _, t in variants(s, k)}), s
+
+
+def test_worked_cases():
+    # a run of equal residues: deleting any one of "AAA" gives the same string
+    assert distinct_count("AAA", 1) == 2          # "AAA", "AA"
+    assert distinct_count("AAA", 2) == 3          # + "A"
+    # the periodic case that a shift-left rule gets wrong: ABAB minus two
+    # adjacent positions gives "AB" three ways and "BA" once
+    assert sorted(t for D, t in variants("ABAB", 2) if len(D) == 2 and canonical("ABAB", D)) == \
+        ["AA", "AB", "BA", "BB"]
+    # no repeated residues: every deletion set is canonical
+    s = "ACDEFGHIKL"
+    assert distinct_count(s, 2) == 1 + 10 + 45
