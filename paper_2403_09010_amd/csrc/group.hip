@@ -107,9 +107,9 @@ __device__ __forceinline__ void variant_positions(uint32_t L, uint32_t v, uint32
   p2 = none ? L + 1 : one ? L : (uint32_t)q2;
 }
 
-// One block per spb sequences. Each wave takes every fourth sequence and
-// enumerates its V(L, k) deletion sets in chunks of 64 lanes, two chunks at a
-// time. DISTINCT: the variant offsets count distinct strings only
+// One block per spb sequences; every V(L, k) deletion set of each is
+// enumerated (see the loop below for how waves share them out). DISTINCT: the
+// variant offsets count distinct strings only
 // (num_distinct_variants), and a wave writes the canonical deletion sets of
 // the sequence compactly, in enumeration order, at its offset.
 template <bool DISTINCT>
@@ -127,6 +127,7 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   __shared__ uint64_t s_c[32];
   __shared__ uint32_t s_len[VG_SEQS];
   __shared__ uint32_t s_n1[VG_SEQS], s_n2[VG_SEQS];  // canonical-test masks
+  __shared__ uint32_t s_roff[VG_SEQS + 1];            // block-local deletion-set prefix
   __shared__ uint32_t s_h[3 * 256];
   // spb <= VG_SEQS sequences per block
   const uint64_t s0 = (uint64_t)blockIdx.x * spb;
@@ -178,48 +179,92 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
     }
   }
   __syncthreads();
+  // block-local first deletion set of each sequence: V(L, k) each
+  if (w == 0) {
+    const uint32_t c = lane < ns ? (DISTINCT ? num_variants(s_len[lane], k)
+                                             : (uint32_t)(s_off[lane + 1] - s_off[lane]))
+                                 : 0u;
+    const uint32_t incl = wave_incl_scan(c);
+    if (lane < ns) s_roff[lane + 1] = incl;
+    if (lane == 0) s_roff[0] = 0;
+  }
+  __syncthreads();
   const uint64_t g0 = s_off[0];
   const uint64_t idmask = (1ull << idbits) - 1;
   const uint32_t sh[3] = {pd.shift[0], pd.shift[1], pd.shift[2]};
   const uint32_t mk[3] = {pd.mask[0], pd.mask[1], pd.mask[2]};
   uint64_t* __restrict__ out = elem + g0;
   const bool tiled = tcounts != nullptr;
-  for (uint32_t x = w; x < ns; x += NWV) {
-    const uint32_t L = s_len[x];
-    const uint32_t n1 = DISTINCT ? s_n1[x] : 0u, n2 = DISTINCT ? s_n2[x] : 0u;
-    const uint32_t nraw = DISTINCT ? num_variants(L, k) : (uint32_t)(s_off[x + 1] - s_off[x]);
-    const uint64_t* P = s_pre + x * VG_PRE;
-    const uint64_t id = s0 + x;
-    uint32_t at = (uint32_t)(s_off[x] - g0);  // next output slot of this sequence
-    const uint32_t end = (uint32_t)(s_off[x + 1] - g0);
-    for (uint32_t c0 = 0; c0 < nraw; c0 += 128) {
-      uint64_t e[2];
-      bool keep[2];
+  // Each wave takes a contiguous quarter of the sequences. A sequence with
+  // more than 64 deletion sets is enumerated alone, 128 at a time; runs of
+  // consecutive smaller ones share one 64-lane chunk (lane -> sequence by a
+  // binary search of the block-local prefix s_roff).
+  auto emit = [&](uint64_t e, bool keep, uint32_t at, uint32_t rank, uint32_t end) {
+    // (the pack kernel's count and the canonical test agree, so the bound
+    // never drops a variant; it keeps any disagreement in range)
+    if (keep && at + rank < end) {
+      out[at + rank] = e;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const uint32_t v = c0 + 64 * u + lane;
-        uint32_t p1, p2;
-        variant_positions(L, v < nraw ? v : 0u, p1, p2);
-        const uint32_t m = L - (uint32_t)(p1 < L) - (uint32_t)(p2 < L);
-        const uint64_t h = s_c[m] ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
-                           __builtin_rotateleft64(P[L] ^ P[p2 + 1], 2);
-        e[u] = (h & ~idmask) | id;
-        keep[u] = v < nraw && (!DISTINCT || variant_canonical(n1, n2, L, p1, p2));
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const uint64_t bal = __ballot(keep[u]);
-        // (the pack kernel's count and the canonical test agree, so the
-        // bound never drops a variant; it keeps any disagreement in range)
-        if (keep[u] && at + mask_rank(bal) < end) {
-          out[at + mask_rank(bal)] = e[u];
-#pragma unroll
-          for (int q = 0; q < 3; ++q)
-            if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e[u] >> sh[q]) & mk[q])], 1u);
-        }
-        at += (uint32_t)__popcll(bal);
-      }
+      for (int q = 0; q < 3; ++q)
+        if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e >> sh[q]) & mk[q])], 1u);
     }
+  };
+  auto variant = [&](uint32_t x, uint32_t v, bool valid, uint64_t& e) -> bool {
+    const uint32_t L = s_len[x];
+    uint32_t p1, p2;
+    variant_positions(L, valid ? v : 0u, p1, p2);
+    const uint32_t m = L - (uint32_t)(p1 < L) - (uint32_t)(p2 < L);
+    const uint64_t* P = s_pre + x * VG_PRE;
+    const uint64_t h = s_c[m] ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
+                       __builtin_rotateleft64(P[L] ^ P[p2 + 1], 2);
+    e = (h & ~idmask) | (s0 + x);
+    return valid && (!DISTINCT || variant_canonical(s_n1[x], s_n2[x], L, p1, p2));
+  };
+  const uint32_t xa = w * ns / NWV, xb = (w + 1) * ns / NWV;
+  for (uint32_t x = xa; x < xb;) {
+    const uint32_t nraw = s_roff[x + 1] - s_roff[x];
+    const uint32_t end_x = (uint32_t)(s_off[x + 1] - g0);
+    if (nraw > 64) {
+      uint32_t at = (uint32_t)(s_off[x] - g0);  // next output slot of this sequence
+      for (uint32_t c0 = 0; c0 < nraw; c0 += 128) {
+        uint64_t e[2];
+        bool keep[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const uint32_t v = c0 + 64 * u + lane;
+          keep[u] = variant(x, v, v < nraw, e[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const uint64_t bal = __ballot(keep[u]);
+          emit(e[u], keep[u], at, mask_rank(bal), end_x);
+          at += (uint32_t)__popcll(bal);
+        }
+      }
+      ++x;
+      continue;
+    }
+    // sequences x .. y - 1 fill at most 64 lanes
+    uint32_t y = x + 1;
+    while (y < xb && s_roff[y + 1] - s_roff[x] <= 64) ++y;
+    const uint32_t slot = s_roff[x] + lane;
+    const bool valid = slot < s_roff[y];
+    uint32_t lo = x, hi = y - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_roff[mid] <= slot)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    uint64_t e;
+    const bool keep = variant(lo, slot - s_roff[lo], valid, e);
+    const uint64_t bal = __ballot(keep);
+    // rank among the kept lanes of the same sequence (a contiguous lane range)
+    const uint32_t zl = s_roff[lo] - s_roff[x];
+    const uint64_t mine = bal & ~((1ull << zl) - 1ull);
+    emit(e, keep, (uint32_t)(s_off[lo] - g0), mask_rank(mine), (uint32_t)(s_off[lo + 1] - g0));
+    x = y;
   }
   __syncthreads();
   // With tcounts, every pass's counts are stored as this block's rows (pass

@@ -167,13 +167,15 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   // then the onesweep passes
   bool flip = false;
   if (!digits.empty()) {
-    const uint64_t tiles = (n + spt - 1) / spt;
+    const uint64_t blocks = (n + spt - 1) / spt;
+    const uint32_t G = vargen_blocks_per_tile(n, nk, spt);
+    const uint64_t tiles = (blocks + G - 1) / G;
     uint32_t* local = cl.sc.get<uint32_t>(tiles * 256);
     uint32_t* bsum = cl.sc.get<uint32_t>((uint64_t)counted_scan_rows(tiles) * 256);
-    launch_counted_scan(tcounts, tiles, local, bsum, s);
-    cl.tm.mark("counted_scan", (double)tiles * 256 * 12, 2);
+    launch_counted_scan(tcounts, blocks, G, local, bsum, s);
+    cl.tm.mark("counted_scan", (double)blocks * 256 * 4 + (double)tiles * 256 * 8, 2);
     launch_counted_scatter(e1, e2, nk, digits[0].shift, digits[0].mask, tiles, local, bsum, voff,
-                           spt, n, cl.lb_err(), s);
+                           spt * G, n, cl.lb_err(), s);
     cl.tm.mark("hash_counted_pass", (double)nk * 16, 1);
     flip = true;
   }

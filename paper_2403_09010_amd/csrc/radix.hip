@@ -257,8 +257,10 @@ constexpr uint32_t CT_CHUNK = NT * CT_ITEMS;
 constexpr int CT_LOADS = 16;  // loads in flight per thread in the count scans
 
 // Per block of R consecutive tiles and per digit: the exclusive running sum
-// inside the block (into local) and the block total (into bsum).
+// inside the block (into local) and the block total (into bsum). A tile's
+// counts are the sum of G consecutive rows of counts (nrows rows in all).
 __global__ __launch_bounds__(RADIX) void k_tile_scan_local(const uint32_t* __restrict__ counts,
+                                                           uint32_t nrows, uint32_t G,
                                                            uint32_t tiles, uint32_t R,
                                                            uint32_t* __restrict__ local,
                                                            uint32_t* __restrict__ bsum) {
@@ -268,8 +270,13 @@ __global__ __launch_bounds__(RADIX) void k_tile_scan_local(const uint32_t* __res
   for (uint32_t t = t0; t < t1; t += CT_LOADS) {
     uint32_t c[CT_LOADS];
 #pragma unroll
-    for (int u = 0; u < CT_LOADS; ++u)
-      c[u] = t + u < t1 ? counts[(uint64_t)(t + u) * RADIX + d] : 0u;
+    for (int u = 0; u < CT_LOADS; ++u) {
+      c[u] = 0;
+      if (t + u < t1) {
+        const uint32_t r0 = (t + u) * G, r1 = min(r0 + G, nrows);
+        for (uint32_t r = r0; r < r1; ++r) c[u] += counts[(uint64_t)r * RADIX + d];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < CT_LOADS; ++u) {
       if (t + u < t1) local[(uint64_t)(t + u) * RADIX + d] = run;
@@ -587,13 +594,14 @@ uint32_t counted_scan_rows(uint64_t tiles) {
   return (uint32_t)((tiles + R - 1) / R);
 }
 
-void launch_counted_scan(const uint32_t* counts, uint64_t tiles, uint32_t* local, uint32_t* bsum,
-                         hipStream_t s) {
-  if (!tiles) return;
+void launch_counted_scan(const uint32_t* counts, uint64_t nrows, uint32_t rows_per_tile,
+                         uint32_t* local, uint32_t* bsum, hipStream_t s) {
+  if (!nrows) return;
+  const uint64_t tiles = (nrows + rows_per_tile - 1) / rows_per_tile;
   const uint32_t R = counted_rows_per_block(tiles);
   const uint32_t nb = counted_scan_rows(tiles);
   hipLaunchKernelGGL(sdk::k_tile_scan_local, dim3(nb), dim3(sdk::RADIX), 0, s, counts,
-                     (uint32_t)tiles, R, local, bsum);
+                     (uint32_t)nrows, rows_per_tile, (uint32_t)tiles, R, local, bsum);
   hipLaunchKernelGGL(sdk::k_tile_scan_blocks, dim3(1), dim3(sdk::CT_SCAN_GROUPS * sdk::RADIX), 0, s,
                      bsum, nb);
 }
@@ -613,7 +621,7 @@ void launch_counted_pass(const uint64_t* in, uint64_t* out, uint32_t n, int shif
                          uint32_t seqs_per_tile, uint64_t nseq, uint32_t* local, uint32_t* bsum,
                          uint32_t* err, hipStream_t s) {
   if (!n || !tiles) return;
-  launch_counted_scan(counts, tiles, local, bsum, s);
+  launch_counted_scan(counts, tiles, 1, local, bsum, s);
   launch_counted_scatter(in, out, n, shift, mask, tiles, local, bsum, voff, seqs_per_tile, nseq,
                          err, s);
 }

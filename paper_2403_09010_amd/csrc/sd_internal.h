@@ -58,9 +58,12 @@ void launch_counted_pass(const uint64_t* in, uint64_t* out, uint32_t n, int shif
                          const uint32_t* counts, uint64_t tiles, const uint64_t* voff,
                          uint32_t seqs_per_tile, uint64_t nseq, uint32_t* local, uint32_t* bsum,
                          uint32_t* err, hipStream_t s);
-// the two halves of launch_counted_pass: the count scans, then the scatter
-void launch_counted_scan(const uint32_t* counts, uint64_t tiles, uint32_t* local, uint32_t* bsum,
-                         hipStream_t s);
+// the two halves of launch_counted_pass: the count scans, then the scatter.
+// Here a tile's counts may be the sum of rows_per_tile consecutive rows of
+// counts (nrows rows); the scatter's tiles are then rows_per_tile times as
+// many sequences.
+void launch_counted_scan(const uint32_t* counts, uint64_t nrows, uint32_t rows_per_tile,
+                         uint32_t* local, uint32_t* bsum, hipStream_t s);
 void launch_counted_scatter(const uint64_t* in, uint64_t* out, uint32_t n, int shift, uint32_t mask,
                             uint64_t tiles, const uint32_t* local, const uint32_t* bsum,
                             const uint64_t* voff, uint32_t seqs_per_tile, uint64_t nseq,
@@ -100,6 +103,14 @@ inline uint32_t vargen_seqs_per_tile(uint64_t nseq, uint64_t nkeys) {
   if (!nseq || !nkeys) return VG_MAX_SEQS_PER_BLOCK;
   const uint64_t per = 3584 * nseq / nkeys;
   return (uint32_t)std::min<uint64_t>(VG_MAX_SEQS_PER_BLOCK, std::max<uint64_t>(1, per));
+}
+// Generator blocks per counted tile: when a block's sequences yield well
+// under 3584 variants (few variants per sequence), several blocks form one
+// tile so that the tile still fills most of a chunk.
+inline uint32_t vargen_blocks_per_tile(uint64_t nseq, uint64_t nkeys, uint32_t spb) {
+  if (!nseq || !nkeys) return 1;
+  const double per_block = (double)nkeys / (double)nseq * spb;
+  return (uint32_t)std::max(1.0, std::floor(3584.0 / per_block));
 }
 // distinct: voff counts distinct variants (launch_pack with distinct) and
 // only the canonical deletion sets are written
