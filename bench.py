@@ -44,6 +44,7 @@ KERNEL_OF_STAGE = {
     "sort_passes": "k_onesweep",
     "emit": "k_emit_runs",
 }
+HBM_STAGES = ("hash_passes", "hash_counted_pass", "sort_passes")
 
 
 def log(msg):
@@ -478,7 +479,10 @@ def main():
                 "algorithmic_bytes_per_launch": per_launch_bytes}
 
     single = [x for x in stage_ms if x in KERNEL_OF_STAGE and stage_launch[x] > 0]
-    dom = max(single, key=lambda x: stage_ms[x] / max(1, stage_launch[x]))
+    # the dominant HBM-bound kernel (variant generation is ALU-bound, the
+    # grouping LDS/latency-bound; their stage times are in stages_ms)
+    hbm = [x for x in single if x in HBM_STAGES] or single
+    dom = max(hbm, key=lambda x: stage_ms[x] / max(1, stage_launch[x]))
     roofline = roof(dom)
     sort_stage = "hash_passes" if "hash_passes" in single else "sort_passes"
     sort_roofline = roof(sort_stage) if sort_stage in single else None

@@ -766,9 +766,14 @@ void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, in
   else
     hipLaunchKernelGGL(sdk::k_vargen_hash<false>, dim3(g), dim3(sdk::VG_NT), 0, s, seq, voff, nseq,
                        k, elem, idbits, npass, pd, hist, npass ? tcounts : nullptr, seqs_per_block);
-  if (tcounts && npass > 1)
-    hipLaunchKernelGGL(sdk::k_hist_rows, dim3(std::min(128u, g), npass - 1), dim3(256), 0, s, tcounts,
-                       g, hist);
+}
+
+void launch_hist_rows(const uint32_t* tcounts, uint64_t nseq, uint32_t seqs_per_block, int npass,
+                      uint32_t* hist, hipStream_t s) {
+  if (!nseq || !tcounts || npass < 2) return;
+  const unsigned g = (unsigned)((nseq + seqs_per_block - 1) / seqs_per_block);
+  hipLaunchKernelGGL(sdk::k_hist_rows, dim3(std::min(128u, g), npass - 1), dim3(256), 0, s, tcounts,
+                     g, hist);
 }
 
 void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_t* seg_start,

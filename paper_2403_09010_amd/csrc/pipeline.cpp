@@ -160,7 +160,11 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   }
   launch_vargen_hash(seq, voff, n, k, true, e1, idbits, (int)digits.size(), shifts, masks, hist,
                      tcounts, spt, s);
-  cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 2);
+  cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 1);
+  if (!digits.empty()) {
+    launch_hist_rows(tcounts, n, spt, (int)digits.size(), hist, s);
+    cl.tm.mark("hist_rows", (double)((n + spt - 1) / spt) * 256 * 4 * digits.size(), 1);
+  }
   std::vector<const uint32_t*> hists;
   for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
   // pass 1 from the generator's counts (the count scans, then the scatter),

@@ -92,6 +92,7 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   }
   launch_vargen_hash(p.seq, p.voff, q.n, k, true, e1, idx->idbits, (int)digits.size(), shifts,
                      masks, hist, tcounts, spt, s);
+  launch_hist_rows(tcounts, q.n, spt, (int)digits.size(), hist, s);
   std::vector<const uint32_t*> hists;
   for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
   const CountedFirst first{tcounts, (q.n + spt - 1) / spt, p.voff, spt, q.n};

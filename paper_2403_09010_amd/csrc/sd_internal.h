@@ -90,11 +90,11 @@ void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* seq_a,
 // hashed grouping (element = hash of the key in the top 64 - idbits bits, id below)
 // Every variant as [hash | id] in voff order; block b generates sequences
 // [b * seqs_per_block, ...) (1 <= seqs_per_block <= VG_MAX_SEQS_PER_BLOCK).
-// hist[q * 256 + d] receives the digit counts of pass q, except pass 0's
-// when tcounts is non-null: then tcounts holds npass * G rows of 256 (G =
-// ceil(nseq / seqs_per_block) blocks, every entry written), pass q's block
-// counts at rows q * G .. q * G + G - 1, and the first G rows are the tiles
-// of a counted first pass.
+// hist[q * 256 + d] receives the digit counts of pass q, unless tcounts is
+// non-null: then tcounts holds npass * G rows of 256 (G = ceil(nseq /
+// seqs_per_block) blocks, every entry written), pass q's block counts at rows
+// q * G .. q * G + G - 1; the first G rows are the tiles of a counted first
+// pass and launch_hist_rows sums the others into hist.
 constexpr uint32_t VG_MAX_SEQS_PER_BLOCK = 64;
 // Sequences per generator block for a counted first pass: tiles of about
 // 3584 elements, which with at most 301 variants per sequence fit the pass's
@@ -118,6 +118,10 @@ void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, in
                         uint64_t* elem, uint32_t idbits, int npass, const uint32_t* shifts,
                         const uint32_t* masks, uint32_t* hist, uint32_t* tcounts,
                         uint32_t seqs_per_block, hipStream_t s);
+// after launch_vargen_hash with tcounts: hist[q * 256 + d] for q >= 1 from the
+// stored block rows
+void launch_hist_rows(const uint32_t* tcounts, uint64_t nseq, uint32_t seqs_per_block, int npass,
+                      uint32_t* hist, hipStream_t s);
 bool group_cap_supported(int cap);
 void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_t* seg_start,
                        uint32_t* seg_end, hipStream_t s);
