@@ -315,7 +315,7 @@ TileOut learned_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, con
   uint64_t nsteps;
   std::memcpy(&nsteps, readback(c, steps, 8, s), 8);
   c->stats.n_probe_steps += (int64_t)nsteps;
-  TileOut v = verify_candidates(cl, p.seq, q.n, idx->ref_seq, idx->n_ref, cand, nc, k, w);
+  TileOut v = verify_candidates(cl, p.seq, p.planes, q.n, idx->ref_seq, idx->n_ref, cand, nc, k, w);
   v.nkeys = nk;
   v.ncand = nc;
   return v;

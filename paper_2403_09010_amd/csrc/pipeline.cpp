@@ -279,16 +279,17 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
 
   // 1-2: pack and variant offsets
   u128* seq = sc.get<u128>(n);
+  u128* planes = sc.get<u128>(n);
   uint32_t* vcnt = sc.get<uint32_t>(n);
   uint64_t* voff = sc.get<uint64_t>(n + 1);
   // the hashed path generates each distinct variant string of a sequence once
-  launch_pack(in.codes, in.offs, n, k, c->path != 1, seq, vcnt, counters + CNT_ERR, s);
+  launch_pack(in.codes, in.offs, n, k, c->path != 1, seq, planes, vcnt, counters + CNT_ERR, s);
   {
     const uint64_t tiles = (n + scan_tile() - 1) / scan_tile();
     const uint32_t epoch = next_epoch(c, tiles, s);
     launch_scan_excl(vcnt, voff, n, c->status, cl.tile_counter(), epoch, cl.lb_err(), s);
   }
-  tm.mark("pack_scan", (double)n * (16 + 16 + 8 + 4 + 4 + 8), 2);
+  tm.mark("pack_scan", (double)n * (16 + 16 + 16 + 8 + 4 + 4 + 8), 2);
   uint64_t nkeys;
   {
     // one read-back: validation flags and the key total
@@ -356,7 +357,7 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
     if (nc) {
       const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
       const uint32_t epoch = next_epoch(c, tiles, s);
-      launch_verify_compact(sorted, nc, seq, seq, k, oi, oj, od, c->status, cl.tile_counter(),
+      launch_verify_compact(sorted, nc, planes, seq, k, oi, oj, od, c->status, cl.tile_counter(),
                             epoch, pcount, cl.lb_err(), s);
       tm.mark("verify", (double)nc * (8 + 32) + (double)nc * 9, 1);
     } else {
@@ -436,8 +437,8 @@ void pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32_t
   uint32_t* counters = fresh_counters(c, CNT_TOTAL, s);
   u128* sa = sc.get<u128>(da.n);
   u128* sb = sc.get<u128>(db.n);
-  launch_pack(da.codes, da.offs, da.n, 0, false, sa, nullptr, counters, s);
-  launch_pack(db.codes, db.offs, db.n, 0, false, sb, nullptr, counters, s);
+  launch_pack(da.codes, da.offs, da.n, 0, false, sa, nullptr, nullptr, counters, s);
+  launch_pack(db.codes, db.offs, db.n, 0, false, sb, nullptr, nullptr, counters, s);
   const uint32_t* h = static_cast<const uint32_t*>(readback(c, counters, 4, s));
   raise_validation(h[0]);
   launch_pair_distance(sa, da.n, sb, db.n, ia, ib, (uint64_t)n, d_out, counters + 1, s);

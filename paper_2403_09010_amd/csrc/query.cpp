@@ -25,10 +25,12 @@ namespace sd {
 Packed pack_and_count(Call& cl, const DevSeqs& in, int k, bool distinct) {
   Packed p;
   p.seq = cl.sc.get<u128>(in.n);
+  p.planes = cl.sc.get<u128>(in.n);
   uint32_t* vcnt = cl.sc.get<uint32_t>(in.n);
   p.voff = cl.sc.get<uint64_t>(in.n + 1);
   launch_fill_u32(cl.counters + CNT_ERR, 0, 1, cl.s);
-  launch_pack(in.codes, in.offs, in.n, k, distinct, p.seq, vcnt, cl.counters + CNT_ERR, cl.s);
+  launch_pack(in.codes, in.offs, in.n, k, distinct, p.seq, p.planes, vcnt, cl.counters + CNT_ERR,
+              cl.s);
   const uint64_t tiles = (in.n + scan_tile() - 1) / scan_tile();
   const uint32_t epoch = next_epoch(cl.c, tiles, cl.s);
   launch_scan_excl(vcnt, p.voff, in.n, cl.c->status, cl.tile_counter(), epoch, cl.lb_err(), cl.s);
@@ -117,7 +119,7 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   uint64_t* cand = cj.p;
   const uint64_t nc = cj.n;
   out.ncand = nc;
-  TileOut v = verify_candidates(cl, p.seq, q.n, idx->ref_seq, idx->n_ref, cand, nc, k, w);
+  TileOut v = verify_candidates(cl, p.seq, p.planes, q.n, idx->ref_seq, idx->n_ref, cand, nc, k, w);
   v.nkeys = out.nkeys;
   v.ncand = nc;
   return v;
@@ -133,7 +135,8 @@ void check_index(const sd_ctx* c, const sd_index* idx, int k) {
 
 // Sort (q, r) candidate pairs over the digits that can differ, then verify
 // (or rescore) and compact them in order.
-TileOut verify_candidates(Call& cl, const u128* qseq, uint64_t nq, const u128* rseq, uint64_t nr,
+TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint64_t nq,
+                          const u128* rseq, uint64_t nr,
                           uint64_t* cand, uint64_t nc, int k, const WeightedSpec* w) {
   sd_ctx* c = cl.c;
   hipStream_t s = cl.s;
@@ -181,7 +184,7 @@ TileOut verify_candidates(Call& cl, const u128* qseq, uint64_t nq, const u128* r
       } else {
         const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
         const uint32_t epoch = next_epoch(c, tiles, s);
-        launch_verify_compact(sorted, nc, qseq, rseq, k, out.i, out.j, out.d, c->status,
+        launch_verify_compact(sorted, nc, qplanes, rseq, k, out.i, out.j, out.d, c->status,
                               cl.tile_counter(), epoch, pcount, cl.lb_err(), s);
       }
     }

@@ -214,13 +214,14 @@ struct TileOut {
 };
 
 // Sort (q, r) candidates, verify (weighted when w) and compact in order.
-TileOut verify_candidates(Call& cl, const u128* qseq, uint64_t nq, const u128* rseq, uint64_t nr,
+TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint64_t nq, const u128* rseq, uint64_t nr,
                           uint64_t* cand, uint64_t nc, int k, const WeightedSpec* w);
 
 // A packed sequence set: 128-bit keys, exclusive variant offsets (n + 1)
 // and the variant total, in pool blocks of the call.
 struct Packed {
   u128* seq = nullptr;
+  u128* planes = nullptr;  // bit-plane form of each sequence (launch_pack)
   uint64_t* voff = nullptr;
   uint64_t nkeys = 0;
 };

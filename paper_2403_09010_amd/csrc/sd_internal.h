@@ -74,15 +74,18 @@ void launch_scan_excl(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* s
 
 // vcnt[i]: the variants of sequence i, all V(L, k) of them or, with
 // distinct, only the distinct strings among them (variant_canonical)
+// planes (optional): per sequence its residues' five bit planes (plane b in
+// bits [24 b, 24 b + 24)) and its length in bits 127..120, the pattern form
+// of the verification's distance
 void launch_pack(const uint8_t* codes, const int64_t* offs, uint64_t n, int k, bool distinct,
-                 u128* seq, uint32_t* vcnt, uint32_t* err, hipStream_t s);
+                 u128* seq, u128* planes, uint32_t* vcnt, uint32_t* err, hipStream_t s);
 void launch_vargen(const u128* seq, const uint64_t* voff, uint64_t nseq, int k,
                    uint64_t* key_lo, uint64_t* key_hi, uint32_t* id, hipStream_t s);
 void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint32_t* id,
                       uint64_t n, uint64_t* cand, uint64_t cap,
                       unsigned long long* counter, hipStream_t s);
 uint64_t compact_tile();
-void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* seq_a,
+void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* planes_a,
                            const u128* seq_b, int k, uint32_t* out_i, uint32_t* out_j,
                            uint8_t* out_d, uint64_t* status, uint32_t* tile_counter,
                            uint32_t epoch, unsigned long long* out_count, uint32_t* err,

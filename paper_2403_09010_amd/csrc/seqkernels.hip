@@ -54,11 +54,53 @@ __device__ __forceinline__ uint32_t lev_keys(u128 a, u128 b) {
   return score;
 }
 
+// The same distance with the pattern as bit planes: plane b (bits [24 b,
+// 24 b + 24) of pa) holds bit b of every residue of a, the length is in bits
+// 127..120. The positions of a that match the text residue c are then
+// ~OR_b (plane_b ^ (bit b of c ? all ones : 0)), a few bit operations per
+// text residue instead of one comparison per pattern position.
+__device__ __forceinline__ uint32_t lev_planes(u128 pa, u128 b) {
+  const uint32_t m = (uint32_t)(pa >> 120), n = key_len(b);
+  if (m == 0) return n;
+  if (n == 0) return m;
+  const uint64_t lo = (uint64_t)pa, hi = (uint64_t)(pa >> 64);
+  const uint32_t P0 = (uint32_t)lo & 0xFFFFFFu, P1 = (uint32_t)(lo >> 24) & 0xFFFFFFu;
+  const uint32_t P2 = (uint32_t)((lo >> 48) | (hi << 16)) & 0xFFFFFFu;
+  const uint32_t P3 = (uint32_t)(hi >> 8) & 0xFFFFFFu, P4 = (uint32_t)(hi >> 32) & 0xFFFFFFu;
+  const uint32_t mmask = (1u << m) - 1u;
+  uint32_t pv = mmask, mv = 0u, score = m;
+  const uint32_t top = 1u << (m - 1);
+  uint64_t th = (uint64_t)(b >> 64), tl = (uint64_t)b;  // residue j at bits 115 - 5j .. 119 - 5j
+  for (uint32_t j = 0; j < n; ++j) {
+    const uint32_t c = (uint32_t)(th >> 51) & 31u;
+    th = (th << 5) | (tl >> 59);
+    tl <<= 5;
+    const uint32_t x = (P0 ^ (0u - (c & 1u))) | (P1 ^ (0u - ((c >> 1) & 1u))) |
+                       (P2 ^ (0u - ((c >> 2) & 1u))) | (P3 ^ (0u - ((c >> 3) & 1u))) |
+                       (P4 ^ (0u - ((c >> 4) & 1u)));
+    const uint32_t eq = ~x & mmask;
+    const uint32_t xv = eq | mv;
+    const uint32_t xh = (((eq & pv) + pv) ^ pv) | eq;
+    uint32_t ph = mv | ~(xh | pv);
+    uint32_t mh = pv & xh;
+    if (ph & top)
+      ++score;
+    else if (mh & top)
+      --score;
+    ph = (ph << 1) | 1u;
+    mh = mh << 1;
+    pv = mh | ~(xv | ph);
+    mv = ph & xv;
+  }
+  return score;
+}
+
 // ------------------------------------------------------------------ pack
 
 __global__ __launch_bounds__(NT) void k_pack(const uint8_t* __restrict__ codes,
                                              const int64_t* __restrict__ offs, uint64_t n, int k,
                                              int distinct, u128* __restrict__ seq,
+                                             u128* __restrict__ planes,
                                              uint32_t* __restrict__ vcnt,
                                              uint32_t* __restrict__ err) {
   const uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x;
@@ -68,18 +110,28 @@ __global__ __launch_bounds__(NT) void k_pack(const uint8_t* __restrict__ codes,
   if (L < 1 || L > KEY_MAX_LEN) {
     atomicOr(err, SD_ERRBIT_LENGTH);
     seq[i] = 0;
+    if (planes) planes[i] = 0;
     if (vcnt) vcnt[i] = 0;
     return;
   }
   u128 key = (u128)L << 120;
+  uint32_t pl[5] = {0, 0, 0, 0, 0};
   bool bad = false;
   for (int t = 0; t < (int)L; ++t) {
     const uint32_t c = codes[a + t];
     bad |= c >= 20u;
     key |= (u128)(c & 31u) << (115 - 5 * t);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) pl[q] |= ((c >> q) & 1u) << t;
   }
   if (bad) atomicOr(err, SD_ERRBIT_ALPHABET);
   seq[i] = key;
+  if (planes) {
+    const uint64_t lo = (uint64_t)pl[0] | ((uint64_t)pl[1] << 24) | ((uint64_t)pl[2] << 48);
+    const uint64_t hi = ((uint64_t)pl[2] >> 16) | ((uint64_t)pl[3] << 8) | ((uint64_t)pl[4] << 32) |
+                        ((uint64_t)L << 56);
+    planes[i] = ((u128)hi << 64) | lo;
+  }
   if (vcnt) vcnt[i] = distinct ? num_distinct_variants(key, k) : num_variants((uint32_t)L, k);
 }
 
@@ -162,7 +214,7 @@ __global__ __launch_bounds__(NT) void k_emit_runs(const uint64_t* __restrict__ k
 constexpr int CITEMS = 8;
 
 __global__ __launch_bounds__(NT) void k_verify_compact(
-    const uint64_t* __restrict__ cand, uint64_t c, const u128* __restrict__ sa,
+    const uint64_t* __restrict__ cand, uint64_t c, const u128* __restrict__ pa,
     const u128* __restrict__ sb, int k, uint32_t* __restrict__ oi, uint32_t* __restrict__ oj,
     uint8_t* __restrict__ od, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter,
     uint32_t epoch, unsigned long long* __restrict__ out_count, uint32_t* __restrict__ err) {
@@ -184,10 +236,10 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
     if (e < c) {
       const uint64_t v = cand[e];
       if (e == 0 || cand[e - 1] != v) {
-        const u128 a = sa[v >> 32], b = sb[(uint32_t)v];
-        const int la = (int)key_len(a), lb = (int)key_len(b);
+        const u128 a = pa[v >> 32], b = sb[(uint32_t)v];
+        const int la = (int)(a >> 120), lb = (int)key_len(b);
         if (abs(la - lb) <= k) {
-          const uint32_t d = lev_keys(a, b);
+          const uint32_t d = lev_planes(a, b);
           if (d <= (uint32_t)k) {
             keepmask |= 1u << x;
             dist[x] = (uint8_t)d;
@@ -240,10 +292,10 @@ namespace sd {
 static unsigned blocks_for(uint64_t n, uint64_t per) { return (unsigned)((n + per - 1) / per); }
 
 void launch_pack(const uint8_t* codes, const int64_t* offs, uint64_t n, int k, bool distinct,
-                 u128* seq, uint32_t* vcnt, uint32_t* err, hipStream_t s) {
+                 u128* seq, u128* planes, uint32_t* vcnt, uint32_t* err, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(sdk::k_pack, dim3(blocks_for(n, sdk::NT)), dim3(sdk::NT), 0, s, codes, offs,
-                     n, k, distinct ? 1 : 0, seq, vcnt, err);
+                     n, k, distinct ? 1 : 0, seq, planes, vcnt, err);
 }
 
 void launch_vargen(const u128* seq, const uint64_t* voff, uint64_t nseq, int k, uint64_t* key_lo,
@@ -264,15 +316,15 @@ void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint
 
 uint64_t compact_tile() { return (uint64_t)sdk::NT * sdk::CITEMS; }
 
-void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* seq_a,
+void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* planes_a,
                            const u128* seq_b, int k, uint32_t* out_i, uint32_t* out_j,
                            uint8_t* out_d, uint64_t* status, uint32_t* tile_counter,
                            uint32_t epoch, unsigned long long* out_count, uint32_t* err,
                            hipStream_t s) {
   if (!c) return;
   hipLaunchKernelGGL(sdk::k_verify_compact, dim3(blocks_for(c, compact_tile())), dim3(sdk::NT), 0,
-                     s, cand, c, seq_a, seq_b, k, out_i, out_j, out_d, status, tile_counter, epoch,
-                     out_count, err);
+                     s, cand, c, planes_a, seq_b, k, out_i, out_j, out_d, status, tile_counter,
+                     epoch, out_count, err);
 }
 
 void launch_pair_distance(const u128* seq_a, uint64_t na, const u128* seq_b, uint64_t nb,
