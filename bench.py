@@ -30,14 +30,13 @@ WORKLOADS = {
 }
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counters, scaled by a
-# 1 GiB copy (profiles/traffic_hashed_path_plain_1m_k2.md), for the kernels and
-# workload they were taken on; other kernels and workloads report null
-TRAFFIC_PER_LAUNCH = {("plain_1m_k2", "k_onesweep_keys"): 1.8365e9,
-                      ("plain_1m_k2", "k_scatter_counted"): 1.6595e9}
+# 1 GiB copy (profiles/traffic_hashed_path_plain_1m_k2.md), for the stages and
+# workload they were taken on; other stages and workloads report null
+TRAFFIC_PER_LAUNCH = {}
 # stages that time exactly one kernel (launched once, or several times alike)
 KERNEL_OF_STAGE = {
     "vargen_hash": "k_vargen_hash",
-    "hash_passes": "k_onesweep_keys",
+    "hash_passes": "k_scatter_counted",
     "hash_counted_pass": "k_scatter_counted",
     "group_local": "k_group_seg",
     "verify": "k_verify_compact",
@@ -469,7 +468,7 @@ def main():
         per_launch_bytes = stage_bytes[stage] / launches
         per_launch_s = ms * 1e-3 / launches
         achieved = per_launch_bytes / per_launch_s / 1e9
-        traffic = TRAFFIC_PER_LAUNCH.get((args.workload, KERNEL_OF_STAGE[stage]))
+        traffic = TRAFFIC_PER_LAUNCH.get((args.workload, stage))
         if args.path or args.group_cap or args.group_bits or args.sort_items or args.group_batches:
             traffic = None  # the counters were taken with the default configuration
         return {"bound": "hbm", "kernel": KERNEL_OF_STAGE[stage], "stage": stage,

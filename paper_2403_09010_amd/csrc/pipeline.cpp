@@ -183,14 +183,22 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
     cl.tm.mark("hash_counted_pass", (double)nk * 16, 1);
     flip = true;
   }
-  if (digits.size() > 1) {
+  // later passes: counted too, from a count of fixed tiles (a read of the
+  // data instead of a look-back chain between tiles)
+  for (size_t x = 1; x < digits.size(); ++x) {
     uint64_t* in = flip ? e2 : e1;
     uint64_t* other = flip ? e1 : e2;
-    const bool f2 = radix_sort(cl, in, nullptr, nullptr, other, nullptr, nullptr, 1, false, nk,
-                               std::vector<Digit>(digits.begin() + 1, digits.end()),
-                               std::vector<const uint32_t*>(hists.begin() + 1, hists.end()));
-    if (f2) flip = !flip;
-    cl.tm.mark("hash_passes", (double)nk * 16 * (digits.size() - 1), (int)digits.size() - 1);
+    const uint64_t tiles = fixed_tiles(nk);
+    uint32_t* counts = cl.sc.get<uint32_t>(tiles * 256);
+    uint32_t* local = cl.sc.get<uint32_t>(tiles * 256);
+    uint32_t* bsum = cl.sc.get<uint32_t>((uint64_t)counted_scan_rows(tiles) * 256);
+    launch_tile_counts(in, nk, digits[x].shift, digits[x].mask, counts, s);
+    launch_counted_scan(counts, tiles, 1, local, bsum, s);
+    cl.tm.mark("tile_counts", (double)nk * 8 + (double)tiles * 256 * 12, 3);
+    launch_counted_scatter(in, other, nk, digits[x].shift, digits[x].mask, tiles, local, bsum,
+                           nullptr, 0, 0, cl.lb_err(), s);
+    cl.tm.mark("hash_passes", (double)nk * 16, 1);
+    flip = !flip;
   }
   passes_out = (int)digits.size();
   const uint64_t* E = flip ? e2 : e1;

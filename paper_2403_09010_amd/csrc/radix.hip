@@ -329,6 +329,30 @@ __global__ __launch_bounds__(CT_SCAN_GROUPS * RADIX) void k_tile_scan_blocks(
   for (uint32_t b = b0; b < b1; ++b) bsum[(uint64_t)b * RADIX + d] += add;
 }
 
+// Digit counts of fixed tiles of CT_CHUNK elements (one row of 256 per tile),
+// for a counted pass over data whose producer did not count it.
+__global__ __launch_bounds__(NT) void k_tile_counts(const uint64_t* __restrict__ in, uint32_t n,
+                                                    int shift, uint32_t mask,
+                                                    uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_h[RADIX];
+  s_h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * CT_CHUNK;
+  const uint32_t nvalid = (uint32_t)min<uint64_t>((uint64_t)CT_CHUNK, (uint64_t)n - base);
+  const uint64_t* __restrict__ tin = in + base;
+  uint64_t v[CT_ITEMS];
+#pragma unroll
+  for (int r = 0; r < CT_ITEMS; ++r) {
+    const uint32_t e = r * NT + threadIdx.x;
+    v[r] = e < nvalid ? tin[e] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < CT_ITEMS; ++r)
+    if (r * NT + threadIdx.x < nvalid) atomicAdd(&s_h[(uint32_t)(v[r] >> shift) & mask], 1u);
+  __syncthreads();
+  counts[(uint64_t)blockIdx.x * RADIX + threadIdx.x] = s_h[threadIdx.x];
+}
+
 // Workgroups are dispatched to the eight XCDs in turn; this maps them so that
 // each XCD takes one contiguous range of tiles in order. Consecutive tiles
 // write adjacent pieces of every digit's run, so the cache lines they share
@@ -357,8 +381,16 @@ __global__ __launch_bounds__(NT) void k_scatter_counted(
   const uint32_t lane = tid & 63u;
   const uint32_t w = tid >> 6;
   const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x);
-  const uint64_t q0 = (uint64_t)tile * spt;
-  const uint64_t a = voff[q0], b = voff[min<uint64_t>(q0 + spt, nseq)];
+  // tiles by sequence ranges (voff), or fixed CHUNK-element tiles (no voff)
+  uint64_t a, b;
+  if (voff) {
+    const uint64_t q0 = (uint64_t)tile * spt;
+    a = voff[q0];
+    b = voff[min<uint64_t>(q0 + spt, nseq)];
+  } else {
+    a = (uint64_t)tile * CHUNK;
+    b = min<uint64_t>(a + CHUNK, n);
+  }
   // this thread's digit (tid) cursor in the output
   uint32_t cur = boff[(uint64_t)(tile / R) * RADIX + tid] + local[(uint64_t)tile * RADIX + tid];
   for (uint64_t c0 = a; c0 < b; c0 += CHUNK) {
@@ -614,6 +646,15 @@ void launch_counted_scatter(const uint64_t* in, uint64_t* out, uint32_t n, int s
   const uint32_t R = counted_rows_per_block(tiles);
   hipLaunchKernelGGL((sdk::k_scatter_counted<sdk::CT_ITEMS>), dim3((unsigned)tiles), dim3(sdk::NT),
                      0, s, in, out, n, shift, mask, local, bsum, R, voff, seqs_per_tile, nseq, err);
+}
+
+uint64_t fixed_tiles(uint64_t n) { return (n + sdk::CT_CHUNK - 1) / sdk::CT_CHUNK; }
+
+void launch_tile_counts(const uint64_t* in, uint32_t n, int shift, uint32_t mask, uint32_t* counts,
+                        hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(sdk::k_tile_counts, dim3((unsigned)fixed_tiles(n)), dim3(sdk::NT), 0, s, in, n,
+                     shift, mask, counts);
 }
 
 void launch_counted_pass(const uint64_t* in, uint64_t* out, uint32_t n, int shift, uint32_t mask,

@@ -58,6 +58,12 @@ void launch_counted_pass(const uint64_t* in, uint64_t* out, uint32_t n, int shif
                          const uint32_t* counts, uint64_t tiles, const uint64_t* voff,
                          uint32_t seqs_per_tile, uint64_t nseq, uint32_t* local, uint32_t* bsum,
                          uint32_t* err, hipStream_t s);
+// Fixed tiles for a counted pass over data nobody counted: fixed_tiles(n)
+// rows of digit counts by launch_tile_counts; the scatter then takes voff =
+// nullptr (tile t is elements [t * 4096, t * 4096 + 4096)).
+uint64_t fixed_tiles(uint64_t n);
+void launch_tile_counts(const uint64_t* in, uint32_t n, int shift, uint32_t mask, uint32_t* counts,
+                        hipStream_t s);
 // the two halves of launch_counted_pass: the count scans, then the scatter.
 // Here a tile's counts may be the sum of rows_per_tile consecutive rows of
 // counts (nrows rows); the scatter's tiles are then rows_per_tile times as
