@@ -433,10 +433,15 @@ def main():
         npairs = p.n
         ctx.free_pairs(p)
         st = ctx.stats()
+        # a stage name can repeat within a search (one mark per pass): its
+        # bytes and launches per search are the sums over its marks
+        step_bytes, step_launch = {}, {}
         for s in st["stages"]:
             stage_ms[s["name"]] = stage_ms.get(s["name"], 0.0) + s["ms"]
-            stage_bytes[s["name"]] = s["bytes"]
-            stage_launch[s["name"]] = s["launches"]
+            step_bytes[s["name"]] = step_bytes.get(s["name"], 0.0) + s["bytes"]
+            step_launch[s["name"]] = step_launch.get(s["name"], 0) + s["launches"]
+        stage_bytes.update(step_bytes)
+        stage_launch.update(step_launch)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     st = ctx.stats()

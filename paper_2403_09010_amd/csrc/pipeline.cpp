@@ -156,19 +156,15 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   const uint32_t spt = vargen_seqs_per_tile(n, nk);
   uint32_t* tcounts = nullptr;
   if (!digits.empty()) {
-    tcounts = cl.sc.get<uint32_t>(((n + spt - 1) / spt) * 256 * digits.size());
+    tcounts = cl.sc.get<uint32_t>(((n + spt - 1) / spt) * 256);
   }
-  launch_vargen_hash(seq, voff, n, k, true, e1, idbits, (int)digits.size(), shifts, masks, hist,
+  // only the first pass's digits are counted by the generator (every later
+  // pass is counted over fixed tiles of its own input)
+  launch_vargen_hash(seq, voff, n, k, true, e1, idbits, digits.empty() ? 0 : 1, shifts, masks, hist,
                      tcounts, spt, s);
   cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 1);
-  if (!digits.empty()) {
-    launch_hist_rows(tcounts, n, spt, (int)digits.size(), hist, s);
-    cl.tm.mark("hist_rows", (double)((n + spt - 1) / spt) * 256 * 4 * digits.size(), 1);
-  }
-  std::vector<const uint32_t*> hists;
-  for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
   // pass 1 from the generator's counts (the count scans, then the scatter),
-  // then the onesweep passes
+  // then the later passes
   bool flip = false;
   if (!digits.empty()) {
     const uint64_t blocks = (n + spt - 1) / spt;
@@ -335,22 +331,25 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
   if (nc > 1) {
     const int nb = bits_for(n - 1);
     std::vector<Digit> pd;
-    std::vector<const uint32_t*> ph;
-    uint32_t* phist = sc.get<uint32_t>(8 * 256);
-    launch_fill_u32(phist, 0, 8 * 256, s);
-    launch_radix_hist(cand.p, nullptr, 1, nc, phist, s);
-    for (int q = 0; q < (nb + 7) / 8; ++q) {
-      pd.push_back(Digit{0, 8 * q, 255u});
-      ph.push_back(phist + q * 256);
+    for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(Digit{0, 8 * q, 255u});
+    for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(Digit{0, 32 + 8 * q, 255u});
+    bool pflip;
+    if (nc >= (1u << 23)) {
+      // large: counted passes over fixed tiles
+      pflip = counted_sort(cl, cand.p, cand2, (uint32_t)nc, pd);
+      tm.mark("pair_sort", (double)nc * 24 * pd.size(), 4 * (int)pd.size());
+    } else {
+      // small: one histogram, then onesweep passes (fewer launches)
+      std::vector<const uint32_t*> ph;
+      uint32_t* phist = sc.get<uint32_t>(8 * 256);
+      launch_fill_u32(phist, 0, 8 * 256, s);
+      launch_radix_hist(cand.p, nullptr, 1, nc, phist, s);
+      for (const Digit& d : pd) ph.push_back(phist + (d.shift / 8) * 256);
+      pflip = radix_sort(cl, cand.p, nullptr, nullptr, cand2, nullptr, nullptr, 1, false,
+                         (uint32_t)nc, pd, ph);
+      tm.mark("pair_sort", (double)nc * 8 + (double)nc * 16 * pd.size(), 2 + (int)pd.size());
     }
-    for (int q = 0; q < (nb + 7) / 8; ++q) {
-      pd.push_back(Digit{0, 32 + 8 * q, 255u});
-      ph.push_back(phist + (4 + q) * 256);
-    }
-    const bool pflip = radix_sort(cl, cand.p, nullptr, nullptr, cand2, nullptr, nullptr, 1, false,
-                                  (uint32_t)nc, pd, ph);
     sorted = pflip ? cand2 : cand.p;
-    tm.mark("pair_sort", (double)nc * 8 + (double)nc * 16 * pd.size(), 2 + (int)pd.size());
   } else {
     tm.mark("pair_sort", 0, 0);
   }

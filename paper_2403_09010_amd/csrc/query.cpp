@@ -90,16 +90,26 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   const uint32_t spt = vargen_seqs_per_tile(q.n, nk);
   uint32_t* tcounts = nullptr;
   if (!digits.empty()) {
-    tcounts = cl.sc.get<uint32_t>(((q.n + spt - 1) / spt) * 256 * digits.size());
+    tcounts = cl.sc.get<uint32_t>(((q.n + spt - 1) / spt) * 256);
   }
-  launch_vargen_hash(p.seq, p.voff, q.n, k, true, e1, idx->idbits, (int)digits.size(), shifts,
+  launch_vargen_hash(p.seq, p.voff, q.n, k, true, e1, idx->idbits, digits.empty() ? 0 : 1, shifts,
                      masks, hist, tcounts, spt, s);
-  launch_hist_rows(tcounts, q.n, spt, (int)digits.size(), hist, s);
   std::vector<const uint32_t*> hists;
   for (size_t x = 0; x < digits.size(); ++x) hists.push_back(hist + 256 * x);
+  // the first pass from the generator's counts, the later ones counted over
+  // fixed tiles
   const CountedFirst first{tcounts, (q.n + spt - 1) / spt, p.voff, spt, q.n};
-  const bool flip = radix_sort(cl, e1, nullptr, nullptr, e2, nullptr, nullptr, 1, false, nk, digits,
-                               hists, &first);
+  bool flip = false;
+  if (!digits.empty()) {
+    flip = radix_sort(cl, e1, nullptr, nullptr, e2, nullptr, nullptr, 1, false, nk,
+                      std::vector<Digit>(digits.begin(), digits.begin() + 1),
+                      std::vector<const uint32_t*>(hists.begin(), hists.begin() + 1), &first);
+    if (digits.size() > 1) {
+      const bool f2 = counted_sort(cl, flip ? e2 : e1, flip ? e1 : e2, nk,
+                                   std::vector<Digit>(digits.begin() + 1, digits.end()));
+      if (f2) flip = !flip;
+    }
+  }
   const uint64_t* Eq = flip ? e2 : e1;
   const uint32_t nseg = 1u << bits;
   uint32_t* qs = cl.sc.get<uint32_t>(nseg);
@@ -147,22 +157,24 @@ TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint6
   const uint64_t* sorted = cand;
   if (nc > 1) {
     uint64_t* cand2 = cl.sc.get<uint64_t>(nc);
-    uint32_t* phist = cl.sc.get<uint32_t>(8 * 256);
-    launch_fill_u32(phist, 0, 8 * 256, s);
-    launch_radix_hist(cand, nullptr, 1, nc, phist, s);
     std::vector<Digit> pd;
-    std::vector<const uint32_t*> ph;
     const int rb = bits_for(nr ? nr - 1 : 0), qb = bits_for(nq ? nq - 1 : 0);
-    for (int x = 0; x < (rb + 7) / 8; ++x) {
-      pd.push_back(Digit{0, 8 * x, 255u});
-      ph.push_back(phist + x * 256);
+    for (int x = 0; x < (rb + 7) / 8; ++x) pd.push_back(Digit{0, 8 * x, 255u});
+    for (int x = 0; x < (qb + 7) / 8; ++x) pd.push_back(Digit{0, 32 + 8 * x, 255u});
+    bool pf;
+    if (nc >= (1u << 23)) {
+      // large: counted passes over fixed tiles
+      pf = counted_sort(cl, cand, cand2, (uint32_t)nc, pd);
+    } else {
+      // small: one histogram, then onesweep passes (fewer launches)
+      uint32_t* phist = cl.sc.get<uint32_t>(8 * 256);
+      launch_fill_u32(phist, 0, 8 * 256, s);
+      launch_radix_hist(cand, nullptr, 1, nc, phist, s);
+      std::vector<const uint32_t*> ph;
+      for (const Digit& d : pd) ph.push_back(phist + (d.shift / 8) * 256);
+      pf = radix_sort(cl, cand, nullptr, nullptr, cand2, nullptr, nullptr, 1, false, (uint32_t)nc,
+                      pd, ph);
     }
-    for (int x = 0; x < (qb + 7) / 8; ++x) {
-      pd.push_back(Digit{0, 32 + 8 * x, 255u});
-      ph.push_back(phist + (4 + x) * 256);
-    }
-    const bool pf = radix_sort(cl, cand, nullptr, nullptr, cand2, nullptr, nullptr, 1, false,
-                               (uint32_t)nc, pd, ph);
     sorted = pf ? cand2 : cand;
   }
   cl.tm.mark("q_pair_sort", (double)nc * 16, 1);

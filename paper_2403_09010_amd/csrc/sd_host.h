@@ -138,6 +138,29 @@ inline bool radix_sort(Call& cl, uint64_t* a0, uint64_t* a1, uint32_t* av, uint6
   return flip;
 }
 
+// Stable LSD sort of 64-bit keys by `digits` (word 0), every pass counted
+// over fixed tiles: a count kernel, the two count scans and the XCD-contiguous
+// scatter; no global histogram and no look-back. Returns whether the result
+// is in b.
+inline bool counted_sort(Call& cl, uint64_t* a, uint64_t* b, uint32_t n,
+                         const std::vector<Digit>& digits) {
+  bool flip = false;
+  const uint64_t tiles = fixed_tiles(n);
+  uint32_t* counts = cl.sc.get<uint32_t>(tiles * 256);
+  uint32_t* local = cl.sc.get<uint32_t>(tiles * 256);
+  uint32_t* bsum = cl.sc.get<uint32_t>((uint64_t)counted_scan_rows(tiles) * 256);
+  for (const Digit& d : digits) {
+    const uint64_t* in = flip ? b : a;
+    uint64_t* out = flip ? a : b;
+    launch_tile_counts(in, n, d.shift, d.mask, counts, cl.s);
+    launch_counted_scan(counts, tiles, 1, local, bsum, cl.s);
+    launch_counted_scatter(in, out, n, d.shift, d.mask, tiles, local, bsum, nullptr, 0, 0,
+                           cl.lb_err(), cl.s);
+    flip = !flip;
+  }
+  return flip;
+}
+
 struct Cands {
   uint64_t* p = nullptr;  // pool block owned by the caller
   uint64_t n = 0;
