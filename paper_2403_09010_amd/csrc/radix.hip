@@ -368,7 +368,8 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t G) {
 template <int ITEMS>
 __global__ __launch_bounds__(NT) void k_scatter_counted(
     const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint32_t n, int shift,
-    uint32_t mask, const uint32_t* __restrict__ local, const uint32_t* __restrict__ boff, uint32_t R,
+    uint32_t mask, const uint32_t* __restrict__ local, const uint32_t* __restrict__ off1,
+    const uint32_t* __restrict__ boff, uint32_t R1, uint32_t R2,
     const uint64_t* __restrict__ voff, uint32_t spt, uint64_t nseq, uint32_t* __restrict__ err) {
   constexpr int CHUNK = NT * ITEMS;
   __shared__ uint32_t s_wh[NWAVE][RADIX];
@@ -392,7 +393,8 @@ __global__ __launch_bounds__(NT) void k_scatter_counted(
     b = min<uint64_t>(a + CHUNK, n);
   }
   // this thread's digit (tid) cursor in the output
-  uint32_t cur = boff[(uint64_t)(tile / R) * RADIX + tid] + local[(uint64_t)tile * RADIX + tid];
+  uint32_t cur = boff[(uint64_t)(tile / R1 / R2) * RADIX + tid] +
+                 off1[(uint64_t)(tile / R1) * RADIX + tid] + local[(uint64_t)tile * RADIX + tid];
   for (uint64_t c0 = a; c0 < b; c0 += CHUNK) {
     for (int x = tid; x < NWAVE * RADIX; x += NT) (&s_wh[0][0])[x] = 0;
     __syncthreads();
@@ -617,25 +619,42 @@ void launch_onesweep(const uint64_t* in0, const uint64_t* in1, const uint32_t* v
                        shift, mask, hist256, status, tile_counter, epoch, err);
 }
 
-static uint32_t counted_rows_per_block(uint64_t tiles) {
-  return (uint32_t)std::max<uint64_t>(64, (tiles + 511) / 512);
+// The count scan in three levels, each a single round of loads per thread:
+// tiles in blocks of R1 = 16 (exclusive sums into local, block sums into
+// sums1), those block sums in blocks of R2 (exclusive sums into off1, block
+// sums into sums2), and sums2 in one block with the digit bases. bsum holds
+// off1 (nb1 rows), sums1 (nb1 rows) and sums2 (nb2 rows).
+struct ScanShape {
+  uint32_t R1, nb1, R2, nb2;
+};
+static ScanShape scan_shape(uint64_t tiles) {
+  ScanShape g;
+  g.R1 = 16;
+  g.nb1 = (uint32_t)((tiles + g.R1 - 1) / g.R1);
+  g.R2 = std::max<uint32_t>(16, (g.nb1 + 255) / 256);
+  g.nb2 = (g.nb1 + g.R2 - 1) / g.R2;
+  return g;
 }
 
 uint32_t counted_scan_rows(uint64_t tiles) {
-  const uint32_t R = counted_rows_per_block(tiles);
-  return (uint32_t)((tiles + R - 1) / R);
+  const ScanShape g = scan_shape(tiles);
+  return 2 * g.nb1 + g.nb2;
 }
 
 void launch_counted_scan(const uint32_t* counts, uint64_t nrows, uint32_t rows_per_tile,
                          uint32_t* local, uint32_t* bsum, hipStream_t s) {
   if (!nrows) return;
   const uint64_t tiles = (nrows + rows_per_tile - 1) / rows_per_tile;
-  const uint32_t R = counted_rows_per_block(tiles);
-  const uint32_t nb = counted_scan_rows(tiles);
-  hipLaunchKernelGGL(sdk::k_tile_scan_local, dim3(nb), dim3(sdk::RADIX), 0, s, counts,
-                     (uint32_t)nrows, rows_per_tile, (uint32_t)tiles, R, local, bsum);
+  const ScanShape g = scan_shape(tiles);
+  uint32_t* off1 = bsum;
+  uint32_t* sums1 = bsum + (uint64_t)g.nb1 * sdk::RADIX;
+  uint32_t* sums2 = bsum + (uint64_t)2 * g.nb1 * sdk::RADIX;
+  hipLaunchKernelGGL(sdk::k_tile_scan_local, dim3(g.nb1), dim3(sdk::RADIX), 0, s, counts,
+                     (uint32_t)nrows, rows_per_tile, (uint32_t)tiles, g.R1, local, sums1);
+  hipLaunchKernelGGL(sdk::k_tile_scan_local, dim3(g.nb2), dim3(sdk::RADIX), 0, s, sums1, g.nb1, 1u,
+                     g.nb1, g.R2, off1, sums2);
   hipLaunchKernelGGL(sdk::k_tile_scan_blocks, dim3(1), dim3(sdk::CT_SCAN_GROUPS * sdk::RADIX), 0, s,
-                     bsum, nb);
+                     sums2, g.nb2);
 }
 
 void launch_counted_scatter(const uint64_t* in, uint64_t* out, uint32_t n, int shift, uint32_t mask,
@@ -643,9 +662,11 @@ void launch_counted_scatter(const uint64_t* in, uint64_t* out, uint32_t n, int s
                             const uint64_t* voff, uint32_t seqs_per_tile, uint64_t nseq,
                             uint32_t* err, hipStream_t s) {
   if (!n || !tiles) return;
-  const uint32_t R = counted_rows_per_block(tiles);
+  const ScanShape g = scan_shape(tiles);
   hipLaunchKernelGGL((sdk::k_scatter_counted<sdk::CT_ITEMS>), dim3((unsigned)tiles), dim3(sdk::NT),
-                     0, s, in, out, n, shift, mask, local, bsum, R, voff, seqs_per_tile, nseq, err);
+                     0, s, in, out, n, shift, mask, local, bsum,
+                     bsum + (uint64_t)2 * g.nb1 * sdk::RADIX, g.R1, g.R2, voff, seqs_per_tile, nseq,
+                     err);
 }
 
 uint64_t fixed_tiles(uint64_t n) { return (n + sdk::CT_CHUNK - 1) / sdk::CT_CHUNK; }
