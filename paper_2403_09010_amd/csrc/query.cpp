@@ -162,7 +162,7 @@ TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint6
     for (int x = 0; x < (rb + 7) / 8; ++x) pd.push_back(Digit{0, 8 * x, 255u});
     for (int x = 0; x < (qb + 7) / 8; ++x) pd.push_back(Digit{0, 32 + 8 * x, 255u});
     bool pf;
-    if (nc >= (1u << 23)) {
+    if (nc >= (1u << 21)) {
       // large: counted passes over fixed tiles
       pf = counted_sort(cl, cand, cand2, (uint32_t)nc, pd);
     } else {
