@@ -85,26 +85,22 @@ struct PassDigits {
 // length starts consecutive rows in different LDS banks
 constexpr int VG_PRE = 27;
 
+// Deletion pairs in colexicographic order (p2 major): pair u is (p1, p2)
+// with u = p2 (p2 - 1) / 2 + p1, the same for every length L (a string of
+// length L uses the first C(L, 2) of them). Entry: p1 | p2 << 8.
+constexpr int VG_PAIRS = KEY_MAX_LEN * (KEY_MAX_LEN - 1) / 2;
+
 // Deletion positions of variant v of a string of length L in the enumeration
 // order (v = 0 the string itself, v = 1..L one deletion at v - 1, then the
-// pairs p1 < p2 in lexicographic order), in the form the prefix-XOR hash
-// takes: p2 = L for one deletion, p1 = L and p2 = L + 1 for none. The pair
-// index u = v - 1 - L is unranked in closed form: T(p) = p (2L - 1 - p) / 2
-// pairs start before p, so p1 is the largest p with T(p) <= u, a root of a
-// quadratic (one correction step each way absorbs the rounding of the
-// hardware square root).
-__device__ __forceinline__ void variant_positions(uint32_t L, uint32_t v, uint32_t& p1,
-                                                  uint32_t& p2) {
-  const int u = max((int)v - 1 - (int)L, 0);
-  const int a = 2 * (int)L - 1;
-  int q1 = (int)((a - __builtin_amdgcn_sqrtf((float)max(a * a - 8 * u, 0))) * 0.5f);
-  q1 = q1 < 0 ? 0 : q1;
-  if ((q1 + 1) * (a - q1 - 1) / 2 <= u) ++q1;
-  if (q1 * (a - q1) / 2 > u) --q1;
-  const int q2 = q1 + 1 + (u - q1 * (a - q1) / 2);
+// pairs in colexicographic order), in the form the prefix-XOR hash takes:
+// p2 = L for one deletion, p1 = L and p2 = L + 1 for none.
+__device__ __forceinline__ void variant_positions(const uint16_t* s_pairs, uint32_t L, uint32_t v,
+                                                  uint32_t& p1, uint32_t& p2) {
+  const uint32_t u = v > L ? v - 1 - L : 0u;
+  const uint32_t pr = s_pairs[u < (uint32_t)VG_PAIRS ? u : 0u];
   const bool none = v == 0, one = v != 0 && v <= L;
-  p1 = none ? L : one ? v - 1 : (uint32_t)q1;
-  p2 = none ? L + 1 : one ? L : (uint32_t)q2;
+  p1 = none ? L : one ? v - 1 : (pr & 0xFFu);
+  p2 = none ? L + 1 : one ? L : (pr >> 8);
 }
 
 // One block per spb sequences; every V(L, k) deletion set of each is
@@ -129,6 +125,7 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   __shared__ uint32_t s_n1[VG_SEQS], s_n2[VG_SEQS];  // canonical-test masks
   __shared__ uint32_t s_roff[VG_SEQS + 1];            // block-local deletion-set prefix
   __shared__ uint32_t s_h[3 * 256];
+  __shared__ uint16_t s_pairs[VG_PAIRS];
   // spb <= VG_SEQS sequences per block
   const uint64_t s0 = (uint64_t)blockIdx.x * spb;
   const uint32_t ns = (uint32_t)min<uint64_t>(spb, nseq - s0);
@@ -136,6 +133,11 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   for (uint32_t x = threadIdx.x; x <= ns; x += VG_NT) s_off[x] = voff[s0 + x];
   for (uint32_t x = threadIdx.x; x < 3 * 256; x += VG_NT) s_h[x] = 0;
   if (threadIdx.x < 32) s_c[threadIdx.x] = kHashTab.c[threadIdx.x];
+  for (uint32_t u = threadIdx.x; u < (uint32_t)VG_PAIRS; u += VG_NT) {
+    uint32_t p2 = 1;
+    while ((p2 + 1) * p2 / 2 <= u) ++p2;
+    s_pairs[u] = (uint16_t)((u - p2 * (p2 - 1) / 2) | (p2 << 8));
+  }
   // prefix XORs: each half-wave takes one sequence, lane t its position t
   {
     const uint32_t half = lane >> 5, t = lane & 31u;
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   auto variant = [&](uint32_t x, uint32_t v, bool valid, uint64_t& e) -> bool {
     const uint32_t L = s_len[x];
     uint32_t p1, p2;
-    variant_positions(L, valid ? v : 0u, p1, p2);
+    variant_positions(s_pairs, L, valid ? v : 0u, p1, p2);
     const uint32_t m = L - (uint32_t)(p1 < L) - (uint32_t)(p2 < L);
     const uint64_t* P = s_pre + x * VG_PRE;
     const uint64_t h = s_c[m] ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
