@@ -69,24 +69,31 @@ __device__ __forceinline__ bool variant_canonical(uint32_t n1, uint32_t n2, uint
 }
 
 // Number of distinct strings among the deletion variants with at most k
-// deletions: the canonical sets above, counted in O(L).
-__device__ __forceinline__ uint32_t num_distinct_variants(u128 key, int k) {
-  const uint32_t L = key_len(key);
+// deletions: the canonical sets above, counted in O(L) from the same masks
+// (the run count is the number of canonical first deletions p1 <= p2 - 2).
+__device__ __forceinline__ uint32_t num_distinct_variants(uint32_t n1, uint32_t n2, uint32_t L,
+                                                          int k) {
   uint32_t c = 1;
-  if (k >= 1)
-    for (uint32_t p = 0; p < L; ++p)
-      c += (p + 1 == L || key_residue(key, (int)p) != key_residue(key, (int)p + 1)) ? 1u : 0u;
-  if (k >= 2) {
-    uint32_t run = 0;  // canonical first deletions p1 <= p2 - 2
-    for (uint32_t p2 = 1; p2 < L; ++p2) {
-      if (p2 >= 2 && key_residue(key, (int)p2 - 2) != key_residue(key, (int)p2 - 1)) ++run;
-      if (p2 + 1 == L || key_residue(key, (int)p2) != key_residue(key, (int)p2 + 1)) {
-        c += run;
-        if (p2 + 1 == L || key_residue(key, (int)p2 - 1) != key_residue(key, (int)p2 + 1)) ++c;
-      }
-    }
-  }
+  if (k >= 1) c += (uint32_t)__popc(n1);
+  if (k >= 2)
+    for (uint32_t p2 = 1; p2 < L; ++p2)
+      if ((n1 >> p2) & 1u)
+        c += (uint32_t)__popc(n1 & ((1u << (p2 - 1)) - 1u)) + ((n2 >> (p2 - 1)) & 1u);
   return c;
+}
+
+// The masks of variant_canonical from a string's five residue bit planes
+// (bit t of plane q is bit q of residue t).
+__device__ __forceinline__ void canonical_masks(const uint32_t (&pl)[5], uint32_t L, uint32_t& n1,
+                                                uint32_t& n2) {
+  uint32_t d1 = 0, d2 = 0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    d1 |= pl[q] ^ (pl[q] >> 1);
+    d2 |= pl[q] ^ (pl[q] >> 2);
+  }
+  n1 = (d1 & ((1u << (L - 1)) - 1u)) | (1u << (L - 1));
+  n2 = L >= 2 ? (d2 & ((1u << (L - 2)) - 1u)) | (1u << (L - 2)) : 0u;
 }
 
 // Variant number v of a key in the enumeration order: v = 0 keeps the

@@ -132,7 +132,15 @@ __global__ __launch_bounds__(NT) void k_pack(const uint8_t* __restrict__ codes,
                         ((uint64_t)L << 56);
     planes[i] = ((u128)hi << 64) | lo;
   }
-  if (vcnt) vcnt[i] = distinct ? num_distinct_variants(key, k) : num_variants((uint32_t)L, k);
+  if (vcnt) {
+    uint32_t c = num_variants((uint32_t)L, k);
+    if (distinct) {
+      uint32_t n1, n2;
+      canonical_masks(pl, (uint32_t)L, n1, n2);
+      c = num_distinct_variants(n1, n2, (uint32_t)L, k);
+    }
+    vcnt[i] = c;
+  }
 }
 
 // ------------------------------------------------------------------ vargen

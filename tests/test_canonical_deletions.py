@@ -78,6 +78,41 @@ def distinct_count(s, k):
     return c
 
 
+def masks(s):
+    """n1 bit p: p = L-1 or s[p] != s[p+1]; n2 bit p: p = L-2 or s[p] != s[p+2]."""
+    L = len(s)
+    n1 = sum(1 << p for p in range(L) if p == L - 1 or s[p] != s[p + 1])
+    n2 = sum(1 << p for p in range(L - 1) if p == L - 2 or s[p] != s[p + 2])
+    return n1, n2
+
+
+def distinct_count_masks(s, k):
+    """The same count from the two masks, as the pack kernel computes it."""
+    L = len(s)
+    n1, n2 = masks(s)
+    c = 1
+    if k >= 1:
+        c += bin(n1).count("1")
+    if k >= 2:
+        for p2 in range(1, L):
+            if (n1 >> p2) & 1:
+                c += bin(n1 & ((1 << (p2 - 1)) - 1)).count("1") + ((n2 >> (p2 - 1)) & 1)
+    return c
+
+
+def canonical_masks(s, D):
+    """variant_canonical's test on the masks."""
+    L = len(s)
+    n1, n2 = masks(s)
+    if len(D) == 0:
+        return True
+    if len(D) == 1:
+        return bool((n1 >> D[0]) & 1)
+    p1, p2 = D
+    a = (n1 >> p1) if p1 + 1 < p2 else (n2 >> p1)
+    return bool(a & (n1 >> p2) & 1)
+
+
 def random_strings(n, seed):
     rng = random.Random(seed)
     for _ in range(n):
@@ -102,7 +137,16 @@ def test_one_canonical_set_per_distinct_string(k):
 @pytest.mark.parametrize("k", [0, 1, 2])
 def test_distinct_count_formula(k):
     for s in random_strings(3000, 23 + k):
-        assert distinct_count(s, k) == len({t for _, t in variants(s, k)}), s
+        distinct = len({t for _, t in variants(s, k)})
+        assert distinct_count(s, k) == distinct, s
+        assert distinct_count_masks(s, k) == distinct, s
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_mask_form_of_the_rule(k):
+    for s in random_strings(2000, 37 + k):
+        for D, _ in variants(s, k):
+            assert canonical_masks(s, D) == canonical(s, D), (s, D)
 
 
 def test_worked_cases():
