@@ -338,15 +338,20 @@ __global__ __launch_bounds__(256) void k_seg_bounds(const uint64_t* __restrict__
 
 // ------------------------------------------------------------------ local grouping
 
-// LDS layout of one batch of at most CAP elements (22 bytes per element):
-//   [0, 8 CAP)        the elements (hash | id)
-//   [8 CAP, 16 CAP)   open-addressing table, 2 CAP slots of element + 1
-//   [16 CAP, 20 CAP)  per representative: the last member pushed (or NONE)
-//   [20 CAP, 22 CAP)  per member: the member pushed before it (or NONE); a
-//                     repeated (hash, id) is marked REPEAT and never pushed
+// LDS layout for a batch of at most CAP elements, which arrive in registers;
+// only the prefilter's candidates (at most MC = CAP / 2 of them) are grouped
+// in LDS, 22 bytes each:
+//   [0, 8 MC)        the compacted candidates (hash | id)
+//   [8 MC, 16 MC)    the prefilter's two bitmaps (16 CAP bits each), then
+//                    the open-addressing table, 2 MC slots of candidate + 1
+//   [16 MC, 20 MC)   per representative: the last member pushed (or NONE)
+//   [20 MC, 22 MC)   per member: the member pushed before it (or NONE); a
+//                    repeated (hash, id) is marked REPEAT and never pushed
+// A batch with more than MC candidates is listed for the sort-and-runs
+// path instead. A split half (<= CAP elements) is staged in [0, 16 MC).
 constexpr uint32_t NONE16 = 0xFFFFu;
 constexpr uint16_t REPEAT16 = 0xFFFEu;
-constexpr int GROUP_LDS_PER_ELEM = 22;
+constexpr int GROUP_LDS_PER_CAND = 22;
 
 // One batch of m_in <= CAP elements whose values arrive in registers
 // (element x = threadIdx.x + r * NTH is in e_in[r]); the caller has already
@@ -381,29 +386,32 @@ __device__ void flush_pairs(const ShardOut& out, const uint64_t* s_pbuf, uint32_
 }
 
 template <int CAP, int NTH>
-__device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, uint32_t idbits,
+__device__ bool group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, uint32_t idbits,
                             const ShardOut& out, unsigned char* lds, uint64_t* s_tmp64,
-                            uint64_t* s_base, uint64_t* s_pbuf, uint32_t& pbuf_n) {
+                            uint64_t* s_base, uint64_t* s_pbuf, uint32_t& pbuf_n, uint64_t ga,
+                            uint64_t gb, uint64_t* __restrict__ big,
+                            unsigned long long* __restrict__ nbig) {
   constexpr int PER = CAP / NTH;
+  constexpr uint32_t MC = CAP / 2;
   constexpr int NW = NTH / 64;
   constexpr int NC = PER * NW;
   static_assert(NC % 4 == 0, "compaction counts are read four at a time");
   __shared__ __align__(16) uint32_t s_cnt[NC];
   uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
-  uint32_t* s_tab = reinterpret_cast<uint32_t*>(lds + CAP * 8);
-  uint32_t* s_chead = reinterpret_cast<uint32_t*>(lds + CAP * 16);
-  uint16_t* s_next = reinterpret_cast<uint16_t*>(lds + CAP * 20);
+  uint32_t* s_tab = reinterpret_cast<uint32_t*>(lds + MC * 8);
+  uint32_t* s_chead = reinterpret_cast<uint32_t*>(lds + MC * 16);
+  uint16_t* s_next = reinterpret_cast<uint16_t*>(lds + MC * 20);
   const uint64_t idmask = (1ull << idbits) - 1;
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
 
   // prefilter: the two bitmaps occupy the (zero) table area
   uint32_t* s_seen = s_tab;
-  uint32_t* s_twice = s_tab + CAP;
+  uint32_t* s_twice = s_tab + MC;
   uint32_t bitx[PER];
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
     const uint32_t x = threadIdx.x + r * NTH;
-    bitx[r] = (uint32_t)(e_in[r] >> idbits) & (32u * CAP - 1);
+    bitx[r] = (uint32_t)(e_in[r] >> idbits) & (32u * MC - 1);
     if (x < m_in) {
       const uint32_t bit = 1u << (bitx[r] & 31u);
       if (atomicOr(&s_seen[bitx[r] >> 5], bit) & bit) atomicOr(&s_twice[bitx[r] >> 5], bit);
@@ -432,13 +440,24 @@ __device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
       m += c[j];
     }
   }
-  for (uint32_t x = threadIdx.x; x < 2 * CAP; x += NTH) s_tab[x] = 0;
+  for (uint32_t x = threadIdx.x; x < 2 * MC; x += NTH) s_tab[x] = 0;
+  if (m > MC) {
+    // too many candidates for the table: the sort-and-runs path takes the
+    // batch's whole range (a pair found twice is dropped at verification)
+    if (threadIdx.x == 0) {
+      const unsigned long long x = atomicAdd(nbig, 1ull);
+      big[2 * x] = ga;
+      big[2 * x + 1] = gb;
+    }
+    __syncthreads();
+    return true;
+  }
 #pragma unroll
   for (int r = 0; r < PER; ++r)
     if ((keep[r] >> lane) & 1u) s_e[before[r] + mask_rank(keep[r])] = e_in[r];
   for (uint32_t x = threadIdx.x; x < m; x += NTH) s_chead[x] = NONE16;
   __syncthreads();
-  if (m == 0) return;
+  if (m == 0) return false;
   uint32_t ts = 64;  // table slots: a power of two >= 2m
   while (ts < 2 * m) ts <<= 1;
 
@@ -539,6 +558,7 @@ __device__ void group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
   // the table is not read by the emission: clear it for the next batch
   for (uint32_t x = threadIdx.x; x < ts; x += NTH) s_tab[x] = 0;
   __syncthreads();  // the next batch rewrites the LDS
+  return false;
 }
 
 // The next batch of a workgroup's segment range starting at segment v:
@@ -625,10 +645,11 @@ __global__ __launch_bounds__(NTH) void k_group_seg(
   __shared__ uint64_t s_base[2];
   __shared__ uint64_t s_pbuf[GROUP_PBUF];
   uint32_t pbuf_n = 0;
+  constexpr uint32_t MC = CAP / 2;
   uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* s_tab = reinterpret_cast<uint32_t*>(lds + MC * 8);
   // group_batch expects a zero table area
-  for (uint32_t x = threadIdx.x; x < 2 * CAP; x += NTH)
-    reinterpret_cast<uint32_t*>(lds + CAP * 8)[x] = 0;
+  for (uint32_t x = threadIdx.x; x < 2 * MC; x += NTH) s_tab[x] = 0;
   __syncthreads();
   const bool can_split = splitbit >= idbits && splitbit < 64;
   const uint32_t v0 = blockIdx.x * spw;
@@ -663,7 +684,14 @@ __global__ __launch_bounds__(NTH) void k_group_seg(
             e[r] = x < m ? s_e[x] : 0;
           }
           __syncthreads();
-          group_batch<CAP, NTH>(e, m, idbits, out, lds, s_tmp64, s_base, s_pbuf, pbuf_n);
+          // the staging overwrote the table area
+          for (uint32_t x = threadIdx.x; x < 2 * MC; x += NTH) s_tab[x] = 0;
+          __syncthreads();
+          // a listed half lists the whole segment: the other half must not
+          // list it again
+          if (group_batch<CAP, NTH>(e, m, idbits, out, lds, s_tmp64, s_base, s_pbuf, pbuf_n, a, b,
+                                    big, nbig))
+            break;
         }
       }
       kind = next_batch<CAP>(seg_start, seg_end, v, v1, a, b, can_split, big, nbig);
@@ -683,7 +711,8 @@ __global__ __launch_bounds__(NTH) void k_group_seg(
       const uint32_t x = threadIdx.x + r * NTH;
       nxt[r] = (nkind == 1 && x < nb - na) ? E[na + x] : 0;
     }
-    group_batch<CAP, NTH>(cur, m, idbits, out, lds, s_tmp64, s_base, s_pbuf, pbuf_n);
+    group_batch<CAP, NTH>(cur, m, idbits, out, lds, s_tmp64, s_base, s_pbuf, pbuf_n, a, b, big,
+                          nbig);
 #pragma unroll
     for (int r = 0; r < PER; ++r) cur[r] = nxt[r];
     a = na;
@@ -735,10 +764,14 @@ __global__ __launch_bounds__(256) void k_emit_hash_runs(const uint64_t* __restri
   if (cnt) {
     uint64_t pos = s_base + excl;
     const uint64_t h = E[p] >> idbits;
-    const uint64_t ip = (E[p] & idmask) << 32;
+    const uint64_t ip = E[p] & idmask;
     for (uint64_t q = p + 1; q < n && (E[q] >> idbits) == h; ++q) {
       if (E[q] != E[q - 1]) {
-        if (pos < cap) cand[pos] = ip | (E[q] & idmask);
+        // (lo, hi): ids ascend inside a run when every listed range is a
+        // contiguous piece of the sorted array listed once (the grouping
+        // kernel never lists a range twice); the order is kept explicitly
+        const uint64_t iq = E[q] & idmask;
+        if (pos < cap) cand[pos] = ip < iq ? (ip << 32) | iq : (iq << 32) | ip;
         ++pos;
       }
     }
@@ -786,7 +819,7 @@ void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_
                      seg_start, seg_end);
 }
 
-static size_t group_lds(int cap) { return (size_t)cap * sdk::GROUP_LDS_PER_ELEM; }
+static size_t group_lds(int cap) { return (size_t)(cap / 2) * sdk::GROUP_LDS_PER_CAND; }
 
 template <int CAP, int NTH>
 static void launch_group_t(const uint64_t* E, const uint32_t* ss, const uint32_t* se,

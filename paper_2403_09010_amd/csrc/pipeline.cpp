@@ -213,7 +213,11 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   const uint32_t per_batch =
       (uint32_t)std::max(1.0, std::floor(0.8 * cap / std::max(mean_seg, 1.0) + 0.5));
   const uint32_t spw = per_batch * (uint32_t)(c->group_batches ? c->group_batches : 4);
-  const uint64_t nbig_cap = nk / cap + 2;
+  // listed ranges: segments over 2 cap elements, split segments with a half
+  // over cap, and batches with over cap / 2 prefilter candidates; each holds
+  // more than cap / 2 elements of its own (a split segment can be listed
+  // once per half), so 4 nk / cap + 2 entries always suffice
+  const uint64_t nbig_cap = 4 * (uint64_t)nk / cap + 2;
   uint64_t* big = cl.sc.get<uint64_t>(2 * nbig_cap);
   unsigned long long* nbig = reinterpret_cast<unsigned long long*>(cl.counters + CNT_NBIG);
   Cands cand = sharded_output(
