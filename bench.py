@@ -39,7 +39,6 @@ KERNEL_OF_STAGE = {
     "vargen_hash": "k_vargen_hash",
     "hash_passes": "k_scatter_counted",
     "hash_counted_pass": "k_scatter_counted",
-    "group_local": "k_group_seg",
     "verify": "k_verify_compact",
     "sort_passes": "k_onesweep",
     "emit": "k_emit_runs",

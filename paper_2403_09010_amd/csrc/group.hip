@@ -339,16 +339,18 @@ __global__ __launch_bounds__(256) void k_seg_bounds(const uint64_t* __restrict__
 // ------------------------------------------------------------------ local grouping
 
 // LDS layout for a batch of at most CAP elements, which arrive in registers;
-// only the prefilter's candidates (at most MC = CAP / 2 of them) are grouped
-// in LDS, 22 bytes each:
+// only the prefilter's candidates (at most MC of them: CAP / 2 in the main
+// grouping kernel, CAP in the second pass over listed ranges) are grouped in
+// LDS, 22 bytes each:
 //   [0, 8 MC)        the compacted candidates (hash | id)
-//   [8 MC, 16 MC)    the prefilter's two bitmaps (16 CAP bits each), then
+//   [8 MC, 16 MC)    the prefilter's two bitmaps (32 MC bits each), then
 //                    the open-addressing table, 2 MC slots of candidate + 1
 //   [16 MC, 20 MC)   per representative: the last member pushed (or NONE)
 //   [20 MC, 22 MC)   per member: the member pushed before it (or NONE); a
 //                    repeated (hash, id) is marked REPEAT and never pushed
-// A batch with more than MC candidates is listed for the sort-and-runs
-// path instead. A split half (<= CAP elements) is staged in [0, 16 MC).
+// A batch with more than MC candidates is listed instead (for the second
+// pass, whose table holds CAP). A split half (<= CAP elements) is staged in
+// [0, 8 CAP), which for MC = CAP / 2 covers the table area.
 constexpr uint32_t NONE16 = 0xFFFFu;
 constexpr uint16_t REPEAT16 = 0xFFFEu;
 constexpr int GROUP_LDS_PER_CAND = 22;
@@ -356,14 +358,14 @@ constexpr int GROUP_LDS_PER_CAND = 22;
 // One batch of m_in <= CAP elements whose values arrive in registers
 // (element x = threadIdx.x + r * NTH is in e_in[r]); the caller has already
 // issued the loads of the next batch, so their latency overlaps this batch's
-// LDS work. On entry and on return the table area (2 CAP words) is zero.
+// LDS work. On entry and on return the table area (2 MC words) is zero.
 //
 // Most elements have a hash no other element of the batch shares. A
 // prefilter finds the rest first: every element sets the bit of its low hash
-// bits in a bitmap of 32 CAP bits (atomicOr returns whether the bit was
+// bits in a bitmap of 32 MC bits (atomicOr returns whether the bit was
 // already set; if so the bit is also set in a second bitmap), and only the
 // elements whose bit ends up in the second bitmap (every element of a group
-// of equal hashes, plus about m / (32 CAP) of the others) are compacted, in
+// of equal hashes, plus about m / (32 MC) of the others) are compacted, in
 // order, and grouped in the table. No pair is lost: equal hashes have equal
 // bits.
 // Pairs collect in an LDS buffer of GROUP_PBUF entries (pbuf_n of them used,
@@ -385,14 +387,15 @@ __device__ void flush_pairs(const ShardOut& out, const uint64_t* s_pbuf, uint32_
   __syncthreads();
 }
 
-template <int CAP, int NTH>
+template <int CAP, int NTH, int MCAND = CAP / 2>
 __device__ bool group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, uint32_t idbits,
                             const ShardOut& out, unsigned char* lds, uint64_t* s_tmp64,
                             uint64_t* s_base, uint64_t* s_pbuf, uint32_t& pbuf_n, uint64_t ga,
                             uint64_t gb, uint64_t* __restrict__ big,
                             unsigned long long* __restrict__ nbig) {
   constexpr int PER = CAP / NTH;
-  constexpr uint32_t MC = CAP / 2;
+  constexpr uint32_t MC = MCAND;
+  static_assert(MC <= (uint32_t)CAP && MC <= 0xFFF0u, "members are 16-bit indices");
   constexpr int NW = NTH / 64;
   constexpr int NC = PER * NW;
   static_assert(NC % 4 == 0, "compaction counts are read four at a time");
@@ -442,8 +445,8 @@ __device__ bool group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
   }
   for (uint32_t x = threadIdx.x; x < 2 * MC; x += NTH) s_tab[x] = 0;
   if (m > MC) {
-    // too many candidates for the table: the sort-and-runs path takes the
-    // batch's whole range (a pair found twice is dropped at verification)
+    // too many candidates for the table: the batch's whole range is listed
+    // for the second pass (a pair found twice is dropped at verification)
     if (threadIdx.x == 0) {
       const unsigned long long x = atomicAdd(nbig, 1ull);
       big[2 * x] = ga;
@@ -565,7 +568,8 @@ __device__ bool group_batch(const uint64_t (&e_in)[CAP / NTH], uint32_t m_in, ui
 // consecutive non-empty segments while they fit in CAP elements (returns 1).
 // A segment of CAP < size <= 2 CAP is returned alone (returns 2) to be
 // grouped in two halves by one more hash bit; a larger one is listed in
-// big[] for the sort-and-runs fallback and skipped. Returns 0 when the range
+// big[] (the second pass hands it on to the sort-and-runs path) and skipped.
+// Returns 0 when the range
 // is exhausted.
 template <int CAP>
 __device__ __forceinline__ int next_batch(const uint32_t* __restrict__ seg_start,
@@ -634,7 +638,7 @@ __device__ uint32_t split_part(const uint64_t* __restrict__ E, uint32_t a, uint3
 // the elements of batch t + 1 are loaded into registers while batch t is
 // grouped.
 template <int CAP, int NTH>
-__global__ __launch_bounds__(NTH) void k_group_seg(
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(CAP == 2048 ? 5 : 1))) void k_group_seg(
     const uint64_t* __restrict__ E, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
     uint32_t splitbit, ShardOut out, uint64_t* __restrict__ big,
@@ -718,6 +722,81 @@ __global__ __launch_bounds__(NTH) void k_group_seg(
     a = na;
     b = nb;
     kind = nkind;
+  }
+  if (pbuf_n) flush_pairs<NTH>(out, s_pbuf, pbuf_n, s_base);
+}
+
+// Second pass over the ranges k_group_seg listed, big[0, 2 *nlisted): batches
+// with more than CAP / 2 prefilter candidates, segments with such a split
+// half, and segments over 2 CAP elements. Each workgroup takes ranges in turn
+// with a table for a whole batch of candidates (MC = CAP, twice the LDS of
+// the main kernel, so fewer workgroups fit on a CU; few ranges come here).
+// The count is read from device memory, so the launch follows k_group_seg's
+// with no host round trip and writes into the same sharded output; a count
+// over max_listed (which the listing cannot reach) is clamped to it.
+// A range over CAP elements is split by one more hash bit, as in k_group_seg;
+// a range that still does not fit is listed in big2[] for the sort-and-runs
+// path.
+template <int CAP, int NTH>
+__global__ __launch_bounds__(NTH) void k_group_listed(
+    const uint64_t* __restrict__ E, const uint64_t* __restrict__ big,
+    const unsigned long long* __restrict__ nlisted_p, uint64_t max_listed, uint32_t idbits,
+    uint32_t splitbit, ShardOut out, uint64_t* __restrict__ big2,
+    unsigned long long* __restrict__ nbig2) {
+  constexpr int PER = CAP / NTH;
+  const uint64_t nlisted = min((uint64_t)*nlisted_p, max_listed);
+  if (blockIdx.x >= nlisted) return;
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ uint64_t s_tmp64[NTH / 64];
+  __shared__ uint64_t s_base[2];
+  __shared__ uint64_t s_pbuf[GROUP_PBUF];
+  uint32_t pbuf_n = 0;
+  uint64_t* s_e = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* s_tab = reinterpret_cast<uint32_t*>(lds + CAP * 8);
+  // group_batch expects a zero table area; it leaves it zero, and the
+  // staging of a split half ([0, 8 CAP)) does not reach it
+  for (uint32_t x = threadIdx.x; x < 2u * CAP; x += NTH) s_tab[x] = 0;
+  __syncthreads();
+  const bool can_split = splitbit >= idbits && splitbit < 64;
+  for (uint64_t g = blockIdx.x; g < nlisted; g += gridDim.x) {
+    const uint32_t a = (uint32_t)big[2 * g], b = (uint32_t)big[2 * g + 1];
+    const uint32_t n = b - a;
+    if (n <= (uint32_t)CAP) {
+      uint64_t e[PER];
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const uint32_t x = threadIdx.x + r * NTH;
+        e[r] = x < n ? E[a + x] : 0;
+      }
+      group_batch<CAP, NTH, CAP>(e, n, idbits, out, lds, s_tmp64, s_base, s_pbuf, pbuf_n, a, b,
+                                 big2, nbig2);
+      continue;
+    }
+    bool whole = !can_split || n > 2u * CAP;
+    if (!whole) {
+      const uint32_t ones = split_part<CAP, NTH>(E, a, b, splitbit, -1, s_e, s_tmp64);
+      whole = ones > (uint32_t)CAP || n - ones > (uint32_t)CAP;
+    }
+    if (whole) {
+      if (threadIdx.x == 0) {
+        const unsigned long long x = atomicAdd(nbig2, 1ull);
+        big2[2 * x] = a;
+        big2[2 * x + 1] = b;
+      }
+      continue;
+    }
+    for (int part = 0; part < 2; ++part) {
+      const uint32_t m = split_part<CAP, NTH>(E, a, b, splitbit, part, s_e, s_tmp64);
+      uint64_t e[PER];
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const uint32_t x = threadIdx.x + r * NTH;
+        e[r] = x < m ? s_e[x] : 0;
+      }
+      __syncthreads();  // group_batch rewrites s_e
+      group_batch<CAP, NTH, CAP>(e, m, idbits, out, lds, s_tmp64, s_base, s_pbuf, pbuf_n, a, b,
+                                 big2, nbig2);
+    }
   }
   if (pbuf_n) flush_pairs<NTH>(out, s_pbuf, pbuf_n, s_base);
 }
@@ -838,6 +917,49 @@ static void launch_group_t(const uint64_t* E, const uint32_t* ss, const uint32_t
   const ShardOut out{a.base, a.region, a.over, a.over_cap, a.counter};
   hipLaunchKernelGGL((sdk::k_group_seg<CAP, NTH>), dim3(g), dim3(NTH), group_lds(CAP), s, E, ss,
                      se, nseg, spw, idbits, splitbit, out, big, nbig);
+}
+
+static size_t listed_lds(int cap) { return (size_t)cap * sdk::GROUP_LDS_PER_CAND; }
+
+template <int CAP, int NTH>
+static void launch_listed_t(const uint64_t* E, const uint64_t* big,
+                            const unsigned long long* nlisted, uint64_t max_listed,
+                            uint32_t idbits, uint32_t splitbit, const ShardArgs& a, uint64_t* big2,
+                            unsigned long long* nbig2, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    attr = true;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&sdk::k_group_listed<CAP, NTH>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)listed_lds(CAP)) != hipSuccess)
+      (void)hipGetLastError();  // the launch reports any real problem
+  }
+  // a few workgroups per CU; each takes listed ranges in turn
+  const unsigned g = (unsigned)std::min<uint64_t>(max_listed, 1024u);
+  const ShardOut out{a.base, a.region, a.over, a.over_cap, a.counter};
+  hipLaunchKernelGGL((sdk::k_group_listed<CAP, NTH>), dim3(g), dim3(NTH), listed_lds(CAP), s, E,
+                     big, nlisted, max_listed, idbits, splitbit, out, big2, nbig2);
+}
+
+void launch_group_listed(int cap, const uint64_t* E, const uint64_t* big,
+                         const unsigned long long* nlisted, uint64_t max_listed, uint32_t idbits,
+                         uint32_t splitbit, const ShardArgs& out, uint64_t* big2,
+                         unsigned long long* nbig2, hipStream_t s) {
+  if (!max_listed) return;
+  switch (cap) {
+    case 4096:
+      launch_listed_t<4096, 512>(E, big, nlisted, max_listed, idbits, splitbit, out, big2, nbig2, s);
+      break;
+    case 2048:
+      launch_listed_t<2048, 256>(E, big, nlisted, max_listed, idbits, splitbit, out, big2, nbig2, s);
+      break;
+    case 1024:
+      launch_listed_t<1024, 128>(E, big, nlisted, max_listed, idbits, splitbit, out, big2, nbig2, s);
+      break;
+    default:
+      launch_listed_t<256, 64>(E, big, nlisted, max_listed, idbits, splitbit, out, big2, nbig2, s);
+      break;
+  }
 }
 
 bool group_cap_supported(int cap) { return cap == 4096 || cap == 2048 || cap == 1024 || cap == 256; }

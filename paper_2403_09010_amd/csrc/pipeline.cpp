@@ -214,26 +214,34 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
       (uint32_t)std::max(1.0, std::floor(0.8 * cap / std::max(mean_seg, 1.0) + 0.5));
   const uint32_t spw = per_batch * (uint32_t)(c->group_batches ? c->group_batches : 4);
   // listed ranges: segments over 2 cap elements, split segments with a half
-  // over cap, and batches with over cap / 2 prefilter candidates; each holds
-  // more than cap / 2 elements of its own (a split segment can be listed
-  // once per half), so 4 nk / cap + 2 entries always suffice
+  // over cap / 2 candidates, and batches with over cap / 2 prefilter
+  // candidates; each is listed once and holds more than cap / 2 elements of
+  // its own, so 2 nk / cap entries suffice (twice that are allocated)
   const uint64_t nbig_cap = 4 * (uint64_t)nk / cap + 2;
   uint64_t* big = cl.sc.get<uint64_t>(2 * nbig_cap);
+  uint64_t* big2 = cl.sc.get<uint64_t>(2 * nbig_cap);
   unsigned long long* nbig = reinterpret_cast<unsigned long long*>(cl.counters + CNT_NBIG);
+  unsigned long long* nbig2 = reinterpret_cast<unsigned long long*>(cl.counters + CNT_NBIG2);
+  static_assert(CNT_NBIG2 == CNT_NBIG + 2, "both counts are cleared by one fill");
   Cands cand = sharded_output(
       cl, nk / 24, "group_local",
       [&](const ShardArgs& out) {
-        launch_fill_u64(reinterpret_cast<uint64_t*>(nbig), 0, 1, s);
+        launch_fill_u64(reinterpret_cast<uint64_t*>(nbig), 0, 2, s);
         const uint32_t splitbit = segshift >= 1 ? segshift - 1 : 64u;
         launch_group_seg(cap, E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
                          nbig, s);
+        // the ranges listed above, with a table for a whole batch of
+        // candidates; what still does not fit goes to big2
+        launch_group_listed(cap, E, big, nbig, nbig_cap, idbits, splitbit, out, big2, nbig2, s);
       },
       [&](uint64_t n) { return (double)nk * 8 + (double)n * 8; });
-  uint64_t nb;
-  std::memcpy(&nb, readback(c, nbig, 8, s), 8);
-  c->stats.n_big_segments = (int64_t)nb;
-  if (nb) {
-    Cands extra = oversized_group(cl, E, big, nb, idbits);
+  uint64_t nb[2];
+  std::memcpy(nb, readback(c, nbig, 16, s), 16);
+  if (nb[0] > nbig_cap) throw Error{SD_E_HIP, "internal error: listed ranges exceed their bound"};
+  const uint64_t nb2 = nb[1];
+  c->stats.n_big_segments = (int64_t)nb2;
+  if (nb2) {
+    Cands extra = oversized_group(cl, E, big2, nb2, idbits);
     if (extra.n) {
       uint64_t* merged = dalloc_t<uint64_t>(c, cand.n + extra.n);
       if (cand.n)

@@ -70,9 +70,10 @@ enum : int {
   CNT_CAND = 96,      // u64 candidate counter
   CNT_PAIRS = 98,     // u64 result counter
   CNT_LBERR = 100,    // look-back bound hits
-  CNT_NBIG = 102,     // u64 count of oversized segments
-  CNT_CAND2 = 104,    // u64 candidate counter of the full-key emission
-  CNT_STEPS = 106,    // u64 search comparisons of learned-index lookups
+  CNT_NBIG = 102,     // u64 count of ranges the grouping kernel lists
+  CNT_NBIG2 = 104,    // u64 count of ranges the second grouping pass lists
+  CNT_CAND2 = 106,    // u64 candidate counter of the full-key emission
+  CNT_STEPS = 108,    // u64 search comparisons of learned-index lookups
   CNT_TOTAL = 128
 };
 

@@ -140,6 +140,13 @@ void launch_group_seg(int cap, const uint64_t* E, const uint32_t* seg_start,
                       const uint32_t* seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
                       uint32_t splitbit, const ShardArgs& out, uint64_t* big,
                       unsigned long long* nbig, hipStream_t s);
+// second pass over the *nlisted (device count, at most max_listed) ranges
+// launch_group_seg listed in big[], with a table for cap candidates; ranges
+// that still do not fit go to big2[]
+void launch_group_listed(int cap, const uint64_t* E, const uint64_t* big,
+                         const unsigned long long* nlisted, uint64_t max_listed, uint32_t idbits,
+                         uint32_t splitbit, const ShardArgs& out, uint64_t* big2,
+                         unsigned long long* nbig2, hipStream_t s);
 void launch_gather_big(const uint64_t* E, const uint64_t* big, const uint64_t* out_off,
                        uint32_t nseg, uint64_t* out, hipStream_t s);
 void launch_emit_hash_runs(const uint64_t* E, uint64_t n, uint32_t idbits, uint64_t* cand,
