@@ -89,6 +89,24 @@ constexpr int VG_PRE = 27;
 // with u = p2 (p2 - 1) / 2 + p1, the same for every length L (a string of
 // length L uses the first C(L, 2) of them). Entry: p1 | p2 << 8.
 constexpr int VG_PAIRS = KEY_MAX_LEN * (KEY_MAX_LEN - 1) / 2;
+static_assert(VG_PAIRS % 2 == 0, "the pair table is copied as 32-bit words");
+
+struct PairTab {
+  uint32_t w[VG_PAIRS / 2];  // entries 2 i and 2 i + 1, low half first
+};
+
+constexpr PairTab make_pair_tab() {
+  PairTab t{};
+  int u = 0;
+  for (int p2 = 1; p2 < KEY_MAX_LEN; ++p2)
+    for (int p1 = 0; p1 < p2; ++p1, ++u) {
+      const uint32_t e = (uint32_t)p1 | ((uint32_t)p2 << 8);
+      t.w[u / 2] |= (u % 2) ? e << 16 : e;
+    }
+  return t;
+}
+
+__constant__ PairTab kPairTab = make_pair_tab();
 
 // Deletion positions of variant v of a string of length L in the enumeration
 // order (v = 0 the string itself, v = 1..L one deletion at v - 1, then the
@@ -124,63 +142,65 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   __shared__ uint32_t s_len[VG_SEQS];
   __shared__ uint32_t s_n1[VG_SEQS], s_n2[VG_SEQS];  // canonical-test masks
   __shared__ uint32_t s_roff[VG_SEQS + 1];            // block-local deletion-set prefix
-  __shared__ uint32_t s_h[3 * 256];
-  __shared__ uint16_t s_pairs[VG_PAIRS];
+  // the digit counts; until the prefix XORs are done, the same LDS holds
+  // the hash's per-residue words
+  __shared__ __align__(16) uint32_t s_h[3 * 256];
+  uint64_t* s_b = reinterpret_cast<uint64_t*>(s_h);  // [32]
+  __shared__ __align__(4) uint16_t s_pairs[VG_PAIRS];
   // spb <= VG_SEQS sequences per block
   const uint64_t s0 = (uint64_t)blockIdx.x * spb;
   const uint32_t ns = (uint32_t)min<uint64_t>(spb, nseq - s0);
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  for (uint32_t x = threadIdx.x; x <= ns; x += VG_NT) s_off[x] = voff[s0 + x];
-  for (uint32_t x = threadIdx.x; x < 3 * 256; x += VG_NT) s_h[x] = 0;
-  if (threadIdx.x < 32) s_c[threadIdx.x] = kHashTab.c[threadIdx.x];
-  for (uint32_t u = threadIdx.x; u < (uint32_t)VG_PAIRS; u += VG_NT) {
-    uint32_t p2 = 1;
-    while ((p2 + 1) * p2 / 2 <= u) ++p2;
-    s_pairs[u] = (uint16_t)((u - p2 * (p2 - 1) / 2) | (p2 << 8));
-  }
-  // prefix XORs: each half-wave takes one sequence, lane t its position t
-  {
-    const uint32_t half = lane >> 5, t = lane & 31u;
-    for (uint32_t x0 = 2 * w; x0 < ns; x0 += 2 * NWV) {
-      const uint32_t x = x0 + half;
-      const bool live = x < ns;
-      const u128 key = live ? seq[s0 + x] : (u128)0;
-      const uint32_t L = key_len(key);
-      uint64_t term = 0;
-      uint32_t r = 32u + t;  // distinct from every residue
-      if (live && t < L) {
-        r = (uint32_t)(key >> (115 - 5 * t)) & 31u;
-        term = __builtin_rotateright64(kHashTab.b[r], t);
-      }
+  // every global load of the set-up is issued at once (one thread loads at
+  // most one offset, one key, one hash word and one pair-table word;
+  // ns <= 64 < VG_NT), so the block waits for one memory round trip
+  const uint32_t tx = threadIdx.x;
+  const uint64_t ld_off = tx <= ns ? voff[s0 + tx] : 0;
+  const u128 key = tx < ns ? seq[s0 + tx] : (u128)0;
+  const uint64_t ld_tab = tx < 32 ? kHashTab.b[tx] : tx < 64 ? kHashTab.c[tx - 32] : 0;
+  const uint32_t ld_pair = tx < (uint32_t)VG_PAIRS / 2 ? kPairTab.w[tx] : 0u;
+  if (tx <= ns) s_off[tx] = ld_off;
+  if (tx < 32) s_b[tx] = ld_tab;
+  else if (tx < 64) s_c[tx - 32] = ld_tab;
+  if (tx < (uint32_t)VG_PAIRS / 2) reinterpret_cast<uint32_t*>(s_pairs)[tx] = ld_pair;
+  __syncthreads();
+  // one thread per sequence: the prefix XORs P[t] of the position terms
+  // rotr(B[s[i]], i), i < t, for t = 0 .. L + 2 (P[L + 1] = P[L + 2] = P[L],
+  // which the hash reads for "no second deletion"), and the canonical-test
+  // masks: n1 bit t = (t = L - 1 or s[t] != s[t + 1]), n2 bit t =
+  // (t = L - 2 or s[t] != s[t + 2])
+  if (tx < ns) {
+    const uint32_t L = key_len(key);
+    uint64_t* P = s_pre + tx * VG_PRE;
+    uint64_t acc = 0;
+    uint32_t n1 = 0, n2 = 0, r1 = 0, r2 = 0;  // r1 = s[t - 1], r2 = s[t - 2]
+    u128 kk = key << 8;                        // residue t at the top 5 bits
+    P[0] = 0;
+    for (uint32_t t = 0; t < L; ++t) {
+      const uint32_t r = (uint32_t)(kk >> 123);
+      kk <<= 5;
+      acc ^= __builtin_rotateright64(s_b[r], t);
+      P[t + 1] = acc;
       if (DISTINCT) {
-        const uint32_t r1 = __shfl_down(r, 1, 32), r2 = __shfl_down(r, 2, 32);
-        const uint64_t b1 = __ballot(t < L && (t + 1 == L || r != r1));
-        const uint64_t b2 = __ballot(t + 1 < L && (t + 2 == L || r != r2));
-        if (live && t == 0) {
-          s_n1[x] = (uint32_t)(b1 >> (32 * half));
-          s_n2[x] = (uint32_t)(b2 >> (32 * half));
-        }
-      }
-      // inclusive XOR scan over the 32 lanes of the half-wave
-      uint32_t lo = (uint32_t)term, hi = (uint32_t)(term >> 32);
-#pragma unroll
-      for (int o = 1; o < 32; o <<= 1) {
-        const uint32_t plo = __shfl_up(lo, o, 32), phi = __shfl_up(hi, o, 32);
-        if (t >= (uint32_t)o) {
-          lo ^= plo;
-          hi ^= phi;
-        }
-      }
-      if (live && t + 1 < (uint32_t)VG_PRE) {
-        s_pre[x * VG_PRE + t + 1] = ((uint64_t)hi << 32) | lo;
-        if (t == 0) {
-          s_pre[x * VG_PRE] = 0;
-          s_len[x] = L;
-        }
+        if (t >= 1) n1 |= (uint32_t)(r1 != r) << (t - 1);
+        if (t >= 2) n2 |= (uint32_t)(r2 != r) << (t - 2);
+        r2 = r1;
+        r1 = r;
       }
     }
+    P[L + 1] = acc;
+    P[L + 2] = acc;
+    if (DISTINCT) {
+      if (L >= 1) n1 |= 1u << (L - 1);
+      if (L >= 2) n2 |= 1u << (L - 2);
+      s_n1[tx] = n1;
+      s_n2[tx] = n2;
+    }
+    s_len[tx] = L;
   }
   __syncthreads();
+  // the keys and table words are dead: the area becomes the digit counts
+  for (uint32_t x = threadIdx.x; x < 3 * 256; x += VG_NT) s_h[x] = 0;
   // block-local first deletion set of each sequence: V(L, k) each
   if (w == 0) {
     const uint32_t c = lane < ns ? (DISTINCT ? num_variants(s_len[lane], k)
