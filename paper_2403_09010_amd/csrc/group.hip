@@ -231,16 +231,36 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
         if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e >> sh[q]) & mk[q])], 1u);
     }
   };
-  auto variant = [&](uint32_t x, uint32_t v, bool valid, uint64_t& e) -> bool {
-    const uint32_t L = s_len[x];
+  // what every variant of sequence x reads, loaded once per sequence: the
+  // length, the extended canonical-test masks, the prefix-XOR row with its
+  // entry P[L], and the length words C[L - d] for d = 0, 1, 2 deletions
+  struct SeqVals {
+    uint32_t L, n1x, n2x;
+    const uint64_t* P;
+    uint64_t pl, c0, c1, c2, id;
+  };
+  auto seq_vals = [&](uint32_t x) {
+    SeqVals q;
+    q.L = s_len[x];
+    q.P = s_pre + x * VG_PRE;
+    q.pl = q.P[q.L];
+    q.c0 = s_c[q.L];
+    q.c1 = s_c[q.L >= 1 ? q.L - 1 : 0u];
+    q.c2 = s_c[q.L >= 2 ? q.L - 2 : 0u];
+    q.n1x = q.n2x = 0;
+    if (DISTINCT) canonical_ext_masks(s_n1[x], s_n2[x], q.L, q.n1x, q.n2x);
+    q.id = s0 + x;
+    return q;
+  };
+  auto variant = [&](SeqVals q, uint32_t v, bool valid, uint64_t& e) -> bool {
     uint32_t p1, p2;
-    variant_positions(s_pairs, L, valid ? v : 0u, p1, p2);
-    const uint32_t m = L - (uint32_t)(p1 < L) - (uint32_t)(p2 < L);
-    const uint64_t* P = s_pre + x * VG_PRE;
-    const uint64_t h = s_c[m] ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
-                       __builtin_rotateleft64(P[L] ^ P[p2 + 1], 2);
-    e = (h & ~idmask) | (s0 + x);
-    return valid && (!DISTINCT || variant_canonical(s_n1[x], s_n2[x], L, p1, p2));
+    variant_positions(s_pairs, q.L, valid ? v : 0u, p1, p2);
+    const uint64_t cm = p2 < q.L ? q.c2 : p1 < q.L ? q.c1 : q.c0;
+    const uint64_t* P = q.P;
+    const uint64_t h = cm ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
+                       __builtin_rotateleft64(q.pl ^ P[p2 + 1], 2);
+    e = (h & ~idmask) | q.id;
+    return valid && (!DISTINCT || variant_canonical_ext(q.n1x, q.n2x, p1, p2));
   };
   const uint32_t xa = w * ns / NWV, xb = (w + 1) * ns / NWV;
   for (uint32_t x = xa; x < xb;) {
@@ -248,13 +268,14 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
     const uint32_t end_x = (uint32_t)(s_off[x + 1] - g0);
     if (nraw > 64) {
       uint32_t at = (uint32_t)(s_off[x] - g0);  // next output slot of this sequence
+      const SeqVals q = seq_vals(x);
       for (uint32_t c0 = 0; c0 < nraw; c0 += 128) {
         uint64_t e[2];
         bool keep[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           const uint32_t v = c0 + 64 * u + lane;
-          keep[u] = variant(x, v, v < nraw, e[u]);
+          keep[u] = variant(q, v, v < nraw, e[u]);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -280,7 +301,7 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
         hi = mid - 1;
     }
     uint64_t e;
-    const bool keep = variant(lo, slot - s_roff[lo], valid, e);
+    const bool keep = variant(seq_vals(lo), slot - s_roff[lo], valid, e);
     const uint64_t bal = __ballot(keep);
     // rank among the kept lanes of the same sequence (a contiguous lane range)
     const uint32_t zl = s_roff[lo] - s_roff[x];

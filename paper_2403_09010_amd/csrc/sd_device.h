@@ -68,6 +68,23 @@ __device__ __forceinline__ bool variant_canonical(uint32_t n1, uint32_t n2, uint
   return (a & (n1 >> p2) & 1u) != 0;
 }
 
+// The same test with no case split: n1 gains bits L and L + 1 and n2 bits
+// L - 1 and L, which only the "one deletion" (p2 = L) and "none" (p1 = L,
+// p2 = L + 1) forms read, so those forms pass exactly when variant_canonical
+// passes them (one deletion at p < L - 1 reads n1 bit p; at L - 1, and none,
+// read forced bits) and a pair p1 < p2 < L reads the original bits.
+__device__ __forceinline__ void canonical_ext_masks(uint32_t n1, uint32_t n2, uint32_t L,
+                                                    uint32_t& n1x, uint32_t& n2x) {
+  n1x = n1 | (3u << L);
+  n2x = n2 | (1u << L) | (L >= 1 ? 1u << (L - 1) : 0u);
+}
+
+__device__ __forceinline__ bool variant_canonical_ext(uint32_t n1x, uint32_t n2x, uint32_t p1,
+                                                      uint32_t p2) {
+  const uint32_t sel = p2 > p1 + 1 ? n1x : n2x;
+  return ((sel >> p1) & (n1x >> p2) & 1u) != 0;
+}
+
 // Number of distinct strings among the deletion variants with at most k
 // deletions: the canonical sets above, counted in O(L) from the same masks
 // (the run count is the number of canonical first deletions p1 <= p2 - 2).

@@ -113,6 +113,24 @@ def canonical_masks(s, D):
     return bool(a & (n1 >> p2) & 1)
 
 
+def canonical_ext(s, D):
+    """The generator's form with no case split: one deletion at p is the
+    position pair (p, L), no deletion is (L, L + 1), and the masks gain bits
+    L, L + 1 (n1) and L - 1, L (n2)."""
+    L = len(s)
+    n1, n2 = masks(s)
+    n1x = n1 | (3 << L)
+    n2x = n2 | (1 << L) | ((1 << (L - 1)) if L >= 1 else 0)
+    if len(D) == 0:
+        p1, p2 = L, L + 1
+    elif len(D) == 1:
+        p1, p2 = D[0], L
+    else:
+        p1, p2 = D
+    sel = n1x if p2 > p1 + 1 else n2x
+    return bool((sel >> p1) & (n1x >> p2) & 1)
+
+
 def random_strings(n, seed):
     rng = random.Random(seed)
     for _ in range(n):
@@ -160,3 +178,10 @@ def test_worked_cases():
     # no repeated residues: every deletion set is canonical
     s = "ACDEFGHIKL"
     assert distinct_count(s, 2) == 1 + 10 + 45
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_extended_mask_form_of_the_rule(k):
+    for s in list(random_strings(2000, 41 + k)) + ["", "A", "AA", "AB", "AAA"]:
+        for D, _ in variants(s, k):
+            assert canonical_ext(s, D) == canonical(s, D), (s, D)
