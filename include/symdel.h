@@ -78,7 +78,8 @@ typedef struct {
   int64_t n_pairs;        /* pairs returned */
   int32_t n_stages;       /* valid entries below (0 unless SD_OPT_TIMING is on) */
   int32_t n_sort_passes;  /* radix passes run by the grouping sort */
-  int64_t n_big_segments; /* hashed path: hash segments too large for LDS (full-key path) */
+  int64_t n_big_segments; /* hashed path: ranges neither grouping kernel could hold in LDS,
+                             grouped by a sort on the full hash instead */
   int64_t n_probe_steps;  /* learned indexes: comparisons made by the lookups' searches */
   char stage_name[SD_MAX_STAGES][24];
   double stage_ms[SD_MAX_STAGES];      /* device time between HIP events on `stream` */

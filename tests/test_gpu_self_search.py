@@ -219,6 +219,22 @@ def test_heavy_groups(cctx):
         assert_same(gpu_triples(cctx, c, o, k), oracle_triples(c, o, k))
 
 
+def test_batches_of_shared_hashes(ctx):
+    # 60 copies each of 40 sequences: every element of an LDS batch shares its
+    # hash with others, so the grouping kernel's half-batch candidate table
+    # overflows and lists each batch; the second pass, with a whole-batch
+    # table, must group them all (nothing is left for the full-hash sort)
+    base, bo = cdr3gen.generate(43, 40)
+    rng = np.random.default_rng(5)
+    pick = rng.permutation(np.repeat(np.arange(40), 60))
+    strings = [base[bo[x]:bo[x + 1]].tobytes() for x in pick]
+    c, o = csr(strings)
+    for k in (1, 2):
+        log(f"self_search 2400 sequences, 60 copies of each of 40, k={k}")
+        assert_same(gpu_triples(ctx, c, o, k), oracle_triples(c, o, k))
+        assert ctx.stats()["n_big_segments"] == 0
+
+
 def test_group_larger_than_lds(ctx):
     # 4500 copies of one sequence: its variants form hash segments larger
     # than the 4096-element LDS capacity, so they take the full-key path
