@@ -221,54 +221,72 @@ __global__ __launch_bounds__(NT) void k_emit_runs(const uint64_t* __restrict__ k
 
 constexpr int CITEMS = 8;
 
+// A tile of NT * CITEMS sorted candidates per workgroup. Repeats (a candidate
+// equal to its predecessor) are dropped first and the distinct candidates
+// listed in LDS in order; the distances then run over that dense list, each
+// thread taking a contiguous piece, so a wave does not run the distance once
+// per candidate slot while most of its lanes hold repeats. Kept pairs are
+// written in candidate order after a look-back over the tiles.
 __global__ __launch_bounds__(NT) void k_verify_compact(
     const uint64_t* __restrict__ cand, uint64_t c, const u128* __restrict__ pa,
     const u128* __restrict__ sb, int k, uint32_t* __restrict__ oi, uint32_t* __restrict__ oj,
     uint8_t* __restrict__ od, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter,
     uint32_t epoch, unsigned long long* __restrict__ out_count, uint32_t* __restrict__ err) {
   constexpr int TILE = NT * CITEMS;
+  constexpr uint8_t DROP = 0xFFu;
   __shared__ uint32_t s_tile;
   __shared__ uint32_t s_tmp[NT / 64];
   __shared__ uint64_t s_excl;
+  __shared__ uint64_t s_list[TILE];  // the tile's distinct candidates, in order
+  __shared__ uint8_t s_dist[TILE];   // their distances, DROP if over k
   if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
   __syncthreads();
   const uint64_t tile = s_tile;
   if (tile >= gridDim.x) return;
   const uint64_t first = tile * TILE + (uint64_t)threadIdx.x * CITEMS;
-  uint32_t keepmask = 0, cnt = 0;
-  uint8_t dist[CITEMS];
+  uint64_t vals[CITEMS];
+  uint32_t umask = 0;
+  uint64_t prev = first > 0 && first - 1 < c ? cand[first - 1] : ~0ull;
 #pragma unroll
   for (int x = 0; x < CITEMS; ++x) {
     const uint64_t e = first + x;
-    dist[x] = 0;
-    if (e < c) {
-      const uint64_t v = cand[e];
-      if (e == 0 || cand[e - 1] != v) {
-        const u128 a = pa[v >> 32], b = sb[(uint32_t)v];
-        const int la = (int)(a >> 120), lb = (int)key_len(b);
-        if (abs(la - lb) <= k) {
-          const uint32_t d = lev_planes(a, b);
-          if (d <= (uint32_t)k) {
-            keepmask |= 1u << x;
-            dist[x] = (uint8_t)d;
-            ++cnt;
-          }
-        }
-      }
+    vals[x] = e < c ? cand[e] : 0;
+    if (e < c && (e == 0 || vals[x] != prev)) umask |= 1u << x;
+    prev = vals[x];
+  }
+  uint32_t ntot;
+  uint32_t at = block_excl_scan<NT>((uint32_t)__popc(umask), s_tmp, &ntot);
+#pragma unroll
+  for (int x = 0; x < CITEMS; ++x)
+    if ((umask >> x) & 1u) s_list[at++] = vals[x];
+  __syncthreads();
+  const uint32_t per = (ntot + NT - 1) / NT;
+  const uint32_t l0 = min(threadIdx.x * per, ntot), l1 = min(l0 + per, ntot);
+  uint32_t cnt = 0;
+  for (uint32_t l = l0; l < l1; ++l) {
+    const uint64_t v = s_list[l];
+    const u128 a = pa[v >> 32], b = sb[(uint32_t)v];
+    const int la = (int)(a >> 120), lb = (int)key_len(b);
+    uint8_t d = DROP;
+    if (abs(la - lb) <= k) {
+      const uint32_t dd = lev_planes(a, b);
+      if (dd <= (uint32_t)k) d = (uint8_t)dd;
     }
+    s_dist[l] = d;  // read back below by this thread only
+    cnt += d != DROP;
   }
   uint32_t total;
   const uint32_t texcl = block_excl_scan<NT>(cnt, s_tmp, &total);
   if (threadIdx.x == 0) s_excl = lb_exclusive(status, tile, 1, epoch, total, err);
   __syncthreads();
   uint64_t pos = s_excl + texcl;
-#pragma unroll
-  for (int x = 0; x < CITEMS; ++x) {
-    if (keepmask & (1u << x)) {
-      const uint64_t v = cand[first + x];
+  for (uint32_t l = l0; l < l1; ++l) {
+    const uint8_t d = s_dist[l];
+    if (d != DROP) {
+      const uint64_t v = s_list[l];
       oi[pos] = (uint32_t)(v >> 32);
       oj[pos] = (uint32_t)v;
-      od[pos] = dist[x];
+      od[pos] = d;
       ++pos;
     }
   }
