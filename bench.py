@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counters, scaled by a
 # 1 GiB copy (profiles/traffic_hashed_path_plain_1m_k2.md), for the stages and
 # workload they were taken on; other stages and workloads report null
-TRAFFIC_PER_LAUNCH = {("plain_1m_k2", "hash_counted_pass"): 1.6616e9,
-                      ("plain_1m_k2", "hash_passes"): 1.6546e9}
+TRAFFIC_PER_LAUNCH = {("plain_1m_k2", "hash_counted_pass"): 1.6599e9,
+                      ("plain_1m_k2", "hash_passes"): 1.6544e9}
 # stages that time exactly one kernel (launched once, or several times alike)
 KERNEL_OF_STAGE = {
     "vargen_hash": "k_vargen_hash",
