@@ -379,7 +379,7 @@ def main():
     ap.add_argument("--json-out", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the search runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched_2m_512":
         return run_batched(args)
