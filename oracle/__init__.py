@@ -10,6 +10,9 @@ Fig. 1).
 
 Functions return ``(a, b, d)`` numpy arrays sorted by ``(a, b)``:
   * ``self_search(codes, offsets, k)``: all i < j with Lev <= k.
+  * ``self_search_sharded(codes, offsets, k, shards, threads)``: the same
+    result on several threads with bounded memory (variant space split into
+    shards by a hash of the variant string).
   * ``query_search(ref, qry, k)``: all (q, r) with Lev(Q_q, R_r) <= k.
   * ``query_weighted(ref, qry, subst, indel, max_score)``: SymDel candidates
     at Levenshtein radius 2, kept when the weighted alignment cost is
@@ -35,7 +38,7 @@ _lib = None
 def build() -> str:
     """Compile the oracle with g++ (always rebuilds)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", tmp, _SRC])
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-pthread", "-fPIC", "-shared", "-o", tmp, _SRC])
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -58,6 +61,8 @@ def _load():
     for name in ("or_self_search", "or_self_candidates", "or_brute_self"):
         getattr(lib, name).restype = P
         getattr(lib, name).argtypes = [P, P, I64, I]
+    lib.or_self_search_sharded.restype = P
+    lib.or_self_search_sharded.argtypes = [P, P, I64, I, I, I]
     for name in ("or_query_search", "or_brute_query"):
         getattr(lib, name).restype = P
         getattr(lib, name).argtypes = [P, P, I64, P, P, I64, I]
@@ -132,6 +137,27 @@ def variants(s, k: int) -> list[bytes]:
 def self_search(codes, offsets, k: int):
     codes, offsets = _u8(codes), _i64(offsets)
     h = _load().or_self_search(codes.ctypes.data, offsets.ctypes.data, len(offsets) - 1, k)
+    return _take(h)
+
+
+def host_threads() -> int:
+    """Host threads the sharded oracle uses by default: OMP_NUM_THREADS if set
+    (the share of the host a job is given), else every hardware thread."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return os.cpu_count() or 1
+
+
+def self_search_sharded(codes, offsets, k: int, shards: int = 0, threads: int = 0):
+    """self_search on several threads with bounded memory: the variant space is
+    split into `shards` parts by a hash of the variant string (0: one per
+    thread); at most min(threads, shards) threads run (0: host_threads()).
+    Returns the same triplets as self_search."""
+    codes, offsets = _u8(codes), _i64(offsets)
+    threads = threads or host_threads()
+    h = _load().or_self_search_sharded(codes.ctypes.data, offsets.ctypes.data, len(offsets) - 1,
+                                       k, int(shards), int(threads))
     return _take(h)
 
 

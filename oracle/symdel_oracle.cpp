@@ -19,11 +19,20 @@
 // finer, substitution-weighted score): score = minimum-cost global alignment
 // with a 20x20 substitution cost table and a fixed indel cost.
 //
-// Everything is single threaded and unoptimised on purpose.
+// Everything is unoptimised on purpose. The plain entry points run on one
+// thread. or_self_search_sharded runs the same steps on all host cores with
+// bounded memory (the CPU-baseline plan for the large workloads): the
+// variant space is split into P shards by a hash of the variant string, each
+// shard regenerates every variant and keeps only its own, so a shard's map
+// holds about 1/P of the variants; equal variants always fall into the same
+// shard, so the union of the shards' bucket pairs is exactly the candidate
+// set of the single map.
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -69,29 +78,18 @@ int weighted_full(const uint8_t* a, int la, const uint8_t* b, int lb, const uint
   return D(la, lb);
 }
 
-// Every string obtained from s by deleting a set of m <= k positions, for
-// m = 0, 1, ..., min(k, |s|), position sets in lexicographic order. A string
-// of length L yields sum_{m<=k} C(L, m) variants counted with multiplicity
-// (56 for L = 10, k = 2, Section II A).
-void deletion_variants(const std::string& s, int k, std::vector<std::string>& out) {
-  out.clear();
-  const int L = (int)s.size();
+// Every set of m <= k positions of a string of length L, for m = 0, 1, ...,
+// min(k, L), each m-subset in lexicographic order: fn(pos, m) is called
+// once per set with pos[0] < ... < pos[m-1].
+template <class F>
+void for_each_deletion_set(int L, int k, F&& fn) {
   const int kk = std::min(k, L);
   std::vector<int> pos;
   for (int m = 0; m <= kk; ++m) {
     pos.resize(m);
     for (int t = 0; t < m; ++t) pos[t] = t;
     while (true) {
-      std::string v;
-      int next = 0;
-      for (int x = 0; x < L; ++x) {
-        if (next < m && pos[next] == x) {
-          ++next;
-          continue;
-        }
-        v.push_back(s[x]);
-      }
-      out.push_back(v);
+      fn(pos, m);
       // advance to the next m-subset in lexicographic order
       int t = m - 1;
       while (t >= 0 && pos[t] == L - m + t) --t;
@@ -100,6 +98,31 @@ void deletion_variants(const std::string& s, int k, std::vector<std::string>& ou
       for (int u = t + 1; u < m; ++u) pos[u] = pos[u - 1] + 1;
     }
   }
+}
+
+// s without the positions pos[0..m-1]
+std::string delete_positions(const std::string& s, const std::vector<int>& pos, int m) {
+  std::string v;
+  int next = 0;
+  for (int x = 0; x < (int)s.size(); ++x) {
+    if (next < m && pos[next] == x) {
+      ++next;
+      continue;
+    }
+    v.push_back(s[x]);
+  }
+  return v;
+}
+
+// Every string obtained from s by deleting a set of m <= k positions, in the
+// order of for_each_deletion_set. A string of length L yields
+// sum_{m<=k} C(L, m) variants counted with multiplicity (56 for L = 10,
+// k = 2, Section II A).
+void deletion_variants(const std::string& s, int k, std::vector<std::string>& out) {
+  out.clear();
+  for_each_deletion_set((int)s.size(), k, [&](const std::vector<int>& pos, int m) {
+    out.push_back(delete_positions(s, pos, m));
+  });
 }
 
 std::string seq_at(const uint8_t* codes, const int64_t* offs, int64_t i) {
@@ -164,6 +187,46 @@ void query_candidates(const MultiMap& refmap, const uint8_t* qc, const int64_t* 
   cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
 }
 
+// FNV-1a (64-bit) over the bytes of a variant; it only decides which shard
+// owns the variant, so any fixed function of the string would do.
+uint64_t fnv1a(const std::string& v) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char ch : v) {
+    h ^= ch;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// fnv1a(delete_positions(s, pos, m)) without building the string
+uint64_t fnv1a_deleted(const std::string& s, const std::vector<int>& pos, int m) {
+  uint64_t h = 1469598103934665603ull;
+  int next = 0;
+  for (int x = 0; x < (int)s.size(); ++x) {
+    if (next < m && pos[next] == x) {
+      ++next;
+      continue;
+    }
+    h ^= (unsigned char)s[x];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+int pick_threads(int nthreads) {
+  if (nthreads > 0) return nthreads;
+  const unsigned hc = std::thread::hardware_concurrency();
+  return hc ? (int)hc : 1;
+}
+
+// Run body(t) for t = 0 .. nthreads-1 on their own threads and join them.
+template <class F>
+void run_threads(int nthreads, F&& body) {
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthreads; ++t) pool.emplace_back(body, t);
+  for (std::thread& th : pool) th.join();
+}
+
 }  // namespace
 
 extern "C" {
@@ -211,6 +274,75 @@ void* or_self_search(const uint8_t* codes, const int64_t* offs, int64_t n, int k
       res->b.push_back(j);
       res->d.push_back(d);
     }
+  }
+  return res;
+}
+
+// Self search by SymDel on several threads with bounded memory: SymDel steps
+// 1-3 per shard of the variant space (shard s keeps the variants whose hash
+// is s modulo nshards), the shards' candidates merged, sorted and
+// de-duplicated, then step 4 on contiguous slices of the sorted candidates
+// (one slice per thread, concatenated in order). Returns the same triplets
+// as or_self_search. At most min(nthreads, nshards) threads run at once
+// (nthreads <= 0: one per hardware thread; nshards <= 0: one per thread).
+void* or_self_search_sharded(const uint8_t* codes, const int64_t* offs, int64_t n, int k,
+                             int nshards, int nthreads) {
+  Result* res = new Result();
+  const int T0 = pick_threads(nthreads);
+  const int P = nshards > 0 ? nshards : T0;
+  const int T = std::min(T0, P);
+  std::vector<std::vector<uint64_t>> shard_cand(P);
+  std::vector<int64_t> shard_raw(P, 0);
+  std::atomic<int> next{0};
+  run_threads(T, [&](int) {
+    for (;;) {
+      const int sh = next.fetch_add(1);
+      if (sh >= P) break;
+      MultiMap map;
+      for (int64_t i = 0; i < n; ++i) {
+        const std::string si = seq_at(codes, offs, i);
+        // the variants of si this shard owns (the hash decides before the
+        // string is built)
+        for_each_deletion_set((int)si.size(), k, [&](const std::vector<int>& pos, int m) {
+          if ((int)(fnv1a_deleted(si, pos, m) % (uint64_t)P) != sh) return;
+          std::vector<uint32_t>& ids = map[delete_positions(si, pos, m)];
+          if (ids.empty() || ids.back() != (uint32_t)i) ids.push_back((uint32_t)i);
+        });
+      }
+      self_candidates(map, shard_cand[sh], shard_raw[sh]);
+    }
+  });
+  std::vector<uint64_t> cand;
+  size_t tot = 0;
+  for (const auto& v : shard_cand) tot += v.size();
+  cand.reserve(tot);
+  for (auto& v : shard_cand) {
+    cand.insert(cand.end(), v.begin(), v.end());
+    std::vector<uint64_t>().swap(v);
+  }
+  for (int64_t r : shard_raw) res->raw += r;
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  // SymDel step 4 on T contiguous slices, kept in order
+  std::vector<Result> part(T);
+  const size_t nc = cand.size();
+  run_threads(T, [&](int t) {
+    const size_t lo = nc * (size_t)t / (size_t)T, hi = nc * (size_t)(t + 1) / (size_t)T;
+    for (size_t x = lo; x < hi; ++x) {
+      const uint32_t i = (uint32_t)(cand[x] >> 32), j = (uint32_t)cand[x];
+      const int d = lev_full(codes + offs[i], (int)(offs[i + 1] - offs[i]), codes + offs[j],
+                             (int)(offs[j + 1] - offs[j]));
+      if (d <= k) {
+        part[t].a.push_back(i);
+        part[t].b.push_back(j);
+        part[t].d.push_back(d);
+      }
+    }
+  });
+  for (const Result& r : part) {
+    res->a.insert(res->a.end(), r.a.begin(), r.a.end());
+    res->b.insert(res->b.end(), r.b.begin(), r.b.end());
+    res->d.insert(res->d.end(), r.d.begin(), r.d.end());
   }
   return res;
 }

@@ -239,6 +239,48 @@ def test_symdel_equals_brute_force_generator_k2(oracle_lib):
     assert {t[2] for t in got} == {0, 1, 2}
 
 
+# ---------------------------------------------------------------- sharded mode
+
+SHARDINGS = [(1, 1), (3, 2), (7, 3), (16, 4)]  # (shards, threads)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("shards,threads", SHARDINGS)
+def test_sharded_equals_brute_force_exhaustive(oracle_lib, k, shards, threads):
+    # every string of length <= 6 over 3 letters: the sharded run must give
+    # brute force's triplets whatever the shard and thread counts
+    _, (c, o) = _exhaustive_set()
+    got = triples(*oracle_lib.self_search_sharded(c, o, k, shards=shards, threads=threads))
+    assert got == triples(*oracle_lib.brute_self(c, o, k))
+
+
+@pytest.mark.parametrize("shards,threads", SHARDINGS)
+def test_sharded_equals_brute_force_generator_k2(oracle_lib, shards, threads):
+    c, o = cdr3gen.subset(*cdr3gen.plain("plain_10k"), 2500)
+    got = triples(*oracle_lib.self_search_sharded(c, o, 2, shards=shards, threads=threads))
+    assert got == triples(*oracle_lib.brute_self(c, o, 2))
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_sharded_equals_plain_10k_config(oracle_lib, k):
+    c, o = cdr3gen.plain("plain_10k")
+    want = oracle_lib.self_search(c, o, k)
+    for shards, threads in ((5, 4), (0, 0)):
+        got = oracle_lib.self_search_sharded(c, o, k, shards=shards, threads=threads)
+        assert all(np.array_equal(x, y) for x, y in zip(got, want))
+
+
+def test_sharded_edge_cases(oracle_lib):
+    # empty input, one sequence, more shards than variants
+    c, o = csr([])
+    assert len(oracle_lib.self_search_sharded(c, o, 2, shards=4, threads=2)[0]) == 0
+    c, o = csr([codes_of("CASSF")])
+    assert len(oracle_lib.self_search_sharded(c, o, 2, shards=4, threads=2)[0]) == 0
+    c, o = csr([codes_of("A"), codes_of("CD"), codes_of("A")])
+    got = triples(*oracle_lib.self_search_sharded(c, o, 2, shards=64, threads=8))
+    assert got == [(0, 1, 2), (0, 2, 0), (1, 2, 2)]
+
+
 @pytest.mark.parametrize("k", [0, 1, 2])
 def test_query_equals_brute_force(oracle_lib, k):
     rc, ro = cdr3gen.generate(11, 1500)
