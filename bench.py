@@ -4,9 +4,12 @@ sequences by symmetric-deletion lookup on one MI355X.
 
 One step = one sd_self_search call: pack, variant generation, grouping sort,
 in-group pair emission, pair sort, verification and compaction, with the
-input already resident in HBM and the result left in HBM. Prints one JSON
-line. The CPU oracle is timed on a bounded sample of the same workload as a
-reported baseline (single thread).
+input already resident in HBM and the result left in HBM (`value`). The
+same search from host codes to host pairs (H2D and D2H included) is reported
+beside it as `end_to_end`. Prints one JSON line. The CPU oracle is timed on
+the host's cores as a reported baseline: the sharded oracle over the whole
+workload where that fits the time bound (1M sequences, k=2), a bounded
+prefix otherwise, and the single-thread oracle on a bounded prefix.
 """
 from __future__ import annotations
 
@@ -31,9 +34,21 @@ WORKLOADS = {
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counters, scaled by a
 # 1 GiB copy (profiles/traffic_hashed_path_plain_1m_k2.md), for the stages and
-# workload they were taken on; other stages and workloads report null
+# workload they were taken on; other stages and workloads report null. They
+# are a stored profile, not a measurement of this run: TRAFFIC_SOURCE names it.
 TRAFFIC_PER_LAUNCH = {("plain_1m_k2", "hash_counted_pass"): 1.6599e9,
                       ("plain_1m_k2", "hash_passes"): 1.6544e9}
+TRAFFIC_SOURCE = ("rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of k_scatter_counted, "
+                  "profiles/traffic_hashed_path_plain_1m_k2.md (kernel unchanged since)")
+# method floor of the end-to-end fraction: every deletion variant written once,
+# read and written by one grouping pass and read once more (20-byte key records)
+E2E_BYTES_PER_KEY = 80
+METRICS = {
+    "plain_10k_k1": "End-to-end s & pairs/s, 10K CDR3 self-search k<=1 (pairs/s)",
+    "plain_1m_k2": "End-to-end s & pairs/s, 1M CDR3 self-search k<=2 (pairs/s)",
+    "plain_10m_k1": "End-to-end s & pairs/s, 10M CDR3 self-search k<=1 (pairs/s)",
+    "plain_10m_k2": "End-to-end s & pairs/s, 10M CDR3 self-search k<=2 (pairs/s)",
+}
 # stages that time exactly one kernel (launched once, or several times alike)
 KERNEL_OF_STAGE = {
     "vargen_hash": "k_vargen_hash",
@@ -50,24 +65,65 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(codes, offsets, k, target_s=15.0):
-    """The oracle, as it stands, on the first S sequences of the workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(codes, offsets, k, target_s=15.0, threads=1):
+    """The oracle, as it stands, on the first S sequences of the workload (S
+    grown until one run takes about target_s); threads > 1 runs the sharded
+    oracle on that many threads."""
     import cdr3gen
     import oracle
     n = 2000
     while True:  # grow the sample until one run takes about target_s
         c, o = cdr3gen.subset(codes, offsets, n)
         t0 = time.perf_counter()
-        a, _, _ = oracle.self_search(c, o, k)
+        if threads > 1:
+            a, _, _ = oracle.self_search_sharded(c, o, k, threads=threads)
+        else:
+            a, _, _ = oracle.self_search(c, o, k)
         dt = time.perf_counter() - t0
         if dt >= 0.5 * target_s or n >= len(offsets) - 1:
             break
         grow = min(8.0, max(1.5, target_s / max(dt, 1e-3)))
         n = min(len(offsets) - 1, int(n * grow))
-    return {"value": len(a) / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} sequences of the workload, k={k}, one thread: "
-                      f"{len(a)} pairs in {dt:.2f} s ({n / dt:.0f} sequences/s)",
-            "seconds": dt, "sample_seqs": n, "sample_pairs": int(len(a))}
+    whole = n >= len(offsets) - 1
+    what = "the whole workload" if whole else f"first {n} sequences of the workload"
+    mode = f"sharded oracle on {threads} threads" if threads > 1 else "oracle on one thread"
+    return {"value": len(a) / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what}, k={k}, {mode}: {len(a)} pairs in {dt:.2f} s "
+                      f"({n / dt:.0f} sequences/s)",
+            "seconds": dt, "sample_seqs": n, "sample_pairs": int(len(a)), "whole_workload": whole,
+            "host_cpu": cpu_model(), "host_nproc": os.cpu_count()}
+
+
+def cpu_baselines(codes, offsets, k, workload):
+    """The sharded oracle on the host's cores (the whole 1M workload fits the
+    bound: about 20-35 s), plus the single-thread oracle on a bounded prefix."""
+    import oracle
+    threads = oracle.host_threads()
+    if workload in ("plain_1m_k2", "plain_10k_k1"):
+        t0 = time.perf_counter()
+        a, _, _ = oracle.self_search_sharded(codes, offsets, k, threads=threads)
+        dt = time.perf_counter() - t0
+        n = len(offsets) - 1
+        allc = {"value": len(a) / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+                "sample": f"the whole workload ({n} sequences), k={k}, sharded oracle on "
+                          f"{threads} threads: {len(a)} pairs in {dt:.2f} s",
+                "seconds": dt, "sample_seqs": n, "sample_pairs": int(len(a)),
+                "whole_workload": True, "host_cpu": cpu_model(), "host_nproc": os.cpu_count()}
+    else:
+        allc = cpu_baseline(codes, offsets, k, target_s=20.0, threads=threads)
+    one = cpu_baseline(codes, offsets, k, target_s=10.0, threads=1)
+    return allc, one
 
 
 def emit(out, args):
@@ -479,6 +535,7 @@ def main():
         return {"bound": "hbm", "kernel": KERNEL_OF_STAGE[stage], "stage": stage,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": TRAFFIC_SOURCE if traffic is not None else None,
                 "launches_per_step": launches, "avg_launch_ms": round(per_launch_s * 1e3, 4),
                 "algorithmic_bytes_per_launch": per_launch_bytes}
 
@@ -492,8 +549,12 @@ def main():
     sort_roofline = roof(sort_stage) if sort_stage in single else None
     counted_roofline = roof("hash_counted_pass") if "hash_counted_pass" in single else None
     value = npairs / dt
+    # end-to-end roofline fraction: the method floor (80 B per deletion
+    # variant) over the measured time, against 8 TB/s
+    nkeys = st["n_keys"]
+    floor_bytes = E2E_BYTES_PER_KEY * nkeys
     out = {
-        "metric": "End-to-end s & pairs/s, 1M CDR3 self-search k<=2 (pairs/s)",
+        "metric": METRICS[args.workload],
         "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u128",
@@ -504,16 +565,26 @@ def main():
                    "group_cap": args.group_cap, "group_bits": args.group_bits,
                    "sort_items": args.sort_items, "group_batches": args.group_batches},
         "stages_ms": {s: round(stage_ms[s] / args.steps, 4) for s in stage_ms},
-        "host_to_host": {"seconds_median_of_5": round(h2h_s, 6),
-                         "pairs_per_s": round(npairs / h2h_s, 1)},
+        "value_is": "pairs / device time of one search, inputs resident in HBM, result left in HBM",
+        "end_to_end": {"seconds_median_of_5": round(h2h_s, 6),
+                       "pairs_per_s": round(npairs / h2h_s, 1),
+                       "what": "host u8 codes and offsets in, host (i, j, d) arrays out "
+                               "(H2D and D2H over PCIe included)",
+                       "frac": round(floor_bytes / h2h_s / (HBM_PEAK_GBS * 1e9), 4),
+                       "device_resident_frac": round(floor_bytes / dt / (HBM_PEAK_GBS * 1e9), 4),
+                       "frac_basis": f"{E2E_BYTES_PER_KEY} B x {nkeys} distinct deletion variants "
+                                     f"(method floor) / time / 8 TB/s"},
         "roofline": roofline,
         "sort_roofline": sort_roofline,
         "counted_pass_roofline": counted_roofline,
     }
     ctx.close()
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(codes, offsets, k)
+        log("timing the CPU oracle on the host cores")
+        allc, one = cpu_baselines(codes, offsets, k, args.workload)
+        out["cpu_baseline"] = allc
+        out["cpu_baseline_one_thread"] = one
+        log(f"cpu baseline: {allc['sample']}; {one['sample']}")
     line = json.dumps(out)
     print(line, flush=True)
     if args.json_out:

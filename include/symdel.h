@@ -27,6 +27,7 @@
 #ifndef SYMDEL_H
 #define SYMDEL_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -96,6 +97,7 @@ typedef struct {
 #define SD_OPT_BATCH_TILE 6 /* query batches: at most this many query sequences per tile (0: 4Mi) */
 #define SD_OPT_PROBE 7      /* learned indexes: 0 = search the model's window, 1 = binary search over the whole index */
 #define SD_OPT_GROUP_BATCHES 8 /* hashed path: LDS batches each workgroup groups in sequence, 0 (automatic: 4) .. 64 */
+#define SD_OPT_PAIR_SORT 9  /* candidate pair sort: 0 automatic, 1 one-sweep LSD passes, 2 counted LSD passes */
 
 /*
  * Create a context on HIP device `device`. hbm_budget_bytes bounds the
@@ -109,6 +111,32 @@ void sd_destroy(sd_ctx* ctx);
 
 /* Set an SD_OPT_* option. Errors: SD_E_INVAL for an unknown option or value. */
 int sd_set_option(sd_ctx* ctx, int option, int64_t value);
+
+/*
+ * Device-memory provider of a context (not a step of the method: the host
+ * framework that owns device memory, e.g. PyTorch's caching allocator, lends
+ * it to the search). With alloc and free_fn set, every device allocation the
+ * context makes -- a call's scratch, device result arrays, the context's
+ * look-back and counter areas, and the arrays of an index built on it -- is
+ * taken from alloc(bytes, user) and given back with free_fn(ptr, user); the
+ * context then keeps no cache of its own (the provider is expected to cache).
+ * alloc must return device memory of the context's device aligned to at
+ * least 256 bytes, usable on the stream of the call that asked for it, or
+ * NULL: the call in progress then fails with SD_E_NOMEM, gives back what it
+ * took and leaves the context usable. free_fn may be handed a block while
+ * work on the call's stream that used it is still queued, so the provider
+ * must only reuse it in that stream's order (PyTorch's allocator does). An
+ * index keeps the free function and user pointer it was built with and
+ * calls them from sd_index_free, so `user` must outlive such an index.
+ * alloc == free_fn == NULL returns to the context's own hipMalloc pool. The
+ * hbm budget of sd_create applies either way. Server workers use contexts of
+ * their own and are not affected.
+ * Errors: SD_E_INVAL (only one of alloc and free_fn given), SD_E_STATE (the
+ * context still holds device results not released with sd_pairs_free).
+ */
+typedef void* (*sd_alloc_fn)(size_t bytes, void* user);
+typedef void (*sd_free_fn)(void* ptr, void* user);
+int sd_set_allocator(sd_ctx* ctx, sd_alloc_fn alloc, sd_free_fn free_fn, void* user);
 
 /*
  * Self search (paper, Appendix A XTNeighbor steps 1-7): every pair i < j of

@@ -9,6 +9,8 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <unordered_set>
+#include <vector>
 
 #include "sd_internal.h"
 
@@ -32,7 +34,7 @@ static size_t size_class(size_t bytes) {
   return (bytes + g - 1) / g * g;
 }
 
-static void release_cache(sd_ctx* c) {
+void release_cache(sd_ctx* c) {
   for (auto& kv : c->cache) {
     (void)hipFree(kv.second);
     c->held -= kv.first;
@@ -40,8 +42,24 @@ static void release_cache(sd_ctx* c) {
   c->cache.clear();
 }
 
+// A block from the allocator hook: counted against the budget, returned to
+// the hook by dfree.
+static void* hook_alloc(sd_ctx* c, size_t sz) {
+  if (c->budget && c->held + sz > c->budget) release_cache(c);
+  if (c->budget && c->held + sz > c->budget)
+    throw Error{SD_E_NOMEM, "device memory budget exceeded: need " + std::to_string(sz) +
+                                " more bytes, holding " + std::to_string(c->held) + " of " +
+                                std::to_string(c->budget)};
+  void* p = c->ualloc(sz, c->uarg);
+  if (!p) throw Error{SD_E_NOMEM, "the allocator hook returned NULL for " + std::to_string(sz) + " bytes"};
+  c->held += sz;
+  c->live[p] = sz;
+  return p;
+}
+
 void* dalloc(sd_ctx* c, size_t bytes) {
   const size_t sz = size_class(bytes);
+  if (c->ualloc) return hook_alloc(c, sz);
   auto it = c->cache.lower_bound(sz);
   if (it != c->cache.end() && it->first <= 2 * sz) {
     void* p = it->second;
@@ -74,8 +92,39 @@ void dfree(sd_ctx* c, void* p) {
   if (!p) return;
   auto it = c->live.find(p);
   if (it == c->live.end()) return;
+  if (c->ualloc) {
+    c->held -= it->second;
+    c->live.erase(it);
+    c->ufree(p, c->uarg);
+    return;
+  }
   c->cache.insert({it->second, p});
   c->live.erase(it);
+}
+
+void* index_alloc(sd_ctx* c, sd_index* idx, size_t bytes) {
+  if (!bytes) bytes = 16;
+  void* p = nullptr;
+  if (c->ualloc) {
+    idx->ufree = c->ufree;
+    idx->uarg = c->uarg;
+    p = c->ualloc(bytes, c->uarg);
+    if (!p) throw Error{SD_E_NOMEM, "the allocator hook returned NULL for an index array"};
+    return p;
+  }
+  if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error{SD_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes for an index failed"};
+  }
+  return p;
+}
+
+void index_release(sd_index* idx, void* p) {
+  if (!p) return;
+  if (idx->ufree)
+    idx->ufree(p, idx->uarg);
+  else
+    (void)hipFree(p);
 }
 
 uint32_t next_epoch(sd_ctx* c, uint64_t words, hipStream_t s) {
@@ -157,9 +206,28 @@ void StageTimer::finish() {
 
 using sd::Error;
 
+// After a failed call: wait for the device (kernels of the call may still be
+// queued), then give back every device block the call took that is still
+// live, except the context's own areas. A failed call returns no result, so
+// nothing it allocated is owned by the caller.
+static void reclaim_failed_call(sd_ctx* c, const std::unordered_set<void*>& before) {
+  (void)hipDeviceSynchronize();
+  (void)hipGetLastError();
+  std::vector<void*> stray;
+  for (auto& kv : c->live)
+    if (!before.count(kv.first) && kv.first != c->status && kv.first != c->counters)
+      stray.push_back(kv.first);
+  for (void* p : stray) sd::dfree(c, p);
+}
+
 template <typename F>
 static int guarded(sd_ctx* c, F&& f) {
-  if (c) c->last_error.clear();
+  std::unordered_set<void*> before;
+  if (c) {
+    c->last_error.clear();
+    for (auto& kv : c->live) before.insert(kv.first);
+  }
+  int code = SD_OK;
   try {
     f();
     const hipError_t e = hipGetLastError();  // a rejected launch is never left behind
@@ -168,14 +236,16 @@ static int guarded(sd_ctx* c, F&& f) {
     return SD_OK;
   } catch (const Error& e) {
     if (c) c->last_error = e.msg;
-    return e.code;
+    code = e.code;
   } catch (const std::bad_alloc&) {
     if (c) c->last_error = "host allocation failed";
-    return SD_E_NOMEM;
+    code = SD_E_NOMEM;
   } catch (const std::exception& e) {
     if (c) c->last_error = e.what();
-    return SD_E_INVAL;
+    code = SD_E_INVAL;
   }
+  if (c) reclaim_failed_call(c, before);
+  return code;
 }
 
 extern "C" {
@@ -204,7 +274,12 @@ void sd_destroy(sd_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  for (auto& kv : c->live) (void)hipFree(kv.first);
+  for (auto& kv : c->live) {
+    if (c->ualloc)
+      c->ufree(kv.first, c->uarg);
+    else
+      (void)hipFree(kv.first);
+  }
   c->live.clear();
   sd::release_cache(c);
   for (auto& kv : c->host_live) (void)hipHostFree(kv.first);
@@ -248,10 +323,40 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
       if (value < 0 || value > 1) return SD_E_INVAL;
       c->probe = (int)value;
       return SD_OK;
+    case SD_OPT_PAIR_SORT:
+      if (value < 0 || value > 2) return SD_E_INVAL;
+      c->pair_sort = (int)value;
+      return SD_OK;
     default:
       c->last_error = "unknown option";
       return SD_E_INVAL;
   }
+}
+
+int sd_set_allocator(sd_ctx* c, sd_alloc_fn alloc, sd_free_fn free_fn, void* user) {
+  if (!c) return SD_E_INVAL;
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    c->last_error = "give both the allocation and the release function, or neither";
+    return SD_E_INVAL;
+  }
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::hip_check(hipDeviceSynchronize(), "synchronise");
+    // the context's own areas move to the new provider; anything else still
+    // live is a result the caller has not released
+    if (c->status) sd::dfree(c, c->status);
+    if (c->counters) sd::dfree(c, c->counters);
+    c->status = nullptr;
+    c->status_words = 0;
+    c->counters = nullptr;
+    c->counters_n = 0;
+    if (!c->live.empty())
+      throw Error{SD_E_STATE, "results of this context are still live (release them with sd_pairs_free first)"};
+    sd::release_cache(c);
+    c->ualloc = alloc;
+    c->ufree = free_fn;
+    c->uarg = user;
+  });
 }
 
 int sd_self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, void* stream) {

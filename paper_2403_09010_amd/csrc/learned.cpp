@@ -31,15 +31,6 @@ constexpr int NP = SD_MLP_PARAMS;
 constexpr int H = SD_MLP_HIDDEN;
 constexpr int GRAPH_STEPS = 25;  // training steps per captured graph
 
-void* lidx_alloc(size_t bytes) {
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess || !p) {
-    (void)hipGetLastError();
-    throw Error{SD_E_NOMEM, "hipMalloc for the learned index failed"};
-  }
-  return p;
-}
-
 // Initial parameters: unit j is a tanh step centred at the sample quantile
 // (j + 1/2) / H, as steep as the local spacing of the quantiles, with output
 // weight 1 / (2H) and bias 1/2, so the untrained network already rises from
@@ -100,8 +91,8 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
     StageTimer tm(c, s);
     Call cl{c, s, sc, tm, fresh_counters(c, CNT_TOTAL, s)};
     const DevSeqs in = stage_seqs(c, sc, ref, s);
-    idx->ref_seq = static_cast<u128*>(lidx_alloc(std::max<uint64_t>(in.n, 1) * 16));
-    idx->params = static_cast<float*>(lidx_alloc(NP * sizeof(float)));
+    idx->ref_seq = static_cast<u128*>(index_alloc(c, idx, std::max<uint64_t>(in.n, 1) * 16));
+    idx->params = static_cast<float*>(index_alloc(c, idx, NP * sizeof(float)));
     uint64_t nk = 0;
     if (in.n) {
       const Packed p = pack_and_count(cl, in, k, false);
@@ -113,8 +104,8 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
       launch_vargen(p.seq, p.voff, in.n, k, klo, khi, kid, s);
       const SortedKeys sk = full_key_sort(cl, klo, khi, kid, (uint32_t)nk);
       check_lookback(cl);
-      idx->keys = static_cast<u128*>(lidx_alloc(nk * 16));
-      idx->kid = static_cast<uint32_t*>(lidx_alloc(nk * 4));
+      idx->keys = static_cast<u128*>(index_alloc(c, idx, nk * 16));
+      idx->kid = static_cast<uint32_t*>(index_alloc(c, idx, nk * 4));
       launch_interleave(sk.hi, sk.lo, nk, idx->keys, s);
       hip_check(hipMemcpyAsync(idx->kid, sk.id, nk * 4, hipMemcpyDeviceToDevice, s), "copy ids");
     }
@@ -123,11 +114,11 @@ sd_index* learned_build(sd_ctx* c, const sd_seqs* ref, int k, const sd_learned_c
     const uint32_t lg = conf.leaves_log2 ? (uint32_t)conf.leaves_log2 : default_leaves_log2(nk);
     idx->nleaves = 1u << lg;
     info.leaves = (int32_t)idx->nleaves;
-    idx->leaves = lidx_alloc((size_t)idx->nleaves * leaf_bytes());
+    idx->leaves = index_alloc(c, idx, (size_t)idx->nleaves * leaf_bytes());
 
     // coordinate model: residue frequencies per (length, position) and
     // length shares, counted over keys at evenly spaced ranks
-    idx->coord = lidx_alloc(coord_bytes());
+    idx->coord = index_alloc(c, idx, coord_bytes());
     {
       const int NLn = coord_lengths();
       const size_t ntab = (size_t)NLn * 24 * 20;

@@ -346,7 +346,7 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
     for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(Digit{0, 8 * q, 255u});
     for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(Digit{0, 32 + 8 * q, 255u});
     bool pflip;
-    if (nc >= (1u << 21)) {
+    if (pair_sort_counted(c, nc)) {
       // large: counted passes over fixed tiles
       pflip = counted_sort(cl, cand.p, cand2, (uint32_t)nc, pd);
       tm.mark("pair_sort", (double)nc * 24 * pd.size(), 4 * (int)pd.size());

@@ -162,7 +162,7 @@ TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint6
     for (int x = 0; x < (rb + 7) / 8; ++x) pd.push_back(Digit{0, 8 * x, 255u});
     for (int x = 0; x < (qb + 7) / 8; ++x) pd.push_back(Digit{0, 32 + 8 * x, 255u});
     bool pf;
-    if (nc >= (1u << 21)) {
+    if (pair_sort_counted(c, nc)) {
       // large: counted passes over fixed tiles
       pf = counted_sort(cl, cand, cand2, (uint32_t)nc, pd);
     } else {
@@ -221,17 +221,8 @@ void index_free(sd_index* idx) {
   (void)hipSetDevice(idx->device);
   for (void* p : {(void*)idx->ref_seq, (void*)idx->E, (void*)idx->seg_start, (void*)idx->seg_end,
                   (void*)idx->keys, (void*)idx->kid, (void*)idx->params, idx->coord, idx->leaves})
-    if (p) (void)hipFree(p);
+    index_release(idx, p);
   delete idx;
-}
-
-static void* idx_alloc(size_t bytes) {
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess || !p) {
-    (void)hipGetLastError();
-    throw Error{SD_E_NOMEM, "hipMalloc for the index failed"};
-  }
-  return p;
 }
 
 sd_index* index_build(sd_ctx* c, const sd_seqs* ref, int k, hipStream_t s) {
@@ -247,7 +238,7 @@ sd_index* index_build(sd_ctx* c, const sd_seqs* ref, int k, hipStream_t s) {
     StageTimer tm(c, s);
     Call cl{c, s, sc, tm, fresh_counters(c, CNT_TOTAL, s)};
     const DevSeqs in = stage_seqs(c, sc, ref, s);
-    idx->ref_seq = static_cast<u128*>(idx_alloc(std::max<uint64_t>(in.n, 1) * 16));
+    idx->ref_seq = static_cast<u128*>(index_alloc(c, idx, std::max<uint64_t>(in.n, 1) * 16));
     uint64_t nk = 0;
     const uint64_t* E = nullptr;
     if (in.n) {
@@ -282,9 +273,9 @@ sd_index* index_build(sd_ctx* c, const sd_seqs* ref, int k, hipStream_t s) {
     idx->n_keys = nk;
     idx->bits = index_bits(nk);
     const uint32_t nseg = 1u << idx->bits;
-    idx->E = static_cast<uint64_t*>(idx_alloc(std::max<uint64_t>(nk, 1) * 8));
-    idx->seg_start = static_cast<uint32_t*>(idx_alloc((size_t)nseg * 4));
-    idx->seg_end = static_cast<uint32_t*>(idx_alloc((size_t)nseg * 4));
+    idx->E = static_cast<uint64_t*>(index_alloc(c, idx, std::max<uint64_t>(nk, 1) * 8));
+    idx->seg_start = static_cast<uint32_t*>(index_alloc(c, idx, (size_t)nseg * 4));
+    idx->seg_end = static_cast<uint32_t*>(index_alloc(c, idx, (size_t)nseg * 4));
     if (nk)
       hip_check(hipMemcpyAsync(idx->E, E, nk * 8, hipMemcpyDeviceToDevice, s), "copy index");
     launch_seg_bounds(idx->E, nk, 64u - (uint32_t)idx->bits, idx->seg_start, idx->seg_end, s);

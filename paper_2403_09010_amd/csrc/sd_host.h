@@ -162,6 +162,13 @@ inline bool counted_sort(Call& cl, uint64_t* a, uint64_t* b, uint32_t n,
   return flip;
 }
 
+// The candidate pair sort takes counted passes from 2^21 candidates up (or
+// as SD_OPT_PAIR_SORT forces), one-sweep passes below.
+inline bool pair_sort_counted(const sd_ctx* c, uint64_t nc) {
+  if (c->pair_sort) return c->pair_sort == 2;
+  return nc >= (1u << 21);
+}
+
 struct Cands {
   uint64_t* p = nullptr;  // pool block owned by the caller
   uint64_t n = 0;

@@ -218,8 +218,13 @@ struct sd_ctx {
   uint64_t budget = 0;  // 0 = unbounded
   uint64_t held = 0;    // bytes of device memory held (live + cached)
   std::string last_error;
-  std::multimap<size_t, void*> cache;      // free device blocks by size
+  std::multimap<size_t, void*> cache;      // free device blocks by size (own hipMalloc blocks)
   std::unordered_map<void*, size_t> live;  // device blocks in use
+  // allocator hook (sd_set_allocator): when set, device blocks come from
+  // ualloc and go back to ufree at once (no cache of our own)
+  sd_alloc_fn ualloc = nullptr;
+  sd_free_fn ufree = nullptr;
+  void* uarg = nullptr;
   std::unordered_map<void*, int> host_live;  // pinned host result arrays
   // look-back state
   uint64_t* status = nullptr;
@@ -236,6 +241,7 @@ struct sd_ctx {
   int group_bits = 0;  // hashed path: hash bits sorted by the LSD passes (0 = automatic)
   int group_batches = 0;  // hashed path: LDS batches per workgroup (0 = automatic)
   int sort_items = 0;  // keys-only radix passes: items per thread, 16 or 32 (0 = automatic)
+  int pair_sort = 0;   // candidate pair sort: 0 automatic, 1 one-sweep passes, 2 counted passes
   int64_t batch_tile_seqs = 0;  // query batches: sequences per tile (0 = automatic)
   int probe = 0;                // learned indexes: 0 model window, 1 whole-array binary search
   std::map<std::string, uint64_t> out_hint;  // last output size of each sharded stage
@@ -246,9 +252,12 @@ struct sd_ctx {
 // the reference set as [hash | ref id], sorted by the full hash without
 // repeats, plus a directory of 2^bits hash segments. Learned kind: the exact
 // keys sorted, their reference ids, and the two-stage position model. Owns
-// its device memory (hipMalloc), read-only after the build.
+// its device memory (index_alloc), read-only after the build.
 struct sd_index {
   int device = 0;
+  // the allocator hook of the building context (null: hipMalloc / hipFree)
+  sd_free_fn ufree = nullptr;
+  void* uarg = nullptr;
   int k = 0;
   int learned = 0;  // 0 hashed, 1 learned
   uint32_t idbits = 24;
@@ -275,6 +284,10 @@ namespace sd {
 // device memory pool (throws Error on failure)
 void* dalloc(sd_ctx* c, size_t bytes);
 void dfree(sd_ctx* c, void* p);
+// a device array owned by an index (from the context's allocator hook if it
+// has one, else hipMalloc); released by index_free
+void* index_alloc(sd_ctx* c, sd_index* idx, size_t bytes);
+void index_release(sd_index* idx, void* p);
 template <typename T>
 T* dalloc_t(sd_ctx* c, uint64_t count) {
   return static_cast<T*>(dalloc(c, (size_t)(count ? count : 1) * sizeof(T)));

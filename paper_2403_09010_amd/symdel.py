@@ -29,6 +29,7 @@ OPT_SORT_ITEMS = 5
 OPT_BATCH_TILE = 6
 OPT_PROBE = 7
 OPT_GROUP_BATCHES = 8
+OPT_PAIR_SORT = 9
 MAX_STAGES = 16
 MLP_HIDDEN = 32
 MLP_PARAMS = 3 * MLP_HIDDEN + 1
@@ -86,6 +87,10 @@ class _TuneResult(ctypes.Structure):
                 ("default_s", ctypes.c_double)]
 
 
+# allocator hook signatures (sd_alloc_fn, sd_free_fn)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 _lib = None
 
 
@@ -108,6 +113,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sd_destroy.restype = None
     lib.sd_set_option.argtypes = [P, I, I64]
     lib.sd_set_option.restype = I
+    lib.sd_set_allocator.argtypes = [P, ALLOC_FN, FREE_FN, P]
+    lib.sd_set_allocator.restype = I
     lib.sd_self_search.argtypes = [P, ctypes.POINTER(_Seqs), I, ctypes.POINTER(_Pairs), P]
     lib.sd_self_search.restype = I
     lib.sd_pair_distance.argtypes = [P, ctypes.POINTER(_Seqs), ctypes.POINTER(_Seqs), P, P, I64,
@@ -260,6 +267,37 @@ class Context:
 
     def set_option(self, option: int, value: int):
         self._check(self._lib.sd_set_option(self._h, option, int(value)), "sd_set_option")
+
+    def set_allocator(self, alloc, free):
+        """Device memory from Python callables (sd_set_allocator): alloc(nbytes)
+        returns a device address (0 or None when it cannot), free(address)
+        gives it back. Both None: the library's own pool again."""
+        if alloc is None and free is None:
+            cb = (ALLOC_FN(), FREE_FN())
+        else:
+            def _alloc(nbytes, _user):
+                try:
+                    return alloc(int(nbytes)) or None
+                except Exception:  # noqa: BLE001 - a failed allocation is reported as NULL
+                    return None
+
+            def _free(ptr, _user):
+                free(int(ptr))
+            cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+        self._check(self._lib.sd_set_allocator(self._h, cb[0], cb[1], None), "sd_set_allocator")
+        # the library calls these until the hook is replaced; indexes built
+        # with them keep calling free until they are released
+        self._alloc_cb = cb
+        self._alloc_cbs = getattr(self, "_alloc_cbs", []) + [cb]
+
+    def use_torch_allocator(self, stream=None):
+        """Take every device allocation of this context from PyTorch's caching
+        allocator, on `stream` (default: the current stream of the device)."""
+        import torch
+        dev = self.device
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev, st),
+                           torch.cuda.caching_allocator_delete)
 
     def _seqs(self, codes, offsets):
         """(sd_seqs, keepalive, on_device) for numpy arrays or torch tensors."""

@@ -1,7 +1,10 @@
 """Parity of the HIP self-search path with the CPU oracle (bit-exact: the
 output is integer triplets). Small workloads are compared element by
-element; the 1M-sequence k=2 workload is checked on sampled outputs the
-oracle computes one by one plus properties that hold at any size."""
+element under every grouping and pair-sort configuration (so the branches
+the full-size runs take are reached at small size too); the full 1M k=2 and
+10M outputs are compared with the oracle's stored pair counts and hashes
+(tests/golden, written by the oracle alone), plus sampled distances,
+sampled completeness and properties that hold at any size."""
 import hashlib
 import json
 import os
@@ -22,7 +25,11 @@ def log(msg):
 
 # grouping configurations: the automatic (hashed) path, the full-key sort
 # path, and hashed runs with a small LDS capacity that send some or all hash
-# segments through the oversized-segment fallback
+# segments through the oversized-segment fallback; with 18 or 20 hash bits
+# the grouping sort takes three LSD passes (20 bits: digits at bits 44, 52
+# and 60, the layout of the 10M workload); pair_sort forces the candidate
+# pair sort's counted passes (the branch of the full-size workloads) or its
+# one-sweep passes
 CONFIGS = {
     "auto": {},
     "fullkey": {"path": 1},
@@ -31,18 +38,23 @@ CONFIGS = {
     "hashed_1024": {"path": 2, "cap": 1024},
     "hashed_cap256": {"path": 2, "cap": 256},
     "hashed_fallback": {"path": 2, "cap": 256, "bits": 4},
+    "counted_pairs": {"pair_sort": 2},
+    "hashed_b20_counted_pairs": {"path": 2, "bits": 20, "pair_sort": 2},
+    "fullkey_counted_pairs": {"path": 1, "pair_sort": 2},
 }
 
 
 def make_ctx(cfg):
     import torch
     from paper_2403_09010_amd import Context
-    from paper_2403_09010_amd.symdel import OPT_GROUP_BITS, OPT_GROUP_CAP, OPT_PATH
+    from paper_2403_09010_amd.symdel import (OPT_GROUP_BITS, OPT_GROUP_CAP, OPT_PAIR_SORT,
+                                             OPT_PATH)
     assert torch.cuda.is_available()
     c = Context(0)
     c.set_option(OPT_PATH, cfg.get("path", 0))
     c.set_option(OPT_GROUP_CAP, cfg.get("cap", 0))
     c.set_option(OPT_GROUP_BITS, cfg.get("bits", 0))
+    c.set_option(OPT_PAIR_SORT, cfg.get("pair_sort", 0))
     return c
 
 
@@ -317,6 +329,55 @@ def test_errors(ctx):
 
 
 # ---------------------------------------------------------------- full size
+
+def assert_golden(got, name, n):
+    """The whole output against the oracle's stored count and hash; on a
+    mismatch, name the first id range whose chunk hash differs and print the
+    GPU's first triplets there."""
+    g = GOLD[name]
+    i, j, d = got
+    d8 = d.astype(np.uint8)
+    if len(i) == g["pairs"] and sha(i, j, d8) == g["sha256"]:
+        return
+    chunks = len(g["chunk_sha256"])
+    edges = np.searchsorted(i, [n * x // chunks for x in range(chunks + 1)])
+    for x, (lo, hi) in enumerate(zip(edges[:-1], edges[1:])):
+        if sha(i[lo:hi], j[lo:hi], d8[lo:hi]) != g["chunk_sha256"][x]:
+            first = list(zip(i[lo:lo + 5].tolist(), j[lo:lo + 5].tolist(), d[lo:lo + 5].tolist()))
+            pytest.fail(f"{name}: {len(i)} pairs against {g['pairs']}; first differing id range "
+                        f"[{n * x // chunks}, {n * (x + 1) // chunks}) holds {hi - lo} GPU "
+                        f"triplets, the first ones {first}")
+    pytest.fail(f"{name}: {len(i)} pairs against {g['pairs']}, hash differs")
+
+
+@pytest.mark.parametrize("cfg", ["auto", "onesweep_pairs", "fullkey"])
+def test_plain_1m_k2_equals_oracle(cfg):
+    """Every triplet of the headline workload equals the oracle's (count and
+    hash of the whole output), through the automatic path (counted pair
+    sort), the one-sweep pair sort and the full-key grouping path."""
+    c, o = cdr3gen.plain("plain_1m")
+    conf = {"auto": {}, "onesweep_pairs": {"pair_sort": 1}, "fullkey": {"path": 1}}[cfg]
+    log(f"self_search plain_1m k=2 config={cfg} against the oracle golden")
+    ctx = make_ctx(conf)
+    try:
+        got = gpu_triples(ctx, c, o, 2)
+    finally:
+        ctx.close()
+    assert_golden(got, "oracle_plain_1m_k2", len(o) - 1)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_plain_10m_equals_oracle(ctx, k):
+    """The 10M workload (40% cluster members; three hash passes, counted
+    pair sort) against the oracle's stored count and hash."""
+    name = f"oracle_plain_10m_k{k}"
+    if name not in GOLD:
+        pytest.skip(f"{name} is not in tests/golden (make_golden.py --only {name})")
+    c, o = cdr3gen.plain("plain_10m")
+    log(f"self_search plain_10m k={k} against the oracle golden")
+    got = gpu_triples(ctx, c, o, k)
+    assert_golden(got, name, len(o) - 1)
+
 
 def test_plain_1m_k2_sampled(ctx):
     import oracle

@@ -1,6 +1,7 @@
 """The continuous-batching server: every request's result in the mix equals
-the same set queried alone (bit-identical), weighted serving equals the
-weighted query, and cancellation / budget rejection behave as documented."""
+the oracle's query result for that set (Levenshtein, or the weighted score),
+equals the same set queried alone (bit-identical), and cancellation / budget
+rejection behave as documented."""
 import threading
 import time
 
@@ -52,9 +53,43 @@ def make_requests(ref, count, seed):
             for x, n in enumerate(sizes)]
 
 
-def test_results_in_the_mix_equal_alone(ctx, ref, index):
+def oracle_per_request(ref, reqs, subst=None):
+    """The oracle's (q, r, d) for every request: one oracle query over the
+    concatenated requests (a query's result does not depend on the others),
+    split by request and with q made local to it."""
+    import oracle
+    codes = np.concatenate([c for c, _ in reqs])
+    offs = [np.zeros(1, np.int64)]
+    base, n = 0, [0]
+    for c, o in reqs:
+        offs.append(o[1:] + base)
+        base += int(o[-1])
+        n.append(n[-1] + len(o) - 1)
+    offs = np.concatenate(offs)
+    if subst is None:
+        a, b, d = oracle.query_search(ref, (codes, offs), 2)
+    else:
+        a, b, d = oracle.query_weighted(ref, (codes, offs), subst, 8, 8)
+    out = []
+    for x in range(len(reqs)):
+        lo, hi = np.searchsorted(a, [n[x], n[x + 1]])
+        out.append(((a[lo:hi] - n[x]).astype(np.uint32), b[lo:hi].astype(np.uint32),
+                    d[lo:hi].astype(np.int32)))
+    return out
+
+
+def equals_oracle(got, want):
+    gi, gj, gd = got.numpy()
+    wi, wj, wd = want
+    return (len(gi) == len(wi) and np.array_equal(gi.astype(np.uint32), wi)
+            and np.array_equal(gj.astype(np.uint32), wj)
+            and np.array_equal(gd.astype(np.int32), wd))
+
+
+def test_results_in_the_mix_equal_alone_and_oracle(ctx, ref, index):
     from paper_2403_09010_amd import Server
     reqs = make_requests(ref, 40, 7)
+    want = oracle_per_request(ref, reqs)
     alone = [ctx.query(index, *r, 2, device_output=False) for r in reqs]
     log("server: 40 requests from two submitting threads, 3 workers")
     with Server(index, k=2, workers=3) as sv:
@@ -72,6 +107,7 @@ def test_results_in_the_mix_equal_alone(ctx, ref, index):
             t.join()
         for x, rid in enumerate(ids):
             got, lat = sv.poll(rid, timeout_ms=60000)
+            assert equals_oracle(got, want[x]), f"request {x} differs from the oracle"
             assert same(got, alone[x]), f"request {x}"
             assert lat > 0
         st = sv.stats()
@@ -83,12 +119,14 @@ def test_results_in_the_mix_equal_alone(ctx, ref, index):
 def test_batches_really_merge(ctx, ref, index):
     from paper_2403_09010_amd import Server
     reqs = make_requests(ref, 24, 8)
+    want = oracle_per_request(ref, reqs)
     # one worker: everything queued while the first batch runs joins the next
     with Server(index, k=2, workers=1) as sv:
         ids = [sv.submit(*r) for r in reqs]
         res = [sv.poll(i, timeout_ms=60000)[0] for i in ids]
         st = sv.stats()
-    for r, got in zip(reqs, res):
+    for x, (r, got) in enumerate(zip(reqs, res)):
+        assert equals_oracle(got, want[x]), f"request {x} differs from the oracle"
         assert same(got, ctx.query(index, *r, 2, device_output=False))
     assert st["max_batch"] > 1 and st["batches"] < len(reqs)
 
@@ -97,10 +135,13 @@ def test_weighted_serving(ctx, ref, index):
     from paper_2403_09010_amd import Server
     subst = cdr3gen.cost_matrix()
     reqs = make_requests(ref, 10, 9)
+    want = oracle_per_request(ref, reqs, subst=subst)
+    assert sum(len(w[0]) for w in want) > 0
     with Server(index, k=2, workers=2, subst=subst, indel=8, max_score=8) as sv:
         ids = [sv.submit(*r) for r in reqs]
-        for r, rid in zip(reqs, ids):
+        for x, (r, rid) in enumerate(zip(reqs, ids)):
             got, _ = sv.poll(rid, timeout_ms=60000)
+            assert equals_oracle(got, want[x]), f"weighted request {x} differs from the oracle"
             assert same(got, ctx.query_weighted(index, *r, subst, 8, 8, device_output=False))
 
 
