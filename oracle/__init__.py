@@ -14,6 +14,9 @@ Functions return ``(a, b, d)`` numpy arrays sorted by ``(a, b)``:
     result on several threads with bounded memory (variant space split into
     shards by a hash of the variant string).
   * ``query_search(ref, qry, k)``: all (q, r) with Lev(Q_q, R_r) <= k.
+  * ``self_search_hamming`` / ``query_search_hamming``: Hamming mode
+    (Section III C): the same candidates, kept when the lengths are equal and
+    at most k positions differ.
   * ``query_weighted(ref, qry, subst, indel, max_score)``: SymDel candidates
     at Levenshtein radius 2, kept when the weighted alignment cost is
     <= max_score (Section III D: a Levenshtein prefilter, then a finer
@@ -58,12 +61,16 @@ def _load():
     lib.or_lev_one_to_many.argtypes = [P, I, P, P, I64, P]
     lib.or_variants.restype = I64
     lib.or_variants.argtypes = [P, I, I, P, P, I64]
-    for name in ("or_self_search", "or_self_candidates", "or_brute_self"):
+    lib.or_hamming.restype = I
+    lib.or_hamming.argtypes = [P, I, P, I]
+    for name in ("or_self_search", "or_self_candidates", "or_brute_self", "or_self_search_hamming",
+                 "or_brute_self_hamming"):
         getattr(lib, name).restype = P
         getattr(lib, name).argtypes = [P, P, I64, I]
     lib.or_self_search_sharded.restype = P
     lib.or_self_search_sharded.argtypes = [P, P, I64, I, I, I]
-    for name in ("or_query_search", "or_brute_query"):
+    for name in ("or_query_search", "or_brute_query", "or_query_search_hamming",
+                 "or_brute_query_hamming"):
         getattr(lib, name).restype = P
         getattr(lib, name).argtypes = [P, P, I64, P, P, I64, I]
     lib.or_query_weighted.restype = P
@@ -107,6 +114,12 @@ def lev(a, b) -> int:
     """Wagner-Fischer edit distance of two code sequences (bytes or arrays)."""
     a, b = _u8(a), _u8(b)
     return _load().or_lev(a.ctypes.data, len(a), b.ctypes.data, len(b))
+
+
+def hamming(a, b) -> int:
+    """Mismatching positions of two equal-length code sequences; -1 if the lengths differ."""
+    a, b = _u8(a), _u8(b)
+    return _load().or_hamming(a.ctypes.data, len(a), b.ctypes.data, len(b))
 
 
 def weighted(a, b, subst: np.ndarray, indel: int) -> int:
@@ -167,6 +180,34 @@ def self_candidates(codes, offsets, k: int):
     h = _load().or_self_candidates(codes.ctypes.data, offsets.ctypes.data, len(offsets) - 1, k)
     a, b, _, raw = _take(h, with_raw=True)
     return a, b, raw
+
+
+def self_search_hamming(codes, offsets, k: int):
+    """Hamming mode (Section III C): SymDel candidates kept when the lengths are
+    equal and at most k positions differ."""
+    codes, offsets = _u8(codes), _i64(offsets)
+    h = _load().or_self_search_hamming(codes.ctypes.data, offsets.ctypes.data, len(offsets) - 1, k)
+    return _take(h)
+
+
+def brute_self_hamming(codes, offsets, k: int):
+    codes, offsets = _u8(codes), _i64(offsets)
+    h = _load().or_brute_self_hamming(codes.ctypes.data, offsets.ctypes.data, len(offsets) - 1, k)
+    return _take(h)
+
+
+def query_search_hamming(ref, qry, k: int):
+    (rc, ro), (qc, qo) = (_u8(ref[0]), _i64(ref[1])), (_u8(qry[0]), _i64(qry[1]))
+    h = _load().or_query_search_hamming(rc.ctypes.data, ro.ctypes.data, len(ro) - 1, qc.ctypes.data,
+                                        qo.ctypes.data, len(qo) - 1, k)
+    return _take(h)
+
+
+def brute_query_hamming(ref, qry, k: int):
+    (rc, ro), (qc, qo) = (_u8(ref[0]), _i64(ref[1])), (_u8(qry[0]), _i64(qry[1]))
+    h = _load().or_brute_query_hamming(rc.ctypes.data, ro.ctypes.data, len(ro) - 1, qc.ctypes.data,
+                                       qo.ctypes.data, len(qo) - 1, k)
+    return _take(h)
 
 
 def brute_self(codes, offsets, k: int):

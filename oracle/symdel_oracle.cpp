@@ -15,6 +15,12 @@
 // hash map, (3) look the variants up again to collect candidate pairs, (4)
 // drop duplicate pairs and pairs above the threshold (Fig. 1C/1D).
 //
+// Hamming mode (Section III C, where the comparison with a Hamming-only tool
+// changes only the final filter of the method): the same SymDel candidates,
+// kept when the two sequences have equal length and differ in at most k
+// positions. Hamming(a, b) <= k implies Lev(a, b) <= k, so the deletion
+// candidates contain every such pair.
+//
 // Weighted mode (Section III D: a Levenshtein prefilter followed by a
 // finer, substitution-weighted score): score = minimum-cost global alignment
 // with a 20x20 substitution cost table and a fixed indel cost.
@@ -56,6 +62,15 @@ int lev_full(const uint8_t* a, int la, const uint8_t* b, int lb) {
       D(x, y) = std::min(sub, std::min(del, ins));
     }
   return D(la, lb);
+}
+
+// Hamming distance: the number of positions at which equal-length strings
+// differ; -1 for strings of different lengths (no Hamming distance).
+int hamming(const uint8_t* a, int la, const uint8_t* b, int lb) {
+  if (la != lb) return -1;
+  int d = 0;
+  for (int x = 0; x < la; ++x) d += a[x] != b[x];
+  return d;
 }
 
 // Minimum-cost global alignment: substitution a->b costs subst[a*20+b],
@@ -233,6 +248,8 @@ extern "C" {
 
 int or_lev(const uint8_t* a, int la, const uint8_t* b, int lb) { return lev_full(a, la, b, lb); }
 
+int or_hamming(const uint8_t* a, int la, const uint8_t* b, int lb) { return hamming(a, la, b, lb); }
+
 int or_weighted(const uint8_t* a, int la, const uint8_t* b, int lb, const uint8_t* subst,
                 int indel) {
   return weighted_full(a, la, b, lb, subst, indel);
@@ -347,6 +364,27 @@ void* or_self_search_sharded(const uint8_t* codes, const int64_t* offs, int64_t 
   return res;
 }
 
+// Self search in Hamming mode: SymDel steps 1-3 as in or_self_search, step 4
+// keeps the candidates with equal lengths and Hamming distance <= k.
+void* or_self_search_hamming(const uint8_t* codes, const int64_t* offs, int64_t n, int k) {
+  Result* res = new Result();
+  MultiMap map;
+  build_map(codes, offs, n, k, map);
+  std::vector<uint64_t> cand;
+  self_candidates(map, cand, res->raw);
+  for (uint64_t c : cand) {
+    uint32_t i = (uint32_t)(c >> 32), j = (uint32_t)c;
+    int d = hamming(codes + offs[i], (int)(offs[i + 1] - offs[i]), codes + offs[j],
+                    (int)(offs[j + 1] - offs[j]));
+    if (d >= 0 && d <= k) {
+      res->a.push_back(i);
+      res->b.push_back(j);
+      res->d.push_back(d);
+    }
+  }
+  return res;
+}
+
 // The candidate pairs of a self search before verification (unique, sorted),
 // with d = -1; raw multiplicity in or_raw.
 void* or_self_candidates(const uint8_t* codes, const int64_t* offs, int64_t n, int k) {
@@ -375,6 +413,27 @@ void* or_query_search(const uint8_t* rc, const int64_t* ro, int64_t nr, const ui
     uint32_t q = (uint32_t)(c >> 32), r = (uint32_t)c;
     int d = lev_full(qc + qo[q], (int)(qo[q + 1] - qo[q]), rc + ro[r], (int)(ro[r + 1] - ro[r]));
     if (d <= k) {
+      res->a.push_back(q);
+      res->b.push_back(r);
+      res->d.push_back(d);
+    }
+  }
+  return res;
+}
+
+// Query search in Hamming mode: (q, r, d) with equal lengths and d =
+// Hamming(Q_q, R_r) <= k, from the SymDel candidates.
+void* or_query_search_hamming(const uint8_t* rc, const int64_t* ro, int64_t nr, const uint8_t* qc,
+                              const int64_t* qo, int64_t nq, int k) {
+  Result* res = new Result();
+  MultiMap map;
+  build_map(rc, ro, nr, k, map);
+  std::vector<uint64_t> cand;
+  query_candidates(map, qc, qo, nq, k, cand, res->raw);
+  for (uint64_t c : cand) {
+    uint32_t q = (uint32_t)(c >> 32), r = (uint32_t)c;
+    int d = hamming(qc + qo[q], (int)(qo[q + 1] - qo[q]), rc + ro[r], (int)(ro[r + 1] - ro[r]));
+    if (d >= 0 && d <= k) {
       res->a.push_back(q);
       res->b.push_back(r);
       res->d.push_back(d);
@@ -421,6 +480,37 @@ void* or_brute_self(const uint8_t* codes, const int64_t* offs, int64_t n, int k)
       if (d <= k) {
         res->a.push_back((uint32_t)i);
         res->b.push_back((uint32_t)j);
+        res->d.push_back(d);
+      }
+    }
+  return res;
+}
+
+// Hamming definitions over every pair: equal lengths, mismatches <= k.
+void* or_brute_self_hamming(const uint8_t* codes, const int64_t* offs, int64_t n, int k) {
+  Result* res = new Result();
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = i + 1; j < n; ++j) {
+      int d = hamming(codes + offs[i], (int)(offs[i + 1] - offs[i]), codes + offs[j],
+                      (int)(offs[j + 1] - offs[j]));
+      if (d >= 0 && d <= k) {
+        res->a.push_back((uint32_t)i);
+        res->b.push_back((uint32_t)j);
+        res->d.push_back(d);
+      }
+    }
+  return res;
+}
+
+void* or_brute_query_hamming(const uint8_t* rc, const int64_t* ro, int64_t nr, const uint8_t* qc,
+                             const int64_t* qo, int64_t nq, int k) {
+  Result* res = new Result();
+  for (int64_t q = 0; q < nq; ++q)
+    for (int64_t r = 0; r < nr; ++r) {
+      int d = hamming(qc + qo[q], (int)(qo[q + 1] - qo[q]), rc + ro[r], (int)(ro[r + 1] - ro[r]));
+      if (d >= 0 && d <= k) {
+        res->a.push_back((uint32_t)q);
+        res->b.push_back((uint32_t)r);
         res->d.push_back(d);
       }
     }

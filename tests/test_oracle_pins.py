@@ -290,6 +290,64 @@ def test_query_equals_brute_force(oracle_lib, k):
     assert got == want and len(got) > 0
 
 
+# ---------------------------------------------------------------- Hamming mode
+
+@pytest.mark.parametrize("a,b,d", [
+    (b"karolin", b"kathrin", 3), (b"karolin", b"kerstin", 3), (b"1011101", b"1001001", 2),
+    (b"2173896", b"2233796", 3), (b"", b"", 0), (b"abc", b"abc", 0), (b"abc", b"ab", -1),
+    (b"a", b"", -1),
+])
+def test_hamming_textbook_values(oracle_lib, a, b, d):
+    assert oracle_lib.hamming(a, b) == d
+
+
+def test_hamming_brute_force_is_the_definition_tiny(oracle_lib):
+    # pure-Python pair loop: equal lengths and at most k differing positions
+    rng = np.random.default_rng(7)
+    strings = [bytes(rng.integers(0, 3, size=rng.integers(0, 6)).tolist()) for _ in range(80)]
+    c, o = csr(strings)
+    for k in (0, 1, 2):
+        want = []
+        for i in range(80):
+            for j in range(i + 1, 80):
+                a, b = strings[i], strings[j]
+                if len(a) == len(b):
+                    d = sum(x != y for x, y in zip(a, b))
+                    if d <= k:
+                        want.append((i, j, d))
+        assert triples(*oracle_lib.brute_self_hamming(c, o, k)) == want
+        assert triples(*oracle_lib.self_search_hamming(c, o, k)) == want
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_hamming_mode_equals_brute_force_exhaustive(oracle_lib, k):
+    # Section III C: the SymDel candidates filtered by Hamming distance are
+    # exactly the Hamming neighbours (Hamming <= k implies Levenshtein <= k)
+    _, (c, o) = _exhaustive_set()
+    got = triples(*oracle_lib.self_search_hamming(c, o, k))
+    assert got == triples(*oracle_lib.brute_self_hamming(c, o, k))
+    lev = set(triples(*oracle_lib.brute_self(c, o, k)))
+    for i, j, d in got:  # every Hamming pair is a Levenshtein pair with Lev <= Hamming
+        assert any((i, j, e) in lev for e in range(d + 1))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_hamming_mode_equals_brute_force_10k_config(oracle_lib, k):
+    c, o = cdr3gen.plain("plain_10k")
+    got = triples(*oracle_lib.self_search_hamming(c, o, k))
+    assert got == triples(*oracle_lib.brute_self_hamming(c, o, k))
+    assert len(got) > 500
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_hamming_query_equals_brute_force(oracle_lib, k):
+    rc, ro = cdr3gen.generate(11, 1500)
+    qc, qo = cdr3gen.generate_query(12, 700, rc, ro, ref_mut_frac=0.3)
+    got = triples(*oracle_lib.query_search_hamming((rc, ro), (qc, qo), k))
+    assert got == triples(*oracle_lib.brute_query_hamming((rc, ro), (qc, qo), k))
+    assert len(got) > 0
+
+
 # ---------------------------------------------------------------- weighted score
 
 def _closed_form_weighted(a: bytes, b: bytes, subst, indel=8, max_score=8):
