@@ -98,6 +98,12 @@ typedef struct {
 #define SD_OPT_PROBE 7      /* learned indexes: 0 = search the model's window, 1 = binary search over the whole index */
 #define SD_OPT_GROUP_BATCHES 8 /* hashed path: LDS batches each workgroup groups in sequence, 0 (automatic: 4) .. 64 */
 #define SD_OPT_PAIR_SORT 9  /* candidate pair sort: 0 automatic, 1 one-sweep LSD passes, 2 counted LSD passes */
+#define SD_OPT_METRIC 10    /* distance of the final filter of every search on the context:
+                               SD_METRIC_LEVENSHTEIN (default) or SD_METRIC_HAMMING */
+
+/* Distances of the final filter (paper, Appendix A step 7; Section III C). */
+#define SD_METRIC_LEVENSHTEIN 0 /* unit-cost insertions, deletions and substitutions */
+#define SD_METRIC_HAMMING 1     /* equal lengths only; the number of differing positions */
 
 /*
  * Create a context on HIP device `device`. hbm_budget_bytes bounds the
@@ -147,6 +153,19 @@ int sd_set_allocator(sd_ctx* ctx, sd_alloc_fn alloc, sd_free_fn free_fn, void* u
  * SD_E_HIP. On error out->n == 0 and nothing needs freeing.
  */
 int sd_self_search(sd_ctx* ctx, const sd_seqs* seqs, int k, sd_pairs* out, void* stream);
+
+/*
+ * Self search in Hamming mode (paper, Section III C: for the comparison with
+ * a Hamming-only tool the method keeps its candidate generation and changes
+ * only the final filter): every pair i < j of equal length whose sequences
+ * differ in at most k positions, sorted by (i, j), with d the Hamming
+ * distance. Sequences of different lengths never pair. The deletion-variant
+ * candidates contain every such pair, since Hamming(a, b) <= k implies
+ * Levenshtein(a, b) <= k. Same as sd_self_search with SD_OPT_METRIC =
+ * SD_METRIC_HAMMING (the context's option is left as it was).
+ * Errors: as sd_self_search.
+ */
+int sd_self_search_hamming(sd_ctx* ctx, const sd_seqs* seqs, int k, sd_pairs* out, void* stream);
 
 /*
  * Exact Levenshtein distance of n given pairs (the verification step, paper
@@ -247,6 +266,16 @@ int sd_mlp_gradients(sd_ctx* ctx, const float* params, const float* x, const flo
  */
 int sd_query(sd_ctx* ctx, const sd_index* index, const sd_seqs* q, int k, sd_pairs* out,
              void* stream);
+
+/*
+ * Query search in Hamming mode (Section III C's filter, as in
+ * sd_self_search_hamming): every (q, r) of equal length with Hamming
+ * distance <= k, returned as (i = q, j = r, d), sorted by (q, r). k must not
+ * exceed the index's k. Same as sd_query with SD_OPT_METRIC =
+ * SD_METRIC_HAMMING. Errors: as sd_query.
+ */
+int sd_query_hamming(sd_ctx* ctx, const sd_index* index, const sd_seqs* q, int k, sd_pairs* out,
+                     void* stream);
 
 /*
  * Batched query search: nsets query sets against one index in as few

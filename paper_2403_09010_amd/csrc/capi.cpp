@@ -248,6 +248,20 @@ static int guarded(sd_ctx* c, F&& f) {
   return code;
 }
 
+// Run f with the context's metric set to `metric`, restoring it afterwards.
+template <typename F>
+static void with_metric(sd_ctx* c, int metric, F&& f) {
+  const int saved = c->metric;
+  c->metric = metric;
+  try {
+    f();
+  } catch (...) {
+    c->metric = saved;
+    throw;
+  }
+  c->metric = saved;
+}
+
 extern "C" {
 
 int sd_create(sd_ctx** out, int device, uint64_t hbm_budget_bytes) {
@@ -327,6 +341,10 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
       if (value < 0 || value > 2) return SD_E_INVAL;
       c->pair_sort = (int)value;
       return SD_OK;
+    case SD_OPT_METRIC:
+      if (value != SD_METRIC_LEVENSHTEIN && value != SD_METRIC_HAMMING) return SD_E_INVAL;
+      c->metric = (int)value;
+      return SD_OK;
     default:
       c->last_error = "unknown option";
       return SD_E_INVAL;
@@ -367,6 +385,19 @@ int sd_self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, void* s
   return guarded(c, [&] {
     sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
     sd::self_search(c, seqs, k, out, static_cast<hipStream_t>(stream));
+  });
+}
+
+int sd_self_search_hamming(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, void* stream) {
+  if (!c || !seqs || !out) return SD_E_INVAL;
+  const int32_t want_device = out->on_device;
+  std::memset(out, 0, sizeof(*out));
+  out->on_device = want_device;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    with_metric(c, SD_METRIC_HAMMING, [&] {
+      sd::self_search(c, seqs, k, out, static_cast<hipStream_t>(stream));
+    });
   });
 }
 
@@ -452,6 +483,18 @@ int sd_query(sd_ctx* c, const sd_index* idx, const sd_seqs* q, int k, sd_pairs* 
   return guarded(c, [&] {
     sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
     sd::query_sets(c, idx, 1, q, k, nullptr, out, static_cast<hipStream_t>(stream));
+  });
+}
+
+int sd_query_hamming(sd_ctx* c, const sd_index* idx, const sd_seqs* q, int k, sd_pairs* out,
+                     void* stream) {
+  if (!c || !q || !out) return SD_E_INVAL;
+  reset_pairs(out);
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    with_metric(c, SD_METRIC_HAMMING, [&] {
+      sd::query_sets(c, idx, 1, q, k, nullptr, out, static_cast<hipStream_t>(stream));
+    });
   });
 }
 

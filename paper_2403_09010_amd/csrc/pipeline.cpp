@@ -376,7 +376,8 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
     if (nc) {
       const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
       const uint32_t epoch = next_epoch(c, tiles, s);
-      launch_verify_compact(sorted, nc, planes, seq, k, oi, oj, od, c->status, cl.tile_counter(),
+      launch_verify_compact(sorted, nc, c->metric == SD_METRIC_HAMMING ? seq : planes, seq, k,
+                            c->metric, oi, oj, od, c->status, cl.tile_counter(),
                             epoch, pcount, cl.lb_err(), s);
       tm.mark("verify", (double)nc * (8 + 32) + (double)nc * 9, 1);
     } else {

@@ -196,7 +196,8 @@ TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint6
       } else {
         const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
         const uint32_t epoch = next_epoch(c, tiles, s);
-        launch_verify_compact(sorted, nc, qplanes, rseq, k, out.i, out.j, out.d, c->status,
+        launch_verify_compact(sorted, nc, c->metric == SD_METRIC_HAMMING ? qseq : qplanes, rseq, k,
+                              c->metric, out.i, out.j, out.d, c->status,
                               cl.tile_counter(), epoch, pcount, cl.lb_err(), s);
       }
     }

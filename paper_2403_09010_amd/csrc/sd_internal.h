@@ -91,11 +91,12 @@ void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint
                       uint64_t n, uint64_t* cand, uint64_t cap,
                       unsigned long long* counter, hipStream_t s);
 uint64_t compact_tile();
-void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* planes_a,
-                           const u128* seq_b, int k, uint32_t* out_i, uint32_t* out_j,
-                           uint8_t* out_d, uint64_t* status, uint32_t* tile_counter,
-                           uint32_t epoch, unsigned long long* out_count, uint32_t* err,
-                           hipStream_t s);
+// metric SD_METRIC_LEVENSHTEIN: a = bit planes of the first sequences (pack);
+// SD_METRIC_HAMMING: a = their packed keys
+void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* a, const u128* seq_b,
+                           int k, int metric, uint32_t* out_i, uint32_t* out_j, uint8_t* out_d,
+                           uint64_t* status, uint32_t* tile_counter, uint32_t epoch,
+                           unsigned long long* out_count, uint32_t* err, hipStream_t s);
 // hashed grouping (element = hash of the key in the top 64 - idbits bits, id below)
 // Every variant as [hash | id] in voff order; block b generates sequences
 // [b * seqs_per_block, ...) (1 <= seqs_per_block <= VG_MAX_SEQS_PER_BLOCK).
@@ -242,6 +243,7 @@ struct sd_ctx {
   int group_batches = 0;  // hashed path: LDS batches per workgroup (0 = automatic)
   int sort_items = 0;  // keys-only radix passes: items per thread, 16 or 32 (0 = automatic)
   int pair_sort = 0;   // candidate pair sort: 0 automatic, 1 one-sweep passes, 2 counted passes
+  int metric = SD_METRIC_LEVENSHTEIN;  // distance of the final filter (SD_OPT_METRIC)
   int64_t batch_tile_seqs = 0;  // query batches: sequences per tile (0 = automatic)
   int probe = 0;                // learned indexes: 0 model window, 1 whole-array binary search
   std::map<std::string, uint64_t> out_hint;  // last output size of each sharded stage

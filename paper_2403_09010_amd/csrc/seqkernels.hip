@@ -6,7 +6,8 @@
 //   k_emit_runs       groups of equal keys in a sorted key array -> id pairs
 //                     (steps 4-5, "uniqueCount" + "expand")
 //   k_verify_compact  drop repeated candidates, keep pairs with Levenshtein
-//                     distance <= k, compact in order (steps 6-7)
+//                     distance <= k (or, in Hamming mode, equal lengths and
+//                     Hamming distance <= k), compact in order (steps 6-7)
 //   k_pair_distance   Levenshtein distance of given pairs
 #include "sd_device.h"
 #include "sd_internal.h"
@@ -93,6 +94,21 @@ __device__ __forceinline__ uint32_t lev_planes(u128 pa, u128 b) {
     mv = ph & xv;
   }
   return score;
+}
+
+// Hamming distance of two packed keys of equal length (Section III C's
+// filter): residues sit in 5-bit fields at bits [5 g, 5 g + 5), so a field of
+// a XOR b is non-zero exactly where the residues differ; OR-ing each field's
+// five bits into its lowest bit and counting those bits gives the distance.
+// Fields past the length are zero in both keys.
+__device__ __forceinline__ uint32_t hamming_keys(u128 a, u128 b) {
+  constexpr uint64_t LOW = 0x0084210842108421ull;  // bits 0, 5, 10, ..., 55
+  const u128 x = a ^ b;
+  const uint64_t lo = (uint64_t)x & ((1ull << 60) - 1ull);         // fields 0..11
+  const uint64_t hi = (uint64_t)(x >> 60) & ((1ull << 60) - 1ull);  // fields 12..23
+  const uint64_t flo = (lo | (lo >> 1) | (lo >> 2) | (lo >> 3) | (lo >> 4)) & LOW;
+  const uint64_t fhi = (hi | (hi >> 1) | (hi >> 2) | (hi >> 3) | (hi >> 4)) & LOW;
+  return (uint32_t)(__popcll(flo) + __popcll(fhi));
 }
 
 // ------------------------------------------------------------------ pack
@@ -227,6 +243,10 @@ constexpr int CITEMS = 8;
 // thread taking a contiguous piece, so a wave does not run the distance once
 // per candidate slot while most of its lanes hold repeats. Kept pairs are
 // written in candidate order after a look-back over the tiles.
+// HAMMING = 0: pa holds the bit-plane form of the first sequences (pack's
+// planes) and the distance is Levenshtein; HAMMING = 1: pa holds their packed
+// keys and the distance is Hamming over equal lengths.
+template <int HAMMING>
 __global__ __launch_bounds__(NT) void k_verify_compact(
     const uint64_t* __restrict__ cand, uint64_t c, const u128* __restrict__ pa,
     const u128* __restrict__ sb, int k, uint32_t* __restrict__ oi, uint32_t* __restrict__ oj,
@@ -268,7 +288,12 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
     const u128 a = pa[v >> 32], b = sb[(uint32_t)v];
     const int la = (int)(a >> 120), lb = (int)key_len(b);
     uint8_t d = DROP;
-    if (abs(la - lb) <= k) {
+    if (HAMMING) {
+      if (la == lb) {
+        const uint32_t dd = hamming_keys(a, b);
+        if (dd <= (uint32_t)k) d = (uint8_t)dd;
+      }
+    } else if (abs(la - lb) <= k) {
       const uint32_t dd = lev_planes(a, b);
       if (dd <= (uint32_t)k) d = (uint8_t)dd;
     }
@@ -342,15 +367,19 @@ void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint
 
 uint64_t compact_tile() { return (uint64_t)sdk::NT * sdk::CITEMS; }
 
-void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* planes_a,
-                           const u128* seq_b, int k, uint32_t* out_i, uint32_t* out_j,
-                           uint8_t* out_d, uint64_t* status, uint32_t* tile_counter,
-                           uint32_t epoch, unsigned long long* out_count, uint32_t* err,
-                           hipStream_t s) {
+void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* a, const u128* seq_b,
+                           int k, int metric, uint32_t* out_i, uint32_t* out_j, uint8_t* out_d,
+                           uint64_t* status, uint32_t* tile_counter, uint32_t epoch,
+                           unsigned long long* out_count, uint32_t* err, hipStream_t s) {
   if (!c) return;
-  hipLaunchKernelGGL(sdk::k_verify_compact, dim3(blocks_for(c, compact_tile())), dim3(sdk::NT), 0,
-                     s, cand, c, planes_a, seq_b, k, out_i, out_j, out_d, status, tile_counter,
-                     epoch, out_count, err);
+  if (metric == SD_METRIC_HAMMING)
+    hipLaunchKernelGGL(sdk::k_verify_compact<1>, dim3(blocks_for(c, compact_tile())), dim3(sdk::NT),
+                       0, s, cand, c, a, seq_b, k, out_i, out_j, out_d, status, tile_counter, epoch,
+                       out_count, err);
+  else
+    hipLaunchKernelGGL(sdk::k_verify_compact<0>, dim3(blocks_for(c, compact_tile())), dim3(sdk::NT),
+                       0, s, cand, c, a, seq_b, k, out_i, out_j, out_d, status, tile_counter, epoch,
+                       out_count, err);
 }
 
 void launch_pair_distance(const u128* seq_a, uint64_t na, const u128* seq_b, uint64_t nb,

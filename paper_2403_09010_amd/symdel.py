@@ -30,6 +30,9 @@ OPT_BATCH_TILE = 6
 OPT_PROBE = 7
 OPT_GROUP_BATCHES = 8
 OPT_PAIR_SORT = 9
+OPT_METRIC = 10
+METRIC_LEVENSHTEIN = 0
+METRIC_HAMMING = 1
 MAX_STAGES = 16
 MLP_HIDDEN = 32
 MLP_PARAMS = 3 * MLP_HIDDEN + 1
@@ -117,6 +120,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sd_set_allocator.restype = I
     lib.sd_self_search.argtypes = [P, ctypes.POINTER(_Seqs), I, ctypes.POINTER(_Pairs), P]
     lib.sd_self_search.restype = I
+    lib.sd_self_search_hamming.argtypes = [P, ctypes.POINTER(_Seqs), I, ctypes.POINTER(_Pairs), P]
+    lib.sd_self_search_hamming.restype = I
     lib.sd_pair_distance.argtypes = [P, ctypes.POINTER(_Seqs), ctypes.POINTER(_Seqs), P, P, I64,
                                      P, P]
     lib.sd_pair_distance.restype = I
@@ -138,6 +143,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sd_index_info.restype = I
     lib.sd_query.argtypes = [P, P, ctypes.POINTER(_Seqs), I, ctypes.POINTER(_Pairs), P]
     lib.sd_query.restype = I
+    lib.sd_query_hamming.argtypes = [P, P, ctypes.POINTER(_Seqs), I, ctypes.POINTER(_Pairs), P]
+    lib.sd_query_hamming.restype = I
     lib.sd_query_batch.argtypes = [P, P, I, ctypes.POINTER(_Seqs), I, ctypes.POINTER(_Pairs), P]
     lib.sd_query_batch.restype = I
     lib.sd_query_weighted.argtypes = [P, P, ctypes.POINTER(_Seqs), P, I, I,
@@ -342,15 +349,17 @@ class Context:
 
     # ------------------------------------------------------------ searches
     def self_search(self, codes, offsets, k: int, device_output: bool | None = None,
-                    stream=None) -> Pairs:
-        """All i < j with Levenshtein(S_i, S_j) <= k, sorted by (i, j)."""
+                    stream=None, hamming: bool = False) -> Pairs:
+        """All i < j with Levenshtein(S_i, S_j) <= k, sorted by (i, j); with
+        hamming, equal-length pairs with Hamming distance <= k instead."""
         s, keep, on_dev = self._seqs(codes, offsets)
         st = _stream_handle(stream, on_dev)
         if device_output is None:
             device_output = on_dev
         p = _Pairs(0, None, None, None, 1 if device_output else 0, 0)
-        rc = self._lib.sd_self_search(self._h, ctypes.byref(s), int(k), ctypes.byref(p), st)
-        self._check(rc, "sd_self_search")
+        fn = self._lib.sd_self_search_hamming if hamming else self._lib.sd_self_search
+        rc = fn(self._h, ctypes.byref(s), int(k), ctypes.byref(p), st)
+        self._check(rc, "sd_self_search_hamming" if hamming else "sd_self_search")
         return self._take(p, device_output, st)
 
     def self_search_raw(self, s: _Seqs, k: int, stream) -> _Pairs:
@@ -423,15 +432,17 @@ class Context:
         return g, float(loss.value)
 
     def query(self, index: Index, codes, offsets, k: int, device_output: bool | None = None,
-              stream=None) -> Pairs:
-        """All (q, r) with Levenshtein(Q_q, R_r) <= k, sorted by (q, r)."""
+              stream=None, hamming: bool = False) -> Pairs:
+        """All (q, r) with Levenshtein(Q_q, R_r) <= k, sorted by (q, r); with
+        hamming, equal-length pairs with Hamming distance <= k instead."""
         s, keep, on_dev = self._seqs(codes, offsets)
         st = _stream_handle(stream, on_dev)
         if device_output is None:
             device_output = on_dev
         p = _Pairs(0, None, None, None, 1 if device_output else 0, 0)
-        self._check(self._lib.sd_query(self._h, index.handle, ctypes.byref(s), int(k),
-                                       ctypes.byref(p), st), "sd_query")
+        fn = self._lib.sd_query_hamming if hamming else self._lib.sd_query
+        self._check(fn(self._h, index.handle, ctypes.byref(s), int(k), ctypes.byref(p), st),
+                    "sd_query_hamming" if hamming else "sd_query")
         return self._take(p, device_output, st)
 
     def query_batch(self, index: Index, sets, k: int, device_output: bool | None = None,
