@@ -14,6 +14,8 @@ Functions return ``(a, b, d)`` numpy arrays sorted by ``(a, b)``:
     result on several threads with bounded memory (variant space split into
     shards by a hash of the variant string).
   * ``query_search(ref, qry, k)``: all (q, r) with Lev(Q_q, R_r) <= k.
+  * ``paired_self_search(a, b, k)``: paired-chain records (Discussion: both
+    chains joined by a non-deletable token); distance Lev(a) + Lev(b).
   * ``self_search_hamming`` / ``query_search_hamming``: Hamming mode
     (Section III C): the same candidates, kept when the lengths are equal and
     at most k positions differ.
@@ -73,6 +75,11 @@ def _load():
                  "or_brute_query_hamming"):
         getattr(lib, name).restype = P
         getattr(lib, name).argtypes = [P, P, I64, P, P, I64, I]
+    for name in ("or_paired_self_search", "or_brute_paired"):
+        getattr(lib, name).restype = P
+        getattr(lib, name).argtypes = [P, P, P, P, I64, I]
+    lib.or_paired_variant_count.restype = I64
+    lib.or_paired_variant_count.argtypes = [P, I, P, I, I]
     lib.or_query_weighted.restype = P
     lib.or_query_weighted.argtypes = [P, P, I64, P, P, I64, I, P, I, I]
     lib.or_brute_weighted.restype = P
@@ -208,6 +215,30 @@ def brute_query_hamming(ref, qry, k: int):
     h = _load().or_brute_query_hamming(rc.ctypes.data, ro.ctypes.data, len(ro) - 1, qc.ctypes.data,
                                        qo.ctypes.data, len(qo) - 1, k)
     return _take(h)
+
+
+def paired_self_search(a, b, k: int):
+    """Paired-chain mode (Discussion): records (a_i, b_i) from two CSR sets
+    with the same count; variants keep a joining token and delete at most k
+    positions in total; kept when Lev(a_i, a_j) + Lev(b_i, b_j) <= k."""
+    (ac, ao), (bc, bo) = (_u8(a[0]), _i64(a[1])), (_u8(b[0]), _i64(b[1]))
+    assert len(ao) == len(bo)
+    h = _load().or_paired_self_search(ac.ctypes.data, ao.ctypes.data, bc.ctypes.data,
+                                      bo.ctypes.data, len(ao) - 1, k)
+    return _take(h)
+
+
+def brute_paired(a, b, k: int):
+    (ac, ao), (bc, bo) = (_u8(a[0]), _i64(a[1])), (_u8(b[0]), _i64(b[1]))
+    assert len(ao) == len(bo)
+    h = _load().or_brute_paired(ac.ctypes.data, ao.ctypes.data, bc.ctypes.data, bo.ctypes.data,
+                                len(ao) - 1, k)
+    return _take(h)
+
+
+def paired_variant_count(a, b, k: int) -> int:
+    a, b = _u8(a), _u8(b)
+    return _load().or_paired_variant_count(a.ctypes.data, len(a), b.ctypes.data, len(b), k)
 
 
 def brute_self(codes, offsets, k: int):

@@ -21,6 +21,14 @@
 // positions. Hamming(a, b) <= k implies Lev(a, b) <= k, so the deletion
 // candidates contain every such pair.
 //
+// Paired-chain mode (Discussion: the CDR3s of both chains joined by a
+// joining token that is never deleted): a record is (a, b); its variants
+// are a' TOKEN b' with a' and b' deletion variants of a and b, at most k
+// positions deleted in total and the token kept. The token must align with
+// itself, so the distance of two records is Lev(a1, a2) + Lev(b1, b2); if
+// that is <= k, deleting per chain as in the single-chain proof gives a
+// shared variant with at most k deletions on each side.
+//
 // Weighted mode (Section III D: a Levenshtein prefilter followed by a
 // finer, substitution-weighted score): score = minimum-cost global alignment
 // with a 20x20 substitution cost table and a fixed indel cost.
@@ -138,6 +146,26 @@ void deletion_variants(const std::string& s, int k, std::vector<std::string>& ou
   for_each_deletion_set((int)s.size(), k, [&](const std::vector<int>& pos, int m) {
     out.push_back(delete_positions(s, pos, m));
   });
+}
+
+// Paired variants a' TOKEN b' of a record (a, b) with at most k deletions in
+// total; TOKEN is a byte no residue takes.
+constexpr char PAIR_TOKEN = (char)0xFF;
+void paired_variants(const std::string& a, const std::string& b, int k, std::vector<std::string>& out) {
+  out.clear();
+  std::vector<std::string> va, vb;
+  for (int m1 = 0; m1 <= k; ++m1) {
+    va.clear();
+    for_each_deletion_set((int)a.size(), m1, [&](const std::vector<int>& pos, int m) {
+      if (m == m1) va.push_back(delete_positions(a, pos, m));
+    });
+    vb.clear();
+    for_each_deletion_set((int)b.size(), k - m1, [&](const std::vector<int>& pos, int m) {
+      vb.push_back(delete_positions(b, pos, m));
+    });
+    for (const std::string& x : va)
+      for (const std::string& y : vb) out.push_back(x + PAIR_TOKEN + y);
+  }
 }
 
 std::string seq_at(const uint8_t* codes, const int64_t* offs, int64_t i) {
@@ -385,6 +413,44 @@ void* or_self_search_hamming(const uint8_t* codes, const int64_t* offs, int64_t 
   return res;
 }
 
+// Paired-chain self search: SymDel steps 1-3 over the paired variants, step
+// 4 keeps Lev(a_i, a_j) + Lev(b_i, b_j) <= k. Records are (a_i, b_i) for
+// i < n, two CSR sets with the same n.
+void* or_paired_self_search(const uint8_t* ac, const int64_t* ao, const uint8_t* bc,
+                            const int64_t* bo, int64_t n, int k) {
+  Result* res = new Result();
+  MultiMap map;
+  std::vector<std::string> vars;
+  for (int64_t i = 0; i < n; ++i) {
+    paired_variants(seq_at(ac, ao, i), seq_at(bc, bo, i), k, vars);
+    for (const std::string& v : vars) {
+      std::vector<uint32_t>& ids = map[v];
+      if (ids.empty() || ids.back() != (uint32_t)i) ids.push_back((uint32_t)i);
+    }
+  }
+  std::vector<uint64_t> cand;
+  self_candidates(map, cand, res->raw);
+  for (uint64_t c : cand) {
+    uint32_t i = (uint32_t)(c >> 32), j = (uint32_t)c;
+    int d = lev_full(ac + ao[i], (int)(ao[i + 1] - ao[i]), ac + ao[j], (int)(ao[j + 1] - ao[j])) +
+            lev_full(bc + bo[i], (int)(bo[i + 1] - bo[i]), bc + bo[j], (int)(bo[j + 1] - bo[j]));
+    if (d <= k) {
+      res->a.push_back(i);
+      res->b.push_back(j);
+      res->d.push_back(d);
+    }
+  }
+  return res;
+}
+
+// Number of paired variants of one record, with multiplicity.
+int64_t or_paired_variant_count(const uint8_t* a, int la, const uint8_t* b, int lb, int k) {
+  std::vector<std::string> vars;
+  paired_variants(std::string(reinterpret_cast<const char*>(a), (size_t)la),
+                  std::string(reinterpret_cast<const char*>(b), (size_t)lb), k, vars);
+  return (int64_t)vars.size();
+}
+
 // The candidate pairs of a self search before verification (unique, sorted),
 // with d = -1; raw multiplicity in or_raw.
 void* or_self_candidates(const uint8_t* codes, const int64_t* offs, int64_t n, int k) {
@@ -511,6 +577,23 @@ void* or_brute_query_hamming(const uint8_t* rc, const int64_t* ro, int64_t nr, c
       if (d >= 0 && d <= k) {
         res->a.push_back((uint32_t)q);
         res->b.push_back((uint32_t)r);
+        res->d.push_back(d);
+      }
+    }
+  return res;
+}
+
+// Paired definition over every pair: Lev(a_i, a_j) + Lev(b_i, b_j) <= k.
+void* or_brute_paired(const uint8_t* ac, const int64_t* ao, const uint8_t* bc, const int64_t* bo,
+                      int64_t n, int k) {
+  Result* res = new Result();
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = i + 1; j < n; ++j) {
+      int d = lev_full(ac + ao[i], (int)(ao[i + 1] - ao[i]), ac + ao[j], (int)(ao[j + 1] - ao[j])) +
+              lev_full(bc + bo[i], (int)(bo[i + 1] - bo[i]), bc + bo[j], (int)(bo[j + 1] - bo[j]));
+      if (d <= k) {
+        res->a.push_back((uint32_t)i);
+        res->b.push_back((uint32_t)j);
         res->d.push_back(d);
       }
     }

@@ -143,7 +143,7 @@ def _exhaustive_set():
     return strings, csr(strings)
 
 
-@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_symdel_equals_brute_force_exhaustive(oracle_lib, k):
     _, (c, o) = _exhaustive_set()
     got = triples(*oracle_lib.self_search(c, o, k))
@@ -237,6 +237,14 @@ def test_symdel_equals_brute_force_generator_k2(oracle_lib):
     got = triples(*oracle_lib.self_search(c, o, 2))
     assert got == triples(*oracle_lib.brute_self(c, o, 2))
     assert {t[2] for t in got} == {0, 1, 2}
+
+
+def test_symdel_equals_brute_force_generator_k3(oracle_lib):
+    # Section III D's larger radius: SymDel at k = 3 against every pair
+    c, o = cdr3gen.subset(*cdr3gen.plain("plain_10k"), 2500)
+    got = triples(*oracle_lib.self_search(c, o, 3))
+    assert got == triples(*oracle_lib.brute_self(c, o, 3))
+    assert {t[2] for t in got} == {0, 1, 2, 3}
 
 
 # ---------------------------------------------------------------- sharded mode
@@ -346,6 +354,96 @@ def test_hamming_query_equals_brute_force(oracle_lib, k):
     got = triples(*oracle_lib.query_search_hamming((rc, ro), (qc, qo), k))
     assert got == triples(*oracle_lib.brute_query_hamming((rc, ro), (qc, qo), k))
     assert len(got) > 0
+
+
+# ---------------------------------------------------------------- paired chains
+
+def _token_aligned_distance(x: bytes, y: bytes, token: int = 255) -> int:
+    """Edit distance of two joined records where the joining token can only
+    be matched with the other token (deleting, inserting or substituting it
+    is not allowed): a plain recursive DP, independent of the oracle."""
+    from functools import lru_cache
+    INF = 10 ** 6
+
+    @lru_cache(None)
+    def f(i, j):
+        if i == 0 and j == 0:
+            return 0
+        best = INF
+        if i > 0 and x[i - 1] != token:
+            best = min(best, f(i - 1, j) + 1)
+        if j > 0 and y[j - 1] != token:
+            best = min(best, f(i, j - 1) + 1)
+        if i > 0 and j > 0:
+            a, b = x[i - 1], y[j - 1]
+            if a == b:
+                best = min(best, f(i - 1, j - 1))
+            elif a != token and b != token:
+                best = min(best, f(i - 1, j - 1) + 1)
+        return best
+    return f(len(x), len(y))
+
+
+def test_paired_distance_is_token_aligned_edit_distance(oracle_lib):
+    # the distance the paired mode reports, Lev(a) + Lev(b), is the edit
+    # distance of the joined strings when the token must stay aligned
+    rng = np.random.default_rng(11)
+    for _ in range(400):
+        a1, b1, a2, b2 = (bytes(rng.integers(0, 3, size=rng.integers(0, 5)).tolist()) for _ in range(4))
+        want = _token_aligned_distance(a1 + b"\xff" + b1, a2 + b"\xff" + b2)
+        assert oracle_lib.lev(a1, a2) + oracle_lib.lev(b1, b2) == want
+
+
+@pytest.mark.parametrize("la,lb", [(0, 0), (1, 0), (3, 2), (10, 12), (15, 15), (24, 24)])
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_paired_variant_count(oracle_lib, la, lb, k):
+    a = bytes(range(la)) if la <= 20 else bytes(x % 20 for x in range(la))
+    b = bytes(range(lb)) if lb <= 20 else bytes(x % 20 for x in range(lb))
+    want = sum(math.comb(la, m1) * math.comb(lb, m2)
+               for m1 in range(k + 1) for m2 in range(k + 1 - m1))
+    assert oracle_lib.paired_variant_count(a, b, k) == want
+
+
+def _paired_exhaustive():
+    chains = [bytes(t) for L in range(1, 4) for t in itertools.product(range(2), repeat=L)]
+    recs = [(x, y) for x in chains for y in chains]
+    return csr([r[0] for r in recs]), csr([r[1] for r in recs])
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_paired_equals_brute_force_exhaustive(oracle_lib, k):
+    a, b = _paired_exhaustive()
+    got = triples(*oracle_lib.paired_self_search(a, b, k))
+    assert got == triples(*oracle_lib.brute_paired(a, b, k))
+    assert (len(got) > 0) == (k > 0)
+
+
+def paired_records(seed, n, fresh=500):
+    """Records (a, b): the first `fresh` from the generator, the others a
+    copy of an earlier record with a substitution in each chain, each with
+    probability one half, so near pairs in both chains occur."""
+    rng = np.random.default_rng(seed)
+    ac, ao = cdr3gen.generate(seed, fresh)
+    bc, bo = cdr3gen.generate(seed + 1, fresh)
+    A = [ac[ao[x]:ao[x + 1]].tobytes() for x in range(fresh)]
+    B = [bc[bo[x]:bo[x + 1]].tobytes() for x in range(fresh)]
+    for i in range(fresh, n):
+        u = int(rng.integers(i))
+        x, y = bytearray(A[u]), bytearray(B[u])
+        for z in (x, y):
+            if rng.random() < 0.5:
+                z[int(rng.integers(len(z)))] = int(rng.integers(20))
+        A.append(bytes(x))
+        B.append(bytes(y))
+    return csr(A), csr(B)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_paired_equals_brute_force_generator(oracle_lib, k):
+    a, b = paired_records(61, 1500)
+    got = triples(*oracle_lib.paired_self_search(a, b, k))
+    assert got == triples(*oracle_lib.brute_paired(a, b, k))
+    assert len(got) > 100
 
 
 # ---------------------------------------------------------------- weighted score
