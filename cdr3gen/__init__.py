@@ -63,12 +63,25 @@ def _load():
     lib.cdr3_poisson_arrivals.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_double, P]
     lib.cdr3_cost_matrix.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, P]
     lib.cdr3_residue_probs.argtypes = [P]
+    lib.cdr3_generate_paired.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_double, P, P,
+                                         P, P]
     _lib = lib
     return lib
 
 
 def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
+
+
+def paired(seed: int, n: int, fresh_frac: float = 0.7):
+    """n paired-chain records: ((codes_a, offsets_a), (codes_b, offsets_b))."""
+    lib = _load()
+    ca = np.empty(max(24 * n, 1), dtype=np.uint8)
+    cb = np.empty(max(24 * n, 1), dtype=np.uint8)
+    oa = np.empty(n + 1, dtype=np.int64)
+    ob = np.empty(n + 1, dtype=np.int64)
+    lib.cdr3_generate_paired(seed, n, fresh_frac, _ptr(ca), _ptr(oa), _ptr(cb), _ptr(ob))
+    return (ca[:oa[-1]].copy(), oa), (cb[:ob[-1]].copy(), ob)
 
 
 def generate(seed: int, n: int, fresh_frac: float = 0.7):

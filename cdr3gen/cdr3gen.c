@@ -193,6 +193,45 @@ int64_t cdr3_generate_query(uint64_t seed, int64_t n, double fresh_frac, double 
   return pos;
 }
 
+/*
+ * Paired-chain records (two CDR3-like chains per record, for the paired
+ * search of the paper's Discussion). Record i is fresh with probability
+ * fresh_frac (i = 0 always): both chains follow the fresh recipe. Otherwise
+ * it copies a uniformly chosen earlier record and applies one mutate() call
+ * (1-2 interior edits) to one of its two chains, chosen uniformly.
+ * Capacities: 24 * n residues per chain.
+ */
+void cdr3_generate_paired(uint64_t seed, int64_t n, double fresh_frac, uint8_t* codes_a,
+                          int64_t* offs_a, uint8_t* codes_b, int64_t* offs_b) {
+  residue_table t;
+  make_table(&t);
+  uint64_t s = seed;
+  uint8_t ba[CDR3_MAX_LEN + 4], bb[CDR3_MAX_LEN + 4];
+  offs_a[0] = 0;
+  offs_b[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int La, Lb;
+    if (i == 0 || u01(&s) < fresh_frac) {
+      La = fresh(&t, &s, ba);
+      Lb = fresh(&t, &s, bb);
+    } else {
+      int64_t u = below(&s, i);
+      La = (int)(offs_a[u + 1] - offs_a[u]);
+      Lb = (int)(offs_b[u + 1] - offs_b[u]);
+      memcpy(ba, codes_a + offs_a[u], (size_t)La);
+      memcpy(bb, codes_b + offs_b[u], (size_t)Lb);
+      if (below(&s, 2) == 0)
+        La = mutate(&t, &s, ba, La);
+      else
+        Lb = mutate(&t, &s, bb, Lb);
+    }
+    memcpy(codes_a + offs_a[i], ba, (size_t)La);
+    offs_a[i + 1] = offs_a[i] + La;
+    memcpy(codes_b + offs_b[i], bb, (size_t)Lb);
+    offs_b[i + 1] = offs_b[i] + Lb;
+  }
+}
+
 /* count integers, each round(exp(U(ln lo, ln hi))) */
 void cdr3_loguniform_sizes(uint64_t seed, int64_t count, double lo, double hi, int64_t* out) {
   uint64_t s = seed;

@@ -35,7 +35,7 @@ extern "C" {
 #endif
 
 #define SD_OK 0
-#define SD_E_INVAL (-1)     /* null pointer, bad size or k outside {0, 1, 2} */
+#define SD_E_INVAL (-1)     /* null pointer, bad size or k outside {0, 1, 2, 3} */
 #define SD_E_ALPHABET (-2)  /* a residue code >= 20 */
 #define SD_E_LENGTH (-3)    /* a sequence length outside [1, 24] */
 #define SD_E_TOO_MANY (-4)  /* more sequences or variants than 32-bit ids allow */
@@ -82,6 +82,7 @@ typedef struct {
   int64_t n_big_segments; /* hashed path: ranges neither grouping kernel could hold in LDS,
                              grouped by a sort on the full hash instead */
   int64_t n_probe_steps;  /* learned indexes: comparisons made by the lookups' searches */
+  int64_t n_stream_groups; /* streamed self search: column groups processed (0: in memory) */
   char stage_name[SD_MAX_STAGES][24];
   double stage_ms[SD_MAX_STAGES];      /* device time between HIP events on `stream` */
   double stage_bytes[SD_MAX_STAGES];   /* algorithmic HBM bytes of the stage */
@@ -100,6 +101,11 @@ typedef struct {
 #define SD_OPT_PAIR_SORT 9  /* candidate pair sort: 0 automatic, 1 one-sweep LSD passes, 2 counted LSD passes */
 #define SD_OPT_METRIC 10    /* distance of the final filter of every search on the context:
                                SD_METRIC_LEVENSHTEIN (default) or SD_METRIC_HAMMING */
+#define SD_OPT_STREAM 11    /* self search in column groups of hash bins (bounded memory):
+                               0 automatic (when the variants exceed 2^32 - 2 or the
+                               in-memory path would exceed the budget), 1 never, 2 always */
+#define SD_OPT_STREAM_ELEMS 12 /* streamed self search: variants per column group at most
+                                  (0: from the budget, or 80% of free device memory) */
 
 /* Distances of the final filter (paper, Appendix A step 7; Section III C). */
 #define SD_METRIC_LEVENSHTEIN 0 /* unit-cost insertions, deletions and substitutions */
@@ -148,7 +154,17 @@ int sd_set_allocator(sd_ctx* ctx, sd_alloc_fn alloc, sd_free_fn free_fn, void* u
  * Self search (paper, Appendix A XTNeighbor steps 1-7): every pair i < j of
  * `seqs` with Levenshtein distance d <= k, sorted by (i, j) ascending, with
  * d the exact unit-cost edit distance. Duplicate input sequences give d = 0
- * pairs. k must be 0, 1 or 2.
+ * pairs. k must be 0, 1, 2 or 3 (three deletions, the paper's Fig. 2C and
+ * Section III D distance 3, run on the hashed grouping path only).
+ *
+ * Bounded memory (Section II C, "Overcoming memory bottlenecks"; the
+ * XTNeighbor-Streaming steps of Appendix A): when the variants exceed
+ * 2^32 - 2 or the in-memory path would exceed the context's HBM budget
+ * (SD_OPT_STREAM 0), the search runs in column groups of hash bins: one
+ * generator pass counts every bin, Next-Fit packs consecutive bins into
+ * groups that fit the budget (or SD_OPT_STREAM_ELEMS), and each group is
+ * generated, grouped, sorted and verified alone before the pairs of all
+ * groups are merged. The result is the same set either way.
  * Errors: SD_E_INVAL, SD_E_ALPHABET, SD_E_LENGTH, SD_E_TOO_MANY, SD_E_NOMEM,
  * SD_E_HIP. On error out->n == 0 and nothing needs freeing.
  */
@@ -168,6 +184,21 @@ int sd_self_search(sd_ctx* ctx, const sd_seqs* seqs, int k, sd_pairs* out, void*
 int sd_self_search_hamming(sd_ctx* ctx, const sd_seqs* seqs, int k, sd_pairs* out, void* stream);
 
 /*
+ * Paired-chain self search (paper, Discussion: the CDR3s of both chains of a
+ * receptor joined by a token that is never deleted). Record i is the pair
+ * (a_i, b_i) of sequences a->codes.. and b->codes.. (both sets hold the same
+ * number of records, each chain 1..24 residues). Returns every pair of
+ * records i < j with d = Lev(a_i, a_j) + Lev(b_i, b_j) <= k, sorted by (i, j).
+ * The deletion variants are those of the joined string a T b with at most k
+ * residues deleted and T kept: two records within d <= k share one (delete
+ * per chain as in the single-chain argument), so the candidates are
+ * complete. k must be 0..3. Errors: as sd_self_search, and SD_E_INVAL when
+ * the two sets differ in size.
+ */
+int sd_paired_self_search(sd_ctx* ctx, const sd_seqs* a, const sd_seqs* b, int k, sd_pairs* out,
+                          void* stream);
+
+/*
  * Exact Levenshtein distance of n given pairs (the verification step, paper
  * Appendix A step 7): d_out[t] = Lev(a[ia[t]], b[ib[t]]) capped at 255.
  * ia, ib and d_out are device pointers; a and b follow their on_device flags.
@@ -182,7 +213,7 @@ int sd_pair_distance(sd_ctx* ctx, const sd_seqs* a, const sd_seqs* b, const uint
  * II A built once for the reference): every <= k-deletion variant of `ref`,
  * stored on the context's device and owned by the index, read-only after the
  * build (several contexts on the same device may query it concurrently).
- * Release with sd_index_free (no context needed). k must be 0, 1 or 2.
+ * Release with sd_index_free (no context needed). k must be 0, 1, 2 or 3.
  * Errors: as sd_self_search.
  */
 typedef struct sd_index sd_index;

@@ -262,6 +262,10 @@ static void with_metric(sd_ctx* c, int metric, F&& f) {
   c->metric = saved;
 }
 
+// pinned host staging for read-backs: the largest one (the full-key sort's
+// digit histograms, 16 KiB) fits, so it never grows after sd_create
+constexpr size_t kPinnedStaging = 65536;
+
 extern "C" {
 
 int sd_create(sd_ctx** out, int device, uint64_t hbm_budget_bytes) {
@@ -280,6 +284,15 @@ int sd_create(sd_ctx** out, int device, uint64_t hbm_budget_bytes) {
   if (!c) return SD_E_NOMEM;
   c->device = device;
   c->budget = hbm_budget_bytes;
+  // the pinned staging area for small read-backs (allocated here so that no
+  // later call has to)
+  if (hipHostMalloc(&c->pinned, kPinnedStaging, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    return SD_E_HIP;
+  }
+  c->pinned_bytes = kPinnedStaging;
   *out = c;
   return SD_OK;
 }
@@ -341,6 +354,14 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
       if (value < 0 || value > 2) return SD_E_INVAL;
       c->pair_sort = (int)value;
       return SD_OK;
+    case SD_OPT_STREAM:
+      if (value < 0 || value > 2) return SD_E_INVAL;
+      c->stream = (int)value;
+      return SD_OK;
+    case SD_OPT_STREAM_ELEMS:
+      if (value < 0) return SD_E_INVAL;
+      c->stream_elems = (uint64_t)value;
+      return SD_OK;
     case SD_OPT_METRIC:
       if (value != SD_METRIC_LEVENSHTEIN && value != SD_METRIC_HAMMING) return SD_E_INVAL;
       c->metric = (int)value;
@@ -398,6 +419,18 @@ int sd_self_search_hamming(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out,
     with_metric(c, SD_METRIC_HAMMING, [&] {
       sd::self_search(c, seqs, k, out, static_cast<hipStream_t>(stream));
     });
+  });
+}
+
+int sd_paired_self_search(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, int k, sd_pairs* out,
+                          void* stream) {
+  if (!c || !a || !b || !out) return SD_E_INVAL;
+  const int32_t want_device = out->on_device;
+  std::memset(out, 0, sizeof(*out));
+  out->on_device = want_device;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::paired_self_search(c, a, b, k, out, static_cast<hipStream_t>(stream));
   });
 }
 

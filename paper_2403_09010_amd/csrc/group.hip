@@ -36,8 +36,8 @@ namespace sdk {
 // case p2 = L, none the case p1 = L, p2 = L + 1 (P is constant past L). Only
 // the load balance and the rate of extra candidates depend on the hash.
 struct HashTab {
-  uint64_t b[32];  // per residue code
-  uint64_t c[32];  // per string length
+  uint64_t b[32];  // per residue code (code 20 is the paired-chain join token)
+  uint64_t c[64];  // per string length (paired-chain variants reach 49)
 };
 
 // splitmix64 (Steele, Lea and Flood, 2014) as a compile-time generator
@@ -53,7 +53,7 @@ constexpr HashTab make_hash_tab() {
   HashTab t{};
   uint64_t state = 0x5D3E1B7A2C4F9081ull;
   for (int x = 0; x < 32; ++x) t.b[x] = splitmix_next(state);
-  for (int x = 0; x < 32; ++x) t.c[x] = splitmix_next(state);
+  for (int x = 0; x < 64; ++x) t.c[x] = splitmix_next(state);
   return t;
 }
 
@@ -81,9 +81,11 @@ struct PassDigits {
   uint32_t mask[3];
 };
 
-// prefix XORs per sequence: indices 0..L + 2 <= 26 are read; an odd row
-// length starts consecutive rows in different LDS banks
+// prefix XORs per sequence: indices 0..L + 2 <= 26 are read (0..L + 3 with
+// three deletions); an odd row length starts consecutive rows in different
+// LDS banks
 constexpr int VG_PRE = 27;
+constexpr int VG_PRE3 = 29;
 
 // Deletion pairs in colexicographic order (p2 major): pair u is (p1, p2)
 // with u = p2 (p2 - 1) / 2 + p1, the same for every length L (a string of
@@ -108,6 +110,59 @@ constexpr PairTab make_pair_tab() {
 
 __constant__ PairTab kPairTab = make_pair_tab();
 
+// C(p, 3) for p = 0..KEY_MAX_LEN: the colexicographic rank of the first
+// triple with largest position p (triples with largest position p3 are the
+// pairs below p3 in their own colexicographic order).
+struct TriTab {
+  uint16_t c3[KEY_MAX_LEN + 1];
+};
+
+constexpr TriTab make_tri_tab() {
+  TriTab t{};
+  for (int p = 0; p <= KEY_MAX_LEN; ++p) t.c3[p] = (uint16_t)(p * (p - 1) * (p - 2) / 6);
+  return t;
+}
+
+__constant__ TriTab kTriTab = make_tri_tab();
+
+// Deletion positions of variant v of a string of length L, with up to three
+// deletions, as a padded triple (see variant_canonical3): v = 0 none, 1..L
+// one, then the C(L, 2) pairs, then the triples, each in colexicographic
+// order. The largest position of a triple is found by binary search of c3.
+__device__ __forceinline__ void variant_positions3(const uint16_t* s_pairs, const uint16_t* s_c3,
+                                                   uint32_t L, uint32_t v, uint32_t& p1,
+                                                   uint32_t& p2, uint32_t& p3) {
+  const uint32_t np = L * (L - 1) / 2;
+  if (v == 0) {
+    p1 = L;
+    p2 = L + 1;
+    p3 = L + 2;
+  } else if (v <= L) {
+    p1 = v - 1;
+    p2 = L;
+    p3 = L + 1;
+  } else if (v <= L + np) {
+    const uint32_t pr = s_pairs[v - 1 - L];
+    p1 = pr & 0xFFu;
+    p2 = pr >> 8;
+    p3 = L;
+  } else {
+    const uint32_t u = v - 1 - L - np;
+    uint32_t lo = 2, hi = L - 1;  // the largest p3 with c3[p3] <= u
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_c3[mid] <= u)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    p3 = lo;
+    const uint32_t pr = s_pairs[u - s_c3[lo]];
+    p1 = pr & 0xFFu;
+    p2 = pr >> 8;
+  }
+}
+
 // Deletion positions of variant v of a string of length L in the enumeration
 // order (v = 0 the string itself, v = 1..L one deletion at v - 1, then the
 // pairs in colexicographic order), in the form the prefix-XOR hash takes:
@@ -125,8 +180,17 @@ __device__ __forceinline__ void variant_positions(const uint16_t* s_pairs, uint3
 // enumerated (see the loop below for how waves share them out). DISTINCT: the
 // variant offsets count distinct strings only
 // (num_distinct_variants), and a wave writes the canonical deletion sets of
-// the sequence compactly, in enumeration order, at its offset.
-template <bool DISTINCT>
+// the sequence compactly, in enumeration order, at its offset. K3: up to
+// three deletions (padded triples, variant_positions3 and
+// variant_canonical3); the hash of a variant with at most two deletions is
+// the same either way.
+// MODE 0 writes every variant at its offset (and counts digits); MODE 1
+// writes nothing and only counts the first digit (the bin histogram of the
+// streamed search); MODE 2 keeps the variants whose bin (top STREAM_BIN_BITS
+// hash bits) lies in [blo, bhi) and appends them to the sharded output sout,
+// one reservation per wave, with the hash rotated left by the bin bits (the
+// bits that still tell variants of one column group apart move to the top).
+template <bool DISTINCT, bool K3, int MODE>
 __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ seq,
                                                        const uint64_t* __restrict__ voff,
                                                        uint64_t nseq, int k,
@@ -134,13 +198,17 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
                                                        uint32_t idbits, int npass, PassDigits pd,
                                                        uint32_t* __restrict__ hist,
                                                        uint32_t* __restrict__ tcounts,
-                                                       uint32_t spb) {
+                                                       uint32_t spb, ShardOut sout, uint32_t blo,
+                                                       uint32_t bhi) {
   constexpr int NWV = VG_NT / 64;
+  constexpr int PRE = K3 ? VG_PRE3 : VG_PRE;
   __shared__ uint64_t s_off[VG_SEQS + 1];
-  __shared__ uint64_t s_pre[VG_SEQS * VG_PRE];
+  __shared__ uint64_t s_pre[VG_SEQS * PRE];
   __shared__ uint64_t s_c[32];
   __shared__ uint32_t s_len[VG_SEQS];
   __shared__ uint32_t s_n1[VG_SEQS], s_n2[VG_SEQS];  // canonical-test masks
+  __shared__ uint32_t s_n3[K3 ? VG_SEQS : 1];
+  __shared__ uint16_t s_c3[K3 ? KEY_MAX_LEN + 1 : 1];
   __shared__ uint32_t s_roff[VG_SEQS + 1];            // block-local deletion-set prefix
   // the digit counts; until the prefix XORs are done, the same LDS holds
   // the hash's per-residue words
@@ -163,6 +231,7 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   if (tx < 32) s_b[tx] = ld_tab;
   else if (tx < 64) s_c[tx - 32] = ld_tab;
   if (tx < (uint32_t)VG_PAIRS / 2) reinterpret_cast<uint32_t*>(s_pairs)[tx] = ld_pair;
+  if (K3 && tx <= (uint32_t)KEY_MAX_LEN) s_c3[tx] = kTriTab.c3[tx];
   __syncthreads();
   // one thread per sequence: the prefix XORs P[t] of the position terms
   // rotr(B[s[i]], i), i < t, for t = 0 .. L + 2 (P[L + 1] = P[L + 2] = P[L],
@@ -171,9 +240,10 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   // (t = L - 2 or s[t] != s[t + 2])
   if (tx < ns) {
     const uint32_t L = key_len(key);
-    uint64_t* P = s_pre + tx * VG_PRE;
+    uint64_t* P = s_pre + tx * PRE;
     uint64_t acc = 0;
     uint32_t n1 = 0, n2 = 0, r1 = 0, r2 = 0;  // r1 = s[t - 1], r2 = s[t - 2]
+    uint32_t n3 = 0, r3 = 0;                  // r3 = s[t - 3]
     u128 kk = key << 8;                        // residue t at the top 5 bits
     P[0] = 0;
     for (uint32_t t = 0; t < L; ++t) {
@@ -184,17 +254,24 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
       if (DISTINCT) {
         if (t >= 1) n1 |= (uint32_t)(r1 != r) << (t - 1);
         if (t >= 2) n2 |= (uint32_t)(r2 != r) << (t - 2);
+        if (K3 && t >= 3) n3 |= (uint32_t)(r3 != r) << (t - 3);
+        r3 = r2;
         r2 = r1;
         r1 = r;
       }
     }
     P[L + 1] = acc;
     P[L + 2] = acc;
+    if (K3) P[L + 3] = acc;
     if (DISTINCT) {
       if (L >= 1) n1 |= 1u << (L - 1);
       if (L >= 2) n2 |= 1u << (L - 2);
       s_n1[tx] = n1;
       s_n2[tx] = n2;
+      if (K3) {  // bits p >= L - 3 hold no residue three places on
+        const uint32_t all = (1u << L) - 1u;
+        s_n3[tx] = n3 | (L >= 3 ? all & ~((1u << (L - 3)) - 1u) : all);
+      }
     }
     s_len[tx] = L;
   }
@@ -225,41 +302,82 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
     // (the pack kernel's count and the canonical test agree, so the bound
     // never drops a variant; it keeps any disagreement in range)
     if (keep && at + rank < end) {
-      out[at + rank] = e;
+      if constexpr (MODE == 0) out[at + rank] = e;
 #pragma unroll
       for (int q = 0; q < 3; ++q)
         if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e >> sh[q]) & mk[q])], 1u);
     }
   };
+  // MODE 2: one shard reservation for the wave's kept lanes (bal is the
+  // wave's ballot of keep, so every lane takes the same branch). A wave
+  // rotates over 16 shards, so the shards fill evenly even when there are
+  // fewer workgroups than shards.
+  uint32_t nres = 0;
+  auto put_sharded = [&](uint64_t e, bool keep, uint64_t bal) {
+    if (!bal) return;
+    const uint32_t sel = (blockIdx.x * NWV + w) * 16u + (nres++ & 15u);
+    uint64_t pos = 0, ob = 0;
+    if (lane == 0) {
+      const ShardResv r = shard_reserve(sout, sel, (uint64_t)__popcll(bal));
+      pos = r.pos;
+      ob = r.obase;
+    }
+    pos = __shfl(pos, 0, 64);
+    ob = __shfl(ob, 0, 64);
+    if (keep) shard_put(sout, sel, ShardResv{pos, ob}, mask_rank(bal), e);
+  };
+  // the element of a variant's hash h (MODE 2: rotated, and only inside the
+  // column group's bins)
+  auto element = [&](uint64_t h, uint64_t id, bool& valid) -> uint64_t {
+    if constexpr (MODE == 2) {
+      const uint32_t bin = (uint32_t)(h >> (64 - sd::STREAM_BIN_BITS));
+      valid = valid && bin >= blo && bin < bhi;
+      return (__builtin_rotateleft64(h, sd::STREAM_BIN_BITS) & ~idmask) | id;
+    }
+    return (h & ~idmask) | id;
+  };
   // what every variant of sequence x reads, loaded once per sequence: the
   // length, the extended canonical-test masks, the prefix-XOR row with its
   // entry P[L], and the length words C[L - d] for d = 0, 1, 2 deletions
   struct SeqVals {
-    uint32_t L, n1x, n2x;
+    uint32_t L, n1x, n2x, n3;
     const uint64_t* P;
-    uint64_t pl, c0, c1, c2, id;
+    uint64_t pl, c0, c1, c2, c3, id;
   };
   auto seq_vals = [&](uint32_t x) {
     SeqVals q;
     q.L = s_len[x];
-    q.P = s_pre + x * VG_PRE;
+    q.P = s_pre + x * PRE;
     q.pl = q.P[q.L];
     q.c0 = s_c[q.L];
     q.c1 = s_c[q.L >= 1 ? q.L - 1 : 0u];
     q.c2 = s_c[q.L >= 2 ? q.L - 2 : 0u];
-    q.n1x = q.n2x = 0;
+    q.c3 = K3 ? s_c[q.L >= 3 ? q.L - 3 : 0u] : 0;
+    q.n1x = q.n2x = q.n3 = 0;
     if (DISTINCT) canonical_ext_masks(s_n1[x], s_n2[x], q.L, q.n1x, q.n2x);
+    if (DISTINCT && K3) q.n3 = s_n3[x];
     q.id = s0 + x;
     return q;
   };
   auto variant = [&](SeqVals q, uint32_t v, bool valid, uint64_t& e) -> bool {
+    if constexpr (K3) {
+      uint32_t p1, p2, p3;
+      variant_positions3(s_pairs, s_c3, q.L, valid ? v : 0u, p1, p2, p3);
+      const uint64_t cm = p3 < q.L ? q.c3 : p2 < q.L ? q.c2 : p1 < q.L ? q.c1 : q.c0;
+      const uint64_t* P = q.P;
+      const uint64_t h = cm ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
+                         __builtin_rotateleft64(P[p3] ^ P[p2 + 1], 2) ^
+                         __builtin_rotateleft64(q.pl ^ P[p3 + 1], 3);
+      e = element(h, q.id, valid);
+      return valid && (!DISTINCT || variant_canonical3(q.n1x, q.n2x, q.n3, q.L, p1, p2, p3));
+    }
     uint32_t p1, p2;
     variant_positions(s_pairs, q.L, valid ? v : 0u, p1, p2);
     const uint64_t cm = p2 < q.L ? q.c2 : p1 < q.L ? q.c1 : q.c0;
     const uint64_t* P = q.P;
     const uint64_t h = cm ^ P[p1] ^ __builtin_rotateleft64(P[p2] ^ P[p1 + 1], 1) ^
                        __builtin_rotateleft64(q.pl ^ P[p2 + 1], 2);
-    e = (h & ~idmask) | q.id;
+    e = element(h, q.id, valid);
     return valid && (!DISTINCT || variant_canonical_ext(q.n1x, q.n2x, p1, p2));
   };
   const uint32_t xa = w * ns / NWV, xb = (w + 1) * ns / NWV;
@@ -280,7 +398,10 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           const uint64_t bal = __ballot(keep[u]);
-          emit(e[u], keep[u], at, mask_rank(bal), end_x);
+          if constexpr (MODE == 2)
+            put_sharded(e[u], keep[u], bal);
+          else
+            emit(e[u], keep[u], at, mask_rank(bal), end_x);
           at += (uint32_t)__popcll(bal);
         }
       }
@@ -303,10 +424,14 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
     uint64_t e;
     const bool keep = variant(seq_vals(lo), slot - s_roff[lo], valid, e);
     const uint64_t bal = __ballot(keep);
-    // rank among the kept lanes of the same sequence (a contiguous lane range)
-    const uint32_t zl = s_roff[lo] - s_roff[x];
-    const uint64_t mine = bal & ~((1ull << zl) - 1ull);
-    emit(e, keep, (uint32_t)(s_off[lo] - g0), mask_rank(mine), (uint32_t)(s_off[lo + 1] - g0));
+    if constexpr (MODE == 2) {
+      put_sharded(e, keep, bal);
+    } else {
+      // rank among the kept lanes of the same sequence (a contiguous lane range)
+      const uint32_t zl = s_roff[lo] - s_roff[x];
+      const uint64_t mine = bal & ~((1ull << zl) - 1ull);
+      emit(e, keep, (uint32_t)(s_off[lo] - g0), mask_rank(mine), (uint32_t)(s_off[lo + 1] - g0));
+    }
     x = y;
   }
   __syncthreads();
@@ -898,6 +1023,126 @@ __global__ __launch_bounds__(256) void k_emit_hash_runs(const uint64_t* __restri
   }
 }
 
+// ------------------------------------------------------------------ paired chains
+//
+// Paired-chain records (Discussion: the CDR3s of both chains of a receptor
+// joined by a token that is never deleted). A record (a, b) is the joined
+// string a T b of length La + 1 + Lb <= 49; its variants delete at most k of
+// the La + Lb residue positions and keep T, so two records within
+// Lev(a) + Lev(b) <= k share a variant (delete per chain as in the
+// single-chain argument). Variants are hashed like single chains (the same
+// rotation hash over the joined string, T as residue code 20) and written
+// with multiplicity at the record's offsets: a repeated variant of one record
+// only repeats a candidate, which the pair sort drops.
+constexpr uint32_t PAIR_TOKEN_CODE = 20;
+constexpr int PV_RECORDS = 64;  // records per generator workgroup
+
+__device__ __forceinline__ uint64_t choose2(uint64_t x) { return x * (x - 1) / 2; }
+__device__ __forceinline__ uint64_t choose3(uint64_t x) { return x * (x - 1) * (x - 2) / 6; }
+
+// Deletion sets of up to k of the D deletable positions, with multiplicity:
+// sum_{m <= k} C(D, m).
+__device__ __forceinline__ uint32_t paired_num_variants(uint32_t D, int k) {
+  uint32_t v = 1;
+  if (k >= 1) v += D;
+  if (k >= 2 && D >= 2) v += (uint32_t)choose2(D);
+  if (k >= 3 && D >= 3) v += (uint32_t)choose3(D);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_paired_count(const u128* __restrict__ sa,
+                                                      const u128* __restrict__ sb, uint64_t n,
+                                                      int k, uint32_t* __restrict__ vcnt) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) vcnt[i] = paired_num_variants(key_len(sa[i]) + key_len(sb[i]), k);
+}
+
+// The largest x with choose2(x) <= u (colexicographic unranking of a pair).
+__device__ __forceinline__ uint32_t colex2_top(uint64_t u) {
+  uint32_t x = (uint32_t)((1.0 + sqrt(1.0 + 8.0 * (double)u)) * 0.5);
+  while (x > 1 && choose2(x) > u) --x;
+  while (choose2(x + 1) <= u) ++x;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t colex3_top(uint64_t u) {
+  uint32_t x = (uint32_t)cbrt(6.0 * (double)u) + 1;
+  while (x > 2 && choose3(x) > u) --x;
+  while (choose3(x + 1) <= u) ++x;
+  return x;
+}
+
+// One thread per variant slot of the workgroup's records: unrank the
+// deletion set (none, one, pairs, then triples, each in colexicographic
+// order over the deletable positions), map deletable index x to joined
+// position x (< La) or x + 1, and hash the remaining joined string.
+__global__ __launch_bounds__(256) void k_vargen_paired(const u128* __restrict__ sa,
+                                                       const u128* __restrict__ sb,
+                                                       const uint64_t* __restrict__ voff,
+                                                       uint64_t n, int k, uint32_t idbits,
+                                                       uint64_t* __restrict__ elem) {
+  __shared__ uint64_t s_off[PV_RECORDS + 1];
+  __shared__ u128 s_a[PV_RECORDS], s_b[PV_RECORDS];
+  __shared__ uint64_t s_hb[32], s_hc[64];
+  const uint64_t r0 = (uint64_t)blockIdx.x * PV_RECORDS;
+  const uint32_t nr = (uint32_t)min<uint64_t>(PV_RECORDS, n - r0);
+  for (uint32_t x = threadIdx.x; x <= nr; x += 256) s_off[x] = voff[r0 + x];
+  for (uint32_t x = threadIdx.x; x < nr; x += 256) {
+    s_a[x] = sa[r0 + x];
+    s_b[x] = sb[r0 + x];
+  }
+  if (threadIdx.x < 32) s_hb[threadIdx.x] = kHashTab.b[threadIdx.x];
+  if (threadIdx.x < 64) s_hc[threadIdx.x] = kHashTab.c[threadIdx.x];
+  __syncthreads();
+  const uint64_t idmask = (1ull << idbits) - 1;
+  const uint64_t g0 = s_off[0], g1 = s_off[nr];
+  for (uint64_t g = g0 + threadIdx.x; g < g1; g += 256) {
+    uint32_t lo = 0, hi = nr - 1;  // the last record with s_off[x] <= g
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= g)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const u128 a = s_a[lo], b = s_b[lo];
+    const uint32_t la = key_len(a), lb = key_len(b), D = la + lb;
+    uint64_t v = g - s_off[lo];
+    uint32_t del[3] = {64, 64, 64};  // deletable indices, ascending
+    uint32_t m = 0;
+    if (v == 0) {
+      m = 0;
+    } else if (v <= D) {
+      m = 1;
+      del[0] = (uint32_t)(v - 1);
+    } else if (v <= D + choose2(D)) {
+      m = 2;
+      const uint64_t u = v - 1 - D;
+      del[1] = colex2_top(u);
+      del[0] = (uint32_t)(u - choose2(del[1]));
+    } else {
+      m = 3;
+      const uint64_t u = v - 1 - D - choose2(D);
+      del[2] = colex3_top(u);
+      const uint64_t r = u - choose3(del[2]);
+      del[1] = colex2_top(r);
+      del[0] = (uint32_t)(r - choose2(del[1]));
+    }
+    uint64_t gone = 0;  // joined positions deleted
+    for (uint32_t q = 0; q < m; ++q) gone |= 1ull << (del[q] < la ? del[q] : del[q] + 1);
+    uint64_t h = s_hc[la + lb + 1 - m];
+    uint32_t j = 0;
+    for (uint32_t t = 0; t <= D; ++t) {
+      if ((gone >> t) & 1u) continue;
+      const uint32_t r = t < la ? key_residue(a, (int)t)
+                                : t == la ? PAIR_TOKEN_CODE : key_residue(b, (int)(t - la - 1));
+      h ^= __builtin_rotateright64(s_hb[r], j);
+      ++j;
+    }
+    elem[g] = (h & ~idmask) | (r0 + lo);
+  }
+}
+
 }  // namespace sdk
 
 namespace sd {
@@ -915,12 +1160,80 @@ void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, in
     pd.mask[q] = q < npass ? masks[q] : 0;
   }
   const unsigned g = (unsigned)((nseq + seqs_per_block - 1) / seqs_per_block);
-  if (distinct)
-    hipLaunchKernelGGL(sdk::k_vargen_hash<true>, dim3(g), dim3(sdk::VG_NT), 0, s, seq, voff, nseq,
-                       k, elem, idbits, npass, pd, hist, npass ? tcounts : nullptr, seqs_per_block);
+  if (k > 3) throw Error{SD_E_INVAL, "internal error: at most three deletions"};
+  uint32_t* tc = npass ? tcounts : nullptr;
+  const ShardOut none{nullptr, 0, nullptr, 0, nullptr};
+  if (distinct && k == 3)
+    hipLaunchKernelGGL((sdk::k_vargen_hash<true, true, 0>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
+                       voff, nseq, k, elem, idbits, npass, pd, hist, tc, seqs_per_block, none, 0u,
+                       0u);
+  else if (distinct)
+    hipLaunchKernelGGL((sdk::k_vargen_hash<true, false, 0>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
+                       voff, nseq, k, elem, idbits, npass, pd, hist, tc, seqs_per_block, none, 0u,
+                       0u);
+  else if (k == 3)
+    hipLaunchKernelGGL((sdk::k_vargen_hash<false, true, 0>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
+                       voff, nseq, k, elem, idbits, npass, pd, hist, tc, seqs_per_block, none, 0u,
+                       0u);
   else
-    hipLaunchKernelGGL(sdk::k_vargen_hash<false>, dim3(g), dim3(sdk::VG_NT), 0, s, seq, voff, nseq,
-                       k, elem, idbits, npass, pd, hist, npass ? tcounts : nullptr, seqs_per_block);
+    hipLaunchKernelGGL((sdk::k_vargen_hash<false, false, 0>), dim3(g), dim3(sdk::VG_NT), 0, s,
+                       seq, voff, nseq, k, elem, idbits, npass, pd, hist, tc, seqs_per_block, none,
+                       0u, 0u);
+}
+
+void launch_vargen_bins(const u128* seq, const uint64_t* voff, uint64_t nseq, int k,
+                        uint32_t idbits, uint32_t* hist, uint32_t seqs_per_block, hipStream_t s) {
+  if (!nseq) return;
+  if (seqs_per_block < 1 || seqs_per_block > (uint32_t)sdk::VG_SEQS || k > 3)
+    throw Error{SD_E_INVAL, "internal error: generator shape out of range"};
+  sdk::PassDigits pd{};
+  pd.shift[0] = 64 - STREAM_BIN_BITS;
+  pd.mask[0] = (1u << STREAM_BIN_BITS) - 1u;
+  const unsigned g = (unsigned)((nseq + seqs_per_block - 1) / seqs_per_block);
+  const ShardOut none{nullptr, 0, nullptr, 0, nullptr};
+  if (k == 3)
+    hipLaunchKernelGGL((sdk::k_vargen_hash<true, true, 1>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
+                       voff, nseq, k, nullptr, idbits, 1, pd, hist, nullptr, seqs_per_block, none,
+                       0u, 0u);
+  else
+    hipLaunchKernelGGL((sdk::k_vargen_hash<true, false, 1>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
+                       voff, nseq, k, nullptr, idbits, 1, pd, hist, nullptr, seqs_per_block, none,
+                       0u, 0u);
+}
+
+void launch_paired_count(const u128* sa, const u128* sb, uint64_t n, int k, uint32_t* vcnt,
+                         hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(sdk::k_paired_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sa,
+                     sb, n, k, vcnt);
+}
+
+void launch_vargen_paired(const u128* sa, const u128* sb, const uint64_t* voff, uint64_t n, int k,
+                          uint32_t idbits, uint64_t* elem, hipStream_t s) {
+  if (!n) return;
+  if (k > 3) throw Error{SD_E_INVAL, "internal error: at most three deletions"};
+  const unsigned g = (unsigned)((n + sdk::PV_RECORDS - 1) / sdk::PV_RECORDS);
+  hipLaunchKernelGGL(sdk::k_vargen_paired, dim3(g), dim3(256), 0, s, sa, sb, voff, n, k, idbits,
+                     elem);
+}
+
+void launch_vargen_stream(const u128* seq, const uint64_t* voff, uint64_t nseq, int k,
+                          uint32_t idbits, uint32_t blo, uint32_t bhi, const ShardArgs& a,
+                          uint32_t seqs_per_block, hipStream_t s) {
+  if (!nseq) return;
+  if (seqs_per_block < 1 || seqs_per_block > (uint32_t)sdk::VG_SEQS || k > 3)
+    throw Error{SD_E_INVAL, "internal error: generator shape out of range"};
+  const sdk::PassDigits pd{};
+  const unsigned g = (unsigned)((nseq + seqs_per_block - 1) / seqs_per_block);
+  const ShardOut out{a.base, a.region, a.over, a.over_cap, a.counter};
+  if (k == 3)
+    hipLaunchKernelGGL((sdk::k_vargen_hash<true, true, 2>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
+                       voff, nseq, k, nullptr, idbits, 0, pd, nullptr, nullptr, seqs_per_block, out,
+                       blo, bhi);
+  else
+    hipLaunchKernelGGL((sdk::k_vargen_hash<true, false, 2>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
+                       voff, nseq, k, nullptr, idbits, 0, pd, nullptr, nullptr, seqs_per_block, out,
+                       blo, bhi);
 }
 
 void launch_hist_rows(const uint32_t* tcounts, uint64_t nseq, uint32_t seqs_per_block, int npass,

@@ -133,6 +133,9 @@ Cands oversized_group(Call& cl, const uint64_t* E, const uint64_t* big, uint64_t
   return out;
 }
 
+Cands group_segments(Call& cl, const uint64_t* E, uint32_t nk, int cap, int bits,
+                     uint32_t idbits);
+
 // Hashed grouping: elements [hash | id], LSD passes over the top `bits` hash
 // bits, grouping of each segment by its full hash in LDS.
 Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, int k, uint32_t nk,
@@ -198,7 +201,17 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
   }
   passes_out = (int)digits.size();
   const uint64_t* E = flip ? e2 : e1;
+  return group_segments(cl, E, nk, cap, bits, idbits);
+}
 
+// Grouping of elements sorted by their top `bits` bits: the segment table,
+// then one workgroup per run of segments groups each by the full stored hash
+// in LDS and emits the id pairs of every group; ranges too large for LDS are
+// sorted by the full hash and emitted by runs.
+Cands group_segments(Call& cl, const uint64_t* E, uint32_t nk, int cap, int bits,
+                     uint32_t idbits) {
+  sd_ctx* c = cl.c;
+  hipStream_t s = cl.s;
   // segment table, then one workgroup per `spw` segment values
   const uint32_t nseg = 1u << bits;
   const uint32_t segshift = 64u - (uint32_t)bits;
@@ -280,9 +293,319 @@ void hashed_plan(const sd_ctx* c, uint64_t nk, int* cap, int* bits) {
   *bits = b;
 }
 
+namespace {
+
+// Steps 6-7 on a candidate array: sort the (i << 32 | j) candidates over the
+// digits that can differ, then drop repeats, keep the pairs within k and
+// compact them in order. n is the number of sequences (ids are below n).
+struct Verified {
+  uint32_t* i = nullptr;
+  uint32_t* j = nullptr;
+  uint8_t* d = nullptr;
+  uint64_t n = 0;
+};
+
+Verified sort_and_verify(Call& cl, uint64_t* cand, uint64_t nc, uint64_t n, int k, const u128* seq,
+                         const u128* planes, const u128* seq2 = nullptr,
+                         const u128* planes2 = nullptr) {
+  sd_ctx* c = cl.c;
+  hipStream_t s = cl.s;
+  if (nc >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "more than 2^32 - 2 candidate pairs"};
+  // 6: sort candidate pairs (only the digits that can differ)
+  uint64_t* cand2 = cl.sc.get<uint64_t>(nc);
+  const uint64_t* sorted = cand;
+  if (nc > 1) {
+    const int nb = bits_for(n - 1);
+    std::vector<Digit> pd;
+    for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(Digit{0, 8 * q, 255u});
+    for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(Digit{0, 32 + 8 * q, 255u});
+    bool pflip;
+    if (pair_sort_counted(c, nc)) {
+      // large: counted passes over fixed tiles
+      pflip = counted_sort(cl, cand, cand2, (uint32_t)nc, pd);
+      cl.tm.mark("pair_sort", (double)nc * 24 * pd.size(), 4 * (int)pd.size());
+    } else {
+      // small: one histogram, then onesweep passes (fewer launches)
+      std::vector<const uint32_t*> ph;
+      uint32_t* phist = cl.sc.get<uint32_t>(8 * 256);
+      launch_fill_u32(phist, 0, 8 * 256, s);
+      launch_radix_hist(cand, nullptr, 1, nc, phist, s);
+      for (const Digit& d : pd) ph.push_back(phist + (d.shift / 8) * 256);
+      pflip = radix_sort(cl, cand, nullptr, nullptr, cand2, nullptr, nullptr, 1, false,
+                         (uint32_t)nc, pd, ph);
+      cl.tm.mark("pair_sort", (double)nc * 8 + (double)nc * 16 * pd.size(), 2 + (int)pd.size());
+    }
+    sorted = pflip ? cand2 : cand;
+  } else {
+    cl.tm.mark("pair_sort", 0, 0);
+  }
+
+  // 7: verify and compact
+  Verified v;
+  v.i = dalloc_t<uint32_t>(c, nc);
+  v.j = dalloc_t<uint32_t>(c, nc);
+  v.d = dalloc_t<uint8_t>(c, nc);
+  try {
+    unsigned long long* pcount = reinterpret_cast<unsigned long long*>(cl.counters + CNT_PAIRS);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(pcount), 0, 1, s);
+    if (nc) {
+      const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
+      const uint32_t epoch = next_epoch(c, tiles, s);
+      launch_verify_compact(sorted, nc, c->metric == SD_METRIC_HAMMING ? seq : planes, seq, k,
+                            c->metric, 1, v.i, v.j, v.d, c->status, cl.tile_counter(), epoch,
+                            pcount, cl.lb_err(), s, planes2, seq2);
+      cl.tm.mark("verify", (double)nc * (8 + 32) + (double)nc * 9, 1);
+    } else {
+      cl.tm.mark("verify", 0, 0);
+    }
+    const uint32_t* h = static_cast<const uint32_t*>(readback(c, cl.counters + CNT_PAIRS, 12, s));
+    uint64_t cnt;
+    std::memcpy(&cnt, h, 8);
+    if (h[2] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
+    if (h[2] & SD_ERRBIT_PLACEMENT) throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
+    v.n = nc ? cnt : 0;
+  } catch (...) {
+    dfree(c, v.i);
+    dfree(c, v.j);
+    dfree(c, v.d);
+    throw;
+  }
+  return v;
+}
+
+// Device bytes per element of a column group at its peak (the sharded
+// generation output and the gathered elements; later, the two sort buffers,
+// tile counts and candidates), and per sequence for what the streamed search
+// keeps throughout (packed keys, bit planes, counts, offsets, pairs found).
+constexpr uint64_t kStreamBytesPerElem = 24;
+constexpr uint64_t kStreamBytesPerSeq = 64;
+
+// Elements per column group of a streamed search, or 0 to search in memory:
+// SD_OPT_STREAM 1 never streams, 2 always does; automatically, a search
+// streams when its variants exceed what 32-bit element counts address or what
+// the in-memory path (two 8-byte element buffers, tile counts and candidates:
+// about 18 bytes per variant) would need beyond the context's budget.
+uint64_t stream_group_elems(const sd_ctx* c, uint64_t n, uint64_t nkeys) {
+  if (c->stream == 1 || c->path == 1) {
+    if (nkeys >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "more than 2^32 - 2 deletion variants"};
+    return 0;
+  }
+  const uint64_t fixed = kStreamBytesPerSeq * n + (1ull << 20);
+  const bool too_many = nkeys >= 0xFFFFFFFFull;
+  const bool over_budget = c->budget && fixed + 18 * nkeys > c->budget;
+  if (c->stream != 2 && !too_many && !over_budget) return 0;
+  uint64_t cap = c->stream_elems;
+  if (!cap) {
+    uint64_t avail = 0;
+    if (c->budget) {
+      avail = c->budget > fixed ? c->budget - fixed : 0;
+    } else {
+      size_t fr = 0, tot = 0;
+      hip_check(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+      avail = (uint64_t)fr / 10 * 8;
+    }
+    cap = avail / kStreamBytesPerElem;
+  }
+  cap = std::min<uint64_t>(cap, 0xFFFFFFFEull);
+  if (cap < 4096) throw Error{SD_E_NOMEM, "the device memory budget leaves no room for a column group"};
+  return cap;
+}
+
+// Streamed self search (Section II C, "Overcoming memory bottlenecks", and
+// the XTNeighbor-Streaming steps of Appendix A), for variant sets larger than
+// device memory or the budget allows. The variant space is cut into
+// 2^STREAM_BIN_BITS bins by the top bits of the variant hash; equal variants
+// share a bin, so every group of equal variants lies in one bin. A first
+// generator pass only counts each bin's variants; Next-Fit packing then
+// forms column groups of consecutive bins that fit the per-group capacity
+// (order-preserving, as in the paper). Each column group is one pass: the
+// generator runs over every sequence again and keeps the group's variants
+// (the paper's 2-D buffer read column-wise: rows are the generator
+// workgroups' sequence ranges, columns the bins), and the in-memory path's
+// grouping, pair sort and verification run on them alone. A pair can share
+// variants in several groups, so the pairs of all groups are sorted, made
+// unique and verified once more at the end (the paper's cross-chunk
+// duplicate removal, bounded by the pairs instead of the candidates).
+Verified streamed_search(Call& cl, const u128* seq, const u128* planes, const uint64_t* voff,
+                         uint64_t n, int k, uint64_t nkeys, uint64_t cap) {
+  sd_ctx* c = cl.c;
+  hipStream_t s = cl.s;
+  const uint32_t idbits = n <= (1ull << 24) ? 24u : 32u;
+  const uint32_t spb = vargen_seqs_per_tile(n, nkeys);
+  constexpr uint32_t NBINS = 1u << STREAM_BIN_BITS;
+  uint32_t* bins = cl.sc.get<uint32_t>(NBINS);
+  launch_fill_u32(bins, 0, NBINS, s);
+  launch_vargen_bins(seq, voff, n, k, idbits, bins, spb, s);
+  cl.tm.mark("stream_bins", (double)n * 24, 1);
+  std::vector<uint64_t> cnt(NBINS);
+  {
+    const uint32_t* h = static_cast<const uint32_t*>(readback(c, bins, NBINS * 4, s));
+    for (uint32_t b = 0; b < NBINS; ++b) cnt[b] = h[b];
+  }
+  // Next-Fit: consecutive bins while they fit the capacity
+  struct Group {
+    uint32_t lo, hi;
+    uint64_t n;
+  };
+  std::vector<Group> groups;
+  for (uint32_t b = 0; b < NBINS; ++b) {
+    if (cnt[b] > cap)
+      throw Error{SD_E_NOMEM, "a hash bin of " + std::to_string(cnt[b]) +
+                                  " variants exceeds the column-group capacity of " +
+                                  std::to_string(cap) + " (raise the device memory budget)"};
+    if (!cnt[b]) continue;
+    if (groups.empty() || groups.back().n + cnt[b] > cap)
+      groups.push_back(Group{b, b + 1, cnt[b]});
+    else {
+      groups.back().hi = b + 1;
+      groups.back().n += cnt[b];
+    }
+  }
+  c->stats.n_stream_groups = (int64_t)groups.size();
+  // the verified pairs of every group, as (i << 32 | j), appended in turn
+  std::vector<std::pair<uint64_t*, uint64_t>> found;
+  uint64_t nfound = 0;
+  int passes = 0;
+  uint64_t raw = 0;
+  try {
+    for (const Group& g : groups) {
+      Scratch gsc(c);
+      Call gcl{c, s, gsc, cl.tm, cl.counters};
+      // the column group's elements, gathered into one array
+      Cands E;
+      {
+        Scratch shard_sc(c);  // the shard regions are given back after the gather
+        Call scl{c, s, shard_sc, cl.tm, cl.counters};
+        E = sharded_output(
+            scl, g.n, "stream_gen",
+            [&](const ShardArgs& a) {
+              launch_vargen_stream(seq, voff, n, k, idbits, g.lo, g.hi, a, spb, s);
+            },
+            [&](uint64_t m) { return (double)n * 24 + (double)m * 8; });
+      }
+      gsc.blocks.push_back(E.p);
+      if (E.n != g.n) throw Error{SD_E_HIP, "internal error: a column group lost variants"};
+      const uint32_t ng = (uint32_t)E.n;
+      int gcap, bits;
+      hashed_plan(c, ng, &gcap, &bits);
+      const std::vector<Digit> digits = bits ? top_digits(64 - bits) : std::vector<Digit>();
+      uint64_t* e2 = gsc.get<uint64_t>(ng);
+      const bool flip = digits.empty() ? false : counted_sort(gcl, E.p, e2, ng, digits);
+      cl.tm.mark("hash_passes", (double)ng * 24 * digits.size(), 4 * (int)digits.size());
+      passes += (int)digits.size();
+      Cands cand = group_segments(gcl, flip ? e2 : E.p, ng, gcap, bits, idbits);
+      gsc.blocks.push_back(cand.p);
+      raw += cand.n;
+      const Verified v = sort_and_verify(gcl, cand.p, cand.n, n, k, seq, planes);
+      gsc.blocks.push_back(v.i);
+      gsc.blocks.push_back(v.j);
+      gsc.blocks.push_back(v.d);
+      uint64_t* ij = dalloc_t<uint64_t>(c, v.n);
+      found.push_back({ij, v.n});
+      launch_join_pairs(v.i, v.j, v.n, ij, s);
+      nfound += v.n;
+    }
+    c->stats.n_sort_passes = passes;
+    c->stats.n_cand_raw = (int64_t)raw;
+    // all groups' pairs: one array, then the cross-group duplicates go
+    uint64_t* all = cl.sc.get<uint64_t>(nfound);
+    uint64_t at = 0;
+    for (auto& f : found) {
+      if (f.second)
+        hip_check(hipMemcpyAsync(all + at, f.first, f.second * 8, hipMemcpyDeviceToDevice, s),
+                  "merge pairs");
+      at += f.second;
+      dfree(c, f.first);
+      f.first = nullptr;
+    }
+    return sort_and_verify(cl, all, nfound, n, k, seq, planes);
+  } catch (...) {
+    for (auto& f : found) dfree(c, f.first);
+    throw;
+  }
+}
+
+}  // namespace
+
+// Paired-chain self search (Discussion: the two chains of a receptor joined
+// by a token that is never deleted): every pair of records i < j with
+// Lev(a_i, a_j) + Lev(b_i, b_j) <= k. Both chains are packed and validated
+// as single chains; the variants of the joined strings go through the hashed
+// grouping, the pair sort and a verification that sums both chains'
+// distances.
+void paired_self_search(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, int k, sd_pairs* out,
+                        hipStream_t s) {
+  check_seqs(a);
+  check_seqs(b);
+  if (a->n != b->n) throw Error{SD_E_INVAL, "both chains must hold the same number of records"};
+  if (k < 0 || k > 3) throw Error{SD_E_INVAL, "k must be 0, 1, 2 or 3"};
+  c->stats = sd_stats{};
+  c->stats.n_seqs = a->n;
+  if (a->n == 0) return;
+  Scratch sc(c);
+  StageTimer tm(c, s);
+  const DevSeqs ia = stage_seqs(c, sc, a, s);
+  const DevSeqs ib = stage_seqs(c, sc, b, s);
+  const uint64_t n = ia.n;
+  Call cl{c, s, sc, tm, fresh_counters(c, CNT_TOTAL, s)};
+  uint32_t* counters = cl.counters;
+  u128* sa = sc.get<u128>(n);
+  u128* pa = sc.get<u128>(n);
+  u128* sb = sc.get<u128>(n);
+  u128* pb = sc.get<u128>(n);
+  uint32_t* vcnt = sc.get<uint32_t>(n);
+  uint64_t* voff = sc.get<uint64_t>(n + 1);
+  launch_pack(ia.codes, ia.offs, n, 0, false, sa, pa, nullptr, counters + CNT_ERR, s);
+  launch_pack(ib.codes, ib.offs, n, 0, false, sb, pb, nullptr, counters + CNT_ERR, s);
+  launch_paired_count(sa, sb, n, k, vcnt, s);
+  {
+    const uint64_t tiles = (n + scan_tile() - 1) / scan_tile();
+    const uint32_t epoch = next_epoch(c, tiles, s);
+    launch_scan_excl(vcnt, voff, n, c->status, cl.tile_counter(), epoch, cl.lb_err(), s);
+  }
+  tm.mark("pack_scan", (double)n * 2 * (16 + 16 + 16 + 8) + (double)n * 12, 4);
+  uint64_t nkeys;
+  {
+    hip_check(hipMemcpyAsync(counters + CNT_NKEYS, voff + n, 8, hipMemcpyDeviceToDevice, s), "copy");
+    const uint32_t* h = static_cast<const uint32_t*>(readback(c, counters, (CNT_NKEYS + 2) * 4, s));
+    raise_validation(h[CNT_ERR]);
+    std::memcpy(&nkeys, h + CNT_NKEYS, 8);
+  }
+  if (nkeys >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "more than 2^32 - 2 deletion variants"};
+  c->stats.n_keys = (int64_t)nkeys;
+  const uint32_t nk = (uint32_t)nkeys;
+  const uint32_t idbits = n <= (1ull << 24) ? 24u : 32u;
+  uint64_t* e1 = sc.get<uint64_t>(nk);
+  uint64_t* e2 = sc.get<uint64_t>(nk);
+  launch_vargen_paired(sa, sb, voff, n, k, idbits, e1, s);
+  tm.mark("vargen_paired", (double)nk * 8 + (double)n * 40, 1);
+  int cap, bits;
+  hashed_plan(c, nk, &cap, &bits);
+  const std::vector<Digit> digits = bits ? top_digits(64 - bits) : std::vector<Digit>();
+  const bool flip = digits.empty() ? false : counted_sort(cl, e1, e2, nk, digits);
+  tm.mark("hash_passes", (double)nk * 24 * digits.size(), 4 * (int)digits.size());
+  c->stats.n_sort_passes = (int)digits.size();
+  Cands cand = group_segments(cl, flip ? e2 : e1, nk, cap, bits, idbits);
+  sc.blocks.push_back(cand.p);
+  c->stats.n_cand_raw = (int64_t)cand.n;
+  const Verified v = sort_and_verify(cl, cand.p, cand.n, n, k, sa, pa, sb, pb);
+  try {
+    tm.finish();
+  } catch (...) {
+    dfree(c, v.i);
+    dfree(c, v.j);
+    dfree(c, v.d);
+    throw;
+  }
+  c->stats.n_pairs = (int64_t)v.n;
+  finish_output(c, v.i, v.j, v.d, v.n, out, s);
+}
+
 void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream_t s) {
   check_seqs(seqs);
-  if (k < 0 || k > 2) throw Error{SD_E_INVAL, "k must be 0, 1 or 2"};
+  if (k < 0 || k > 3) throw Error{SD_E_INVAL, "k must be 0, 1, 2 or 3"};
+  if (k == 3 && c->path == 1)
+    throw Error{SD_E_INVAL, "k = 3 runs on the hashed grouping path only (SD_OPT_PATH 0 or 2)"};
   c->stats = sd_stats{};
   c->stats.n_seqs = seqs->n;
   if (seqs->n == 0) return;
@@ -314,90 +637,43 @@ void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream
     raise_validation(h[CNT_ERR]);
     std::memcpy(&nkeys, h + CNT_NKEYS, 8);
   }
-  if (nkeys >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "more than 2^32 - 2 deletion variants"};
   c->stats.n_keys = (int64_t)nkeys;
-  const uint32_t nk = (uint32_t)nkeys;
 
-  // 3-5: grouping and in-group emission
-  Cands cand;
-  int passes = 0;
-  if (c->path == 1) {
-    uint64_t* klo = sc.get<uint64_t>(nk);
-    uint64_t* khi = sc.get<uint64_t>(nk);
-    uint32_t* kid = sc.get<uint32_t>(nk);
-    launch_vargen(seq, voff, n, k, klo, khi, kid, s);
-    tm.mark("vargen", (double)nk * 20 + (double)n * 24, 1);
-    cand = fullkey_group(cl, klo, khi, kid, nk, passes);
+  Verified v;
+  const uint64_t group_elems = stream_group_elems(c, n, nkeys);
+  if (group_elems) {
+    v = streamed_search(cl, seq, planes, voff, n, k, nkeys, group_elems);
   } else {
-    cand = hashed_group(cl, seq, voff, n, k, nk, passes);
-  }
-  sc.blocks.push_back(cand.p);
-  c->stats.n_sort_passes = passes;
-  const uint64_t nc = cand.n;
-  c->stats.n_cand_raw = (int64_t)nc;
-  if (nc >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "more than 2^32 - 2 candidate pairs"};
-
-  // 6: sort candidate pairs (only the digits that can differ)
-  uint64_t* cand2 = sc.get<uint64_t>(nc);
-  const uint64_t* sorted = cand.p;
-  if (nc > 1) {
-    const int nb = bits_for(n - 1);
-    std::vector<Digit> pd;
-    for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(Digit{0, 8 * q, 255u});
-    for (int q = 0; q < (nb + 7) / 8; ++q) pd.push_back(Digit{0, 32 + 8 * q, 255u});
-    bool pflip;
-    if (pair_sort_counted(c, nc)) {
-      // large: counted passes over fixed tiles
-      pflip = counted_sort(cl, cand.p, cand2, (uint32_t)nc, pd);
-      tm.mark("pair_sort", (double)nc * 24 * pd.size(), 4 * (int)pd.size());
+    // 3-5: grouping and in-group emission
+    const uint32_t nk = (uint32_t)nkeys;
+    Cands cand;
+    int passes = 0;
+    if (c->path == 1) {
+      uint64_t* klo = sc.get<uint64_t>(nk);
+      uint64_t* khi = sc.get<uint64_t>(nk);
+      uint32_t* kid = sc.get<uint32_t>(nk);
+      launch_vargen(seq, voff, n, k, klo, khi, kid, s);
+      tm.mark("vargen", (double)nk * 20 + (double)n * 24, 1);
+      cand = fullkey_group(cl, klo, khi, kid, nk, passes);
     } else {
-      // small: one histogram, then onesweep passes (fewer launches)
-      std::vector<const uint32_t*> ph;
-      uint32_t* phist = sc.get<uint32_t>(8 * 256);
-      launch_fill_u32(phist, 0, 8 * 256, s);
-      launch_radix_hist(cand.p, nullptr, 1, nc, phist, s);
-      for (const Digit& d : pd) ph.push_back(phist + (d.shift / 8) * 256);
-      pflip = radix_sort(cl, cand.p, nullptr, nullptr, cand2, nullptr, nullptr, 1, false,
-                         (uint32_t)nc, pd, ph);
-      tm.mark("pair_sort", (double)nc * 8 + (double)nc * 16 * pd.size(), 2 + (int)pd.size());
+      cand = hashed_group(cl, seq, voff, n, k, nk, passes);
     }
-    sorted = pflip ? cand2 : cand.p;
-  } else {
-    tm.mark("pair_sort", 0, 0);
+    sc.blocks.push_back(cand.p);
+    c->stats.n_sort_passes = passes;
+    c->stats.n_cand_raw = (int64_t)cand.n;
+    // 6-7: pair sort, verification
+    v = sort_and_verify(cl, cand.p, cand.n, n, k, seq, planes);
   }
-
-  // 7: verify and compact
-  uint32_t* oi = dalloc_t<uint32_t>(c, nc);
-  uint32_t* oj = dalloc_t<uint32_t>(c, nc);
-  uint8_t* od = dalloc_t<uint8_t>(c, nc);
-  uint64_t npairs = 0;
   try {
-    unsigned long long* pcount = reinterpret_cast<unsigned long long*>(counters + CNT_PAIRS);
-    if (nc) {
-      const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
-      const uint32_t epoch = next_epoch(c, tiles, s);
-      launch_verify_compact(sorted, nc, c->metric == SD_METRIC_HAMMING ? seq : planes, seq, k,
-                            c->metric, oi, oj, od, c->status, cl.tile_counter(),
-                            epoch, pcount, cl.lb_err(), s);
-      tm.mark("verify", (double)nc * (8 + 32) + (double)nc * 9, 1);
-    } else {
-      tm.mark("verify", 0, 0);
-    }
-    const uint32_t* h = static_cast<const uint32_t*>(readback(c, counters + CNT_PAIRS, 12, s));
-    uint64_t cnt;
-    std::memcpy(&cnt, h, 8);
-    if (h[2] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
-    if (h[2] & SD_ERRBIT_PLACEMENT) throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
-    npairs = nc ? cnt : 0;
     tm.finish();
   } catch (...) {
-    dfree(c, oi);
-    dfree(c, oj);
-    dfree(c, od);
+    dfree(c, v.i);
+    dfree(c, v.j);
+    dfree(c, v.d);
     throw;
   }
-  c->stats.n_pairs = (int64_t)npairs;
-  finish_output(c, oi, oj, od, npairs, out, s);
+  c->stats.n_pairs = (int64_t)v.n;
+  finish_output(c, v.i, v.j, v.d, v.n, out, s);
 }
 
 void finish_output(sd_ctx* c, uint32_t* oi, uint32_t* oj, uint8_t* od, uint64_t npairs,

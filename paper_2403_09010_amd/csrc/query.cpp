@@ -197,7 +197,7 @@ TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint6
         const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
         const uint32_t epoch = next_epoch(c, tiles, s);
         launch_verify_compact(sorted, nc, c->metric == SD_METRIC_HAMMING ? qseq : qplanes, rseq, k,
-                              c->metric, out.i, out.j, out.d, c->status,
+                              c->metric, 0, out.i, out.j, out.d, c->status,
                               cl.tile_counter(), epoch, pcount, cl.lb_err(), s);
       }
     }
@@ -228,7 +228,7 @@ void index_free(sd_index* idx) {
 
 sd_index* index_build(sd_ctx* c, const sd_seqs* ref, int k, hipStream_t s) {
   check_seqs(ref);
-  if (k < 0 || k > 2) throw Error{SD_E_INVAL, "k must be 0, 1 or 2"};
+  if (k < 0 || k > 3) throw Error{SD_E_INVAL, "k must be 0, 1, 2 or 3"};
   sd_index* idx = new sd_index();
   idx->device = c->device;
   idx->k = k;

@@ -41,6 +41,7 @@ __host__ __device__ __forceinline__ uint32_t num_variants(uint32_t L, int k) {
   uint32_t v = 1;
   if (k >= 1 && L >= 1) v += L;
   if (k >= 2 && L >= 2) v += L * (L - 1) / 2;
+  if (k >= 3 && L >= 3) v += L * (L - 1) * (L - 2) / 6;
   return v;
 }
 
@@ -111,6 +112,51 @@ __device__ __forceinline__ void canonical_masks(const uint32_t (&pl)[5], uint32_
   }
   n1 = (d1 & ((1u << (L - 1)) - 1u)) | (1u << (L - 1));
   n2 = L >= 2 ? (d2 & ((1u << (L - 2)) - 1u)) | (1u << (L - 2)) : 0u;
+}
+
+// Three deletions (k = 3). In general D is D* iff every deleted position p
+// whose next kept position q(p) exists holds a different residue than q(p)
+// (greedy reaches p with everything before matched and would match s[p]
+// where t continues with s[q(p)]). For |D| <= 3, q(p) - p is 1, 2 or 3, so a
+// third mask n3 bit p = (p >= L - 3 or s[p] != s[p + 3]) completes the test.
+// Sets are taken as padded triples p1 < p2 < p3 (a pair is (p1, p2, L), one
+// deletion (p1, L, L + 1), none (L, L + 1, L + 2)); n1x and n2x are the
+// extended masks of canonical_ext_masks.
+__device__ __forceinline__ bool variant_canonical3(uint32_t n1x, uint32_t n2x, uint32_t n3,
+                                                   uint32_t L, uint32_t p1, uint32_t p2,
+                                                   uint32_t p3) {
+  const bool run3 = p3 < L && p3 == p2 + 1;  // p2 and p3 both deleted, adjacent
+  const bool c3 = p3 >= L || ((n1x >> p3) & 1u);
+  const bool c2 = p2 >= L || (((run3 ? n2x : n1x) >> p2) & 1u);
+  const uint32_t m1 = p2 > p1 + 1 ? n1x : (p2 < L && run3) ? n3 : n2x;
+  const bool c1 = p1 >= L || ((m1 >> p1) & 1u);
+  return c1 && c2 && c3;
+}
+
+// Canonical sets of exactly three deletions, in O(L^2) from the masks: for
+// every canonical last two deletions (p2, p3), first deletions p1 <= p2 - 2
+// need n1, and p1 = p2 - 1 needs n2 (p3 > p2 + 1) or n3 (p3 = p2 + 1).
+__device__ __forceinline__ uint32_t num_distinct_triples(uint32_t n1, uint32_t n2, uint32_t n3,
+                                                         uint32_t L) {
+  uint32_t c = 0;
+  for (uint32_t p3 = 2; p3 < L; ++p3) {
+    if (!((n1 >> p3) & 1u)) continue;
+    for (uint32_t p2 = 1; p2 < p3; ++p2) {
+      const bool adj = p3 == p2 + 1;
+      if (!(((adj ? n2 : n1) >> p2) & 1u)) continue;
+      c += (uint32_t)__popc(n1 & ((1u << (p2 - 1)) - 1u)) + (((adj ? n3 : n2) >> (p2 - 1)) & 1u);
+    }
+  }
+  return c;
+}
+
+// n3 of variant_canonical3 from the residue bit planes.
+__device__ __forceinline__ uint32_t canonical_mask3(const uint32_t (&pl)[5], uint32_t L) {
+  uint32_t d3 = 0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) d3 |= pl[q] ^ (pl[q] >> 3);
+  const uint32_t hi = L >= 3 ? ~((1u << (L - 3)) - 1u) : ~0u;  // bits p >= L - 3
+  return (d3 | hi) & ((1u << L) - 1u);
 }
 
 // Variant number v of a key in the enumeration order: v = 0 keeps the

@@ -91,12 +91,19 @@ void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint
                       uint64_t n, uint64_t* cand, uint64_t cap,
                       unsigned long long* counter, hipStream_t s);
 uint64_t compact_tile();
+// out[t] = (uint64_t)i[t] << 32 | j[t]
+void launch_join_pairs(const uint32_t* i, const uint32_t* j, uint64_t n, uint64_t* out,
+                       hipStream_t s);
 // metric SD_METRIC_LEVENSHTEIN: a = bit planes of the first sequences (pack);
 // SD_METRIC_HAMMING: a = their packed keys
+// self_pairs: drop candidates with i >= j (self search). With a2 and seq_b2
+// (paired-chain records: the second chains' planes and keys), the distance
+// is the sum over both chains and metric is not used.
 void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* a, const u128* seq_b,
-                           int k, int metric, uint32_t* out_i, uint32_t* out_j, uint8_t* out_d,
-                           uint64_t* status, uint32_t* tile_counter, uint32_t epoch,
-                           unsigned long long* out_count, uint32_t* err, hipStream_t s);
+                           int k, int metric, int self_pairs, uint32_t* out_i, uint32_t* out_j,
+                           uint8_t* out_d, uint64_t* status, uint32_t* tile_counter, uint32_t epoch,
+                           unsigned long long* out_count, uint32_t* err, hipStream_t s,
+                           const u128* a2 = nullptr, const u128* seq_b2 = nullptr);
 // hashed grouping (element = hash of the key in the top 64 - idbits bits, id below)
 // Every variant as [hash | id] in voff order; block b generates sequences
 // [b * seqs_per_block, ...) (1 <= seqs_per_block <= VG_MAX_SEQS_PER_BLOCK).
@@ -128,6 +135,24 @@ void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, in
                         uint64_t* elem, uint32_t idbits, int npass, const uint32_t* shifts,
                         const uint32_t* masks, uint32_t* hist, uint32_t* tcounts,
                         uint32_t seqs_per_block, hipStream_t s);
+// Streamed search (column groups of hash bins): STREAM_BIN_BITS top hash
+// bits name a variant's bin. launch_vargen_bins adds every distinct
+// variant's bin to hist[1 << STREAM_BIN_BITS] (zeroed by the caller);
+// launch_vargen_stream appends the elements of the variants whose bin lies
+// in [blo, bhi) to the sharded output, hash rotated left by the bin bits.
+constexpr int STREAM_BIN_BITS = 8;
+void launch_vargen_bins(const u128* seq, const uint64_t* voff, uint64_t nseq, int k,
+                        uint32_t idbits, uint32_t* hist, uint32_t seqs_per_block, hipStream_t s);
+void launch_vargen_stream(const u128* seq, const uint64_t* voff, uint64_t nseq, int k,
+                          uint32_t idbits, uint32_t blo, uint32_t bhi, const ShardArgs& a,
+                          uint32_t seqs_per_block, hipStream_t s);
+// Paired-chain records (a_i, b_i): vcnt[i] = deletion sets of up to k of the
+// La + Lb residue positions; the generator writes every such variant of the
+// joined string a T b as [hash | id] at voff[i] (with multiplicity).
+void launch_paired_count(const u128* sa, const u128* sb, uint64_t n, int k, uint32_t* vcnt,
+                         hipStream_t s);
+void launch_vargen_paired(const u128* sa, const u128* sb, const uint64_t* voff, uint64_t n, int k,
+                          uint32_t idbits, uint64_t* elem, hipStream_t s);
 // after launch_vargen_hash with tcounts: hist[q * 256 + d] for q >= 1 from the
 // stored block rows
 void launch_hist_rows(const uint32_t* tcounts, uint64_t nseq, uint32_t seqs_per_block, int npass,
@@ -244,6 +269,8 @@ struct sd_ctx {
   int sort_items = 0;  // keys-only radix passes: items per thread, 16 or 32 (0 = automatic)
   int pair_sort = 0;   // candidate pair sort: 0 automatic, 1 one-sweep passes, 2 counted passes
   int metric = SD_METRIC_LEVENSHTEIN;  // distance of the final filter (SD_OPT_METRIC)
+  int stream = 0;              // streamed self search: 0 automatic, 1 never, 2 always
+  uint64_t stream_elems = 0;   // elements per column group (0: from the budget)
   int64_t batch_tile_seqs = 0;  // query batches: sequences per tile (0 = automatic)
   int probe = 0;                // learned indexes: 0 model window, 1 whole-array binary search
   std::map<std::string, uint64_t> out_hint;  // last output size of each sharded stage
@@ -334,6 +361,8 @@ struct StageTimer {
 // the search pipelines
 void hashed_plan(const sd_ctx* c, uint64_t nk, int* cap, int* bits);
 void self_search(sd_ctx* c, const sd_seqs* seqs, int k, sd_pairs* out, hipStream_t s);
+void paired_self_search(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, int k, sd_pairs* out,
+                        hipStream_t s);
 void pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32_t* ia,
                    const uint32_t* ib, int64_t n, uint8_t* d_out, hipStream_t s);
 struct WeightedSpec;

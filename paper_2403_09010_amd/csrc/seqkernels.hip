@@ -154,6 +154,7 @@ __global__ __launch_bounds__(NT) void k_pack(const uint8_t* __restrict__ codes,
       uint32_t n1, n2;
       canonical_masks(pl, (uint32_t)L, n1, n2);
       c = num_distinct_variants(n1, n2, (uint32_t)L, k);
+      if (k >= 3) c += num_distinct_triples(n1, n2, canonical_mask3(pl, (uint32_t)L), (uint32_t)L);
     }
     vcnt[i] = c;
   }
@@ -243,15 +244,19 @@ constexpr int CITEMS = 8;
 // thread taking a contiguous piece, so a wave does not run the distance once
 // per candidate slot while most of its lanes hold repeats. Kept pairs are
 // written in candidate order after a look-back over the tiles.
-// HAMMING = 0: pa holds the bit-plane form of the first sequences (pack's
-// planes) and the distance is Levenshtein; HAMMING = 1: pa holds their packed
-// keys and the distance is Hamming over equal lengths.
-template <int HAMMING>
+// MODE 0: pa holds the bit-plane form of the first sequences (pack's planes)
+// and the distance is Levenshtein; MODE 1: pa holds their packed keys and the
+// distance is Hamming over equal lengths; MODE 2 (paired-chain records): pa
+// and sb are the first chains (planes, keys), pa2 and sb2 the second, and the
+// distance is the sum of the two chains' Levenshtein distances.
+template <int MODE>
 __global__ __launch_bounds__(NT) void k_verify_compact(
     const uint64_t* __restrict__ cand, uint64_t c, const u128* __restrict__ pa,
-    const u128* __restrict__ sb, int k, uint32_t* __restrict__ oi, uint32_t* __restrict__ oj,
-    uint8_t* __restrict__ od, uint64_t* __restrict__ status, uint32_t* __restrict__ tile_counter,
-    uint32_t epoch, unsigned long long* __restrict__ out_count, uint32_t* __restrict__ err) {
+    const u128* __restrict__ sb, const u128* __restrict__ pa2, const u128* __restrict__ sb2,
+    int k, int self_pairs, uint32_t* __restrict__ oi,
+    uint32_t* __restrict__ oj, uint8_t* __restrict__ od, uint64_t* __restrict__ status,
+    uint32_t* __restrict__ tile_counter, uint32_t epoch, unsigned long long* __restrict__ out_count,
+    uint32_t* __restrict__ err) {
   constexpr int TILE = NT * CITEMS;
   constexpr uint8_t DROP = 0xFFu;
   __shared__ uint32_t s_tile;
@@ -271,7 +276,10 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
   for (int x = 0; x < CITEMS; ++x) {
     const uint64_t e = first + x;
     vals[x] = e < c ? cand[e] : 0;
-    if (e < c && (e == 0 || vals[x] != prev)) umask |= 1u << x;
+    // a self search pairs i < j only (a candidate of one sequence with itself
+    // can come from two of its variants that share a hash)
+    const bool ordered = !self_pairs || (uint32_t)(vals[x] >> 32) < (uint32_t)vals[x];
+    if (e < c && (e == 0 || vals[x] != prev) && ordered) umask |= 1u << x;
     prev = vals[x];
   }
   uint32_t ntot;
@@ -288,10 +296,20 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
     const u128 a = pa[v >> 32], b = sb[(uint32_t)v];
     const int la = (int)(a >> 120), lb = (int)key_len(b);
     uint8_t d = DROP;
-    if (HAMMING) {
+    if (MODE == 1) {
       if (la == lb) {
         const uint32_t dd = hamming_keys(a, b);
         if (dd <= (uint32_t)k) d = (uint8_t)dd;
+      }
+    } else if (MODE == 2) {
+      const u128 a2 = pa2[v >> 32], b2 = sb2[(uint32_t)v];
+      const int la2 = (int)(a2 >> 120), lb2 = (int)key_len(b2);
+      if (abs(la - lb) + abs(la2 - lb2) <= k) {
+        const uint32_t d1 = lev_planes(a, b);
+        if (d1 <= (uint32_t)k) {
+          const uint32_t dd = d1 + lev_planes(a2, b2);
+          if (dd <= (uint32_t)k) d = (uint8_t)dd;
+        }
       }
     } else if (abs(la - lb) <= k) {
       const uint32_t dd = lev_planes(a, b);
@@ -316,6 +334,13 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
     }
   }
   if (threadIdx.x == 0 && tile == gridDim.x - 1) *out_count = s_excl + total;
+}
+
+__global__ __launch_bounds__(NT) void k_join_pairs(const uint32_t* __restrict__ i,
+                                                   const uint32_t* __restrict__ j, uint64_t n,
+                                                   uint64_t* __restrict__ out) {
+  const uint64_t t = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  if (t < n) out[t] = ((uint64_t)i[t] << 32) | j[t];
 }
 
 __global__ __launch_bounds__(NT) void k_pair_distance(const u128* __restrict__ sa, uint64_t na,
@@ -367,19 +392,32 @@ void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint
 
 uint64_t compact_tile() { return (uint64_t)sdk::NT * sdk::CITEMS; }
 
+void launch_join_pairs(const uint32_t* i, const uint32_t* j, uint64_t n, uint64_t* out,
+                       hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(sdk::k_join_pairs, dim3(blocks_for(n, sdk::NT)), dim3(sdk::NT), 0, s, i, j, n,
+                     out);
+}
+
 void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* a, const u128* seq_b,
-                           int k, int metric, uint32_t* out_i, uint32_t* out_j, uint8_t* out_d,
-                           uint64_t* status, uint32_t* tile_counter, uint32_t epoch,
-                           unsigned long long* out_count, uint32_t* err, hipStream_t s) {
+                           int k, int metric, int self_pairs, uint32_t* out_i, uint32_t* out_j,
+                           uint8_t* out_d, uint64_t* status, uint32_t* tile_counter, uint32_t epoch,
+                           unsigned long long* out_count, uint32_t* err, hipStream_t s,
+                           const u128* a2, const u128* seq_b2) {
   if (!c) return;
-  if (metric == SD_METRIC_HAMMING)
-    hipLaunchKernelGGL(sdk::k_verify_compact<1>, dim3(blocks_for(c, compact_tile())), dim3(sdk::NT),
-                       0, s, cand, c, a, seq_b, k, out_i, out_j, out_d, status, tile_counter, epoch,
+  const dim3 g(blocks_for(c, compact_tile()));
+  if (a2)
+    hipLaunchKernelGGL(sdk::k_verify_compact<2>, g, dim3(sdk::NT), 0, s, cand, c, a, seq_b, a2,
+                       seq_b2, k, self_pairs, out_i, out_j, out_d, status, tile_counter, epoch,
                        out_count, err);
+  else if (metric == SD_METRIC_HAMMING)
+    hipLaunchKernelGGL(sdk::k_verify_compact<1>, g, dim3(sdk::NT), 0, s, cand, c, a, seq_b,
+                       nullptr, nullptr, k, self_pairs, out_i, out_j, out_d, status, tile_counter,
+                       epoch, out_count, err);
   else
-    hipLaunchKernelGGL(sdk::k_verify_compact<0>, dim3(blocks_for(c, compact_tile())), dim3(sdk::NT),
-                       0, s, cand, c, a, seq_b, k, out_i, out_j, out_d, status, tile_counter, epoch,
-                       out_count, err);
+    hipLaunchKernelGGL(sdk::k_verify_compact<0>, g, dim3(sdk::NT), 0, s, cand, c, a, seq_b,
+                       nullptr, nullptr, k, self_pairs, out_i, out_j, out_d, status, tile_counter,
+                       epoch, out_count, err);
 }
 
 void launch_pair_distance(const u128* seq_a, uint64_t na, const u128* seq_b, uint64_t nb,

@@ -21,6 +21,8 @@ ERRORS = {
     -1: "SD_E_INVAL", -2: "SD_E_ALPHABET", -3: "SD_E_LENGTH", -4: "SD_E_TOO_MANY",
     -5: "SD_E_NOMEM", -6: "SD_E_HIP", -7: "SD_E_CANCELLED", -8: "SD_E_STATE",
 }
+SD_E_INVAL, SD_E_ALPHABET, SD_E_LENGTH, SD_E_TOO_MANY = -1, -2, -3, -4
+SD_E_NOMEM, SD_E_HIP, SD_E_CANCELLED, SD_E_STATE = -5, -6, -7, -8
 OPT_TIMING = 1
 OPT_PATH = 2
 OPT_GROUP_CAP = 3
@@ -31,6 +33,8 @@ OPT_PROBE = 7
 OPT_GROUP_BATCHES = 8
 OPT_PAIR_SORT = 9
 OPT_METRIC = 10
+OPT_STREAM = 11
+OPT_STREAM_ELEMS = 12
 METRIC_LEVENSHTEIN = 0
 METRIC_HAMMING = 1
 MAX_STAGES = 16
@@ -61,7 +65,7 @@ class _Stats(ctypes.Structure):
                 ("n_cand_raw", ctypes.c_int64), ("n_cand_unique", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("n_stages", ctypes.c_int32),
                 ("n_sort_passes", ctypes.c_int32), ("n_big_segments", ctypes.c_int64),
-                ("n_probe_steps", ctypes.c_int64),
+                ("n_probe_steps", ctypes.c_int64), ("n_stream_groups", ctypes.c_int64),
                 ("stage_name", (ctypes.c_char * 24) * MAX_STAGES),
                 ("stage_ms", ctypes.c_double * MAX_STAGES),
                 ("stage_bytes", ctypes.c_double * MAX_STAGES),
@@ -122,6 +126,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sd_self_search.restype = I
     lib.sd_self_search_hamming.argtypes = [P, ctypes.POINTER(_Seqs), I, ctypes.POINTER(_Pairs), P]
     lib.sd_self_search_hamming.restype = I
+    lib.sd_paired_self_search.argtypes = [P, ctypes.POINTER(_Seqs), ctypes.POINTER(_Seqs), I,
+                                          ctypes.POINTER(_Pairs), P]
+    lib.sd_paired_self_search.restype = I
     lib.sd_pair_distance.argtypes = [P, ctypes.POINTER(_Seqs), ctypes.POINTER(_Seqs), P, P, I64,
                                      P, P]
     lib.sd_pair_distance.restype = I
@@ -362,6 +369,21 @@ class Context:
         self._check(rc, "sd_self_search_hamming" if hamming else "sd_self_search")
         return self._take(p, device_output, st)
 
+    def paired_self_search(self, a, b, k: int, device_output: bool | None = None,
+                           stream=None) -> Pairs:
+        """Paired-chain records (a[i], b[i]), each a (codes, offsets) pair: all
+        i < j with Lev(a_i, a_j) + Lev(b_i, b_j) <= k (sd_paired_self_search)."""
+        sa, keep_a, on_dev = self._seqs(*a)
+        sb, keep_b, on_dev_b = self._seqs(*b)
+        st = _stream_handle(stream, on_dev or on_dev_b)
+        if device_output is None:
+            device_output = on_dev
+        p = _Pairs(0, None, None, None, 1 if device_output else 0, 0)
+        self._check(self._lib.sd_paired_self_search(self._h, ctypes.byref(sa), ctypes.byref(sb),
+                                                    int(k), ctypes.byref(p), st),
+                    "sd_paired_self_search")
+        return self._take(p, device_output, st)
+
     def self_search_raw(self, s: _Seqs, k: int, stream) -> _Pairs:
         """Device-resident result left in library memory (free with free_pairs)."""
         p = _Pairs(0, None, None, None, 1, 0)
@@ -518,7 +540,8 @@ class Context:
         return dict(n_seqs=st.n_seqs, n_keys=st.n_keys, n_cand_raw=st.n_cand_raw,
                     n_cand_unique=st.n_cand_unique, n_pairs=st.n_pairs,
                     n_sort_passes=st.n_sort_passes, n_big_segments=st.n_big_segments,
-                    n_probe_steps=st.n_probe_steps, stages=stages)
+                    n_probe_steps=st.n_probe_steps, n_stream_groups=st.n_stream_groups,
+                    stages=stages)
 
 
 class _ServerConfig(ctypes.Structure):

@@ -185,3 +185,108 @@ def test_extended_mask_form_of_the_rule(k):
     for s in list(random_strings(2000, 41 + k)) + ["", "A", "AA", "AB", "AAA"]:
         for D, _ in variants(s, k):
             assert canonical_ext(s, D) == canonical(s, D), (s, D)
+
+
+# ---------------------------------------------------------------- k = 3
+#
+# For any D the greedy test reads: every deleted position p whose next kept
+# position q(p) exists must hold a different residue (s[p] != s[q(p)]). For
+# |D| <= 3, q(p) is p + 1, p + 2 or p + 3, so three masks suffice: n1, n2 and
+# n3 bit p = (p >= L - 3 or s[p] != s[p + 3]). The generator enumerates
+# every set as a padded triple p1 < p2 < p3 (a pair is (p1, p2, L), one
+# deletion (p1, L, L + 1), none (L, L + 1, L + 2)); positions >= L are not
+# deletions.
+
+def canonical_general(s, D):
+    """The greedy rule for any deletion set."""
+    L, Dset = len(s), set(D)
+    for p in D:
+        q = p + 1
+        while q in Dset:
+            q += 1
+        if q < L and s[p] == s[q]:
+            return False
+    return True
+
+
+def masks3(s):
+    L = len(s)
+    n1, n2 = masks(s)
+    n3 = sum(1 << p for p in range(L) if p >= L - 3 or s[p] != s[p + 3])
+    return n1, n2, n3
+
+
+def padded(D, L):
+    D = tuple(D) + tuple(range(L, L + 3 - len(D)))
+    return D
+
+
+def canonical_triple(s, D):
+    """The generator's test on a padded triple and the extended masks (n2
+    gains bits L - 1 and L, as in canonical_ext; n1 gains L and L + 1)."""
+    L = len(s)
+    n1, n2, n3 = masks3(s)
+    n1x = n1 | (3 << L)
+    n2x = n2 | (1 << L) | ((1 << (L - 1)) if L >= 1 else 0)
+    p1, p2, p3 = padded(D, L)
+    real2, real3 = p2 < L, p3 < L
+    c3 = not real3 or (n1x >> p3) & 1
+    c2 = not real2 or ((n2x if (real3 and p3 == p2 + 1) else n1x) >> p2) & 1
+    if p1 >= L:
+        c1 = 1
+    elif p2 > p1 + 1:
+        c1 = (n1x >> p1) & 1
+    elif real2 and real3 and p3 == p2 + 1:
+        c1 = (n3 >> p1) & 1
+    else:
+        c1 = (n2x >> p1) & 1
+    return bool(c1 and c2 and c3)
+
+
+def distinct_count3_masks(s):
+    """Canonical sets of exactly three deletions in O(L^2) from the masks
+    (the pack kernel's form): for each canonical (p2, p3), the first
+    deletions p1 <= p2 - 2 need n1, and p1 = p2 - 1 needs n2 (p3 > p2 + 1)
+    or n3 (p3 = p2 + 1)."""
+    L = len(s)
+    n1, n2, n3 = masks3(s)
+    c = 0
+    for p3 in range(2, L):
+        if not (n1 >> p3) & 1:
+            continue
+        for p2 in range(1, p3):
+            adj = p3 == p2 + 1
+            if not ((n2 if adj else n1) >> p2) & 1:
+                continue
+            c += bin(n1 & ((1 << (p2 - 1)) - 1)).count("1") if p2 >= 1 else 0
+            c += ((n3 if adj else n2) >> (p2 - 1)) & 1
+    return c
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_general_rule_one_set_per_distinct_string(k):
+    for s in random_strings(1500, 51 + k):
+        by_string = {}
+        for D, t in variants(s, k):
+            by_string.setdefault(t, []).append(D)
+        for t, Ds in by_string.items():
+            canon = [D for D in Ds if canonical_general(s, D)]
+            assert canon == [greedy_deleted(s, t)], (s, t, Ds)
+        if k <= 2:
+            for D, _ in variants(s, k):
+                assert canonical_general(s, D) == canonical(s, D), (s, D)
+
+
+def test_padded_triple_form_of_the_rule():
+    for s in list(random_strings(1500, 61)) + ["", "A", "AA", "AAA", "AAAA", "ABAB", "ABCABC"]:
+        for D, _ in variants(s, 3):
+            assert canonical_triple(s, D) == canonical_general(s, D), (s, D)
+
+
+def test_distinct_count_k3():
+    for s in list(random_strings(2000, 71)) + ["A", "AA", "AAA", "AAAA", "ABAB", "ABCABC"]:
+        distinct3 = len({t for D, t in variants(s, 3) if len(D) == 3})
+        assert distinct_count3_masks(s) == distinct3, s
+        # strings with exactly three deletions never equal shorter-deletion ones
+        assert distinct_count_masks(s, 2) + distinct3 == len({t for _, t in variants(s, 3)}), s
+    assert distinct_count3_masks("ACDEFGHIKL") == 120

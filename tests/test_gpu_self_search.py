@@ -282,9 +282,11 @@ def test_group_larger_than_lds(ctx):
 
 def test_budget_error_keeps_context_usable():
     from paper_2403_09010_amd import Context, SymdelError
-    log("self_search over a 4 MiB device budget")
+    from paper_2403_09010_amd.symdel import OPT_STREAM
+    log("self_search over a 4 MiB device budget (streaming off)")
     c, o = cdr3gen.plain("plain_10k")
     with Context(0, hbm_budget=4 << 20) as small:
+        small.set_option(OPT_STREAM, 1)
         with pytest.raises(SymdelError) as e:
             small.self_search(*to_dev(c, o), 2)
         assert e.value.name == "SD_E_NOMEM"
@@ -321,7 +323,7 @@ def test_errors(ctx):
     assert e.value.name == "SD_E_LENGTH"
     c, o = csr([bytes([1, 2])])
     with pytest.raises(SymdelError) as e:
-        ctx.self_search(c, o, 3)
+        ctx.self_search(c, o, 4)
     assert e.value.name == "SD_E_INVAL"
     # the context stays usable after errors
     c, o = cdr3gen.plain("plain_10k")

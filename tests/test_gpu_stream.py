@@ -1,0 +1,139 @@
+"""The streamed self search (Section II C; the XTNeighbor-Streaming steps of
+Appendix A): the variant space is cut into hash bins, Next-Fit packs
+consecutive bins into column groups that fit a capacity, and every group is
+generated, grouped, sorted and verified on its own before the pairs of all
+groups are merged. Its output must equal the oracle's exactly, whatever the
+number of groups: forced small capacities at small size (many groups, k = 1,
+2, 3), heavy groups of copies, and the 10M workload under a device memory
+budget that forces at least four groups (against the oracle's stored hash)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import cdr3gen
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "oracle_results.json")))
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def to_dev(codes, offsets):
+    import torch
+    return (torch.from_numpy(np.ascontiguousarray(codes)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(offsets)).cuda())
+
+
+def stream_ctx(elems=0, budget=0, mode=2):
+    from paper_2403_09010_amd import Context
+    from paper_2403_09010_amd.symdel import OPT_STREAM, OPT_STREAM_ELEMS
+    c = Context(0, hbm_budget=budget)
+    c.set_option(OPT_STREAM, mode)
+    c.set_option(OPT_STREAM_ELEMS, elems)
+    return c
+
+
+def triples(ctx, codes, offsets, k):
+    i, j, d = ctx.self_search(*to_dev(codes, offsets), k).numpy()
+    return i.astype(np.uint32), j.astype(np.uint32), d.astype(np.int32)
+
+
+def assert_same(got, want):
+    assert len(got[0]) == len(want[0]), (len(got[0]), len(want[0]))
+    for g, w in zip(got, want):
+        assert np.array_equal(g, np.asarray(w).astype(g.dtype))
+
+
+def csr(strings):
+    offs = np.zeros(len(strings) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(s) for s in strings])
+    return np.frombuffer(b"".join(strings), dtype=np.uint8).copy(), offs
+
+
+@pytest.mark.parametrize("k,elems", [(1, 20000), (2, 150000), (2, 400000), (2, 0)])
+def test_streamed_10k_equals_oracle(k, elems):
+    import oracle
+    c, o = cdr3gen.plain("plain_10k")
+    with stream_ctx(elems) as ctx:
+        log(f"streamed self search plain_10k k={k}, group capacity {elems or 'automatic'}")
+        got = triples(ctx, c, o, k)
+        groups = ctx.stats()["n_stream_groups"]
+    log(f"  {groups} column groups, {len(got[0])} pairs")
+    assert groups >= (4 if elems else 1)
+    assert_same(got, oracle.self_search(c, o, k))
+
+
+def test_streamed_k3_equals_oracle():
+    import oracle
+    c, o = cdr3gen.subset(*cdr3gen.plain("plain_10k"), 3000)
+    with stream_ctx(200000) as ctx:
+        log("streamed self search, 3000 sequences, k=3")
+        got = triples(ctx, c, o, 3)
+        assert ctx.stats()["n_stream_groups"] >= 4
+    assert_same(got, oracle.self_search(c, o, 3))
+
+
+def test_streamed_heavy_groups_and_copies():
+    """Copies make bins with far more than their share of variants; groups of
+    equal hashes larger than LDS take the sort-and-runs path inside a group."""
+    import oracle
+    base, bo = cdr3gen.generate(41, 40)
+    rng = np.random.default_rng(2)
+    pick = rng.integers(0, 40, 3000)
+    strings = [base[bo[x]:bo[x + 1]].tobytes() for x in pick]
+    x = cdr3gen.generate(51, 1)[0].tobytes()
+    strings += [x] * 2500
+    c, o = csr(strings)
+    with stream_ctx(120000) as ctx:
+        for k in (1, 2):
+            log(f"streamed self search, copies, k={k}")
+            assert_same(triples(ctx, c, o, k), oracle.self_search(c, o, k))
+
+
+def test_streamed_bin_over_capacity_fails_cleanly():
+    """One bin holds more variants than a group may: SD_E_NOMEM, and the
+    context stays usable."""
+    import oracle
+    from paper_2403_09010_amd import SymdelError
+    x = cdr3gen.generate(51, 1)[0].tobytes()
+    c, o = csr([x] * 5000)
+    with stream_ctx(4096) as ctx:
+        with pytest.raises(SymdelError) as e:
+            triples(ctx, c, o, 1)
+        assert e.value.name == "SD_E_NOMEM"
+        c2, o2 = cdr3gen.subset(*cdr3gen.plain("plain_10k"), 500)
+        assert_same(triples(ctx, c2, o2, 1), oracle.self_search(c2, o2, 1))
+
+
+def test_budget_streams_automatically():
+    """With a budget too small for the in-memory path, the automatic mode
+    streams (and the result is the oracle's)."""
+    import oracle
+    c, o = cdr3gen.plain("plain_10k")
+    with stream_ctx(budget=17 << 20, mode=0) as ctx:
+        log("self search plain_10k k=2 under a 17 MiB budget")
+        got = triples(ctx, c, o, 2)
+        assert ctx.stats()["n_stream_groups"] >= 2
+    assert_same(got, oracle.self_search(c, o, 2))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_streamed_10m_under_budget_equals_oracle(k):
+    """The 10M workload under a device budget that forces at least four
+    column groups: every triplet equals the oracle's (count and hash)."""
+    from test_gpu_self_search import assert_golden
+    name = f"oracle_plain_10m_k{k}"
+    c, o = cdr3gen.plain("plain_10m")
+    budget = (4 << 30) if k == 2 else (1 << 30)
+    with stream_ctx(budget=budget, mode=0) as ctx:
+        log(f"self search plain_10m k={k} under a {budget >> 20} MiB budget")
+        got = triples(ctx, c, o, k)
+        groups = ctx.stats()["n_stream_groups"]
+    log(f"  {groups} column groups, {len(got[0])} pairs")
+    assert groups >= 4
+    assert_golden(got, name, len(o) - 1)
