@@ -28,9 +28,13 @@ WORKLOADS = {
     # name: (generator config, k)
     "plain_10k_k1": ("plain_10k", 1),
     "plain_1m_k2": ("plain_1m", 2),
+    "plain_1m_k3": ("plain_1m", 3),
     "plain_10m_k1": ("plain_10m", 1),
     "plain_10m_k2": ("plain_10m", 2),
+    "paired_1m_k2": ("paired_1m", 2),
 }
+# paired-chain records: seed and count of cdr3gen.paired
+PAIRED_CONFIGS = {"paired_1m": (9, 1_000_000)}
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counters, scaled by a
 # 1 GiB copy (profiles/traffic_hashed_path_plain_1m_k2.md), for the stages and
@@ -48,6 +52,8 @@ METRICS = {
     "plain_1m_k2": "End-to-end s & pairs/s, 1M CDR3 self-search k<=2 (pairs/s)",
     "plain_10m_k1": "End-to-end s & pairs/s, 10M CDR3 self-search k<=1 (pairs/s)",
     "plain_10m_k2": "End-to-end s & pairs/s, 10M CDR3 self-search k<=2 (pairs/s)",
+    "plain_1m_k3": "End-to-end s & pairs/s, 1M CDR3 self-search k<=3 (pairs/s)",
+    "paired_1m_k2": "End-to-end s & pairs/s, 1M paired-chain records, Lev(a)+Lev(b)<=2 (pairs/s)",
 }
 # stages that time exactly one kernel (launched once, or several times alike)
 KERNEL_OF_STAGE = {
@@ -76,17 +82,20 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(codes, offsets, k, target_s=15.0, threads=1):
-    """The oracle, as it stands, on the first S sequences of the workload (S
-    grown until one run takes about target_s); threads > 1 runs the sharded
-    oracle on that many threads."""
+def cpu_baseline(codes, offsets, k, target_s=15.0, threads=1, paired=None):
+    """The oracle, as it stands, on the first S sequences (or records) of the
+    workload (S grown until one run takes about target_s); threads > 1 runs the
+    sharded oracle on that many threads. paired: the second chains (codes,
+    offsets) of paired-chain records (the oracle's paired mode, one thread)."""
     import cdr3gen
     import oracle
     n = 2000
     while True:  # grow the sample until one run takes about target_s
         c, o = cdr3gen.subset(codes, offsets, n)
         t0 = time.perf_counter()
-        if threads > 1:
+        if paired is not None:
+            a, _, _ = oracle.paired_self_search((c, o), cdr3gen.subset(*paired, n), k)
+        elif threads > 1:
             a, _, _ = oracle.self_search_sharded(c, o, k, threads=threads)
         else:
             a, _, _ = oracle.self_search(c, o, k)
@@ -96,8 +105,10 @@ def cpu_baseline(codes, offsets, k, target_s=15.0, threads=1):
         grow = min(8.0, max(1.5, target_s / max(dt, 1e-3)))
         n = min(len(offsets) - 1, int(n * grow))
     whole = n >= len(offsets) - 1
-    what = "the whole workload" if whole else f"first {n} sequences of the workload"
-    mode = f"sharded oracle on {threads} threads" if threads > 1 else "oracle on one thread"
+    unit = "records" if paired is not None else "sequences"
+    what = "the whole workload" if whole else f"first {n} {unit} of the workload"
+    mode = ("paired-chain oracle on one thread" if paired is not None else
+            f"sharded oracle on {threads} threads" if threads > 1 else "oracle on one thread")
     return {"value": len(a) / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{what}, k={k}, {mode}: {len(a)} pairs in {dt:.2f} s "
                       f"({n / dt:.0f} sequences/s)",
@@ -105,11 +116,14 @@ def cpu_baseline(codes, offsets, k, target_s=15.0, threads=1):
             "host_cpu": cpu_model(), "host_nproc": os.cpu_count()}
 
 
-def cpu_baselines(codes, offsets, k, workload):
+def cpu_baselines(codes, offsets, k, workload, paired=None):
     """The sharded oracle on the host's cores (the whole 1M workload fits the
     bound: about 20-35 s), plus the single-thread oracle on a bounded prefix."""
     import oracle
     threads = oracle.host_threads()
+    if workload.startswith("paired"):
+        one = cpu_baseline(codes, offsets, k, target_s=15.0, threads=1, paired=paired)
+        return one, one
     if workload in ("plain_1m_k2", "plain_10k_k1"):
         t0 = time.perf_counter()
         a, _, _ = oracle.self_search_sharded(codes, offsets, k, threads=threads)
@@ -428,6 +442,12 @@ def main():
     ap.add_argument("--group-bits", type=int, default=0, help="hashed path hash bits (0 auto)")
     ap.add_argument("--sort-items", type=int, default=0, help="keys-only radix items/thread (0 auto)")
     ap.add_argument("--group-batches", type=int, default=0, help="hashed path LDS batches per workgroup (0 auto)")
+    ap.add_argument("--group-shape", type=int, default=0, help="grouping kernel shape at capacity 2048 (0-2)")
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="device memory budget of the context in GiB (0: none); a search "
+                         "that does not fit streams in column groups")
+    ap.add_argument("--stream", type=int, default=0, help="streamed search: 0 auto, 1 never, 2 always")
+    ap.add_argument("--stream-elems", type=int, default=0, help="streamed search: variants per group (0 auto)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this size first (a known-size kernel for counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -448,22 +468,49 @@ def main():
     import cdr3gen
     from paper_2403_09010_amd import Context
     from paper_2403_09010_amd.symdel import (OPT_GROUP_BATCHES, OPT_GROUP_BITS, OPT_GROUP_CAP,
-                                             OPT_PATH, OPT_SORT_ITEMS, OPT_TIMING, _Seqs)
+                                             OPT_GROUP_SHAPE, OPT_PATH, OPT_SORT_ITEMS,
+                                             OPT_STREAM, OPT_STREAM_ELEMS, OPT_TIMING, _Seqs)
 
     gen_name, k = WORKLOADS[args.workload]
     log(f"generating {gen_name}")
-    codes, offsets = cdr3gen.plain(gen_name)
+    paired = gen_name in PAIRED_CONFIGS
+    chain_b = None
+    if paired:
+        seed = PAIRED_CONFIGS[gen_name][0]
+        (codes, offsets), chain_b = cdr3gen.paired(*PAIRED_CONFIGS[gen_name])
+    else:
+        seed = cdr3gen.PLAIN_CONFIGS[gen_name][0]
+        codes, offsets = cdr3gen.plain(gen_name)
     n = len(offsets) - 1
     dev = torch.device("cuda", 0)
     codes_t = torch.from_numpy(codes).to(dev)
     offs_t = torch.from_numpy(offsets).to(dev)
     seqs = _Seqs(codes_t.data_ptr(), offs_t.data_ptr(), n, 1)
-    ctx = Context(0)
+    seqs_b = None
+    if paired:
+        codes_bt = torch.from_numpy(chain_b[0]).to(dev)
+        offs_bt = torch.from_numpy(chain_b[1]).to(dev)
+        seqs_b = _Seqs(codes_bt.data_ptr(), offs_bt.data_ptr(), n, 1)
+    ctx = Context(0, hbm_budget=int(args.budget_gb * (1 << 30)))
     ctx.set_option(OPT_PATH, args.path)
     ctx.set_option(OPT_GROUP_CAP, args.group_cap)
     ctx.set_option(OPT_GROUP_BITS, args.group_bits)
     ctx.set_option(OPT_SORT_ITEMS, args.sort_items)
     ctx.set_option(OPT_GROUP_BATCHES, args.group_batches)
+    ctx.set_option(OPT_GROUP_SHAPE, args.group_shape)
+    ctx.set_option(OPT_STREAM, args.stream)
+    ctx.set_option(OPT_STREAM_ELEMS, args.stream_elems)
+
+    def search_raw():
+        if paired:
+            return ctx.paired_self_search_raw(seqs, seqs_b, k, sh)
+
+        return ctx.self_search_raw(seqs, k, sh)
+
+    def search_host():
+        if paired:
+            return ctx.paired_self_search((codes, offsets), chain_b, k, device_output=False)
+        return ctx.self_search(codes, offsets, k, device_output=False)
     if args.copy_calibration_mb:
         src = torch.empty(args.copy_calibration_mb << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -475,7 +522,7 @@ def main():
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
-        ctx.free_pairs(ctx.self_search_raw(seqs, k, sh))
+        ctx.free_pairs(search_raw())
     torch.cuda.synchronize()
 
     # timed region: K whole searches, stage events recorded on the same stream
@@ -485,7 +532,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(args.steps):
-        p = ctx.self_search_raw(seqs, k, sh)
+        p = search_raw()
         npairs = p.n
         ctx.free_pairs(p)
         st = ctx.stats()
@@ -511,11 +558,11 @@ def main():
     # host-to-host: u8 codes and offsets in host memory, pairs back in host
     # memory (H2D and D2H included); one warm-up, median of five
     ctx.set_option(OPT_TIMING, 0)
-    ctx.self_search(codes, offsets, k, device_output=False)
+    search_host()
     h2h = []
     for _ in range(5):
         t1 = time.perf_counter()
-        r = ctx.self_search(codes, offsets, k, device_output=False)
+        r = search_host()
         h2h.append(time.perf_counter() - t1)
     h2h_s = float(np.median(h2h))
     assert len(r) == npairs
@@ -530,7 +577,8 @@ def main():
         per_launch_s = ms * 1e-3 / launches
         achieved = per_launch_bytes / per_launch_s / 1e9
         traffic = TRAFFIC_PER_LAUNCH.get((args.workload, stage))
-        if args.path or args.group_cap or args.group_bits or args.sort_items or args.group_batches:
+        if (args.path or args.group_cap or args.group_bits or args.sort_items or args.group_batches
+                or args.group_shape or args.budget_gb or args.stream):
             traffic = None  # the counters were taken with the default configuration
         return {"bound": "hbm", "kernel": KERNEL_OF_STAGE[stage], "stage": stage,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -559,11 +607,13 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u128",
         "data": "synthetic (seeded CDR3-like generator)",
-        "config": {"workload": args.workload, "n_seqs": n, "k": k, "seed": cdr3gen.PLAIN_CONFIGS[gen_name][0],
+        "config": {"workload": args.workload, "n_seqs": n, "k": k, "seed": seed,
                    "pairs": int(npairs), "keys": st["n_keys"], "candidates_raw": st["n_cand_raw"],
                    "seconds_per_search": round(dt, 6), "path": args.path,
                    "group_cap": args.group_cap, "group_bits": args.group_bits,
-                   "sort_items": args.sort_items, "group_batches": args.group_batches},
+                   "sort_items": args.sort_items, "group_batches": args.group_batches,
+                   "group_shape": args.group_shape, "budget_gb": args.budget_gb,
+                   "stream": args.stream, "stream_groups": st["n_stream_groups"]},
         "stages_ms": {s: round(stage_ms[s] / args.steps, 4) for s in stage_ms},
         "value_is": "pairs / device time of one search, inputs resident in HBM, result left in HBM",
         "end_to_end": {"seconds_median_of_5": round(h2h_s, 6),
@@ -581,7 +631,7 @@ def main():
     ctx.close()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the host cores")
-        allc, one = cpu_baselines(codes, offsets, k, args.workload)
+        allc, one = cpu_baselines(codes, offsets, k, args.workload, paired=chain_b)
         out["cpu_baseline"] = allc
         out["cpu_baseline_one_thread"] = one
         log(f"cpu baseline: {allc['sample']}; {one['sample']}")

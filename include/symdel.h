@@ -104,6 +104,8 @@ typedef struct {
 #define SD_OPT_STREAM 11    /* self search in column groups of hash bins (bounded memory):
                                0 automatic (when the variants exceed 2^32 - 2 or the
                                in-memory path would exceed the budget), 1 never, 2 always */
+#define SD_OPT_GROUP_SHAPE 13 /* hashed path grouping kernel at LDS capacity 2048: 0 (256 threads,
+                                 five waves per SIMD), 1 (256 threads, four), 2 (512 threads, four) */
 #define SD_OPT_STREAM_ELEMS 12 /* streamed self search: variants per column group at most
                                   (0: from the budget, or 80% of free device memory) */
 

@@ -60,8 +60,11 @@ static void* hook_alloc(sd_ctx* c, size_t sz) {
 void* dalloc(sd_ctx* c, size_t bytes) {
   const size_t sz = size_class(bytes);
   if (c->ualloc) return hook_alloc(c, sz);
+  // a cached block up to twice the size serves the request; under a budget
+  // only up to an eighth more, so that a reused block does not hold much
+  // memory the budget could give to another request
   auto it = c->cache.lower_bound(sz);
-  if (it != c->cache.end() && it->first <= 2 * sz) {
+  if (it != c->cache.end() && it->first <= (c->budget ? sz + sz / 8 : 2 * sz)) {
     void* p = it->second;
     c->live[p] = it->first;
     c->cache.erase(it);
@@ -150,6 +153,7 @@ uint32_t* fresh_counters(sd_ctx* c, size_t n, hipStream_t s) {
     c->counters_n = n;
   }
   launch_fill_u32(c->counters, 0, n, s);
+  c->tile_slot = 0;  // every slot is zero again
   return c->counters;
 }
 
@@ -353,6 +357,10 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
     case SD_OPT_PAIR_SORT:
       if (value < 0 || value > 2) return SD_E_INVAL;
       c->pair_sort = (int)value;
+      return SD_OK;
+    case SD_OPT_GROUP_SHAPE:
+      if (value < 0 || value > 2) return SD_E_INVAL;
+      c->group_shape = (int)value;
       return SD_OK;
     case SD_OPT_STREAM:
       if (value < 0 || value > 2) return SD_E_INVAL;

@@ -802,9 +802,10 @@ __device__ uint32_t split_part(const uint64_t* __restrict__ E, uint32_t a, uint3
 
 // One workgroup per `spw` consecutive segment values, processed as batches;
 // the elements of batch t + 1 are loaded into registers while batch t is
-// grouped.
-template <int CAP, int NTH>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(CAP == 2048 ? 5 : 1))) void k_group_seg(
+// grouped. WPE is the occupancy the register allocation aims at (waves per
+// SIMD; 1 leaves it to the compiler).
+template <int CAP, int NTH, int WPE>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(WPE))) void k_group_seg(
     const uint64_t* __restrict__ E, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
     uint32_t splitbit, ShardOut out, uint64_t* __restrict__ big,
@@ -1254,7 +1255,7 @@ void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_
 
 static size_t group_lds(int cap) { return (size_t)(cap / 2) * sdk::GROUP_LDS_PER_CAND; }
 
-template <int CAP, int NTH>
+template <int CAP, int NTH, int WPE>
 static void launch_group_t(const uint64_t* E, const uint32_t* ss, const uint32_t* se,
                            uint32_t nseg, uint32_t spw, uint32_t idbits, uint32_t splitbit,
                            const ShardArgs& a, uint64_t* big, unsigned long long* nbig,
@@ -1262,14 +1263,14 @@ static void launch_group_t(const uint64_t* E, const uint32_t* ss, const uint32_t
   static bool attr = false;
   if (!attr) {
     attr = true;
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&sdk::k_group_seg<CAP, NTH>),
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&sdk::k_group_seg<CAP, NTH, WPE>),
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)group_lds(CAP)) != hipSuccess)
       (void)hipGetLastError();  // the launch reports any real problem
   }
   const unsigned g = (nseg + spw - 1) / spw;
   const ShardOut out{a.base, a.region, a.over, a.over_cap, a.counter};
-  hipLaunchKernelGGL((sdk::k_group_seg<CAP, NTH>), dim3(g), dim3(NTH), group_lds(CAP), s, E, ss,
+  hipLaunchKernelGGL((sdk::k_group_seg<CAP, NTH, WPE>), dim3(g), dim3(NTH), group_lds(CAP), s, E, ss,
                      se, nseg, spw, idbits, splitbit, out, big, nbig);
 }
 
@@ -1318,23 +1319,34 @@ void launch_group_listed(int cap, const uint64_t* E, const uint64_t* big,
 
 bool group_cap_supported(int cap) { return cap == 4096 || cap == 2048 || cap == 1024 || cap == 256; }
 
-void launch_group_seg(int cap, const uint64_t* E, const uint32_t* seg_start,
+void launch_group_seg(int cap, int shape, const uint64_t* E, const uint32_t* seg_start,
                       const uint32_t* seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
                       uint32_t splitbit, const ShardArgs& out, uint64_t* big,
                       unsigned long long* nbig, hipStream_t s) {
   if (!nseg) return;
   switch (cap) {
     case 4096:
-      launch_group_t<4096, 512>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big, nbig, s);
+      launch_group_t<4096, 512, 1>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
+                                   nbig, s);
       break;
     case 2048:
-      launch_group_t<2048, 256>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big, nbig, s);
+      if (shape == 1)  // 256 threads, registers for four waves per SIMD (no spills)
+        launch_group_t<2048, 256, 4>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
+                                     nbig, s);
+      else if (shape == 2)  // 512 threads, four elements per thread
+        launch_group_t<2048, 512, 4>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
+                                     nbig, s);
+      else  // 256 threads, registers for five waves per SIMD
+        launch_group_t<2048, 256, 5>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
+                                     nbig, s);
       break;
     case 1024:
-      launch_group_t<1024, 128>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big, nbig, s);
+      launch_group_t<1024, 128, 1>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
+                                   nbig, s);
       break;
     default:
-      launch_group_t<256, 64>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big, nbig, s);
+      launch_group_t<256, 64, 1>(E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
+                                 nbig, s);
       break;
   }
 }

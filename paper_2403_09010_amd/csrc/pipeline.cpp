@@ -241,7 +241,7 @@ Cands group_segments(Call& cl, const uint64_t* E, uint32_t nk, int cap, int bits
       [&](const ShardArgs& out) {
         launch_fill_u64(reinterpret_cast<uint64_t*>(nbig), 0, 2, s);
         const uint32_t splitbit = segshift >= 1 ? segshift - 1 : 64u;
-        launch_group_seg(cap, E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
+        launch_group_seg(cap, c->group_shape, E, seg_start, seg_end, nseg, spw, idbits, splitbit, out, big,
                          nbig, s);
         // the ranges listed above, with a table for a whole batch of
         // candidates; what still does not fit goes to big2
@@ -481,7 +481,7 @@ Verified streamed_search(Call& cl, const u128* seq, const u128* planes, const ui
             [&](const ShardArgs& a) {
               launch_vargen_stream(seq, voff, n, k, idbits, g.lo, g.hi, a, spb, s);
             },
-            [&](uint64_t m) { return (double)n * 24 + (double)m * 8; });
+            [&](uint64_t m) { return (double)n * 24 + (double)m * 8; }, true);
       }
       gsc.blocks.push_back(E.p);
       if (E.n != g.n) throw Error{SD_E_HIP, "internal error: a column group lost variants"};
@@ -490,8 +490,27 @@ Verified streamed_search(Call& cl, const u128* seq, const u128* planes, const ui
       hashed_plan(c, ng, &gcap, &bits);
       const std::vector<Digit> digits = bits ? top_digits(64 - bits) : std::vector<Digit>();
       uint64_t* e2 = gsc.get<uint64_t>(ng);
-      const bool flip = digits.empty() ? false : counted_sort(gcl, E.p, e2, ng, digits);
-      cl.tm.mark("hash_passes", (double)ng * 24 * digits.size(), 4 * (int)digits.size());
+      // counted LSD passes over fixed tiles (a count of each pass's input,
+      // the count scans, the XCD-contiguous scatter), timed as the in-memory
+      // path's later passes are
+      bool flip = false;
+      if (!digits.empty()) {
+        const uint64_t tiles = fixed_tiles(ng);
+        uint32_t* counts = gsc.get<uint32_t>(tiles * 256);
+        uint32_t* local = gsc.get<uint32_t>(tiles * 256);
+        uint32_t* bsum = gsc.get<uint32_t>((uint64_t)counted_scan_rows(tiles) * 256);
+        for (const Digit& d : digits) {
+          const uint64_t* in = flip ? e2 : E.p;
+          uint64_t* outp = flip ? E.p : e2;
+          launch_tile_counts(in, ng, d.shift, d.mask, counts, s);
+          launch_counted_scan(counts, tiles, 1, local, bsum, s);
+          cl.tm.mark("tile_counts", (double)ng * 8 + (double)tiles * 256 * 12, 3);
+          launch_counted_scatter(in, outp, ng, d.shift, d.mask, tiles, local, bsum, nullptr, 0, 0,
+                                 cl.lb_err(), s);
+          cl.tm.mark("hash_passes", (double)ng * 16, 1);
+          flip = !flip;
+        }
+      }
       passes += (int)digits.size();
       Cands cand = group_segments(gcl, flip ? e2 : E.p, ng, gcap, bits, idbits);
       gsc.blocks.push_back(cand.p);

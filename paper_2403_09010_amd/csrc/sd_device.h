@@ -322,7 +322,7 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
 // The wait is bounded: after LB_SPIN_LIMIT polls of one word the tile sets
 // SD_ERRBIT_LOOKBACK in *err and stops waiting (the host then reports an
 // error), so every wave exits even if an earlier tile never publishes.
-constexpr uint32_t LB_SPIN_LIMIT = 1u << 22;
+constexpr uint32_t LB_SPIN_LIMIT = 1u << 16;
 __device__ __forceinline__ uint64_t lb_exclusive(uint64_t* status, uint64_t tile, uint64_t stride,
                                                  uint64_t epoch, uint64_t aggregate,
                                                  uint32_t* err) {

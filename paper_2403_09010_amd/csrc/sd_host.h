@@ -77,19 +77,24 @@ enum : int {
   CNT_TOTAL = 128
 };
 
+// The state of one library call on one stream. Several Call objects of one
+// call (a streamed search's column groups) share the counter area, so the
+// cursor over its tile-counter slots lives in the context: a slot handed out
+// once is never handed out again until the whole block of slots is zeroed.
 struct Call {
   sd_ctx* c;
   hipStream_t s;
   Scratch& sc;
   StageTimer& tm;
   uint32_t* counters;
-  int slot = CNT_TILE0;
+  // a zeroed tile counter (the dynamic tile ids of one look-back kernel)
   uint32_t* tile_counter() {
-    if (slot >= CNT_TILE_END) {  // recycle: zero a fresh block of slots
+    if (c->tile_slot < CNT_TILE0) c->tile_slot = CNT_TILE0;  // fresh counter area
+    if (c->tile_slot >= CNT_TILE_END) {  // recycle: zero a fresh block of slots
       launch_fill_u32(counters + CNT_TILE0, 0, CNT_TILE_END - CNT_TILE0, s);
-      slot = CNT_TILE0;
+      c->tile_slot = CNT_TILE0;
     }
-    return counters + slot++;
+    return counters + c->tile_slot++;
   }
   uint32_t* lb_err() { return counters + CNT_LBERR; }
 };
@@ -182,14 +187,19 @@ struct Cands {
 // "gather_out") into one dense pool block owned by the caller. `guess` is the
 // expected total.
 template <class Launch, class Bytes>
-Cands sharded_output(Call& cl, uint64_t guess, const char* stage, Launch&& launch, Bytes&& bytes) {
+Cands sharded_output(Call& cl, uint64_t guess, const char* stage, Launch&& launch, Bytes&& bytes,
+                     bool exact_guess = false) {
   const uint32_t NS = out_shards();
   sd_ctx* c = cl.c;
   // the size the same stage produced last time on this context, if larger
   auto hint = c->out_hint.find(stage);
-  if (hint != c->out_hint.end()) guess = std::max(guess, hint->second);
-  const uint64_t region = guess / NS + guess / (2 * NS) + 16;
-  uint64_t over_cap = guess / 4 + 4096;
+  if (!exact_guess && hint != c->out_hint.end()) guess = std::max(guess, hint->second);
+  // regions at 1.5 times the mean share and a quarter of the guess for
+  // overflow; with an exact total spread evenly over the shards (exact_guess),
+  // 1.125 times and a sixteenth
+  const uint64_t region =
+      exact_guess ? guess / NS + guess / (8 * NS) + 64 : guess / NS + guess / (2 * NS) + 16;
+  uint64_t over_cap = exact_guess ? guess / 16 + 4096 : guess / 4 + 4096;
   unsigned long long* ctr = cl.sc.get<unsigned long long>(NS + 1);
   std::vector<unsigned long long> h(NS + 1);
   ShardArgs a{};

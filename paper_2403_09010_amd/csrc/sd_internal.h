@@ -162,7 +162,9 @@ void launch_seg_bounds(const uint64_t* E, uint64_t n, uint32_t segshift, uint32_
                        uint32_t* seg_end, hipStream_t s);
 // splitbit: the hash bit below the segment bits (segments of up to 2 cap
 // elements are grouped in two halves by it); 64 disables splitting
-void launch_group_seg(int cap, const uint64_t* E, const uint32_t* seg_start,
+// shape (capacity 2048 only): 0 = 256 threads at five waves per SIMD, 1 = 256
+// threads at four, 2 = 512 threads at four
+void launch_group_seg(int cap, int shape, const uint64_t* E, const uint32_t* seg_start,
                       const uint32_t* seg_end, uint32_t nseg, uint32_t spw, uint32_t idbits,
                       uint32_t splitbit, const ShardArgs& out, uint64_t* big,
                       unsigned long long* nbig, hipStream_t s);
@@ -258,6 +260,7 @@ struct sd_ctx {
   uint32_t epoch = 0;
   uint32_t* counters = nullptr;  // small device counter area
   size_t counters_n = 0;
+  int tile_slot = 0;  // next tile-counter slot of the current call (0: none handed out yet)
   void* pinned = nullptr;  // pinned host staging for small read-backs
   size_t pinned_bytes = 0;
   sd_stats stats{};
@@ -268,6 +271,7 @@ struct sd_ctx {
   int group_batches = 0;  // hashed path: LDS batches per workgroup (0 = automatic)
   int sort_items = 0;  // keys-only radix passes: items per thread, 16 or 32 (0 = automatic)
   int pair_sort = 0;   // candidate pair sort: 0 automatic, 1 one-sweep passes, 2 counted passes
+  int group_shape = 0; // hashed path grouping kernel shape at capacity 2048 (SD_OPT_GROUP_SHAPE)
   int metric = SD_METRIC_LEVENSHTEIN;  // distance of the final filter (SD_OPT_METRIC)
   int stream = 0;              // streamed self search: 0 automatic, 1 never, 2 always
   uint64_t stream_elems = 0;   // elements per column group (0: from the budget)

@@ -35,6 +35,7 @@ OPT_PAIR_SORT = 9
 OPT_METRIC = 10
 OPT_STREAM = 11
 OPT_STREAM_ELEMS = 12
+OPT_GROUP_SHAPE = 13
 METRIC_LEVENSHTEIN = 0
 METRIC_HAMMING = 1
 MAX_STAGES = 16
@@ -383,6 +384,14 @@ class Context:
                                                     int(k), ctypes.byref(p), st),
                     "sd_paired_self_search")
         return self._take(p, device_output, st)
+
+    def paired_self_search_raw(self, sa: _Seqs, sb: _Seqs, k: int, stream) -> _Pairs:
+        """Paired-chain search with the device result left in library memory."""
+        p = _Pairs(0, None, None, None, 1, 0)
+        self._check(self._lib.sd_paired_self_search(self._h, ctypes.byref(sa), ctypes.byref(sb),
+                                                    int(k), ctypes.byref(p), stream),
+                    "sd_paired_self_search")
+        return p
 
     def self_search_raw(self, s: _Seqs, k: int, stream) -> _Pairs:
         """Device-resident result left in library memory (free with free_pairs)."""
