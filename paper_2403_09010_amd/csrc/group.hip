@@ -199,7 +199,7 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
                                                        uint32_t* __restrict__ hist,
                                                        uint32_t* __restrict__ tcounts,
                                                        uint32_t spb, ShardOut sout, uint32_t blo,
-                                                       uint32_t bhi) {
+                                                       uint32_t bhi, uint32_t ftile) {
   constexpr int NWV = VG_NT / 64;
   constexpr int PRE = K3 ? VG_PRE3 : VG_PRE;
   __shared__ uint64_t s_off[VG_SEQS + 1];
@@ -294,6 +294,15 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   const uint32_t mk[3] = {pd.mask[0], pd.mask[1], pd.mask[2]};
   uint64_t* __restrict__ out = elem + g0;
   const bool tiled = tcounts != nullptr;
+  // ftile != 0 (with tcounts, one pass): the first pass's digits are counted
+  // per fixed output tile of ftile elements instead of per block, so that the
+  // first LSD pass runs over aligned tiles like the later ones. The block's
+  // elements [g0, g0 + its count) meet at most three tiles in LDS (slots 0-2
+  // of s_h, from tile0 on; local offsets b1 and b2 start slots 1 and 2);
+  // anything further goes to global memory directly.
+  const uint64_t tile0 = ftile ? g0 / ftile : 0;
+  const uint32_t b1 = ftile ? (uint32_t)((tile0 + 1) * ftile - g0) : 0u;
+  const uint32_t b2 = b1 + ftile, b3 = b2 + ftile;
   // Each wave takes a contiguous quarter of the sequences. A sequence with
   // more than 64 deletion sets is enumerated alone, 128 at a time; runs of
   // consecutive smaller ones share one 64-lane chunk (lane -> sequence by a
@@ -303,19 +312,29 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
     // never drops a variant; it keeps any disagreement in range)
     if (keep && at + rank < end) {
       if constexpr (MODE == 0) out[at + rank] = e;
+      if (ftile) {
+        const uint32_t lo = at + rank;
+        const uint32_t d = (uint32_t)(e >> sh[0]) & mk[0];
+        if (lo < b3)
+          atomicAdd(&s_h[((lo >= b1) + (lo >= b2)) * 256u + d], 1u);
+        else
+          atomicAdd(&tcounts[(tile0 + 3 + (lo - b3) / ftile) * 256 + d], 1u);
+      } else {
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e >> sh[q]) & mk[q])], 1u);
+        for (int q = 0; q < 3; ++q)
+          if (q < npass) atomicAdd(&s_h[q * 256 + ((uint32_t)(e >> sh[q]) & mk[q])], 1u);
+      }
     }
   };
   // MODE 2: one shard reservation for the wave's kept lanes (bal is the
-  // wave's ballot of keep, so every lane takes the same branch). A wave
-  // rotates over 16 shards, so the shards fill evenly even when there are
-  // fewer workgroups than shards.
+  // wave's ballot of keep, so every lane takes the same branch). A wave's
+  // reservations go to consecutive shards from a start that is odd multiple
+  // of its wave index, so every shard is equally likely to be any wave's
+  // first, second, ... (the shards fill evenly, also with few workgroups).
   uint32_t nres = 0;
   auto put_sharded = [&](uint64_t e, bool keep, uint64_t bal) {
     if (!bal) return;
-    const uint32_t sel = (blockIdx.x * NWV + w) * 16u + (nres++ & 15u);
+    const uint32_t sel = (blockIdx.x * NWV + w) * 17u + nres++;
     uint64_t pos = 0, ob = 0;
     if (lane == 0) {
       const ShardResv r = shard_reserve(sout, sel, (uint64_t)__popcll(bal));
@@ -439,7 +458,11 @@ __global__ __launch_bounds__(VG_NT) void k_vargen_hash(const u128* __restrict__ 
   // q's rows start at q * gridDim.x): pass 0's are the tiles of the counted
   // first pass, the others are summed by k_hist_rows (plain stores instead
   // of thousands of blocks adding into the same 256 counters).
-  if (tiled) {
+  if (tiled && ftile) {
+    // neighbouring blocks share the tiles at their edges: add
+    for (uint32_t x = threadIdx.x; x < 3u * 256; x += VG_NT)
+      if (s_h[x]) atomicAdd(&tcounts[(tile0 + (x >> 8)) * 256 + (x & 255u)], s_h[x]);
+  } else if (tiled) {
     for (uint32_t x = threadIdx.x; x < (uint32_t)npass * 256; x += VG_NT)
       tcounts[((uint64_t)(x >> 8) * gridDim.x + blockIdx.x) * 256 + (x & 255u)] = s_h[x];
   } else {
@@ -1151,7 +1174,7 @@ namespace sd {
 void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, int k, bool distinct,
                         uint64_t* elem, uint32_t idbits, int npass, const uint32_t* shifts,
                         const uint32_t* masks, uint32_t* hist, uint32_t* tcounts,
-                        uint32_t seqs_per_block, hipStream_t s) {
+                        uint32_t seqs_per_block, hipStream_t s, uint32_t ftile) {
   if (!nseq) return;
   if (seqs_per_block < 1 || seqs_per_block > (uint32_t)sdk::VG_SEQS)
     throw Error{SD_E_INVAL, "internal error: sequences per generator block out of range"};
@@ -1167,19 +1190,19 @@ void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, in
   if (distinct && k == 3)
     hipLaunchKernelGGL((sdk::k_vargen_hash<true, true, 0>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
                        voff, nseq, k, elem, idbits, npass, pd, hist, tc, seqs_per_block, none, 0u,
-                       0u);
+                       0u, ftile);
   else if (distinct)
     hipLaunchKernelGGL((sdk::k_vargen_hash<true, false, 0>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
                        voff, nseq, k, elem, idbits, npass, pd, hist, tc, seqs_per_block, none, 0u,
-                       0u);
+                       0u, ftile);
   else if (k == 3)
     hipLaunchKernelGGL((sdk::k_vargen_hash<false, true, 0>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
                        voff, nseq, k, elem, idbits, npass, pd, hist, tc, seqs_per_block, none, 0u,
-                       0u);
+                       0u, ftile);
   else
     hipLaunchKernelGGL((sdk::k_vargen_hash<false, false, 0>), dim3(g), dim3(sdk::VG_NT), 0, s,
                        seq, voff, nseq, k, elem, idbits, npass, pd, hist, tc, seqs_per_block, none,
-                       0u, 0u);
+                       0u, 0u, ftile);
 }
 
 void launch_vargen_bins(const u128* seq, const uint64_t* voff, uint64_t nseq, int k,
@@ -1195,11 +1218,11 @@ void launch_vargen_bins(const u128* seq, const uint64_t* voff, uint64_t nseq, in
   if (k == 3)
     hipLaunchKernelGGL((sdk::k_vargen_hash<true, true, 1>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
                        voff, nseq, k, nullptr, idbits, 1, pd, hist, nullptr, seqs_per_block, none,
-                       0u, 0u);
+                       0u, 0u, 0u);
   else
     hipLaunchKernelGGL((sdk::k_vargen_hash<true, false, 1>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
                        voff, nseq, k, nullptr, idbits, 1, pd, hist, nullptr, seqs_per_block, none,
-                       0u, 0u);
+                       0u, 0u, 0u);
 }
 
 void launch_paired_count(const u128* sa, const u128* sb, uint64_t n, int k, uint32_t* vcnt,
@@ -1230,11 +1253,11 @@ void launch_vargen_stream(const u128* seq, const uint64_t* voff, uint64_t nseq, 
   if (k == 3)
     hipLaunchKernelGGL((sdk::k_vargen_hash<true, true, 2>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
                        voff, nseq, k, nullptr, idbits, 0, pd, nullptr, nullptr, seqs_per_block, out,
-                       blo, bhi);
+                       blo, bhi, 0u);
   else
     hipLaunchKernelGGL((sdk::k_vargen_hash<true, false, 2>), dim3(g), dim3(sdk::VG_NT), 0, s, seq,
                        voff, nseq, k, nullptr, idbits, 0, pd, nullptr, nullptr, seqs_per_block, out,
-                       blo, bhi);
+                       blo, bhi, 0u);
 }
 
 void launch_hist_rows(const uint32_t* tcounts, uint64_t nseq, uint32_t seqs_per_block, int npass,

@@ -155,30 +155,30 @@ Cands hashed_group(Call& cl, const u128* seq, const uint64_t* voff, uint64_t n, 
     shifts[x] = (uint32_t)digits[x].shift;
     masks[x] = digits[x].mask;
   }
-  // the first pass's digits are counted per tile during generation
+  // the first pass's digits are counted during generation, per fixed tile of
+  // the generator's output (the tiles every counted pass uses)
   const uint32_t spt = vargen_seqs_per_tile(n, nk);
+  const uint64_t ftiles = fixed_tiles(nk);
   uint32_t* tcounts = nullptr;
   if (!digits.empty()) {
-    tcounts = cl.sc.get<uint32_t>(((n + spt - 1) / spt) * 256);
+    tcounts = cl.sc.get<uint32_t>(ftiles * 256);
+    launch_fill_u32(tcounts, 0, ftiles * 256, s);
   }
   // only the first pass's digits are counted by the generator (every later
   // pass is counted over fixed tiles of its own input)
   launch_vargen_hash(seq, voff, n, k, true, e1, idbits, digits.empty() ? 0 : 1, shifts, masks, hist,
-                     tcounts, spt, s);
-  cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 1);
+                     tcounts, spt, s, fixed_tile_elems());
+  cl.tm.mark("vargen_hash", (double)nk * 8 + (double)n * 24, 2);
   // pass 1 from the generator's counts (the count scans, then the scatter),
   // then the later passes
   bool flip = false;
   if (!digits.empty()) {
-    const uint64_t blocks = (n + spt - 1) / spt;
-    const uint32_t G = vargen_blocks_per_tile(n, nk, spt);
-    const uint64_t tiles = (blocks + G - 1) / G;
-    uint32_t* local = cl.sc.get<uint32_t>(tiles * 256);
-    uint32_t* bsum = cl.sc.get<uint32_t>((uint64_t)counted_scan_rows(tiles) * 256);
-    launch_counted_scan(tcounts, blocks, G, local, bsum, s);
-    cl.tm.mark("counted_scan", (double)blocks * 256 * 4 + (double)tiles * 256 * 8, 2);
-    launch_counted_scatter(e1, e2, nk, digits[0].shift, digits[0].mask, tiles, local, bsum, voff,
-                           spt * G, n, cl.lb_err(), s);
+    uint32_t* local = cl.sc.get<uint32_t>(ftiles * 256);
+    uint32_t* bsum = cl.sc.get<uint32_t>((uint64_t)counted_scan_rows(ftiles) * 256);
+    launch_counted_scan(tcounts, ftiles, 1, local, bsum, s);
+    cl.tm.mark("counted_scan", (double)ftiles * 256 * 12, 2);
+    launch_counted_scatter(e1, e2, nk, digits[0].shift, digits[0].mask, ftiles, local, bsum,
+                           nullptr, 0, 0, cl.lb_err(), s);
     cl.tm.mark("hash_counted_pass", (double)nk * 16, 1);
     flip = true;
   }

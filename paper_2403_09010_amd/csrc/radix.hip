@@ -671,6 +671,8 @@ void launch_counted_scatter(const uint64_t* in, uint64_t* out, uint32_t n, int s
 
 uint64_t fixed_tiles(uint64_t n) { return (n + sdk::CT_CHUNK - 1) / sdk::CT_CHUNK; }
 
+uint32_t fixed_tile_elems() { return sdk::CT_CHUNK; }
+
 void launch_tile_counts(const uint64_t* in, uint32_t n, int shift, uint32_t mask, uint32_t* counts,
                         hipStream_t s) {
   if (!n) return;

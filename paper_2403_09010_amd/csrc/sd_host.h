@@ -202,11 +202,12 @@ Cands sharded_output(Call& cl, uint64_t guess, const char* stage, Launch&& launc
   uint64_t over_cap = exact_guess ? guess / 16 + 4096 : guess / 4 + 4096;
   unsigned long long* ctr = cl.sc.get<unsigned long long>(NS + 1);
   std::vector<unsigned long long> h(NS + 1);
-  ShardArgs a{};
+  // the second run rewrites the same regions and only needs a larger overflow
+  ShardArgs a{cl.sc.get<uint64_t>(region * NS), region, nullptr, over_cap, ctr};
   int runs = 0;
   for (int attempt = 0; attempt < 2; ++attempt) {
-    a = ShardArgs{cl.sc.get<uint64_t>(region * NS), region, cl.sc.get<uint64_t>(over_cap),
-                  over_cap, ctr};
+    a.over = cl.sc.get<uint64_t>(over_cap);
+    a.over_cap = over_cap;
     launch_fill_u64(reinterpret_cast<uint64_t*>(ctr), 0, NS + 1, cl.s);
     launch(a);
     ++runs;
@@ -214,6 +215,7 @@ Cands sharded_output(Call& cl, uint64_t guess, const char* stage, Launch&& launc
     if (h[NS] <= over_cap) break;
     if (attempt == 1) throw Error{SD_E_HIP, "internal error: output overflow region exceeded twice"};
     over_cap = h[NS] + h[NS] / 8 + 4096;  // the same reservations spill the same amount again
+    cl.sc.release(a.over);  // the readback waited for the run: nothing uses it any more
   }
   Cands out;
   for (uint32_t x = 0; x < NS; ++x) out.n += std::min<uint64_t>(h[x], region);

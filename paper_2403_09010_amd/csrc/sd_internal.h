@@ -131,10 +131,15 @@ inline uint32_t vargen_blocks_per_tile(uint64_t nseq, uint64_t nkeys, uint32_t s
 }
 // distinct: voff counts distinct variants (launch_pack with distinct) and
 // only the canonical deletion sets are written
+// ftile != 0 (one pass, with tcounts zeroed by the caller): tcounts holds the
+// first digit's counts per fixed output tile of ftile elements (the tiles of
+// launch_counted_scatter without voff) instead of one row per block.
 void launch_vargen_hash(const u128* seq, const uint64_t* voff, uint64_t nseq, int k, bool distinct,
                         uint64_t* elem, uint32_t idbits, int npass, const uint32_t* shifts,
                         const uint32_t* masks, uint32_t* hist, uint32_t* tcounts,
-                        uint32_t seqs_per_block, hipStream_t s);
+                        uint32_t seqs_per_block, hipStream_t s, uint32_t ftile = 0);
+// elements per fixed tile of the counted passes
+uint32_t fixed_tile_elems();
 // Streamed search (column groups of hash bins): STREAM_BIN_BITS top hash
 // bits name a variant's bin. launch_vargen_bins adds every distinct
 // variant's bin to hist[1 << STREAM_BIN_BITS] (zeroed by the caller);
@@ -335,6 +340,16 @@ struct Scratch {
     T* p = dalloc_t<T>(c, count);
     blocks.push_back(p);
     return p;
+  }
+  // give one block back before the scope ends (it leaves the list, so the
+  // destructor does not free whatever later reuses its address)
+  void release(void* p) {
+    for (size_t x = 0; x < blocks.size(); ++x)
+      if (blocks[x] == p) {
+        blocks.erase(blocks.begin() + (long)x);
+        dfree(c, p);
+        return;
+      }
   }
   ~Scratch() {
     for (void* p : blocks) dfree(c, p);

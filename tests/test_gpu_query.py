@@ -171,3 +171,25 @@ def test_query_at_scale_sampled(ctx):
         truth = {(int(x), int(r), int(dist[r])) for r in np.nonzero(dist <= 2)[0]}
         sel = np.nonzero(i == x)[0]
         assert {(int(i[t]), int(j[t]), int(d[t])) for t in sel} == truth
+
+
+def test_batch_of_24_sets_against_oracle(ctx, ref, index2):
+    """24 query sets of log-uniform sizes (one empty, one larger than the
+    tile limit) in one batched call: every set's result equals the oracle's
+    query of that set alone, under the automatic tiling and under a tile
+    limit that puts the sets into many tiles."""
+    from paper_2403_09010_amd.symdel import OPT_BATCH_TILE
+    sizes = [int(x) for x in cdr3gen.loguniform_sizes(77, 24, 20, 2500)]
+    sizes[5] = 0
+    sizes[11] = 3200  # larger than the 1500-sequence tile limit below
+    sets = [cdr3gen.generate_query(300 + x, n, *ref, ref_mut_frac=0.25) if n else
+            (np.zeros(0, np.uint8), np.zeros(1, np.int64)) for x, n in enumerate(sizes)]
+    want = [oracle_query(ref, s, 2) if len(s[1]) > 1 else [] for s in sets]
+    assert sum(len(w) for w in want) > 500
+    for tile in (0, 1500):
+        ctx.set_option(OPT_BATCH_TILE, tile)
+        log(f"query_batch of 24 sets ({sum(sizes)} sequences), tile limit {tile}")
+        outs = ctx.query_batch(index2, [to_dev(*s) for s in sets], 2)
+        for x, (o, w) in enumerate(zip(outs, want)):
+            assert triples(o) == w, f"set {x} (size {sizes[x]}) differs from the oracle"
+    ctx.set_option(OPT_BATCH_TILE, 0)
