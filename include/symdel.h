@@ -201,6 +201,40 @@ int sd_paired_self_search(sd_ctx* ctx, const sd_seqs* a, const sd_seqs* b, int k
                           void* stream);
 
 /*
+ * Self search that allocates nothing: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The result equals sd_self_search's on
+ * the same context options (every pair i < j with distance <= k, sorted by
+ * (i, j)), written to the caller's device arrays out_i, out_j, out_d of
+ * `capacity` entries each; *n_out is the number of pairs.
+ *
+ * No device memory and no pinned host memory is allocated: every scratch
+ * buffer of the call is carved from a fixed device array of
+ * SD_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends (its address is resolved by sd_create), and the
+ * read-back staging area is the one sd_create allocated. The allocator hook
+ * and the HBM budget do not apply. Inputs should be device memory (host
+ * inputs are copied into the fixed array). The call returns after its work
+ * on `stream` has finished.
+ *
+ * All calls on one device share that array and each overwrites what the
+ * previous one left: calls that overlap on one device (two host threads, or
+ * streams without ordering between them) race and must not be made.
+ *
+ * Errors: as sd_self_search; SD_E_TOO_MANY for more than
+ * SD_NOALLOC_MAX_SEQS sequences; SD_E_NOMEM when the call's scratch does
+ * not fit the fixed array (heavily repeated inputs make many candidates) or
+ * when the result exceeds `capacity` (then *n_out holds the size needed and
+ * the arrays are untouched); SD_E_INVAL for a negative capacity or missing
+ * output arrays.
+ */
+#define SD_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+#define SD_NOALLOC_MAX_SEQS 16384
+int sd_self_search_noalloc(sd_ctx* ctx, const sd_seqs* seqs, int k, uint32_t* out_i,
+                           uint32_t* out_j, uint8_t* out_d, int64_t capacity, int64_t* n_out,
+                           void* stream);
+
+/*
  * Exact Levenshtein distance of n given pairs (the verification step, paper
  * Appendix A step 7): d_out[t] = Lev(a[ia[t]], b[ib[t]]) capped at 255.
  * ia, ib and d_out are device pointers; a and b follow their on_device flags.

@@ -57,7 +57,26 @@ static void* hook_alloc(sd_ctx* c, size_t sz) {
   return p;
 }
 
+// A block carved from the fixed area of a no-allocation call: 256-byte
+// aligned, in order; exhausting the area fails the call.
+static void* arena_alloc(sd_ctx* c, size_t bytes) {
+  const size_t at = (c->arena_used + 255) / 256 * 256;
+  const size_t sz = bytes ? bytes : 1;
+  if (at > c->arena_size || sz > c->arena_size - at)
+    throw Error{SD_E_NOMEM, "the fixed scratch area (" + std::to_string(c->arena_size) +
+                                " bytes) is too small for this input: " + std::to_string(at) +
+                                " bytes in use, " + std::to_string(sz) + " more needed"};
+  c->arena_used = at + sz;
+  return c->arena + at;
+}
+
+static bool in_arena(const sd_ctx* c, const void* p) {
+  const unsigned char* q = static_cast<const unsigned char*>(p);
+  return c->arena && q >= c->arena && q < c->arena + c->arena_size;
+}
+
 void* dalloc(sd_ctx* c, size_t bytes) {
+  if (c->arena) return arena_alloc(c, bytes);
   const size_t sz = size_class(bytes);
   if (c->ualloc) return hook_alloc(c, sz);
   // a cached block up to twice the size serves the request; under a budget
@@ -92,7 +111,7 @@ void* dalloc(sd_ctx* c, size_t bytes) {
 }
 
 void dfree(sd_ctx* c, void* p) {
-  if (!p) return;
+  if (!p || in_arena(c, p)) return;
   auto it = c->live.find(p);
   if (it == c->live.end()) return;
   if (c->ualloc) {
@@ -159,6 +178,9 @@ uint32_t* fresh_counters(sd_ctx* c, size_t n, hipStream_t s) {
 
 void* readback(sd_ctx* c, const void* dptr, size_t bytes, hipStream_t s) {
   if (bytes > c->pinned_bytes) {
+    if (c->arena)
+      throw Error{SD_E_NOMEM, "a read-back of " + std::to_string(bytes) +
+                                  " bytes exceeds the staging area allocated at set-up"};
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
     size_t want = bytes < 65536 ? 65536 : bytes;
@@ -288,9 +310,11 @@ int sd_create(sd_ctx** out, int device, uint64_t hbm_budget_bytes) {
   if (!c) return SD_E_NOMEM;
   c->device = device;
   c->budget = hbm_budget_bytes;
-  // the pinned staging area for small read-backs (allocated here so that no
-  // later call has to)
-  if (hipHostMalloc(&c->pinned, kPinnedStaging, hipHostMallocDefault) != hipSuccess) {
+  // set-up of the no-allocation entry point: the per-device address of its
+  // fixed scratch area, and the pinned staging area for small read-backs
+  // (allocated here so that no later call has to)
+  if (sd::noalloc_setup(device) != SD_OK ||
+      hipHostMalloc(&c->pinned, kPinnedStaging, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
@@ -439,6 +463,18 @@ int sd_paired_self_search(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, int k, 
   return guarded(c, [&] {
     sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
     sd::paired_self_search(c, a, b, k, out, static_cast<hipStream_t>(stream));
+  });
+}
+
+int sd_self_search_noalloc(sd_ctx* c, const sd_seqs* seqs, int k, uint32_t* out_i,
+                           uint32_t* out_j, uint8_t* out_d, int64_t capacity, int64_t* n_out,
+                           void* stream) {
+  if (!c || !seqs || !n_out) return SD_E_INVAL;
+  *n_out = 0;
+  return guarded(c, [&] {
+    sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
+    sd::self_search_noalloc(c, seqs, k, out_i, out_j, out_d, capacity, n_out,
+                            static_cast<hipStream_t>(stream));
   });
 }
 

@@ -258,6 +258,11 @@ struct sd_ctx {
   sd_alloc_fn ualloc = nullptr;
   sd_free_fn ufree = nullptr;
   void* uarg = nullptr;
+  // fixed-area mode (sd_self_search_noalloc): while arena is set, device
+  // blocks are carved from [arena, arena + arena_size) in order and never
+  // released one by one; the whole area is reused by the next such call
+  unsigned char* arena = nullptr;
+  size_t arena_size = 0, arena_used = 0;
   std::unordered_map<void*, int> host_live;  // pinned host result arrays
   // look-back state
   uint64_t* status = nullptr;
@@ -283,6 +288,7 @@ struct sd_ctx {
   int64_t batch_tile_seqs = 0;  // query batches: sequences per tile (0 = automatic)
   int probe = 0;                // learned indexes: 0 model window, 1 whole-array binary search
   std::map<std::string, uint64_t> out_hint;  // last output size of each sharded stage
+  std::map<std::string, uint64_t> noalloc_hint;  // the same, for no-allocation calls
   std::vector<hipEvent_t> events;
 };
 
@@ -357,6 +363,14 @@ struct Scratch {
 };
 
 void hip_check(hipError_t e, const char* what);
+// once per device, with that device current: resolve the device address of
+// the no-allocation entry point's fixed scratch area (SD_OK or SD_E_HIP)
+int noalloc_setup(int device);
+// sd_self_search_noalloc: the self search with every device block carved
+// from the device's fixed scratch area, the result copied to the caller's
+// arrays (*n_out = the result size, also when it exceeds capacity)
+void self_search_noalloc(sd_ctx* c, const sd_seqs* seqs, int k, uint32_t* out_i, uint32_t* out_j,
+                         uint8_t* out_d, int64_t capacity, int64_t* n_out, hipStream_t s);
 // look-back status area with at least `words` words; returns a fresh epoch
 uint32_t next_epoch(sd_ctx* c, uint64_t words, hipStream_t s);
 // zeroed device counters (at least n), on stream s

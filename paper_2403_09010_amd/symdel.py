@@ -23,6 +23,7 @@ ERRORS = {
 }
 SD_E_INVAL, SD_E_ALPHABET, SD_E_LENGTH, SD_E_TOO_MANY = -1, -2, -3, -4
 SD_E_NOMEM, SD_E_HIP, SD_E_CANCELLED, SD_E_STATE = -5, -6, -7, -8
+NOALLOC_MAX_SEQS = 16384
 OPT_TIMING = 1
 OPT_PATH = 2
 OPT_GROUP_CAP = 3
@@ -130,6 +131,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sd_paired_self_search.argtypes = [P, ctypes.POINTER(_Seqs), ctypes.POINTER(_Seqs), I,
                                           ctypes.POINTER(_Pairs), P]
     lib.sd_paired_self_search.restype = I
+    lib.sd_self_search_noalloc.argtypes = [P, ctypes.POINTER(_Seqs), I, P, P, P, I64,
+                                           ctypes.POINTER(I64), P]
+    lib.sd_self_search_noalloc.restype = I
     lib.sd_pair_distance.argtypes = [P, ctypes.POINTER(_Seqs), ctypes.POINTER(_Seqs), P, P, I64,
                                      P, P]
     lib.sd_pair_distance.restype = I
@@ -399,6 +403,27 @@ class Context:
         self._check(self._lib.sd_self_search(self._h, ctypes.byref(s), int(k), ctypes.byref(p),
                                              stream), "sd_self_search")
         return p
+
+    def self_search_noalloc(self, codes, offsets, k: int, out_i, out_j, out_d,
+                            stream=None) -> int:
+        """sd_self_search_noalloc: the self search into caller-owned device
+        tensors (int32 i, int32 j, uint8 d of equal length = the capacity),
+        with no allocation by the library; returns the number of pairs."""
+        s, keep, on_dev = self._seqs(codes, offsets)
+        st = _stream_handle(stream, True)
+        cap = int(out_i.numel())
+        assert out_j.numel() == cap and out_d.numel() == cap
+        n = ctypes.c_int64(0)
+        rc = self._lib.sd_self_search_noalloc(
+            self._h, ctypes.byref(s), int(k), out_i.data_ptr() if cap else None,
+            out_j.data_ptr() if cap else None, out_d.data_ptr() if cap else None, cap,
+            ctypes.byref(n), st)
+        if rc != SD_OK:
+            err = SymdelError(rc, "sd_self_search_noalloc: " + (
+                self._lib.sd_last_error(self._h).decode() or self._lib.sd_strerror(rc).decode()))
+            err.needed = int(n.value)
+            raise err
+        return int(n.value)
 
     def free_pairs(self, p: _Pairs):
         self._lib.sd_pairs_free(self._h, ctypes.byref(p))
