@@ -160,11 +160,13 @@ def make_batched_sets(ref, nsets, scale):
 
 def run_batched(args):
     """512 query sets against one 2M-sequence reference index at k=2: one set
-    per launch (sd_query) versus all sets in one batched call (sd_query_batch)."""
+    per launch (sd_query) versus all sets in one batched call (sd_query_batch),
+    eagerly in tiles and as one captured HIP graph (captured in the warm-up,
+    replayed in the timed steps)."""
     import torch
     import cdr3gen
     from paper_2403_09010_amd import Context
-    from paper_2403_09010_amd.symdel import _Seqs
+    from paper_2403_09010_amd.symdel import OPT_BATCH_GRAPH, _Seqs
     p = cdr3gen.BATCHED
     k = 2
     nsets = args.sets
@@ -207,8 +209,14 @@ def run_batched(args):
         return tot
 
     res = {}
-    for name, fn in (("plain", plain_once), ("batched", batched_once)):
-        for _ in range(args.warmup):
+    graph_stats = None
+    modes = [m for m in ("plain", "batched", "graph") if m in args.batched_modes.split(",")]
+    assert modes, "--batched-modes names none of plain, batched, graph"
+    fns = {"plain": plain_once, "batched": batched_once, "graph": batched_once}
+    for name in modes:
+        fn = fns[name]
+        ctx.set_option(OPT_BATCH_GRAPH, 1 if name == "graph" else 0)
+        for _ in range(max(1, args.warmup) if name == "graph" else args.warmup):
             fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -217,9 +225,22 @@ def run_batched(args):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         res[name] = (dt, pairs)
+        if name == "graph":
+            graph_stats = {x: ctx.stats()[x] for x in ("n_graph_captures", "n_graph_launches",
+                                                       "n_graph_retries")}
         log(f"{name}: {dt * 1e3:.1f} ms per run, {pairs} pairs")
-    assert res["plain"][1] == res["batched"][1]
-    dt, pairs = res["batched"]
+    ctx.set_option(OPT_BATCH_GRAPH, 0)
+    assert len({res[m][1] for m in modes}) == 1, {m: res[m][1] for m in modes}
+    head = modes[-1]  # the graph if timed, else the eager batch
+    dt, pairs = res[head]
+
+    def mode_rec(m):
+        if m not in res:
+            return None
+        return {"seconds": round(res[m][0], 4), "pairs_per_s": round(res[m][1] / res[m][0], 1)}
+
+    def ratio(a, b):
+        return round(res[a][0] / res[b][0], 3) if a in res and b in res else None
     out = {
         "metric": "Batched query: 512 repertoires vs 2M reference, k=2 (pairs/s)",
         "value": round(pairs / dt, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
@@ -229,10 +250,15 @@ def run_batched(args):
         "config": {"workload": "batched_2m_512", "ref_n": p["ref_n"], "sets": nsets,
                    "query_seqs": nq, "k": k, "pairs": int(pairs),
                    "index_keys": info["n_keys"], "index_build_s": round(t_index, 3)},
-        "plain_one_set_per_launch": {"seconds": round(res["plain"][0], 4),
-                                     "pairs_per_s": round(res["plain"][1] / res["plain"][0], 1)},
-        "batched": {"seconds": round(dt, 4), "pairs_per_s": round(pairs / dt, 1)},
-        "speedup_batched_vs_plain": round(res["plain"][0] / dt, 3),
+        "plain_one_set_per_launch": mode_rec("plain"),
+        "batched_tiles": mode_rec("batched"),
+        "graph": dict(mode_rec("graph"), last_call=graph_stats) if "graph" in res else None,
+        "value_is": {"graph": "pairs / seconds of one sd_query_batch call as a replayed captured graph",
+                     "batched": "pairs / seconds of one sd_query_batch call (eager tiles)",
+                     "plain": "pairs / seconds of 512 sd_query calls, one set each"}[head],
+        "speedup_graph_vs_plain": ratio("plain", "graph"),
+        "speedup_graph_vs_tiles": ratio("batched", "graph"),
+        "speedup_tiles_vs_plain": ratio("plain", "batched"),
         "autotune": tune,
     }
     idx.free()
@@ -446,6 +472,10 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=0.0,
                     help="device memory budget of the context in GiB (0: none); a search "
                          "that does not fit streams in column groups")
+    ap.add_argument("--pair-sort", type=int, default=0,
+                    help="candidate pair sort (0 auto: bucketed in LDS, 1 one-sweep, 2 counted)")
+    ap.add_argument("--batched-modes", default="plain,batched,graph",
+                    help="batched: which of plain, batched, graph to time")
     ap.add_argument("--stream", type=int, default=0, help="streamed search: 0 auto, 1 never, 2 always")
     ap.add_argument("--stream-elems", type=int, default=0, help="streamed search: variants per group (0 auto)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -468,8 +498,9 @@ def main():
     import cdr3gen
     from paper_2403_09010_amd import Context
     from paper_2403_09010_amd.symdel import (OPT_GROUP_BATCHES, OPT_GROUP_BITS, OPT_GROUP_CAP,
-                                             OPT_GROUP_SHAPE, OPT_PATH, OPT_SORT_ITEMS,
-                                             OPT_STREAM, OPT_STREAM_ELEMS, OPT_TIMING, _Seqs)
+                                             OPT_GROUP_SHAPE, OPT_PAIR_SORT, OPT_PATH,
+                                             OPT_SORT_ITEMS, OPT_STREAM, OPT_STREAM_ELEMS,
+                                             OPT_TIMING, _Seqs)
 
     gen_name, k = WORKLOADS[args.workload]
     log(f"generating {gen_name}")
@@ -498,6 +529,7 @@ def main():
     ctx.set_option(OPT_SORT_ITEMS, args.sort_items)
     ctx.set_option(OPT_GROUP_BATCHES, args.group_batches)
     ctx.set_option(OPT_GROUP_SHAPE, args.group_shape)
+    ctx.set_option(OPT_PAIR_SORT, args.pair_sort)
     ctx.set_option(OPT_STREAM, args.stream)
     ctx.set_option(OPT_STREAM_ELEMS, args.stream_elems)
 
@@ -578,7 +610,7 @@ def main():
         achieved = per_launch_bytes / per_launch_s / 1e9
         traffic = TRAFFIC_PER_LAUNCH.get((args.workload, stage))
         if (args.path or args.group_cap or args.group_bits or args.sort_items or args.group_batches
-                or args.group_shape or args.budget_gb or args.stream):
+                or args.group_shape or args.budget_gb or args.stream or args.pair_sort):
             traffic = None  # the counters were taken with the default configuration
         return {"bound": "hbm", "kernel": KERNEL_OF_STAGE[stage], "stage": stage,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -612,7 +644,8 @@ def main():
                    "seconds_per_search": round(dt, 6), "path": args.path,
                    "group_cap": args.group_cap, "group_bits": args.group_bits,
                    "sort_items": args.sort_items, "group_batches": args.group_batches,
-                   "group_shape": args.group_shape, "budget_gb": args.budget_gb,
+                   "group_shape": args.group_shape, "pair_sort": args.pair_sort,
+                   "pair_buckets": st["n_pair_buckets"], "budget_gb": args.budget_gb,
                    "stream": args.stream, "stream_groups": st["n_stream_groups"]},
         "stages_ms": {s: round(stage_ms[s] / args.steps, 4) for s in stage_ms},
         "value_is": "pairs / device time of one search, inputs resident in HBM, result left in HBM",

@@ -83,6 +83,12 @@ typedef struct {
                              grouped by a sort on the full hash instead */
   int64_t n_probe_steps;  /* learned indexes: comparisons made by the lookups' searches */
   int64_t n_stream_groups; /* streamed self search: column groups processed (0: in memory) */
+  int64_t n_graph_captures; /* batched queries: graphs captured (SD_OPT_BATCH_GRAPH) */
+  int64_t n_graph_launches; /* batched queries: graph launches (a replay reuses a capture) */
+  int64_t n_graph_retries;  /* batched queries: tiles run again eagerly after a candidate overflow */
+  int64_t n_pair_buckets;   /* self search: buckets of the LDS pair sort (0: global passes) */
+  int64_t n_pair_fallbacks; /* self search: bucketed pair sorts redone with global passes because
+                               a bucket outgrew LDS */
   char stage_name[SD_MAX_STAGES][24];
   double stage_ms[SD_MAX_STAGES];      /* device time between HIP events on `stream` */
   double stage_bytes[SD_MAX_STAGES];   /* algorithmic HBM bytes of the stage */
@@ -98,12 +104,17 @@ typedef struct {
 #define SD_OPT_BATCH_TILE 6 /* query batches: at most this many query sequences per tile (0: 4Mi) */
 #define SD_OPT_PROBE 7      /* learned indexes: 0 = search the model's window, 1 = binary search over the whole index */
 #define SD_OPT_GROUP_BATCHES 8 /* hashed path: LDS batches each workgroup groups in sequence, 0 (automatic: 4) .. 64 */
-#define SD_OPT_PAIR_SORT 9  /* candidate pair sort: 0 automatic, 1 one-sweep LSD passes, 2 counted LSD passes */
+#define SD_OPT_PAIR_SORT 9  /* candidate pair sort of self searches: 0 automatic (buckets by the
+                               top bits of i, each sorted and verified in LDS, up to 2^22
+                               sequences; else global passes), 1 one-sweep LSD passes,
+                               2 counted LSD passes */
 #define SD_OPT_METRIC 10    /* distance of the final filter of every search on the context:
                                SD_METRIC_LEVENSHTEIN (default) or SD_METRIC_HAMMING */
 #define SD_OPT_STREAM 11    /* self search in column groups of hash bins (bounded memory):
                                0 automatic (when the variants exceed 2^32 - 2 or the
                                in-memory path would exceed the budget), 1 never, 2 always */
+#define SD_OPT_BATCH_GRAPH 14 /* sd_query_batch as one captured HIP graph: 0 off (tiles with host
+                                 synchronisations), 1 on (capture once per batch shape, then replay) */
 #define SD_OPT_GROUP_SHAPE 13 /* hashed path grouping kernel at LDS capacity 2048: 0 (256 threads,
                                  five waves per SIMD), 1 (256 threads, four), 2 (512 threads, four) */
 #define SD_OPT_STREAM_ELEMS 12 /* streamed self search: variants per column group at most
@@ -420,12 +431,22 @@ void sd_server_destroy(sd_server* server);
 /*
  * Autotuner: run a sample through candidate values of the context's tunables
  * and keep the fastest in the context (results never depend on them).
- * index == NULL tunes the self search on sets[0] (nsets must be 1): grouping
- * path, SD_OPT_GROUP_CAP and SD_OPT_SORT_ITEMS. With an index it tunes
- * sd_query_batch over the nsets sets: SD_OPT_BATCH_TILE and
- * SD_OPT_SORT_ITEMS. Each candidate runs once to warm up and then `reps`
- * times (1..100); the score is the mean wall time of the call. On error the
- * context keeps its previous options.
+ * index == NULL tunes the self search on sets[0] (nsets must be 1) in two
+ * stages: a grid over the grouping path, SD_OPT_GROUP_CAP and
+ * SD_OPT_SORT_ITEMS, then, one at a time from the best of the grid,
+ * SD_OPT_GROUP_BITS (the radix width of the grouping sort: the automatic
+ * count plus one or two bits), SD_OPT_PAIR_SORT and SD_OPT_GROUP_SHAPE. With
+ * an index it tunes sd_query_batch over the nsets sets: a grid over
+ * SD_OPT_BATCH_TILE and SD_OPT_SORT_ITEMS, then SD_OPT_BATCH_GRAPH. Each
+ * candidate runs once to warm up and then `reps` times (1..100); the score
+ * is the mean wall time of the call. On error the context keeps its
+ * previous options.
+ * With a cache file set by sd_autotune_cache, a choice stored under the same
+ * key (device architecture; self, or query with floor(log2) of the
+ * reference count; floor(log2) of the sequence count and of the set count;
+ * k) is applied without trials (from_cache = 1,
+ * trials = 0, best_s = default_s = 0); otherwise the new choice is added to
+ * the file.
  */
 typedef struct {
   int32_t trials;
@@ -433,9 +454,22 @@ typedef struct {
   int64_t batch_tile;                  /* the chosen SD_OPT_BATCH_TILE */
   double best_s;                       /* mean seconds per call with the chosen options */
   double default_s;                    /* the same with the options the context had before */
+  int32_t group_bits, pair_sort;       /* the chosen SD_OPT_GROUP_BITS, SD_OPT_PAIR_SORT */
+  int32_t group_shape, batch_graph;    /* the chosen SD_OPT_GROUP_SHAPE, SD_OPT_BATCH_GRAPH */
+  int32_t from_cache;                  /* 1: applied from the cache file without trials */
+  int32_t reserved;
 } sd_tune_result;
 int sd_autotune(sd_ctx* ctx, const sd_index* index, int nsets, const sd_seqs* sets, int k,
                 int reps, sd_tune_result* out, void* stream);
+/*
+ * Set (path != NULL) or clear (path == NULL) the JSON file sd_autotune reads
+ * and writes: an object of keys "<arch>/self/s<log2 seqs>/n<log2 sets>/k<k>"
+ * or "<arch>/query/r<log2 refs>/s<log2 seqs>/n<log2 sets>/k<k>", each an object of option name -> integer. A file that does
+ * not exist or does not parse counts as empty and is rewritten whole (via a
+ * temporary file beside it) when a new choice is stored. Nothing is read
+ * until sd_autotune runs. SD_E_INVAL if path is longer than 4095 bytes.
+ */
+int sd_autotune_cache(sd_ctx* ctx, const char* path);
 
 /* Counters and stage timings of the last successful search on ctx. */
 int sd_get_stats(const sd_ctx* ctx, sd_stats* out);

@@ -12,6 +12,7 @@
 #include <unordered_set>
 #include <vector>
 
+#include "sd_host.h"
 #include "sd_internal.h"
 
 namespace sd {
@@ -328,6 +329,7 @@ int sd_create(sd_ctx** out, int device, uint64_t hbm_budget_bytes) {
 void sd_destroy(sd_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  sd::graph_plans_release(c);  // synchronises the device first
   (void)hipDeviceSynchronize();
   for (auto& kv : c->live) {
     if (c->ualloc)
@@ -381,6 +383,11 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
     case SD_OPT_PAIR_SORT:
       if (value < 0 || value > 2) return SD_E_INVAL;
       c->pair_sort = (int)value;
+      return SD_OK;
+    case SD_OPT_BATCH_GRAPH:
+      if (value < 0 || value > 1) return SD_E_INVAL;
+      c->batch_graph = (int)value;
+      if (!value) sd::graph_plans_release(c);
       return SD_OK;
     case SD_OPT_GROUP_SHAPE:
       if (value < 0 || value > 2) return SD_E_INVAL;
@@ -536,6 +543,13 @@ int sd_autotune(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
     sd::hip_check(hipSetDevice(c->device), "hipSetDevice");
     sd::autotune(c, idx, nsets, sets, k, reps, out, static_cast<hipStream_t>(stream));
   });
+}
+
+int sd_autotune_cache(sd_ctx* c, const char* path) {
+  if (!c) return SD_E_INVAL;
+  if (path && std::strlen(path) > 4095) return SD_E_INVAL;
+  c->tune_cache = path ? path : "";
+  return SD_OK;
 }
 
 int sd_mlp_gradients(sd_ctx* c, const float* params, const float* x, const float* y, uint32_t n,

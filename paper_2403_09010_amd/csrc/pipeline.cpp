@@ -273,6 +273,43 @@ Cands group_segments(Call& cl, const uint64_t* E, uint32_t nk, int cap, int bits
 
 }  // namespace
 
+uint64_t bucket_sort_verify(Call& cl, const BucketPlan& p, uint64_t* cand, uint64_t nc,
+                            uint64_t* cand2, const u128* a, const u128* sb, int k, int self_pairs,
+                            uint32_t* oi, uint32_t* oj, uint8_t* od, bool* over,
+                            const char* sort_stage, const char* verify_stage, const u128* a2,
+                            const u128* sb2) {
+  sd_ctx* c = cl.c;
+  hipStream_t s = cl.s;
+  unsigned long long* pcount = reinterpret_cast<unsigned long long*>(cl.counters + CNT_PAIRS);
+  launch_fill_u64(reinterpret_cast<uint64_t*>(pcount), 0, 1, s);
+  BucketBufs b{cl.sc.get<uint32_t>(p.counts), cl.sc.get<uint64_t>(p.counts + 1),
+               cl.sc.get<uint32_t>(p.nb),     cl.sc.get<uint64_t>(p.nb + 1),
+               nullptr,                       cl.tile_counter(),
+               0,                             cl.tile_counter(),
+               0,                             cl.lb_err()};
+  // two epochs of one status array (each scan sees only its own words)
+  b.scan_epoch = next_epoch(c, bucket_status_words(p), s);
+  b.scan2_epoch = next_epoch(c, bucket_status_words(p), s);
+  b.status = c->status;
+  launch_bucket_count(cand, nc, p.shift, p.nb, b.cnt, s);
+  launch_scan_excl(b.cnt, b.off, p.counts, b.status, b.scan_ctr, b.scan_epoch, b.err, s);
+  launch_bucket_scatter(cand, nc, p.shift, p.nb, b.off, cand2, s);
+  cl.tm.mark(sort_stage, (double)nc * 24 + (double)p.counts * 24, 3);
+  launch_bucket_verify(cand2, cand, b.off, nc, p.nb, p.jb, p.low, a, sb, k, c->metric, self_pairs,
+                       b.bcount, b.err, s, a2, sb2);
+  launch_scan_excl(b.bcount, b.bpos, p.nb, b.status, b.scan2_ctr, b.scan2_epoch, b.err, s);
+  launch_bucket_place(cand, b.off, nc, p.nb, p.jb, p.low, b.bcount, b.bpos, oi, oj, od, pcount, s);
+  cl.tm.mark(verify_stage, (double)nc * 8, 3);
+  const uint32_t* h = static_cast<const uint32_t*>(readback(c, cl.counters + CNT_PAIRS, 12, s));
+  uint64_t cntp;
+  std::memcpy(&cntp, h, 8);
+  if (h[2] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
+  if (h[2] & SD_ERRBIT_PLACEMENT) throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
+  *over = (h[2] & SD_ERRBIT_BUCKET) != 0;
+  if (*over) launch_fill_u32(cl.lb_err(), 0, 1, s);
+  return cntp;
+}
+
 // Tunables of the hashed path for a key count: the LDS capacity of a batch
 // and the number of hash bits the LSD passes sort by. Segment sizes are close
 // to Poisson(mean), so the bits are the fewest for which mean + 3.5 sqrt(mean)
@@ -311,8 +348,40 @@ Verified sort_and_verify(Call& cl, uint64_t* cand, uint64_t nc, uint64_t n, int 
   sd_ctx* c = cl.c;
   hipStream_t s = cl.s;
   if (nc >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "more than 2^32 - 2 candidate pairs"};
-  // 6: sort candidate pairs (only the digits that can differ)
   uint64_t* cand2 = cl.sc.get<uint64_t>(nc);
+  const int jb = std::max(1, bits_for(n - 1));
+  const BucketPlan bp = bucket_plan(c, nc, jb, jb);
+  if (bp.bits >= 0) {
+    // 6-7 bucketed: one scatter by the top bits of i, then per bucket a sort,
+    // the repeats dropped and the verification, all in LDS
+    c->stats.n_pair_buckets += bp.nb;
+    Verified v;
+    v.i = dalloc_t<uint32_t>(c, nc);
+    v.j = dalloc_t<uint32_t>(c, nc);
+    v.d = dalloc_t<uint8_t>(c, nc);
+    bool over = false;
+    try {
+      v.n = bucket_sort_verify(cl, bp, cand, nc, cand2,
+                               c->metric == SD_METRIC_HAMMING ? seq : planes, seq, k, 1, v.i, v.j,
+                               v.d, &over, "pair_sort", "verify", planes2, seq2);
+    } catch (...) {
+      dfree(c, v.i);
+      dfree(c, v.j);
+      dfree(c, v.d);
+      throw;
+    }
+    if (!over) return v;
+    // a bucket too large even for one workgroup's sort in global memory
+    // (very many candidates of a few sequences): sort and verify the whole
+    // bucketed copy with global passes instead (the first array was
+    // overwritten)
+    dfree(c, v.i);
+    dfree(c, v.j);
+    dfree(c, v.d);
+    c->stats.n_pair_fallbacks += 1;
+    std::swap(cand, cand2);
+  }
+  // 6: sort candidate pairs (only the digits that can differ)
   const uint64_t* sorted = cand;
   if (nc > 1) {
     const int nb = bits_for(n - 1);

@@ -135,6 +135,14 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   return v;
 }
 
+}  // namespace
+
+TileOut query_tile_eager(Call& cl, const sd_index* idx, const DevSeqs& q, int k) {
+  return query_tile(cl, idx, q, k, nullptr);
+}
+
+namespace {
+
 void check_index(const sd_ctx* c, const sd_index* idx, int k) {
   if (!idx) throw Error{SD_E_INVAL, "null index"};
   if (idx->device != c->device) throw Error{SD_E_INVAL, "index lives on another device"};
@@ -152,6 +160,35 @@ TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint6
   hipStream_t s = cl.s;
   TileOut out;
   if (nc >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "more than 2^32 - 2 candidate pairs"};
+
+  // unweighted: buckets by the top bits of q, each sorted and verified in LDS
+  const int rbits = bits_for(nr ? nr - 1 : 0), qbits = bits_for(nq ? nq - 1 : 0);
+  const BucketPlan bp = w ? BucketPlan() : bucket_plan(c, nc, qbits, rbits);
+  if (bp.bits >= 0) {
+    c->stats.n_pair_buckets += bp.nb;
+    uint64_t* cand2 = cl.sc.get<uint64_t>(nc);
+    out.i = dalloc_t<uint32_t>(c, nc);
+    out.j = dalloc_t<uint32_t>(c, nc);
+    out.d = dalloc_t<uint8_t>(c, nc);
+    bool over = false;
+    try {
+      out.n = bucket_sort_verify(cl, bp, cand, nc, cand2,
+                                 c->metric == SD_METRIC_HAMMING ? qseq : qplanes, rseq, k, 0,
+                                 out.i, out.j, out.d, &over, "q_pair_sort", "q_verify");
+    } catch (...) {
+      dfree(c, out.i);
+      dfree(c, out.j);
+      dfree(c, out.d);
+      throw;
+    }
+    if (!over) return out;
+    dfree(c, out.i);
+    dfree(c, out.j);
+    dfree(c, out.d);
+    out = TileOut();
+    c->stats.n_pair_fallbacks += 1;
+    cand = cand2;  // every candidate, bucketed (the first array was overwritten)
+  }
 
   // sort (q, r) pairs over the digits that can differ
   const uint64_t* sorted = cand;
@@ -297,30 +334,27 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
   check_index(c, idx, k);
   if (nsets < 0 || (nsets > 0 && (!sets || !outs))) throw Error{SD_E_INVAL, "bad set arrays"};
   for (int x = 0; x < nsets; ++x) check_seqs(&sets[x]);
+  // the captured-graph batch takes unweighted queries on a hashed index
+  if (c->batch_graph && !w && !idx->learned && nsets > 0) {
+    query_sets_graph(c, idx, nsets, sets, k, outs, s);
+    return;
+  }
   c->stats = sd_stats{};
   const uint64_t id_limit = (1ull << idx->idbits) - 2;
   const uint64_t tile_limit =
       std::min<uint64_t>(id_limit, c->batch_tile_seqs ? (uint64_t)c->batch_tile_seqs : (4ull << 20));
   int first = 0;
   while (first < nsets) {
-    // the tile: sets [first, last)
-    uint64_t tot = 0, codes_tot = 0;
+    // the tile: sets [first, last), whole sets while they fit
+    uint64_t tot = 0;
     int last = first;
-    std::vector<int64_t> ncodes;
+    bool all_dev = true;
     while (last < nsets) {
       const sd_seqs& st = sets[last];
       if ((uint64_t)st.n > id_limit) throw Error{SD_E_TOO_MANY, "a query set exceeds the index id width"};
       if (last > first && tot + (uint64_t)st.n > tile_limit) break;
-      int64_t nc = 0;
-      if (st.n) {
-        if (st.on_device)
-          hip_check(hipMemcpy(&nc, st.offsets + st.n, 8, hipMemcpyDeviceToHost), "read offsets");
-        else
-          nc = st.offsets[st.n];
-      }
-      ncodes.push_back(nc);
       tot += (uint64_t)st.n;
-      codes_tot += (uint64_t)nc;
+      all_dev = all_dev && (st.n == 0 || st.on_device);
       ++last;
     }
     Scratch sc(c);
@@ -329,17 +363,62 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
     // concatenate the tile's sets into one device CSR
     DevSeqs q{nullptr, nullptr, tot};
     std::vector<uint32_t> base(last - first + 1, 0);
+    {
+      uint64_t qpos = 0;
+      for (int x = first; x < last; ++x) {
+        base[x - first] = (uint32_t)qpos;
+        qpos += (uint64_t)sets[x].n;
+      }
+      base[last - first] = (uint32_t)qpos;
+    }
     if (last - first == 1 && sets[first].on_device) {
       q = DevSeqs{sets[first].codes, sets[first].offsets, (uint64_t)sets[first].n};
-      base[1] = (uint32_t)tot;
+    } else if (all_dev) {
+      // device sets: their code spans in one pass, then one gather
+      std::vector<BatchPiece> pcs;
+      for (int x = first; x < last; ++x)
+        if (sets[x].n) {
+          BatchPiece b;
+          b.set = x;
+          b.count = sets[x].n;
+          pcs.push_back(b);
+        }
+      stage_spans(c, sc, sets, pcs, false, s);
+      int64_t codes_tot = 0;
+      for (const BatchPiece& b : pcs) codes_tot += b.hi - b.lo;
+      uint8_t* codes = sc.get<uint8_t>((uint64_t)codes_tot + 1);
+      int64_t* offs = sc.get<int64_t>(tot + 1);
+      launch_fill_u64(reinterpret_cast<uint64_t*>(offs), 0, 1, s);  // (all sets empty)
+      int64_t cpos = 0;
+      for (BatchPiece& b : pcs) {
+        b.dst_offs = offs + base[b.set - first];
+        b.dst_codes = codes + cpos;
+        b.cbase = cpos;
+        cpos += b.hi - b.lo;
+      }
+      stage_gather(c, sc, sets, pcs, s);
+      q = DevSeqs{codes, offs, tot};
     } else {
+      std::vector<int64_t> ncodes;
+      uint64_t codes_tot = 0;
+      for (int x = first; x < last; ++x) {
+        const sd_seqs& st = sets[x];
+        int64_t nc = 0;
+        if (st.n) {
+          if (st.on_device)
+            hip_check(hipMemcpy(&nc, st.offsets + st.n, 8, hipMemcpyDeviceToHost), "read offsets");
+          else
+            nc = st.offsets[st.n];
+        }
+        ncodes.push_back(nc);
+        codes_tot += (uint64_t)nc;
+      }
       uint8_t* codes = sc.get<uint8_t>(codes_tot + 1);
       int64_t* offs = sc.get<int64_t>(tot + 1);
       std::vector<int64_t> hoffs(tot + 1);
       uint64_t qpos = 0, cpos = 0;
       for (int x = first; x < last; ++x) {
         const sd_seqs& st = sets[x];
-        base[x - first] = (uint32_t)qpos;
         if (st.n) {
           std::vector<int64_t> so(st.n + 1);
           if (st.on_device)
@@ -361,7 +440,6 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
         }
       }
       hoffs[tot] = (int64_t)cpos;
-      base[last - first] = (uint32_t)qpos;
       hip_check(hipMemcpyAsync(offs, hoffs.data(), (tot + 1) * 8, hipMemcpyHostToDevice, s),
                 "copy offsets");
       hip_check(hipStreamSynchronize(s), "synchronise");  // host vectors go out of scope
@@ -390,7 +468,7 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
           uint32_t* oi = dalloc_t<uint32_t>(c, n);
           uint32_t* oj = dalloc_t<uint32_t>(c, n);
           uint8_t* od = dalloc_t<uint8_t>(c, n);
-          launch_slice_rebase(r.i, r.j, r.d, lo, n, base[x], oi, oj, od, s);
+          launch_slice_rebase(r.i, r.j, r.d, lo, n, -(int64_t)base[x], oi, oj, od, s);
           finish_output(c, oi, oj, od, n, &outs[first + x], s);
         }
       } catch (...) {

@@ -301,12 +301,13 @@ __global__ __launch_bounds__(QNT) void k_verify_weighted(
 // bounds[s] = first result index whose query id is >= set_base[s] (s <= nsets,
 // set_base[nsets] = total queries); the result's query ids are ascending.
 __global__ void k_set_ranges(const uint32_t* __restrict__ qi, uint64_t n,
+                             const unsigned long long* __restrict__ n_dev,
                              const uint32_t* __restrict__ set_base, uint32_t nb,
                              uint64_t* __restrict__ bounds) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nb) return;
   const uint32_t key = set_base[s];
-  uint64_t lo = 0, hi = n;
+  uint64_t lo = 0, hi = n_dev ? min(n, (uint64_t)*n_dev) : n;
   while (lo < hi) {
     const uint64_t mid = (lo + hi) >> 1;
     if (qi[mid] < key)
@@ -319,14 +320,72 @@ __global__ void k_set_ranges(const uint32_t* __restrict__ qi, uint64_t n,
 
 __global__ void k_slice_rebase(const uint32_t* __restrict__ qi, const uint32_t* __restrict__ rj,
                                const uint8_t* __restrict__ d, uint64_t lo, uint64_t n,
-                               uint32_t base, uint32_t* __restrict__ oi,
+                               int64_t shift, uint32_t* __restrict__ oi,
                                uint32_t* __restrict__ oj, uint8_t* __restrict__ od) {
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (uint64_t)gridDim.x * blockDim.x) {
-    oi[t] = qi[lo + t] - base;
+    oi[t] = (uint32_t)((int64_t)qi[lo + t] + shift);
     oj[t] = rj[lo + t];
     od[t] = d[lo + t];
   }
+}
+
+// ------------------------------------------------------------------ batch staging
+//
+// The sets of a batch arrive as separate device CSR arrays. Instead of one
+// synchronous read of every set's offsets, two kernels stage a whole batch:
+// k_stage_spans reads every piece's offsets once (the length histogram, the
+// code span, the offset checks) for one read-back, and k_stage_gather writes
+// the tiles' concatenated CSR.
+
+constexpr uint32_t STAGE_CHUNK = 8192;  // sequences per workgroup
+using sd::STAGE_BINS;
+using sd::StageChunk;
+using sd::StagePiece;
+
+__global__ __launch_bounds__(QNT) void k_stage_spans(const StagePiece* __restrict__ pieces,
+                                                     const StageChunk* __restrict__ chunks,
+                                                     uint32_t* __restrict__ hist,
+                                                     int64_t* __restrict__ spans,
+                                                     uint32_t* __restrict__ err) {
+  __shared__ uint32_t s_h[STAGE_BINS];
+  const StageChunk ch = chunks[blockIdx.x];
+  const StagePiece P = pieces[ch.piece];
+  if (hist)
+    for (uint32_t b = threadIdx.x; b < STAGE_BINS; b += QNT) s_h[b] = 0;
+  __syncthreads();
+  bool bad = false;
+  for (int64_t y = ch.first + threadIdx.x; y < ch.first + ch.count; y += QNT) {
+    const int64_t a = P.offs[y], b = P.offs[y + 1];
+    const int64_t L = b - a;
+    bad |= L < 0 || (y == 0 && a != 0);
+    if (hist) atomicAdd(&s_h[L >= 1 && L <= KEY_MAX_LEN ? (uint32_t)L : 0u], 1u);
+  }
+  if (bad) atomicOr(err, SD_ERRBIT_OFFSETS);
+  __syncthreads();
+  if (hist)
+    for (uint32_t b = threadIdx.x; b < STAGE_BINS; b += QNT)
+      if (s_h[b]) atomicAdd(&hist[(uint64_t)ch.piece * STAGE_BINS + b], s_h[b]);
+  if (threadIdx.x == 0) {
+    if (ch.first == P.first) spans[2 * (uint64_t)ch.piece] = P.offs[P.first];
+    if (ch.first + ch.count == P.first + P.count)
+      spans[2 * (uint64_t)ch.piece + 1] = P.offs[P.first + P.count];
+  }
+}
+
+// Tile offsets (each piece's rebased by its code base) and codes (the
+// chunk's contiguous code span, copied byte-coalesced).
+__global__ __launch_bounds__(QNT) void k_stage_gather(const StagePiece* __restrict__ pieces,
+                                                      const StageChunk* __restrict__ chunks) {
+  const StageChunk ch = chunks[blockIdx.x];
+  const StagePiece P = pieces[ch.piece];
+  const int64_t shift = P.cbase - P.lo;
+  for (int64_t y = ch.first + threadIdx.x; y < ch.first + ch.count; y += QNT)
+    P.dst_offs[y - P.first] = P.offs[y] + shift;
+  if (threadIdx.x == 0 && ch.first + ch.count == P.first + P.count)
+    P.dst_offs[P.count] = P.offs[P.first + P.count] + shift;
+  const int64_t c0 = P.offs[ch.first], c1 = P.offs[ch.first + ch.count];
+  for (int64_t b = c0 + threadIdx.x; b < c1; b += QNT) P.dst_codes[b - P.lo] = P.codes[b];
 }
 
 }  // namespace sdk
@@ -370,21 +429,36 @@ void launch_verify_weighted(const uint64_t* cand, uint64_t c, const u128* sa, co
                      tile_counter, epoch, out_count, err);
 }
 
+uint32_t stage_chunk() { return sdk::STAGE_CHUNK; }
+
+void launch_stage_spans(const StagePiece* pieces, const StageChunk* chunks, uint32_t nchunks,
+                        uint32_t* hist, int64_t* spans, uint32_t* err, hipStream_t s) {
+  if (!nchunks) return;
+  hipLaunchKernelGGL(sdk::k_stage_spans, dim3(nchunks), dim3(sdk::QNT), 0, s, pieces, chunks, hist,
+                     spans, err);
+}
+
+void launch_stage_gather(const StagePiece* pieces, const StageChunk* chunks, uint32_t nchunks,
+                         hipStream_t s) {
+  if (!nchunks) return;
+  hipLaunchKernelGGL(sdk::k_stage_gather, dim3(nchunks), dim3(sdk::QNT), 0, s, pieces, chunks);
+}
+
 void launch_set_ranges(const uint32_t* qi, uint64_t n, const uint32_t* set_base, uint32_t nb,
-                       uint64_t* bounds, hipStream_t s) {
+                       uint64_t* bounds, hipStream_t s, const unsigned long long* n_dev) {
   if (!nb) return;
-  hipLaunchKernelGGL(sdk::k_set_ranges, dim3((nb + 255) / 256), dim3(256), 0, s, qi, n, set_base,
-                     nb, bounds);
+  hipLaunchKernelGGL(sdk::k_set_ranges, dim3((nb + 255) / 256), dim3(256), 0, s, qi, n, n_dev,
+                     set_base, nb, bounds);
 }
 
 void launch_slice_rebase(const uint32_t* qi, const uint32_t* rj, const uint8_t* d, uint64_t lo,
-                         uint64_t n, uint32_t base, uint32_t* oi, uint32_t* oj, uint8_t* od,
+                         uint64_t n, int64_t shift, uint32_t* oi, uint32_t* oj, uint8_t* od,
                          hipStream_t s) {
   if (!n) return;
   uint64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(sdk::k_slice_rebase, dim3((unsigned)g), dim3(256), 0, s, qi, rj, d, lo, n,
-                     base, oi, oj, od);
+                     shift, oi, oj, od);
 }
 
 }  // namespace sd

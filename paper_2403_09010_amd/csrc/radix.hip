@@ -513,16 +513,18 @@ __global__ __launch_bounds__(256) void k_gather_shards(const uint64_t* __restric
                                                        uint64_t over_cap,
                                                        const unsigned long long* __restrict__ counter,
                                                        const uint64_t* __restrict__ off,
-                                                       uint64_t* __restrict__ out) {
+                                                       uint64_t* __restrict__ out, uint64_t cap) {
   const uint32_t sh = blockIdx.x;
   if (sh < OUT_SHARDS) {
-    const uint64_t cnt = min((uint64_t)counter[sh], region);
+    const uint64_t o = off[sh];
+    const uint64_t cnt = min(min((uint64_t)counter[sh], region), o < cap ? cap - o : 0);
     const uint64_t* src = base + (uint64_t)sh * region;
-    uint64_t* dst = out + off[sh];
+    uint64_t* dst = out + o;
     for (uint64_t x = threadIdx.x; x < cnt; x += 256) dst[x] = src[x];
   } else {
-    const uint64_t cnt = min((uint64_t)counter[OUT_SHARDS], over_cap);
-    uint64_t* dst = out + off[OUT_SHARDS];
+    const uint64_t o = off[OUT_SHARDS];
+    const uint64_t cnt = min(min((uint64_t)counter[OUT_SHARDS], over_cap), o < cap ? cap - o : 0);
+    uint64_t* dst = out + o;
     const uint64_t nb = gridDim.x - OUT_SHARDS;
     for (uint64_t x = (uint64_t)(sh - OUT_SHARDS) * 256 + threadIdx.x; x < cnt; x += nb * 256)
       dst[x] = over[x];
@@ -564,10 +566,10 @@ uint32_t out_shards() { return OUT_SHARDS; }
 // off: OUT_SHARDS + 1 scratch words
 void launch_gather_shards(const uint64_t* base, uint64_t region, const uint64_t* over,
                           uint64_t over_cap, const unsigned long long* counter, uint64_t* off,
-                          uint64_t* out, hipStream_t s) {
+                          uint64_t* out, hipStream_t s, uint64_t cap) {
   hipLaunchKernelGGL(sdk::k_shard_offsets, dim3(1), dim3(OUT_SHARDS), 0, s, counter, region, off);
   hipLaunchKernelGGL(sdk::k_gather_shards, dim3(OUT_SHARDS + 256), dim3(256), 0, s, base, region,
-                     over, over_cap, counter, off, out);
+                     over, over_cap, counter, off, out, cap);
 }
 
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {

@@ -47,6 +47,8 @@ inline void raise_validation(uint32_t err) {
   if (err & SD_ERRBIT_LENGTH) throw Error{SD_E_LENGTH, "a sequence length is outside [1, 24]"};
   if (err & SD_ERRBIT_ALPHABET) throw Error{SD_E_ALPHABET, "a residue code is >= 20"};
   if (err & SD_ERRBIT_INDEX) throw Error{SD_E_INVAL, "an index is out of range"};
+  if (err & SD_ERRBIT_OFFSETS)
+    throw Error{SD_E_INVAL, "offsets must start at 0 and must not decrease"};
 }
 
 inline int bits_for(uint64_t maxval) {
@@ -174,6 +176,112 @@ inline bool pair_sort_counted(const sd_ctx* c, uint64_t nc) {
   return nc >= (1u << 21);
 }
 
+// Bucketed pair sort (steps 6-7): candidates (i << 32 | j) go to buckets by
+// the top `bits` bits of i, and each bucket is sorted, deduplicated and
+// verified in one workgroup's LDS. About 2048 candidates per bucket (a
+// quarter of what LDS holds), at most bucket_max() buckets, and enough
+// bucket bits that i's remaining bits and j fit a 32-bit key.
+struct BucketPlan {
+  int bits = -1;  // -1: the bucketed sort does not apply
+  uint32_t nb = 0, low = 0, jb = 0, shift = 0;
+  uint64_t ntiles = 0;  // counting tiles
+  uint64_t counts = 0;  // entries of the count table (and of its scan, plus one)
+};
+
+// For nc candidates whose first ids have ib bits and second ids jb bits.
+// SD_OPT_PAIR_SORT 1 and 2 choose the global passes instead.
+inline BucketPlan bucket_plan(const sd_ctx* c, uint64_t nc, int ib, int jb) {
+  BucketPlan p;
+  if (c->pair_sort == 1 || c->pair_sort == 2 || nc == 0) return p;
+  ib = std::max(ib, 1);
+  jb = std::max(jb, 1);
+  int b = 0;
+  while (b < 12 && (nc >> b) > 2048) ++b;
+  b = std::min(std::max(b, ib + jb - 32), ib);
+  if (b > bits_for(bucket_max() - 1) || ib - b + jb > 32) return p;
+  p.bits = b;
+  p.nb = 1u << b;
+  p.low = (uint32_t)(ib - b);
+  p.jb = (uint32_t)jb;
+  p.shift = 32 + p.low;
+  p.ntiles = (nc + bucket_chunk() - 1) / bucket_chunk();
+  p.counts = p.ntiles * p.nb;
+  return p;
+}
+
+// The buffers and look-back state of one bucketed sort: the count table and
+// its scan (p.counts and p.counts + 1 entries), the bucket pair counts and
+// their scan (p.nb and p.nb + 1), a status array of at least the scan tiles
+// of p.counts words, two zeroed tile counters and the two scans' epochs.
+struct BucketBufs {
+  uint32_t* cnt;
+  uint64_t* off;
+  uint32_t* bcount;
+  uint64_t* bpos;
+  uint64_t* status;
+  uint32_t* scan_ctr;
+  uint32_t scan_epoch;
+  uint32_t* scan2_ctr;
+  uint32_t scan2_epoch;
+  uint32_t* err;
+};
+
+// Status words the two scans of a bucketed sort need.
+inline uint64_t bucket_status_words(const BucketPlan& p) {
+  return (std::max<uint64_t>(p.counts, p.nb) + scan_tile() - 1) / scan_tile() + 1;
+}
+
+// Count, scan and scatter into cand2 (nc entries), then sort and verify
+// every bucket and place its pairs; the pair count goes to *pcount. No host
+// synchronisation (a capture can hold it). cand is overwritten (it holds
+// every bucket's packed pairs, and large buckets are sorted through it); a
+// bucket too large even for that sets SD_ERRBIT_BUCKET.
+inline void bucket_enqueue(const BucketPlan& p, const BucketBufs& b, uint64_t* cand,
+                           uint64_t nc, uint64_t* cand2, const u128* a, const u128* sb, int k,
+                           int metric, int self_pairs, uint32_t* oi, uint32_t* oj, uint8_t* od,
+                           unsigned long long* pcount, hipStream_t s, const u128* a2 = nullptr,
+                           const u128* sb2 = nullptr) {
+  launch_bucket_count(cand, nc, p.shift, p.nb, b.cnt, s);
+  launch_scan_excl(b.cnt, b.off, p.counts, b.status, b.scan_ctr, b.scan_epoch, b.err, s);
+  launch_bucket_scatter(cand, nc, p.shift, p.nb, b.off, cand2, s);
+  launch_bucket_verify(cand2, cand, b.off, nc, p.nb, p.jb, p.low, a, sb, k, metric, self_pairs,
+                       b.bcount, b.err, s, a2, sb2);
+  launch_scan_excl(b.bcount, b.bpos, p.nb, b.status, b.scan2_ctr, b.scan2_epoch, b.err, s);
+  launch_bucket_place(cand, b.off, nc, p.nb, p.jb, p.low, b.bcount, b.bpos, oi, oj, od, pcount, s);
+}
+
+// The eager form on a call's scratch and status array: returns the pair
+// count, or sets *over when a bucket was too large (the output is then
+// incomplete, and the caller sorts cand2, which holds every candidate, the
+// other way; cand is overwritten).
+uint64_t bucket_sort_verify(Call& cl, const BucketPlan& p, uint64_t* cand, uint64_t nc,
+                            uint64_t* cand2, const u128* a, const u128* sb, int k, int self_pairs,
+                            uint32_t* oi, uint32_t* oj, uint8_t* od, bool* over,
+                            const char* sort_stage, const char* verify_stage,
+                            const u128* a2 = nullptr, const u128* sb2 = nullptr);
+
+// A run of consecutive sequences of one set of a batch, and what staging
+// learns and needs of it.
+struct BatchPiece {
+  int set = 0;
+  int64_t first = 0, count = 0;  // the set's sequences [first, first + count)
+  int64_t lo = 0, hi = 0;        // offs[first], offs[first + count] (stage_spans)
+  uint32_t hist[STAGE_BINS] = {};  // sequences per length (stage_spans with want_hist)
+  int64_t* dst_offs = nullptr;   // where stage_gather writes the piece's count + 1 offsets
+  uint8_t* dst_codes = nullptr;  // and its codes
+  int64_t cbase = 0;             // the code position dst_codes stands for
+};
+
+// Device sets only: the spans (and, with want_hist, the length histograms)
+// of every piece after one pass and one read-back. Raises SD_E_INVAL for bad
+// offsets and SD_E_LENGTH for a length outside [1, 24] (with want_hist).
+void stage_spans(sd_ctx* c, Scratch& sc, const sd_seqs* sets, std::vector<BatchPiece>& pieces,
+                 bool want_hist, hipStream_t s);
+// Write every piece's rebased offsets and codes (one launch); returns after
+// the copies are done.
+void stage_gather(sd_ctx* c, Scratch& sc, const sd_seqs* sets,
+                  const std::vector<BatchPiece>& pieces, hipStream_t s);
+
 struct Cands {
   uint64_t* p = nullptr;  // pool block owned by the caller
   uint64_t n = 0;
@@ -287,6 +395,14 @@ SortedKeys full_key_sort(Call& cl, uint64_t* klo, uint64_t* khi, uint32_t* kid, 
 
 // one query tile against a learned index (probe lookups, then verification)
 TileOut learned_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const WeightedSpec* w);
+// one tile of queries through the eager pipeline (host synchronisations
+// included): (tile-local q, r, d) sorted by (q, r)
+TileOut query_tile_eager(Call& cl, const sd_index* idx, const DevSeqs& q, int k);
+// sd_query_batch as one captured graph (graphbatch.cpp)
+void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, int k,
+                      sd_pairs* outs, hipStream_t s);
+// release the context's captured batch plans (waits for the device)
+void graph_plans_release(sd_ctx* c);
 
 // Hand a finished result (pool blocks oi/oj/od holding n triplets) to the
 // caller: device arrays as they are, or pinned host copies.

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -20,6 +21,8 @@ typedef unsigned __int128 u128;
 #define SD_ERRBIT_INDEX 4u
 #define SD_ERRBIT_LOOKBACK 8u  // a look-back wait hit its bound (internal error)
 #define SD_ERRBIT_PLACEMENT 16u  // a counted pass computed a position past the end (internal error)
+#define SD_ERRBIT_BUCKET 32u  // a pair bucket exceeded what one workgroup sorts (the host takes another path)
+#define SD_ERRBIT_OFFSETS 64u  // a set's offsets do not start at 0 or decrease
 
 namespace sd {
 
@@ -27,9 +30,13 @@ namespace sd {
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 uint32_t out_shards();
+// (writes stop at cap elements of out; off[] receives the shard offsets and,
+// at [OUT_SHARDS], the overflow's offset, so the total is off[OUT_SHARDS] +
+// min(counter[OUT_SHARDS], over_cap))
 void launch_gather_shards(const uint64_t* base, uint64_t region, const uint64_t* over,
                           uint64_t over_cap, const unsigned long long* counter, uint64_t* off,
-                          uint64_t* out, hipStream_t s);
+                          uint64_t* out, hipStream_t s,
+                          uint64_t cap = ~0ull);
 // a sharded output as passed to the producing kernels (sd_device.h ShardOut)
 struct ShardArgs {
   uint64_t* base;
@@ -75,6 +82,38 @@ void launch_counted_scatter(const uint64_t* in, uint64_t* out, uint32_t n, int s
                             const uint64_t* voff, uint32_t seqs_per_tile, uint64_t nseq,
                             uint32_t* err, hipStream_t s);
 uint64_t scan_tile();
+// Bucketed pair sort (steps 6-7): candidates per counting tile, the largest
+// bucket sorted in LDS, the most buckets.
+uint32_t bucket_chunk();
+uint32_t bucket_cap();
+uint32_t bucket_max();
+// cnt[b * ntiles + t] = candidates of tile t (bucket_chunk() each) whose
+// value >> shift is b, for b < nb <= bucket_max().
+void launch_bucket_count(const uint64_t* cand, uint64_t nc, uint32_t shift, uint32_t nb,
+                         uint32_t* cnt, hipStream_t s);
+// Scatter by bucket from the exclusive scan `off` of that table (bucket-major).
+void launch_bucket_scatter(const uint64_t* cand, uint64_t nc, uint32_t shift, uint32_t nb,
+                           const uint64_t* off, uint64_t* out, hipStream_t s);
+// Per bucket (the range off[b * ntiles] .. of cand): sort, drop repeats
+// (and i >= j if self_pairs), verify as launch_verify_compact does, and
+// write the kept pairs in order, packed as key << 8 | distance (key = i's
+// `low` bits below the bucket bits above j's jb bits, low + jb <= 32), at
+// the start of the bucket's range of scratch; bcount[b] = their number. A
+// bucket over bucket_cap() candidates is sorted through scratch and its own
+// range of cand (both overwritten). A bucket over 2^18 candidates, or one
+// that cannot be cut into pieces of bucket_cap(), sets SD_ERRBIT_BUCKET in
+// *err and counts 0. Values >> shift >= nb (the ~0 of an unused candidate
+// slot) are in no bucket.
+void launch_bucket_verify(uint64_t* cand, uint64_t* scratch, const uint64_t* off, uint64_t nc,
+                          uint32_t nb, uint32_t jb, uint32_t low, const u128* a, const u128* seq_b,
+                          int k, int metric, int self_pairs, uint32_t* bcount, uint32_t* err,
+                          hipStream_t s, const u128* a2 = nullptr, const u128* seq_b2 = nullptr);
+// Every bucket's packed pairs to out_*[bpos[b] ..) (bpos = exclusive scan of
+// bcount, nb + 1 entries); *out_count = bpos[nb].
+void launch_bucket_place(const uint64_t* packed, const uint64_t* off, uint64_t nc, uint32_t nb,
+                         uint32_t jb, uint32_t low, const uint32_t* bcount, const uint64_t* bpos,
+                         uint32_t* out_i, uint32_t* out_j, uint8_t* out_d,
+                         unsigned long long* out_count, hipStream_t s);
 void launch_scan_excl(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* status,
                       uint32_t* tile_counter, uint32_t epoch, uint32_t* err, hipStream_t s);
 
@@ -203,10 +242,41 @@ void launch_verify_weighted(const uint64_t* cand, uint64_t c, const u128* sa, co
                             uint32_t* oi, uint32_t* oj, uint8_t* od, uint64_t* status,
                             uint32_t* tile_counter, uint32_t epoch, unsigned long long* out_count,
                             uint32_t* err, hipStream_t s);
+// bounds[s] = first position of qi[0, n) (n = min(n, *n_dev) with n_dev) whose
+// value is >= set_base[s]
+// Batch staging. A piece is a run of consecutive sequences of one device
+// set; a chunk is at most stage_chunk() sequences of one piece (one
+// workgroup each).
+struct StagePiece {
+  const int64_t* offs;   // the set's offsets (device)
+  const uint8_t* codes;  // the set's codes (device)
+  int64_t first, count;  // the piece's sequences in the set
+  int64_t* dst_offs;     // tile offsets at the piece's first tile-local id
+  uint8_t* dst_codes;    // tile codes at the piece's first code
+  int64_t lo;            // offs[first] (from the spans pass)
+  int64_t cbase;         // the piece's first code position in the tile
+};
+struct StageChunk {
+  uint32_t piece, pad;
+  int64_t first, count;
+};
+constexpr uint32_t STAGE_BINS = 26;  // length histogram: bin L for 1 <= L <= 24, bin 0 otherwise
+uint32_t stage_chunk();
+// Per piece: hist[piece * STAGE_BINS + L] += sequences of length L (hist may
+// be null), spans[2 piece] = offs[first], spans[2 piece + 1] =
+// offs[first + count]; SD_ERRBIT_OFFSETS in *err if a set's first offset is
+// not 0 or an offset decreases.
+void launch_stage_spans(const StagePiece* pieces, const StageChunk* chunks, uint32_t nchunks,
+                        uint32_t* hist, int64_t* spans, uint32_t* err, hipStream_t s);
+// Per piece: dst_offs[0..count] = offs[first..first + count] - lo + cbase
+// and the codes [lo, offs[first + count]) to dst_codes.
+void launch_stage_gather(const StagePiece* pieces, const StageChunk* chunks, uint32_t nchunks,
+                         hipStream_t s);
 void launch_set_ranges(const uint32_t* qi, uint64_t n, const uint32_t* set_base, uint32_t nb,
-                       uint64_t* bounds, hipStream_t s);
+                       uint64_t* bounds, hipStream_t s, const unsigned long long* n_dev = nullptr);
+// oi[t] = qi[lo + t] + shift, oj[t] = rj[lo + t], od[t] = d[lo + t] for t < n
 void launch_slice_rebase(const uint32_t* qi, const uint32_t* rj, const uint8_t* d, uint64_t lo,
-                         uint64_t n, uint32_t base, uint32_t* oi, uint32_t* oj, uint8_t* od,
+                         uint64_t n, int64_t shift, uint32_t* oi, uint32_t* oj, uint8_t* od,
                          hipStream_t s);
 // learned index
 size_t leaf_bytes();
@@ -236,6 +306,8 @@ void launch_probe(const u128* qseq, const uint64_t* qvoff, uint64_t nq, const u1
                   hipStream_t s);
 
 // ------------------------------------------------------------------ errors
+
+struct GraphPlan;  // a captured batched query (graphbatch.cpp)
 
 struct Error {
   int code;
@@ -286,10 +358,17 @@ struct sd_ctx {
   int stream = 0;              // streamed self search: 0 automatic, 1 never, 2 always
   uint64_t stream_elems = 0;   // elements per column group (0: from the budget)
   int64_t batch_tile_seqs = 0;  // query batches: sequences per tile (0 = automatic)
+  std::string tune_cache;       // autotuner cache file (empty: none)
   int probe = 0;                // learned indexes: 0 model window, 1 whole-array binary search
   std::map<std::string, uint64_t> out_hint;  // last output size of each sharded stage
   std::map<std::string, uint64_t> noalloc_hint;  // the same, for no-allocation calls
   std::vector<hipEvent_t> events;
+  // graph-captured batches (SD_OPT_BATCH_GRAPH): the cached plan of the last
+  // batch shape, and the candidates per query variant seen so far (sizes the
+  // candidate capacity of the next plan)
+  int batch_graph = 0;
+  std::vector<std::shared_ptr<sd::GraphPlan>> graph_plans;
+  double graph_cand_ratio = 1.0 / 8.0;
 };
 
 // A reference deletion index. Hashed kind: every <= k-deletion variant of

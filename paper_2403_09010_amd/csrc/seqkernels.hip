@@ -237,18 +237,52 @@ __global__ __launch_bounds__(NT) void k_emit_runs(const uint64_t* __restrict__ k
 // ------------------------------------------------------------------ verify
 
 constexpr int CITEMS = 8;
+constexpr uint8_t DROP = 0xFFu;  // verdict of a pair over k
+
+// The final filter of one candidate pair (i, j): its distance, or DROP.
+// MODE 0: pa holds the bit-plane form of the first sequences (pack's planes)
+// and the distance is Levenshtein; MODE 1: pa holds their packed keys and the
+// distance is Hamming over equal lengths; MODE 2 (paired-chain records): pa
+// and sb are the first chains (planes, keys), pa2 and sb2 the second, and the
+// distance is the sum of the two chains' Levenshtein distances. The length
+// difference bounds each distance from below and skips most far pairs.
+template <int MODE>
+__device__ __forceinline__ uint8_t pair_verdict(const u128* __restrict__ pa,
+                                                const u128* __restrict__ sb,
+                                                const u128* __restrict__ pa2,
+                                                const u128* __restrict__ sb2, uint32_t i,
+                                                uint32_t j, int k) {
+  const u128 a = pa[i], b = sb[j];
+  const int la = (int)(a >> 120), lb = (int)key_len(b);
+  if (MODE == 1) {
+    if (la == lb) {
+      const uint32_t dd = hamming_keys(a, b);
+      if (dd <= (uint32_t)k) return (uint8_t)dd;
+    }
+  } else if (MODE == 2) {
+    const u128 a2 = pa2[i], b2 = sb2[j];
+    const int la2 = (int)(a2 >> 120), lb2 = (int)key_len(b2);
+    if (abs(la - lb) + abs(la2 - lb2) <= k) {
+      const uint32_t d1 = lev_planes(a, b);
+      if (d1 <= (uint32_t)k) {
+        const uint32_t dd = d1 + lev_planes(a2, b2);
+        if (dd <= (uint32_t)k) return (uint8_t)dd;
+      }
+    }
+  } else if (abs(la - lb) <= k) {
+    const uint32_t dd = lev_planes(a, b);
+    if (dd <= (uint32_t)k) return (uint8_t)dd;
+  }
+  return DROP;
+}
 
 // A tile of NT * CITEMS sorted candidates per workgroup. Repeats (a candidate
 // equal to its predecessor) are dropped first and the distinct candidates
 // listed in LDS in order; the distances then run over that dense list, each
 // thread taking a contiguous piece, so a wave does not run the distance once
 // per candidate slot while most of its lanes hold repeats. Kept pairs are
-// written in candidate order after a look-back over the tiles.
-// MODE 0: pa holds the bit-plane form of the first sequences (pack's planes)
-// and the distance is Levenshtein; MODE 1: pa holds their packed keys and the
-// distance is Hamming over equal lengths; MODE 2 (paired-chain records): pa
-// and sb are the first chains (planes, keys), pa2 and sb2 the second, and the
-// distance is the sum of the two chains' Levenshtein distances.
+// written in candidate order after a look-back over the tiles. MODE and the
+// sequence arrays are those of pair_verdict.
 template <int MODE>
 __global__ __launch_bounds__(NT) void k_verify_compact(
     const uint64_t* __restrict__ cand, uint64_t c, const u128* __restrict__ pa,
@@ -258,7 +292,6 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
     uint32_t* __restrict__ tile_counter, uint32_t epoch, unsigned long long* __restrict__ out_count,
     uint32_t* __restrict__ err) {
   constexpr int TILE = NT * CITEMS;
-  constexpr uint8_t DROP = 0xFFu;
   __shared__ uint32_t s_tile;
   __shared__ uint32_t s_tmp[NT / 64];
   __shared__ uint64_t s_excl;
@@ -279,7 +312,8 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
     // a self search pairs i < j only (a candidate of one sequence with itself
     // can come from two of its variants that share a hash)
     const bool ordered = !self_pairs || (uint32_t)(vals[x] >> 32) < (uint32_t)vals[x];
-    if (e < c && (e == 0 || vals[x] != prev) && ordered) umask |= 1u << x;
+    // ~0 marks an unused slot of a fixed-capacity candidate array (it sorts last)
+    if (e < c && (e == 0 || vals[x] != prev) && ordered && vals[x] != ~0ull) umask |= 1u << x;
     prev = vals[x];
   }
   uint32_t ntot;
@@ -293,28 +327,7 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
   uint32_t cnt = 0;
   for (uint32_t l = l0; l < l1; ++l) {
     const uint64_t v = s_list[l];
-    const u128 a = pa[v >> 32], b = sb[(uint32_t)v];
-    const int la = (int)(a >> 120), lb = (int)key_len(b);
-    uint8_t d = DROP;
-    if (MODE == 1) {
-      if (la == lb) {
-        const uint32_t dd = hamming_keys(a, b);
-        if (dd <= (uint32_t)k) d = (uint8_t)dd;
-      }
-    } else if (MODE == 2) {
-      const u128 a2 = pa2[v >> 32], b2 = sb2[(uint32_t)v];
-      const int la2 = (int)(a2 >> 120), lb2 = (int)key_len(b2);
-      if (abs(la - lb) + abs(la2 - lb2) <= k) {
-        const uint32_t d1 = lev_planes(a, b);
-        if (d1 <= (uint32_t)k) {
-          const uint32_t dd = d1 + lev_planes(a2, b2);
-          if (dd <= (uint32_t)k) d = (uint8_t)dd;
-        }
-      }
-    } else if (abs(la - lb) <= k) {
-      const uint32_t dd = lev_planes(a, b);
-      if (dd <= (uint32_t)k) d = (uint8_t)dd;
-    }
+    const uint8_t d = pair_verdict<MODE>(pa, sb, pa2, sb2, (uint32_t)(v >> 32), (uint32_t)v, k);
     s_dist[l] = d;  // read back below by this thread only
     cnt += d != DROP;
   }
@@ -334,6 +347,339 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
     }
   }
   if (threadIdx.x == 0 && tile == gridDim.x - 1) *out_count = s_excl + total;
+}
+
+// ------------------------------------------------------------------ bucketed pair sort
+//
+// Steps 6-7 in one sort pass over HBM: candidates (i << 32 | j) are first
+// scattered into buckets by the top B bits of i (counted per tile, one
+// exclusive scan over the bucket-major count table, a scatter with LDS
+// cursors); every bucket then fits one workgroup's LDS, where it is sorted,
+// deduplicated and verified, and its kept pairs are written in order after a
+// look-back over the buckets. Within a bucket the key (i's low bits, j)
+// fits 32 bits. Buckets hold candidates of disjoint i ranges in increasing
+// order, so the concatenation of the sorted buckets is the sorted array.
+
+constexpr int PB_NT = 512;             // threads of the bucket kernels
+constexpr int PB_NW = PB_NT / 64;
+constexpr uint32_t PB_CHUNK = 16384;   // candidates per counting tile
+constexpr uint32_t PB_MAX_BUCKETS = 4096;
+constexpr uint32_t PB_CAP = 8192;      // largest bucket sorted in LDS
+
+// cnt[b * ntiles + t] = candidates of tile t in bucket b (v >> shift)
+__global__ __launch_bounds__(PB_NT) void k_bucket_count(const uint64_t* __restrict__ cand,
+                                                        uint64_t nc, uint32_t shift, uint32_t nb,
+                                                        uint32_t ntiles,
+                                                        uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t s_h[PB_MAX_BUCKETS];
+  for (uint32_t b = threadIdx.x; b < nb; b += PB_NT) s_h[b] = 0;
+  __syncthreads();
+  const uint64_t t = blockIdx.x;
+  const uint64_t e0 = t * PB_CHUNK, e1 = min<uint64_t>(nc, e0 + PB_CHUNK);
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += PB_NT) {
+    const uint32_t b = (uint32_t)(cand[e] >> shift);
+    if (b < nb) atomicAdd(&s_h[b], 1u);
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nb; b += PB_NT) cnt[(uint64_t)b * ntiles + t] = s_h[b];
+}
+
+// out[off[b * ntiles + t] + rank] = the tile's candidates of bucket b (the
+// order inside a bucket is not kept: the bucket is sorted afterwards)
+__global__ __launch_bounds__(PB_NT) void k_bucket_scatter(const uint64_t* __restrict__ cand,
+                                                          uint64_t nc, uint32_t shift, uint32_t nb,
+                                                          uint32_t ntiles,
+                                                          const uint64_t* __restrict__ off,
+                                                          uint64_t* __restrict__ out) {
+  __shared__ uint32_t s_at[PB_MAX_BUCKETS];
+  const uint64_t t = blockIdx.x;
+  for (uint32_t b = threadIdx.x; b < nb; b += PB_NT) s_at[b] = (uint32_t)off[(uint64_t)b * ntiles + t];
+  __syncthreads();
+  const uint64_t e0 = t * PB_CHUNK, e1 = min<uint64_t>(nc, e0 + PB_CHUNK);
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += PB_NT) {
+    const uint64_t v = cand[e];
+    const uint32_t b = (uint32_t)(v >> shift);
+    if (b < nb) out[atomicAdd(&s_at[b], 1u)] = v;
+  }
+}
+
+// One stable LSD pass over 8 bits of n <= PB_CAP keys in LDS, src -> dst.
+// Wave w ranks the 64-key chunks [w * cpw, (w + 1) * cpw) in order: lanes
+// with equal digits find each other by ballots (match_digit8), the lowest of
+// them adds the group to the wave's count of that digit, and the rank of a
+// lane is the number of equal lanes below it. Counts are scanned digit-major,
+// wave-minor, so the pass keeps the order of equal digits.
+__device__ __forceinline__ void lds_radix_pass(const uint32_t* src, uint32_t* dst, uint32_t n,
+                                               uint32_t shift, uint32_t* s_cnt, uint32_t* s_tmp) {
+  const uint32_t lane = lane_id(), w = threadIdx.x / 64;
+  const uint32_t chunks = (n + 63) / 64, cpw = (chunks + PB_NW - 1) / PB_NW;
+  const uint32_t c0 = min(chunks, w * cpw), c1 = min(chunks, c0 + cpw);
+  for (uint32_t x = threadIdx.x; x < PB_NW * 256; x += PB_NT) s_cnt[x] = 0;
+  __syncthreads();
+  uint32_t* mine = s_cnt + w * 256;
+  for (uint32_t c = c0; c < c1; ++c) {
+    const uint32_t x = c * 64 + lane;
+    const bool valid = x < n;
+    const uint32_t d = valid ? (src[x] >> shift) & 255u : 0u;
+    const uint64_t peers = match_digit8(d, __ballot(valid));
+    if (valid && mask_rank(peers) == 0) mine[d] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // per digit: exclusive over the waves, then over the digits
+  uint32_t tot = 0;
+  if (threadIdx.x < 256) {
+    for (int v = 0; v < PB_NW; ++v) {
+      const uint32_t cv = s_cnt[v * 256 + threadIdx.x];
+      s_cnt[v * 256 + threadIdx.x] = tot;
+      tot += cv;
+    }
+  }
+  uint32_t all;
+  const uint32_t base = block_excl_scan<PB_NT>(tot, s_tmp, &all);
+  if (threadIdx.x < 256)
+    for (int v = 0; v < PB_NW; ++v) s_cnt[v * 256 + threadIdx.x] += base;
+  __syncthreads();
+  for (uint32_t c = c0; c < c1; ++c) {
+    const uint32_t x = c * 64 + lane;
+    const bool valid = x < n;
+    const uint32_t key = valid ? src[x] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    const uint64_t peers = match_digit8(d, __ballot(valid));
+    const uint32_t rank = mask_rank(peers);
+    const uint32_t at = mine[d];
+    if (valid) dst[at + rank] = key;
+    if (valid && rank == 0) mine[d] = at + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+}
+
+// Bucket by bucket, independently: load the bucket's candidates as 32-bit
+// keys (i's low `low` bits above j's `jb` bits), sort them, drop repeats
+// (and, for a self search, pairs with i >= j), verify the rest
+// (pair_verdict) and write the kept pairs, packed as key << 8 | distance, in
+// order at the start of the bucket's range of `scratch`; bcount[b] = their
+// number. k_bucket_place then moves every bucket's pairs to its place in the
+// output. No bucket waits for another, so a large one costs only its own
+// time.
+// A bucket of up to PB_CAP candidates is sorted in LDS. A larger one (the
+// candidates of a cluster of near-equal sequences, which repeat once per
+// shared variant) is split by the next 12 key bits into sub-buckets: one
+// count, a scan and a scatter into `scratch`, then consecutive sub-buckets
+// are grouped into runs of at most PB_CAP and each run is sorted and
+// verified in LDS like a small bucket; its sorted keys and verdicts wait in
+// the bucket's own range of `cand` until the bucket's pairs are written. A
+// bucket over PB_BIG candidates, or with a sub-bucket over PB_CAP / 2, is
+// left out: it sets SD_ERRBIT_BUCKET in *err and counts as empty, and the
+// host sorts and verifies the whole array the other way.
+constexpr uint32_t PB_BIG = 1u << 18;
+constexpr uint32_t PB_SUB_BITS = 12;
+constexpr uint32_t PB_GROUP = PB_CAP / 2;  // group starts are PB_GROUP apart
+constexpr uint32_t PB_MAXG = PB_BIG / PB_GROUP;
+constexpr uint32_t PB_WCHUNK = PB_NT * 8;  // positions per write round of a large bucket
+
+// Sort n <= PB_CAP keys in LDS (LSD passes over `bits` bits); returns the
+// buffer that holds them.
+__device__ __forceinline__ uint32_t* lds_sort(uint32_t* a, uint32_t* b, uint32_t n, uint32_t bits,
+                                              uint32_t* s_cnt, uint32_t* s_tmp) {
+  for (uint32_t sh = 0; sh < bits; sh += 8) {
+    lds_radix_pass(a, b, n, sh, s_cnt, s_tmp);
+    uint32_t* q = a;
+    a = b;
+    b = q;
+  }
+  return a;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(PB_NT) void k_bucket_verify(
+    uint64_t* __restrict__ cand, uint64_t* __restrict__ scratch,
+    const uint64_t* __restrict__ off, uint32_t ntiles, uint32_t nb, uint32_t jb, uint32_t low,
+    const u128* __restrict__ pa, const u128* __restrict__ sb, const u128* __restrict__ pa2,
+    const u128* __restrict__ sb2, int k, int self_pairs, uint32_t* __restrict__ bcount,
+    uint32_t* __restrict__ err) {
+  __shared__ uint32_t s_a[PB_CAP];
+  __shared__ uint32_t s_b[PB_CAP];
+  __shared__ uint32_t s_cnt[PB_NW * 256];
+  __shared__ uint32_t s_tmp[PB_NW];
+  __shared__ uint32_t s_grp[PB_MAXG + 1];
+  __shared__ uint32_t s_bad;
+  const uint32_t t = blockIdx.x;
+  const uint64_t b0 = off[(uint64_t)t * ntiles], b1 = off[(uint64_t)(t + 1) * ntiles];
+  const uint32_t m = (uint32_t)min<uint64_t>(b1 - b0, (uint64_t)PB_BIG + 1);
+  const uint32_t jmask = jb >= 32 ? ~0u : (1u << jb) - 1u;
+  const uint32_t lmask = (1u << low) - 1u;
+  const uint32_t ibase = t << low;
+  const uint32_t kbits = low + jb;
+  auto first_of = [&](uint32_t key) { return ibase | (key >> jb); };
+  auto key_of = [&](uint64_t v) {
+    return ((((uint32_t)(v >> 32)) & lmask) << jb) | ((uint32_t)v & jmask);
+  };
+  auto keep_of = [&](const uint32_t* keys, uint32_t x) {
+    const uint32_t key = keys[x];
+    return (x == 0 || keys[x - 1] != key) && (!self_pairs || first_of(key) < (key & jmask));
+  };
+  uint64_t* __restrict__ outp = scratch + b0;  // packed pairs, in order
+  if (m > PB_BIG) {
+    if (threadIdx.x == 0) {
+      atomicOr(err, SD_ERRBIT_BUCKET);
+      bcount[t] = 0;
+    }
+    return;
+  }
+  if (m <= PB_CAP) {
+    // (a separate code path, so that it addresses LDS directly)
+    for (uint32_t x = threadIdx.x; x < m; x += PB_NT) s_a[x] = key_of(cand[b0 + x]);
+    __syncthreads();
+    uint32_t* src = lds_sort(s_a, s_b, m, kbits, s_cnt, s_tmp);
+    uint32_t* dst = src == s_a ? s_b : s_a;
+    // distinct ordered pairs, listed in order in the other buffer
+    const uint32_t per = (m + PB_NT - 1) / PB_NT;
+    const uint32_t x0 = min(threadIdx.x * per, m), x1 = min(x0 + per, m);
+    uint32_t keep = 0;
+    for (uint32_t x = x0; x < x1; ++x) keep += keep_of(src, x);
+    uint32_t ntot;
+    uint32_t at = block_excl_scan<PB_NT>(keep, s_tmp, &ntot);
+    for (uint32_t x = x0; x < x1; ++x)
+      if (keep_of(src, x)) dst[at++] = src[x];
+    __syncthreads();
+    uint8_t* s_dist = reinterpret_cast<uint8_t*>(src);  // (where the sorted keys were)
+    const uint32_t per2 = (ntot + PB_NT - 1) / PB_NT;
+    const uint32_t l0 = min(threadIdx.x * per2, ntot), l1 = min(l0 + per2, ntot);
+    uint32_t cnt = 0;
+    for (uint32_t l = l0; l < l1; ++l) {
+      const uint32_t key = dst[l];
+      const uint8_t d = pair_verdict<MODE>(pa, sb, pa2, sb2, first_of(key), key & jmask, k);
+      s_dist[l] = d;  // read back below by this thread only
+      cnt += d != DROP;
+    }
+    uint32_t total;
+    uint32_t pos = block_excl_scan<PB_NT>(cnt, s_tmp, &total);
+    for (uint32_t l = l0; l < l1; ++l)
+      if (s_dist[l] != DROP) outp[pos++] = ((uint64_t)dst[l] << 8) | s_dist[l];
+    if (threadIdx.x == 0) bcount[t] = total;
+    return;
+  }
+  // large bucket: sub-bucket counts (kept in s_b while grouping and scattering)
+  const uint32_t sbits = min(PB_SUB_BITS, kbits), ssh = kbits - sbits, nsub = 1u << sbits;
+  uint32_t* starts = s_b;
+  for (uint32_t x = threadIdx.x; x < nsub; x += PB_NT) starts[x] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (uint32_t x = threadIdx.x; x < m; x += PB_NT) atomicAdd(&starts[key_of(cand[b0 + x]) >> ssh], 1u);
+  __syncthreads();
+  {
+    // exclusive scan, eight entries a thread; a sub-bucket over PB_CAP -
+    // PB_GROUP cannot be grouped
+    constexpr uint32_t PER = (1u << PB_SUB_BITS) / PB_NT;
+    const uint32_t e0 = threadIdx.x * PER;
+    uint32_t v[PER], sum = 0, big = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+      v[q] = e0 + q < nsub ? starts[e0 + q] : 0u;
+      big |= v[q] > PB_CAP - PB_GROUP;
+      sum += v[q];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<PB_NT>(sum, s_tmp, &tot);
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q)
+      if (e0 + q < nsub) {
+        starts[e0 + q] = run;
+        run += v[q];
+      }
+    if (big) s_bad = 1;
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (threadIdx.x == 0) {
+      atomicOr(err, SD_ERRBIT_BUCKET);
+      bcount[t] = 0;
+    }
+    return;
+  }
+  // group g: the sub-buckets that start in [g PB_GROUP, (g + 1) PB_GROUP),
+  // at most PB_GROUP + (PB_CAP - PB_GROUP) candidates
+  const uint32_t ng = (m + PB_GROUP - 1) / PB_GROUP;
+  for (uint32_t g = threadIdx.x; g <= ng; g += PB_NT) {
+    uint32_t lo = 0, hi = nsub;  // first sub-bucket starting at or after g PB_GROUP
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (starts[mid] < g * PB_GROUP)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    s_grp[g] = g == ng || lo == nsub ? m : starts[lo];
+  }
+  __syncthreads();
+  // scatter by sub-bucket into scratch (the order inside a sub-bucket is not kept)
+  uint32_t* A = reinterpret_cast<uint32_t*>(scratch + b0);
+  for (uint32_t x = threadIdx.x; x < m; x += PB_NT) {
+    const uint32_t key = key_of(cand[b0 + x]);
+    A[atomicAdd(&starts[key >> ssh], 1u)] = key;
+  }
+  __syncthreads();
+  // per group: sort and verify in LDS; sorted keys and verdicts wait in cand
+  uint32_t* S = reinterpret_cast<uint32_t*>(cand + b0);
+  uint8_t* V = reinterpret_cast<uint8_t*>(S + m);
+  uint32_t total = 0;
+  for (uint32_t g = 0; g < ng; ++g) {
+    const uint32_t lo = s_grp[g], n = s_grp[g + 1] - lo;
+    if (n == 0) continue;
+    for (uint32_t x = threadIdx.x; x < n; x += PB_NT) s_a[x] = A[lo + x];
+    __syncthreads();
+    const uint32_t* src = lds_sort(s_a, s_b, n, kbits, s_cnt, s_tmp);
+    uint32_t cnt = 0;
+    for (uint32_t x = threadIdx.x; x < n; x += PB_NT) {
+      const uint32_t key = src[x];
+      uint8_t d = DROP;
+      if (keep_of(src, x)) d = pair_verdict<MODE>(pa, sb, pa2, sb2, first_of(key), key & jmask, k);
+      S[lo + x] = key;
+      V[lo + x] = d;
+      cnt += d != DROP;
+    }
+    uint32_t gt;
+    (void)block_excl_scan<PB_NT>(cnt, s_tmp, &gt);
+    total += gt;
+  }
+  __syncthreads();
+  // the kept pairs in order, PB_WCHUNK positions a round, 8 a thread
+  uint32_t base = 0;
+  for (uint32_t c0 = 0; c0 < m; c0 += PB_WCHUNK) {
+    const uint32_t x0 = min(c0 + threadIdx.x * 8u, m), x1 = min(x0 + 8u, m);
+    uint32_t cnt = 0;
+    for (uint32_t x = x0; x < x1; ++x) cnt += V[x] != DROP;
+    uint32_t round;
+    uint32_t pos = base + block_excl_scan<PB_NT>(cnt, s_tmp, &round);
+    for (uint32_t x = x0; x < x1; ++x)
+      if (V[x] != DROP) outp[pos++] = ((uint64_t)S[x] << 8) | V[x];
+    base += round;
+  }
+  if (threadIdx.x == 0) bcount[t] = total;
+}
+
+// Every bucket's packed pairs to their place (bpos, the exclusive scan of
+// the bucket counts) in the output arrays; *out_count = the total.
+__global__ __launch_bounds__(PB_NT) void k_bucket_place(
+    const uint64_t* __restrict__ packed, const uint64_t* __restrict__ off, uint32_t ntiles,
+    uint32_t nb, uint32_t jb, uint32_t low, const uint32_t* __restrict__ bcount,
+    const uint64_t* __restrict__ bpos, uint32_t* __restrict__ oi, uint32_t* __restrict__ oj,
+    uint8_t* __restrict__ od, unsigned long long* __restrict__ out_count) {
+  const uint32_t jmask = jb >= 32 ? ~0u : (1u << jb) - 1u;
+  for (uint32_t t = blockIdx.x; t < nb; t += gridDim.x) {
+    const uint64_t* src = packed + off[(uint64_t)t * ntiles];
+    const uint32_t cnt = bcount[t];
+    const uint64_t pos = bpos[t];
+    const uint32_t ibase = t << low;
+    for (uint32_t r = threadIdx.x; r < cnt; r += PB_NT) {
+      const uint64_t v = src[r];
+      const uint32_t key = (uint32_t)(v >> 8);
+      oi[pos + r] = ibase | (key >> jb);
+      oj[pos + r] = key & jmask;
+      od[pos + r] = (uint8_t)v;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out_count = bpos[nb];
 }
 
 __global__ __launch_bounds__(NT) void k_join_pairs(const uint32_t* __restrict__ i,
@@ -391,6 +737,53 @@ void launch_emit_runs(const uint64_t* key_lo, const uint64_t* key_hi, const uint
 }
 
 uint64_t compact_tile() { return (uint64_t)sdk::NT * sdk::CITEMS; }
+
+uint32_t bucket_chunk() { return sdk::PB_CHUNK; }
+uint32_t bucket_cap() { return sdk::PB_CAP; }
+uint32_t bucket_max() { return sdk::PB_MAX_BUCKETS; }
+
+void launch_bucket_count(const uint64_t* cand, uint64_t nc, uint32_t shift, uint32_t nb,
+                         uint32_t* cnt, hipStream_t s) {
+  if (!nc) return;
+  const uint32_t nt = blocks_for(nc, sdk::PB_CHUNK);
+  hipLaunchKernelGGL(sdk::k_bucket_count, dim3(nt), dim3(sdk::PB_NT), 0, s, cand, nc, shift, nb,
+                     nt, cnt);
+}
+
+void launch_bucket_scatter(const uint64_t* cand, uint64_t nc, uint32_t shift, uint32_t nb,
+                           const uint64_t* off, uint64_t* out, hipStream_t s) {
+  if (!nc) return;
+  const uint32_t nt = blocks_for(nc, sdk::PB_CHUNK);
+  hipLaunchKernelGGL(sdk::k_bucket_scatter, dim3(nt), dim3(sdk::PB_NT), 0, s, cand, nc, shift, nb,
+                     nt, off, out);
+}
+
+void launch_bucket_verify(uint64_t* cand, uint64_t* scratch, const uint64_t* off, uint64_t nc,
+                          uint32_t nb, uint32_t jb, uint32_t low, const u128* a, const u128* seq_b,
+                          int k, int metric, int self_pairs, uint32_t* bcount, uint32_t* err,
+                          hipStream_t s, const u128* a2, const u128* seq_b2) {
+  if (!nc) return;
+  const uint32_t nt = blocks_for(nc, sdk::PB_CHUNK);
+  if (a2)
+    hipLaunchKernelGGL(sdk::k_bucket_verify<2>, dim3(nb), dim3(sdk::PB_NT), 0, s, cand, scratch,
+                       off, nt, nb, jb, low, a, seq_b, a2, seq_b2, k, self_pairs, bcount, err);
+  else if (metric == SD_METRIC_HAMMING)
+    hipLaunchKernelGGL(sdk::k_bucket_verify<1>, dim3(nb), dim3(sdk::PB_NT), 0, s, cand, scratch,
+                       off, nt, nb, jb, low, a, seq_b, nullptr, nullptr, k, self_pairs, bcount, err);
+  else
+    hipLaunchKernelGGL(sdk::k_bucket_verify<0>, dim3(nb), dim3(sdk::PB_NT), 0, s, cand, scratch,
+                       off, nt, nb, jb, low, a, seq_b, nullptr, nullptr, k, self_pairs, bcount, err);
+}
+
+void launch_bucket_place(const uint64_t* packed, const uint64_t* off, uint64_t nc, uint32_t nb,
+                         uint32_t jb, uint32_t low, const uint32_t* bcount, const uint64_t* bpos,
+                         uint32_t* out_i, uint32_t* out_j, uint8_t* out_d,
+                         unsigned long long* out_count, hipStream_t s) {
+  if (!nc) return;
+  const uint32_t nt = blocks_for(nc, sdk::PB_CHUNK);
+  hipLaunchKernelGGL(sdk::k_bucket_place, dim3(std::min<uint32_t>(nb, 2048)), dim3(sdk::PB_NT), 0,
+                     s, packed, off, nt, nb, jb, low, bcount, bpos, out_i, out_j, out_d, out_count);
+}
 
 void launch_join_pairs(const uint32_t* i, const uint32_t* j, uint64_t n, uint64_t* out,
                        hipStream_t s) {

@@ -37,6 +37,7 @@ OPT_METRIC = 10
 OPT_STREAM = 11
 OPT_STREAM_ELEMS = 12
 OPT_GROUP_SHAPE = 13
+OPT_BATCH_GRAPH = 14
 METRIC_LEVENSHTEIN = 0
 METRIC_HAMMING = 1
 MAX_STAGES = 16
@@ -68,6 +69,9 @@ class _Stats(ctypes.Structure):
                 ("n_pairs", ctypes.c_int64), ("n_stages", ctypes.c_int32),
                 ("n_sort_passes", ctypes.c_int32), ("n_big_segments", ctypes.c_int64),
                 ("n_probe_steps", ctypes.c_int64), ("n_stream_groups", ctypes.c_int64),
+                ("n_graph_captures", ctypes.c_int64), ("n_graph_launches", ctypes.c_int64),
+                ("n_graph_retries", ctypes.c_int64),
+                ("n_pair_buckets", ctypes.c_int64), ("n_pair_fallbacks", ctypes.c_int64),
                 ("stage_name", (ctypes.c_char * 24) * MAX_STAGES),
                 ("stage_ms", ctypes.c_double * MAX_STAGES),
                 ("stage_bytes", ctypes.c_double * MAX_STAGES),
@@ -93,7 +97,10 @@ class _TuneResult(ctypes.Structure):
     _fields_ = [("trials", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("group_cap", ctypes.c_int32), ("sort_items", ctypes.c_int32),
                 ("batch_tile", ctypes.c_int64), ("best_s", ctypes.c_double),
-                ("default_s", ctypes.c_double)]
+                ("default_s", ctypes.c_double), ("group_bits", ctypes.c_int32),
+                ("pair_sort", ctypes.c_int32), ("group_shape", ctypes.c_int32),
+                ("batch_graph", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 # allocator hook signatures (sd_alloc_fn, sd_free_fn)
@@ -172,6 +179,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sd_autotune.argtypes = [P, P, I, ctypes.POINTER(_Seqs), I, I,
                                 ctypes.POINTER(_TuneResult), P]
     lib.sd_autotune.restype = I
+    lib.sd_autotune_cache.argtypes = [P, ctypes.c_char_p]
+    lib.sd_autotune_cache.restype = I
     _lib = lib
     return lib
 
@@ -472,7 +481,12 @@ class Context:
         self._check(self._lib.sd_autotune(self._h, index.handle if index is not None else None, n,
                                           arr, int(k), int(reps), ctypes.byref(res), st),
                     "sd_autotune")
-        return {f: getattr(res, f) for f, _ in _TuneResult._fields_}
+        return {f: getattr(res, f) for f, _ in _TuneResult._fields_ if f != "reserved"}
+
+    def set_tune_cache(self, path: str | None):
+        """Use the JSON file at `path` as the autotuner's cache (None: no cache)."""
+        self._check(self._lib.sd_autotune_cache(
+            self._h, None if path is None else os.fsencode(path)), "sd_autotune_cache")
 
     def mlp_gradients(self, params, x, y):
         """(grad, loss) of the stage-1 training loss from the device kernels."""
@@ -575,6 +589,9 @@ class Context:
                     n_cand_unique=st.n_cand_unique, n_pairs=st.n_pairs,
                     n_sort_passes=st.n_sort_passes, n_big_segments=st.n_big_segments,
                     n_probe_steps=st.n_probe_steps, n_stream_groups=st.n_stream_groups,
+                    n_graph_captures=st.n_graph_captures, n_graph_launches=st.n_graph_launches,
+                    n_graph_retries=st.n_graph_retries,
+                    n_pair_buckets=st.n_pair_buckets, n_pair_fallbacks=st.n_pair_fallbacks,
                     stages=stages)
 
 

@@ -27,9 +27,9 @@ def log(msg):
 # path, and hashed runs with a small LDS capacity that send some or all hash
 # segments through the oversized-segment fallback; with 18 or 20 hash bits
 # the grouping sort takes three LSD passes (20 bits: digits at bits 44, 52
-# and 60, the layout of the 10M workload); pair_sort forces the candidate
-# pair sort's counted passes (the branch of the full-size workloads) or its
-# one-sweep passes
+# and 60, the layout of the 10M workload); the automatic pair sort buckets
+# the candidates by i and sorts each bucket in LDS, pair_sort forces the
+# global counted passes (the branch above 2^22 sequences) or one-sweep passes
 CONFIGS = {
     "auto": {},
     "fullkey": {"path": 1},
@@ -41,6 +41,7 @@ CONFIGS = {
     "counted_pairs": {"pair_sort": 2},
     "hashed_b20_counted_pairs": {"path": 2, "bits": 20, "pair_sort": 2},
     "fullkey_counted_pairs": {"path": 1, "pair_sort": 2},
+    "onesweep_pairs": {"pair_sort": 1},
 }
 
 
@@ -69,6 +70,7 @@ def ctx():
 def cctx(request):
     c = make_ctx(CONFIGS[request.param])
     c.name = request.param
+    c.cfg = CONFIGS[request.param]
     yield c
     c.close()
 
@@ -167,7 +169,12 @@ def test_plain_10k_matches_oracle(cctx, k):
     c, o = cdr3gen.plain("plain_10k")
     log(f"self_search plain_10k k={k} config={cctx.name}")
     got = gpu_triples(cctx, c, o, k)
+    st = cctx.stats()
     assert_same(got, oracle_triples(c, o, k))
+    if cctx.cfg.get("pair_sort", 0) == 0:
+        assert st["n_pair_buckets"] > 0 and st["n_pair_fallbacks"] == 0
+    else:
+        assert st["n_pair_buckets"] == 0
     g = GOLD[f"oracle_plain_10k_k{k}"]
     assert len(got[0]) == g["pairs"]
     assert sha(got[0], got[1], got[2].astype(np.uint8)) == g["sha256"]
@@ -261,7 +268,11 @@ def test_group_larger_than_lds(ctx):
     k = 1
     log("self_search 4500 identical sequences + 300 others, k=1")
     got = gpu_triples(ctx, c, o, k)
-    assert ctx.stats()["n_big_segments"] > 0
+    st = ctx.stats()
+    assert st["n_big_segments"] > 0
+    # the copies' pairs overfill LDS in the first pair buckets (about 135,000
+    # candidates each): one workgroup sorts each of them in global memory
+    assert st["n_pair_buckets"] > 0 and st["n_pair_fallbacks"] == 0
     want = []
     nx = 4500
     dx = [oracle.lev(xs, t) for t in others]
@@ -278,6 +289,28 @@ def test_group_larger_than_lds(ctx):
     assert len(got[0]) == len(w)
     assert np.array_equal(got[0], w[:, 0]) and np.array_equal(got[1], w[:, 1])
     assert np.array_equal(got[2], w[:, 2])
+
+
+def test_pair_bucket_over_the_workgroup_limit(ctx):
+    # 1000 copies of one 24-residue sequence with no repeated residue at
+    # k = 2: every pair of copies shares all 301 deletion variants, so the
+    # first id's bucket holds 999 * 301 candidates, more than one workgroup
+    # sorts (2^18): the whole array takes the global passes instead
+    rng = np.random.default_rng(12)
+    x = rng.permutation(20)
+    s24 = bytes(np.concatenate([x, x[:4]]).astype(np.uint8))
+    # no residue equals the next or the one after, so the 1 + 24 + 276
+    # deletion sets give distinct strings
+    assert all(s24[t] != s24[t + 1] for t in range(23)) and all(s24[t] != s24[t + 2] for t in range(22))
+    c, o = csr([s24] * 1000)
+    log("self_search 1000 copies of one 24-residue sequence, k=2")
+    got = gpu_triples(ctx, c, o, 2)
+    st = ctx.stats()
+    assert st["n_pair_fallbacks"] == 1
+    iu, ju = np.triu_indices(1000, 1)
+    assert len(got[0]) == len(iu)
+    assert np.array_equal(got[0], iu) and np.array_equal(got[1], ju)
+    assert not got[2].any()
 
 
 def test_budget_error_keeps_context_usable():
@@ -352,13 +385,15 @@ def assert_golden(got, name, n):
     pytest.fail(f"{name}: {len(i)} pairs against {g['pairs']}, hash differs")
 
 
-@pytest.mark.parametrize("cfg", ["auto", "onesweep_pairs", "fullkey"])
+@pytest.mark.parametrize("cfg", ["auto", "counted_pairs", "onesweep_pairs", "fullkey"])
 def test_plain_1m_k2_equals_oracle(cfg):
     """Every triplet of the headline workload equals the oracle's (count and
-    hash of the whole output), through the automatic path (counted pair
-    sort), the one-sweep pair sort and the full-key grouping path."""
+    hash of the whole output), through the automatic path (bucketed pair
+    sort), the counted and one-sweep pair sorts and the full-key grouping
+    path."""
     c, o = cdr3gen.plain("plain_1m")
-    conf = {"auto": {}, "onesweep_pairs": {"pair_sort": 1}, "fullkey": {"path": 1}}[cfg]
+    conf = {"auto": {}, "counted_pairs": {"pair_sort": 2}, "onesweep_pairs": {"pair_sort": 1},
+            "fullkey": {"path": 1}}[cfg]
     log(f"self_search plain_1m k=2 config={cfg} against the oracle golden")
     ctx = make_ctx(conf)
     try:
