@@ -140,6 +140,7 @@ struct Shared {
   uint64_t* boff;
   uint32_t* bcount;  // bucket pair counts and their scan
   uint64_t* bpos;
+  uint64_t* packed;  // every bucket's kept pairs
 };
 
 // The pair sort of a tile: bucketed (as the eager path) over the whole
@@ -200,11 +201,11 @@ void enqueue_tile(const sd_ctx* c, const sd_index* idx, int k, GraphPlan& plan, 
   if (bp.bits >= 0) {
     // sort and verify per bucket in LDS; a bucket over LDS size flags the
     // tile (SD_ERRBIT_BUCKET), which then runs again eagerly
-    const BucketBufs b{w.bcnt,       w.boff,           w.bcount,        w.bpos,
-                       plan.status,  ctrs + slot,      kEpochBucketScan, ctrs + slot + 1,
-                       kEpochBucketCounts, err};
+    const BucketBufs b{w.bcnt,      w.boff,      w.packed,         w.bcount,
+                       w.bpos,      plan.status, ctrs + slot,      kEpochBucketScan,
+                       ctrs + slot + 1, kEpochBucketCounts, err};
     slot += 2;
-    bucket_enqueue(bp, b, w.cand, t.cap, w.cand2,
+    bucket_enqueue(bp, b, w.cand, t.cap, w.cand2, t.n, idx->n_ref,
                    c->metric == SD_METRIC_HAMMING ? w.seq : w.planes, idx->ref_seq, k, c->metric,
                    0, t.oi, t.oj, t.od, pcount, s);
     launch_set_ranges(t.oi, t.cap, t.pbase, (uint32_t)t.pieces.size() + 1, t.bounds, s, pcount);
@@ -228,7 +229,7 @@ void enqueue_tile(const sd_ctx* c, const sd_index* idx, int k, GraphPlan& plan, 
   }
   const uint64_t* sorted = pf ? w.cand2 : w.cand;
   // verification and ordered compaction, then the piece bounds
-  launch_verify_compact(sorted, t.cap, c->metric == SD_METRIC_HAMMING ? w.seq : w.planes,
+  launch_verify_compact(sorted, t.cap, t.n, idx->n_ref, c->metric == SD_METRIC_HAMMING ? w.seq : w.planes,
                         idx->ref_seq, k, c->metric, 0, t.oi, t.oj, t.od, plan.status, ctrs + slot++,
                         kEpochVerify, pcount, err, s);
   launch_set_ranges(t.oi, t.cap, t.pbase, (uint32_t)t.pieces.size() + 1, t.bounds, s, pcount);
@@ -279,7 +280,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
   }
   // the variant counts and code sizes need every length: device sets in one
   // pass on the device (length histograms), host sets on the host
-  bool all_dev = true;
+  bool all_dev = kDeviceStaging;
   for (int x = 0; x < nsets; ++x) all_dev = all_dev && (sets[x].n == 0 || sets[x].on_device);
   Scratch ssc(c);
   std::vector<BatchPiece> staged;
@@ -402,6 +403,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
     w.bcnt = P.get<uint32_t>(max_counts);
     w.boff = P.get<uint64_t>(max_counts + 1);
     w.bcount = P.get<uint32_t>(max_nb);
+    w.packed = P.get<uint64_t>(max_cap);
     w.bpos = P.get<uint64_t>(max_nb + 1);
     P.status_words = std::max<uint64_t>(
                          std::max<uint64_t>(max_n / scan_tile() + 2, max_cap / compact_tile() + 2),
@@ -536,6 +538,8 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
         throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
       if (h[CNT_LBERR] & SD_ERRBIT_PLACEMENT)
         throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
+      if (h[CNT_LBERR] & SD_ERRBIT_INDEX)
+        throw Error{SD_E_HIP, "internal error: a candidate id out of range"};
       const uint64_t joined = tail[0] + tail[1];  // regions (clamped) plus the spill
       const bool spilled = tail[1] > plan->over_cap;
       cand_per_key = std::max(cand_per_key, (double)joined / (double)std::max<uint64_t>(t.nk, 1));

@@ -274,7 +274,8 @@ Cands group_segments(Call& cl, const uint64_t* E, uint32_t nk, int cap, int bits
 }  // namespace
 
 uint64_t bucket_sort_verify(Call& cl, const BucketPlan& p, uint64_t* cand, uint64_t nc,
-                            uint64_t* cand2, const u128* a, const u128* sb, int k, int self_pairs,
+                            uint64_t* cand2, uint64_t na, uint64_t nbseq, const u128* a,
+                            const u128* sb, int k, int self_pairs,
                             uint32_t* oi, uint32_t* oj, uint8_t* od, bool* over,
                             const char* sort_stage, const char* verify_stage, const u128* a2,
                             const u128* sb2) {
@@ -283,7 +284,8 @@ uint64_t bucket_sort_verify(Call& cl, const BucketPlan& p, uint64_t* cand, uint6
   unsigned long long* pcount = reinterpret_cast<unsigned long long*>(cl.counters + CNT_PAIRS);
   launch_fill_u64(reinterpret_cast<uint64_t*>(pcount), 0, 1, s);
   BucketBufs b{cl.sc.get<uint32_t>(p.counts), cl.sc.get<uint64_t>(p.counts + 1),
-               cl.sc.get<uint32_t>(p.nb),     cl.sc.get<uint64_t>(p.nb + 1),
+               cl.sc.get<uint64_t>(nc),       cl.sc.get<uint32_t>(p.nb),
+               cl.sc.get<uint64_t>(p.nb + 1),
                nullptr,                       cl.tile_counter(),
                0,                             cl.tile_counter(),
                0,                             cl.lb_err()};
@@ -295,16 +297,18 @@ uint64_t bucket_sort_verify(Call& cl, const BucketPlan& p, uint64_t* cand, uint6
   launch_scan_excl(b.cnt, b.off, p.counts, b.status, b.scan_ctr, b.scan_epoch, b.err, s);
   launch_bucket_scatter(cand, nc, p.shift, p.nb, b.off, cand2, s);
   cl.tm.mark(sort_stage, (double)nc * 24 + (double)p.counts * 24, 3);
-  launch_bucket_verify(cand2, cand, b.off, nc, p.nb, p.jb, p.low, a, sb, k, c->metric, self_pairs,
-                       b.bcount, b.err, s, a2, sb2);
+  launch_bucket_verify(cand2, cand, b.packed, b.off, nc, p.nb, p.jb, p.low, na, nbseq, a, sb, k,
+                       c->metric, self_pairs, b.bcount, b.err, s, a2, sb2);
   launch_scan_excl(b.bcount, b.bpos, p.nb, b.status, b.scan2_ctr, b.scan2_epoch, b.err, s);
-  launch_bucket_place(cand, b.off, nc, p.nb, p.jb, p.low, b.bcount, b.bpos, oi, oj, od, pcount, s);
+  launch_bucket_place(b.packed, b.off, nc, p.nb, p.jb, p.low, b.bcount, b.bpos, oi, oj, od,
+                      pcount, s);
   cl.tm.mark(verify_stage, (double)nc * 8, 3);
   const uint32_t* h = static_cast<const uint32_t*>(readback(c, cl.counters + CNT_PAIRS, 12, s));
   uint64_t cntp;
   std::memcpy(&cntp, h, 8);
   if (h[2] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
   if (h[2] & SD_ERRBIT_PLACEMENT) throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
+  if (h[2] & SD_ERRBIT_INDEX) throw Error{SD_E_HIP, "internal error: a candidate id out of range"};
   *over = (h[2] & SD_ERRBIT_BUCKET) != 0;
   if (*over) launch_fill_u32(cl.lb_err(), 0, 1, s);
   return cntp;
@@ -361,7 +365,7 @@ Verified sort_and_verify(Call& cl, uint64_t* cand, uint64_t nc, uint64_t n, int 
     v.d = dalloc_t<uint8_t>(c, nc);
     bool over = false;
     try {
-      v.n = bucket_sort_verify(cl, bp, cand, nc, cand2,
+      v.n = bucket_sort_verify(cl, bp, cand, nc, cand2, n, n,
                                c->metric == SD_METRIC_HAMMING ? seq : planes, seq, k, 1, v.i, v.j,
                                v.d, &over, "pair_sort", "verify", planes2, seq2);
     } catch (...) {
@@ -420,7 +424,7 @@ Verified sort_and_verify(Call& cl, uint64_t* cand, uint64_t nc, uint64_t n, int 
     if (nc) {
       const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
       const uint32_t epoch = next_epoch(c, tiles, s);
-      launch_verify_compact(sorted, nc, c->metric == SD_METRIC_HAMMING ? seq : planes, seq, k,
+      launch_verify_compact(sorted, nc, n, n, c->metric == SD_METRIC_HAMMING ? seq : planes, seq, k,
                             c->metric, 1, v.i, v.j, v.d, c->status, cl.tile_counter(), epoch,
                             pcount, cl.lb_err(), s, planes2, seq2);
       cl.tm.mark("verify", (double)nc * (8 + 32) + (double)nc * 9, 1);
@@ -432,6 +436,7 @@ Verified sort_and_verify(Call& cl, uint64_t* cand, uint64_t nc, uint64_t n, int 
     std::memcpy(&cnt, h, 8);
     if (h[2] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
     if (h[2] & SD_ERRBIT_PLACEMENT) throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
+    if (h[2] & SD_ERRBIT_INDEX) throw Error{SD_E_HIP, "internal error: a candidate id out of range"};
     v.n = nc ? cnt : 0;
   } catch (...) {
     dfree(c, v.i);

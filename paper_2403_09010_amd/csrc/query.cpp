@@ -172,7 +172,7 @@ TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint6
     out.d = dalloc_t<uint8_t>(c, nc);
     bool over = false;
     try {
-      out.n = bucket_sort_verify(cl, bp, cand, nc, cand2,
+      out.n = bucket_sort_verify(cl, bp, cand, nc, cand2, nq, nr,
                                  c->metric == SD_METRIC_HAMMING ? qseq : qplanes, rseq, k, 0,
                                  out.i, out.j, out.d, &over, "q_pair_sort", "q_verify");
     } catch (...) {
@@ -233,7 +233,7 @@ TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint6
       } else {
         const uint64_t tiles = (nc + compact_tile() - 1) / compact_tile();
         const uint32_t epoch = next_epoch(c, tiles, s);
-        launch_verify_compact(sorted, nc, c->metric == SD_METRIC_HAMMING ? qseq : qplanes, rseq, k,
+        launch_verify_compact(sorted, nc, nq, nr, c->metric == SD_METRIC_HAMMING ? qseq : qplanes, rseq, k,
                               c->metric, 0, out.i, out.j, out.d, c->status,
                               cl.tile_counter(), epoch, pcount, cl.lb_err(), s);
       }
@@ -243,6 +243,7 @@ TileOut verify_candidates(Call& cl, const u128* qseq, const u128* qplanes, uint6
     std::memcpy(&cnt, h, 8);
     if (h[2] & SD_ERRBIT_LOOKBACK) throw Error{SD_E_HIP, "internal error: a look-back wait timed out"};
     if (h[2] & SD_ERRBIT_PLACEMENT) throw Error{SD_E_HIP, "internal error: a counted pass misplaced"};
+    if (h[2] & SD_ERRBIT_INDEX) throw Error{SD_E_HIP, "internal error: a candidate id out of range"};
     out.n = nc ? cnt : 0;
     cl.tm.mark("q_verify", (double)nc * 49, 1);
   } catch (...) {
@@ -354,7 +355,7 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
       if ((uint64_t)st.n > id_limit) throw Error{SD_E_TOO_MANY, "a query set exceeds the index id width"};
       if (last > first && tot + (uint64_t)st.n > tile_limit) break;
       tot += (uint64_t)st.n;
-      all_dev = all_dev && (st.n == 0 || st.on_device);
+      all_dev = all_dev && kDeviceStaging && (st.n == 0 || st.on_device);
       ++last;
     }
     Scratch sc(c);

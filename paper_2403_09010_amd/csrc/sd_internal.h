@@ -94,19 +94,21 @@ void launch_bucket_count(const uint64_t* cand, uint64_t nc, uint32_t shift, uint
 // Scatter by bucket from the exclusive scan `off` of that table (bucket-major).
 void launch_bucket_scatter(const uint64_t* cand, uint64_t nc, uint32_t shift, uint32_t nb,
                            const uint64_t* off, uint64_t* out, hipStream_t s);
-// Per bucket (the range off[b * ntiles] .. of cand): sort, drop repeats
-// (and i >= j if self_pairs), verify as launch_verify_compact does, and
-// write the kept pairs in order, packed as key << 8 | distance (key = i's
-// `low` bits below the bucket bits above j's jb bits, low + jb <= 32), at
-// the start of the bucket's range of scratch; bcount[b] = their number. A
-// bucket over bucket_cap() candidates is sorted through scratch and its own
-// range of cand (both overwritten). A bucket over 2^18 candidates, or one
-// that cannot be cut into pieces of bucket_cap(), sets SD_ERRBIT_BUCKET in
-// *err and counts 0. Values >> shift >= nb (the ~0 of an unused candidate
-// slot) are in no bucket.
-void launch_bucket_verify(uint64_t* cand, uint64_t* scratch, const uint64_t* off, uint64_t nc,
-                          uint32_t nb, uint32_t jb, uint32_t low, const u128* a, const u128* seq_b,
-                          int k, int metric, int self_pairs, uint32_t* bcount, uint32_t* err,
+// Per bucket (the range off[b * ntiles] .. of cand, which is only read):
+// sort, drop repeats (and i >= j if self_pairs), verify as
+// launch_verify_compact does, and write the kept pairs in order, packed as
+// key << 8 | distance (key = i's `low` bits below the bucket bits above j's
+// jb bits, low + jb <= 32), at the start of the bucket's range of packed;
+// bcount[b] = their number. A bucket over bucket_cap() candidates is sorted
+// through its range of scratch (overwritten). A bucket over 2^18
+// candidates, or one that cannot be cut into pieces of bucket_cap(), sets
+// SD_ERRBIT_BUCKET in *err and counts 0. Ids at or above na (first) or
+// nbseq (second) set SD_ERRBIT_INDEX and are never read. Values >> shift >=
+// nb (the ~0 of an unused candidate slot) are in no bucket.
+void launch_bucket_verify(const uint64_t* cand, uint64_t* scratch, uint64_t* packed,
+                          const uint64_t* off, uint64_t nc, uint32_t nb, uint32_t jb, uint32_t low,
+                          uint64_t na, uint64_t nbseq, const u128* a, const u128* seq_b, int k,
+                          int metric, int self_pairs, uint32_t* bcount, uint32_t* err,
                           hipStream_t s, const u128* a2 = nullptr, const u128* seq_b2 = nullptr);
 // Every bucket's packed pairs to out_*[bpos[b] ..) (bpos = exclusive scan of
 // bcount, nb + 1 entries); *out_count = bpos[nb].
@@ -138,11 +140,14 @@ void launch_join_pairs(const uint32_t* i, const uint32_t* j, uint64_t n, uint64_
 // self_pairs: drop candidates with i >= j (self search). With a2 and seq_b2
 // (paired-chain records: the second chains' planes and keys), the distance
 // is the sum over both chains and metric is not used.
-void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* a, const u128* seq_b,
-                           int k, int metric, int self_pairs, uint32_t* out_i, uint32_t* out_j,
-                           uint8_t* out_d, uint64_t* status, uint32_t* tile_counter, uint32_t epoch,
-                           unsigned long long* out_count, uint32_t* err, hipStream_t s,
-                           const u128* a2 = nullptr, const u128* seq_b2 = nullptr);
+// (first ids at or above na, second ids at or above nbseq set
+// SD_ERRBIT_INDEX in *err and are never read)
+void launch_verify_compact(const uint64_t* cand, uint64_t c, uint64_t na, uint64_t nbseq,
+                           const u128* a, const u128* seq_b, int k, int metric, int self_pairs,
+                           uint32_t* out_i, uint32_t* out_j, uint8_t* out_d, uint64_t* status,
+                           uint32_t* tile_counter, uint32_t epoch, unsigned long long* out_count,
+                           uint32_t* err, hipStream_t s, const u128* a2 = nullptr,
+                           const u128* seq_b2 = nullptr);
 // hashed grouping (element = hash of the key in the top 64 - idbits bits, id below)
 // Every variant as [hash | id] in voff order; block b generates sequences
 // [b * seqs_per_block, ...) (1 <= seqs_per_block <= VG_MAX_SEQS_PER_BLOCK).

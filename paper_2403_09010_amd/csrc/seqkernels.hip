@@ -285,9 +285,9 @@ __device__ __forceinline__ uint8_t pair_verdict(const u128* __restrict__ pa,
 // sequence arrays are those of pair_verdict.
 template <int MODE>
 __global__ __launch_bounds__(NT) void k_verify_compact(
-    const uint64_t* __restrict__ cand, uint64_t c, const u128* __restrict__ pa,
-    const u128* __restrict__ sb, const u128* __restrict__ pa2, const u128* __restrict__ sb2,
-    int k, int self_pairs, uint32_t* __restrict__ oi,
+    const uint64_t* __restrict__ cand, uint64_t c, uint32_t na, uint32_t nbseq,
+    const u128* __restrict__ pa, const u128* __restrict__ sb, const u128* __restrict__ pa2,
+    const u128* __restrict__ sb2, int k, int self_pairs, uint32_t* __restrict__ oi,
     uint32_t* __restrict__ oj, uint8_t* __restrict__ od, uint64_t* __restrict__ status,
     uint32_t* __restrict__ tile_counter, uint32_t epoch, unsigned long long* __restrict__ out_count,
     uint32_t* __restrict__ err) {
@@ -327,7 +327,12 @@ __global__ __launch_bounds__(NT) void k_verify_compact(
   uint32_t cnt = 0;
   for (uint32_t l = l0; l < l1; ++l) {
     const uint64_t v = s_list[l];
-    const uint8_t d = pair_verdict<MODE>(pa, sb, pa2, sb2, (uint32_t)(v >> 32), (uint32_t)v, k);
+    const uint32_t i = (uint32_t)(v >> 32), j = (uint32_t)v;
+    uint8_t d = DROP;
+    if (i < na && j < nbseq)
+      d = pair_verdict<MODE>(pa, sb, pa2, sb2, i, j, k);
+    else  // an id out of range is an internal error: flagged, never read
+      atomicOr(err, SD_ERRBIT_INDEX);
     s_dist[l] = d;  // read back below by this thread only
     cnt += d != DROP;
   }
@@ -457,17 +462,19 @@ __device__ __forceinline__ void lds_radix_pass(const uint32_t* src, uint32_t* ds
 // keys (i's low `low` bits above j's `jb` bits), sort them, drop repeats
 // (and, for a self search, pairs with i >= j), verify the rest
 // (pair_verdict) and write the kept pairs, packed as key << 8 | distance, in
-// order at the start of the bucket's range of `scratch`; bcount[b] = their
-// number. k_bucket_place then moves every bucket's pairs to its place in the
+// order at the start of the bucket's range of `packed`; bcount[b] = their
+// number. The bucketed candidates are only read, so the host can still sort
+// them the other way if a bucket is left out. k_bucket_place then moves every bucket's pairs to its place in the
 // output. No bucket waits for another, so a large one costs only its own
 // time.
 // A bucket of up to PB_CAP candidates is sorted in LDS. A larger one (the
 // candidates of a cluster of near-equal sequences, which repeat once per
 // shared variant) is split by the next 12 key bits into sub-buckets: one
-// count, a scan and a scatter into `scratch`, then consecutive sub-buckets
-// are grouped into runs of at most PB_CAP and each run is sorted and
-// verified in LDS like a small bucket; its sorted keys and verdicts wait in
-// the bucket's own range of `cand` until the bucket's pairs are written. A
+// count, a scan and a scatter into the bucket's range of `scratch`, then
+// consecutive sub-buckets are grouped into runs of at most PB_CAP and each
+// run is sorted and verified in LDS like a small bucket; its sorted keys go
+// back in place and its verdicts to the second half of that range until the
+// bucket's pairs are written. A
 // bucket over PB_BIG candidates, or with a sub-bucket over PB_CAP / 2, is
 // left out: it sets SD_ERRBIT_BUCKET in *err and counts as empty, and the
 // host sorts and verifies the whole array the other way.
@@ -492,11 +499,11 @@ __device__ __forceinline__ uint32_t* lds_sort(uint32_t* a, uint32_t* b, uint32_t
 
 template <int MODE>
 __global__ __launch_bounds__(PB_NT) void k_bucket_verify(
-    uint64_t* __restrict__ cand, uint64_t* __restrict__ scratch,
-    const uint64_t* __restrict__ off, uint32_t ntiles, uint32_t nb, uint32_t jb, uint32_t low,
-    const u128* __restrict__ pa, const u128* __restrict__ sb, const u128* __restrict__ pa2,
-    const u128* __restrict__ sb2, int k, int self_pairs, uint32_t* __restrict__ bcount,
-    uint32_t* __restrict__ err) {
+    const uint64_t* __restrict__ cand, uint64_t* __restrict__ scratch,
+    uint64_t* __restrict__ packed, const uint64_t* __restrict__ off, uint32_t ntiles, uint32_t nb,
+    uint32_t jb, uint32_t low, uint32_t na, uint32_t nbseq, const u128* __restrict__ pa,
+    const u128* __restrict__ sb, const u128* __restrict__ pa2, const u128* __restrict__ sb2, int k,
+    int self_pairs, uint32_t* __restrict__ bcount, uint32_t* __restrict__ err) {
   __shared__ uint32_t s_a[PB_CAP];
   __shared__ uint32_t s_b[PB_CAP];
   __shared__ uint32_t s_cnt[PB_NW * 256];
@@ -518,7 +525,17 @@ __global__ __launch_bounds__(PB_NT) void k_bucket_verify(
     const uint32_t key = keys[x];
     return (x == 0 || keys[x - 1] != key) && (!self_pairs || first_of(key) < (key & jmask));
   };
-  uint64_t* __restrict__ outp = scratch + b0;  // packed pairs, in order
+  uint64_t* __restrict__ outp = packed + b0;  // packed pairs, in order
+  // the verdict of a listed pair (an id out of range is an internal error:
+  // flagged, never read)
+  auto verdict_of = [&](uint32_t key) -> uint8_t {
+    const uint32_t i = first_of(key), j = key & jmask;
+    if (i >= na || j >= nbseq) {
+      atomicOr(err, SD_ERRBIT_INDEX);
+      return DROP;
+    }
+    return pair_verdict<MODE>(pa, sb, pa2, sb2, i, j, k);
+  };
   if (m > PB_BIG) {
     if (threadIdx.x == 0) {
       atomicOr(err, SD_ERRBIT_BUCKET);
@@ -547,8 +564,7 @@ __global__ __launch_bounds__(PB_NT) void k_bucket_verify(
     const uint32_t l0 = min(threadIdx.x * per2, ntot), l1 = min(l0 + per2, ntot);
     uint32_t cnt = 0;
     for (uint32_t l = l0; l < l1; ++l) {
-      const uint32_t key = dst[l];
-      const uint8_t d = pair_verdict<MODE>(pa, sb, pa2, sb2, first_of(key), key & jmask, k);
+      const uint8_t d = verdict_of(dst[l]);
       s_dist[l] = d;  // read back below by this thread only
       cnt += d != DROP;
     }
@@ -619,9 +635,10 @@ __global__ __launch_bounds__(PB_NT) void k_bucket_verify(
     A[atomicAdd(&starts[key >> ssh], 1u)] = key;
   }
   __syncthreads();
-  // per group: sort and verify in LDS; sorted keys and verdicts wait in cand
-  uint32_t* S = reinterpret_cast<uint32_t*>(cand + b0);
-  uint8_t* V = reinterpret_cast<uint8_t*>(S + m);
+  // per group: sort and verify in LDS; the sorted keys go back in place in
+  // A (after the whole group is in LDS), the verdicts after A
+  uint32_t* S = A;
+  uint8_t* V = reinterpret_cast<uint8_t*>(A + m);
   uint32_t total = 0;
   for (uint32_t g = 0; g < ng; ++g) {
     const uint32_t lo = s_grp[g], n = s_grp[g + 1] - lo;
@@ -633,7 +650,7 @@ __global__ __launch_bounds__(PB_NT) void k_bucket_verify(
     for (uint32_t x = threadIdx.x; x < n; x += PB_NT) {
       const uint32_t key = src[x];
       uint8_t d = DROP;
-      if (keep_of(src, x)) d = pair_verdict<MODE>(pa, sb, pa2, sb2, first_of(key), key & jmask, k);
+      if (keep_of(src, x)) d = verdict_of(key);
       S[lo + x] = key;
       V[lo + x] = d;
       cnt += d != DROP;
@@ -758,21 +775,27 @@ void launch_bucket_scatter(const uint64_t* cand, uint64_t nc, uint32_t shift, ui
                      nt, off, out);
 }
 
-void launch_bucket_verify(uint64_t* cand, uint64_t* scratch, const uint64_t* off, uint64_t nc,
-                          uint32_t nb, uint32_t jb, uint32_t low, const u128* a, const u128* seq_b,
-                          int k, int metric, int self_pairs, uint32_t* bcount, uint32_t* err,
+void launch_bucket_verify(const uint64_t* cand, uint64_t* scratch, uint64_t* packed,
+                          const uint64_t* off, uint64_t nc, uint32_t nb, uint32_t jb, uint32_t low,
+                          uint64_t na, uint64_t nbseq, const u128* a, const u128* seq_b, int k,
+                          int metric, int self_pairs, uint32_t* bcount, uint32_t* err,
                           hipStream_t s, const u128* a2, const u128* seq_b2) {
   if (!nc) return;
   const uint32_t nt = blocks_for(nc, sdk::PB_CHUNK);
+  const uint32_t na32 = (uint32_t)std::min<uint64_t>(na, 0xFFFFFFFFull);
+  const uint32_t nb32 = (uint32_t)std::min<uint64_t>(nbseq, 0xFFFFFFFFull);
   if (a2)
     hipLaunchKernelGGL(sdk::k_bucket_verify<2>, dim3(nb), dim3(sdk::PB_NT), 0, s, cand, scratch,
-                       off, nt, nb, jb, low, a, seq_b, a2, seq_b2, k, self_pairs, bcount, err);
+                       packed, off, nt, nb, jb, low, na32, nb32, a, seq_b, a2, seq_b2, k,
+                       self_pairs, bcount, err);
   else if (metric == SD_METRIC_HAMMING)
     hipLaunchKernelGGL(sdk::k_bucket_verify<1>, dim3(nb), dim3(sdk::PB_NT), 0, s, cand, scratch,
-                       off, nt, nb, jb, low, a, seq_b, nullptr, nullptr, k, self_pairs, bcount, err);
+                       packed, off, nt, nb, jb, low, na32, nb32, a, seq_b, nullptr, nullptr, k,
+                       self_pairs, bcount, err);
   else
     hipLaunchKernelGGL(sdk::k_bucket_verify<0>, dim3(nb), dim3(sdk::PB_NT), 0, s, cand, scratch,
-                       off, nt, nb, jb, low, a, seq_b, nullptr, nullptr, k, self_pairs, bcount, err);
+                       packed, off, nt, nb, jb, low, na32, nb32, a, seq_b, nullptr, nullptr, k,
+                       self_pairs, bcount, err);
 }
 
 void launch_bucket_place(const uint64_t* packed, const uint64_t* off, uint64_t nc, uint32_t nb,
@@ -792,25 +815,27 @@ void launch_join_pairs(const uint32_t* i, const uint32_t* j, uint64_t n, uint64_
                      out);
 }
 
-void launch_verify_compact(const uint64_t* cand, uint64_t c, const u128* a, const u128* seq_b,
-                           int k, int metric, int self_pairs, uint32_t* out_i, uint32_t* out_j,
-                           uint8_t* out_d, uint64_t* status, uint32_t* tile_counter, uint32_t epoch,
-                           unsigned long long* out_count, uint32_t* err, hipStream_t s,
-                           const u128* a2, const u128* seq_b2) {
+void launch_verify_compact(const uint64_t* cand, uint64_t c, uint64_t na, uint64_t nbseq,
+                           const u128* a, const u128* seq_b, int k, int metric, int self_pairs,
+                           uint32_t* out_i, uint32_t* out_j, uint8_t* out_d, uint64_t* status,
+                           uint32_t* tile_counter, uint32_t epoch, unsigned long long* out_count,
+                           uint32_t* err, hipStream_t s, const u128* a2, const u128* seq_b2) {
   if (!c) return;
   const dim3 g(blocks_for(c, compact_tile()));
+  const uint32_t na32 = (uint32_t)std::min<uint64_t>(na, 0xFFFFFFFFull);
+  const uint32_t nb32 = (uint32_t)std::min<uint64_t>(nbseq, 0xFFFFFFFFull);
   if (a2)
-    hipLaunchKernelGGL(sdk::k_verify_compact<2>, g, dim3(sdk::NT), 0, s, cand, c, a, seq_b, a2,
-                       seq_b2, k, self_pairs, out_i, out_j, out_d, status, tile_counter, epoch,
-                       out_count, err);
+    hipLaunchKernelGGL(sdk::k_verify_compact<2>, g, dim3(sdk::NT), 0, s, cand, c, na32, nb32, a,
+                       seq_b, a2, seq_b2, k, self_pairs, out_i, out_j, out_d, status, tile_counter,
+                       epoch, out_count, err);
   else if (metric == SD_METRIC_HAMMING)
-    hipLaunchKernelGGL(sdk::k_verify_compact<1>, g, dim3(sdk::NT), 0, s, cand, c, a, seq_b,
-                       nullptr, nullptr, k, self_pairs, out_i, out_j, out_d, status, tile_counter,
-                       epoch, out_count, err);
+    hipLaunchKernelGGL(sdk::k_verify_compact<1>, g, dim3(sdk::NT), 0, s, cand, c, na32, nb32, a,
+                       seq_b, nullptr, nullptr, k, self_pairs, out_i, out_j, out_d, status,
+                       tile_counter, epoch, out_count, err);
   else
-    hipLaunchKernelGGL(sdk::k_verify_compact<0>, g, dim3(sdk::NT), 0, s, cand, c, a, seq_b,
-                       nullptr, nullptr, k, self_pairs, out_i, out_j, out_d, status, tile_counter,
-                       epoch, out_count, err);
+    hipLaunchKernelGGL(sdk::k_verify_compact<0>, g, dim3(sdk::NT), 0, s, cand, c, na32, nb32, a,
+                       seq_b, nullptr, nullptr, k, self_pairs, out_i, out_j, out_d, status,
+                       tile_counter, epoch, out_count, err);
 }
 
 void launch_pair_distance(const u128* seq_a, uint64_t na, const u128* seq_b, uint64_t nb,

@@ -171,10 +171,10 @@ def test_plain_10k_matches_oracle(cctx, k):
     got = gpu_triples(cctx, c, o, k)
     st = cctx.stats()
     assert_same(got, oracle_triples(c, o, k))
-    if cctx.cfg.get("pair_sort", 0) == 0:
-        assert st["n_pair_buckets"] > 0 and st["n_pair_fallbacks"] == 0
-    else:
-        assert st["n_pair_buckets"] == 0
+    # the bucketed pair sort is switched off (see
+    # test_pair_bucket_over_the_workgroup_limit): every pair sort takes the
+    # global passes
+    assert st["n_pair_buckets"] == 0 and st["n_pair_fallbacks"] == 0
     g = GOLD[f"oracle_plain_10k_k{k}"]
     assert len(got[0]) == g["pairs"]
     assert sha(got[0], got[1], got[2].astype(np.uint8)) == g["sha256"]
@@ -270,9 +270,6 @@ def test_group_larger_than_lds(ctx):
     got = gpu_triples(ctx, c, o, k)
     st = ctx.stats()
     assert st["n_big_segments"] > 0
-    # the copies' pairs overfill LDS in the first pair buckets (about 135,000
-    # candidates each): one workgroup sorts each of them in global memory
-    assert st["n_pair_buckets"] > 0 and st["n_pair_fallbacks"] == 0
     want = []
     nx = 4500
     dx = [oracle.lev(xs, t) for t in others]
@@ -291,6 +288,9 @@ def test_group_larger_than_lds(ctx):
     assert np.array_equal(got[2], w[:, 2])
 
 
+@pytest.mark.skip(reason="the bucketed pair sort is switched off: its version with independent "
+                         "buckets made the GPU take a memory fault on the first small self search "
+                         "(10K sequences, k = 0), twice, cause not found yet")
 def test_pair_bucket_over_the_workgroup_limit(ctx):
     # 1000 copies of one 24-residue sequence with no repeated residue at
     # k = 2: every pair of copies shares all 301 deletion variants, so the
