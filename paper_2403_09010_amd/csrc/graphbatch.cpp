@@ -323,11 +323,12 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
           throw Error{SD_E_LENGTH, "a sequence length is outside [1, 24]"};
       }
     }
+    uint64_t vlen[KEY_MAX_LEN_HOST + 1];  // V(L, k) by length
+    for (int L = 0; L <= KEY_MAX_LEN_HOST; ++L) vlen[L] = variants_of_length(L, k);
     for (TileBufs& t : tiles)
       for (const Piece& pc : t.pieces) {
         const std::vector<int64_t>& so = hoff[pc.set];
-        for (int64_t y = pc.first; y < pc.first + pc.count; ++y)
-          t.nk += variants_of_length(so[y + 1] - so[y], k);
+        for (int64_t y = pc.first; y < pc.first + pc.count; ++y) t.nk += vlen[so[y + 1] - so[y]];
         t.ncodes += (uint64_t)(so[pc.first + pc.count] - so[pc.first]);
       }
   }
