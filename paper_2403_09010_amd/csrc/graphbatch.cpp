@@ -351,7 +351,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
   // candidate capacity from the candidates per variant seen before
   const double ratio = std::max(c->graph_cand_ratio, kMinCandRatio);
   for (TileBufs& t : tiles)
-    t.cap = std::min<uint64_t>(0xFFFFFFF0ull, (uint64_t)((double)t.nk * ratio * 1.25) + 65536);
+    t.cap = std::min<uint64_t>(0xFFFFFFF0ull, (uint64_t)((double)t.nk * ratio * 1.1) + 65536);
   const std::string key = plan_key(c, idx, k, T, tiles);
 
   GraphPlan* plan = nullptr;
@@ -577,12 +577,12 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
       hip_check(hipStreamSynchronize(s), "synchronise");
     }
     // the capacity follows the candidates per variant: up at once after an
-    // overflow, down (to 1.5 times what was seen) once it is three times
-    // too large, so that a steady workload keeps its captured graph
+    // overflow, down (to 1.2 times what was seen) once it is twice too
+    // large, so that a steady workload keeps its captured graph
     if (cand_per_key > c->graph_cand_ratio)
       c->graph_cand_ratio = cand_per_key;
-    else if (3.0 * cand_per_key < c->graph_cand_ratio)
-      c->graph_cand_ratio = std::max(1.5 * cand_per_key, kMinCandRatio);
+    else if (2.0 * cand_per_key < c->graph_cand_ratio)
+      c->graph_cand_ratio = std::max(1.2 * cand_per_key, kMinCandRatio);
     // per set: its pieces' slices in order, query ids made set-local
     std::vector<uint64_t> total(nsets, 0);
     for (size_t x = 0; x < plan->tiles.size(); ++x)
