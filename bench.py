@@ -150,16 +150,6 @@ def emit(out, args):
             f.write(line + "\n")
 
 
-def make_batched_sets(ref, nsets, scale):
-    """Query sets of log-uniform sizes in [1e3, 2e5] (seeded), 10% reference mutants."""
-    import cdr3gen
-    p = cdr3gen.BATCHED
-    sizes = cdr3gen.loguniform_sizes(p["size_seed"], nsets, p["size_lo"], p["size_hi"])
-    sizes = np.maximum(1, (sizes * scale).astype(np.int64))
-    return [cdr3gen.generate_query(p["set_seed_base"] + q, int(n), *ref,
-                                   ref_mut_frac=p["ref_mut_frac"]) for q, n in enumerate(sizes)]
-
-
 def run_batched(args):
     """512 query sets against one 2M-sequence reference index at k=2: one set
     per launch (sd_query) versus all sets in one batched call (sd_query_batch),
@@ -174,7 +164,7 @@ def run_batched(args):
     nsets = args.sets
     log(f"generating the {p['ref_n']}-sequence reference and {nsets} query sets")
     ref = cdr3gen.generate(p["ref_seed"], p["ref_n"])
-    sets = make_batched_sets(ref, nsets, args.set_scale)
+    sets = cdr3gen.batched_sets(ref, nsets, args.set_scale)
     nq = sum(len(o) - 1 for _, o in sets)
     dev = torch.device("cuda", 0)
     ctx = Context(0)

@@ -118,6 +118,16 @@ def loguniform_sizes(seed: int, count: int, lo: float, hi: float) -> np.ndarray:
     return out
 
 
+def batched_sets(ref, nsets: int = BATCHED["sets"], scale: float = 1.0):
+    """The batched workload's query sets: log-uniform sizes in [1e3, 2e5]
+    (seeded, times `scale`), each with 10% mutants of the reference."""
+    p = BATCHED
+    sizes = loguniform_sizes(p["size_seed"], nsets, p["size_lo"], p["size_hi"])
+    sizes = np.maximum(1, (sizes * scale).astype(np.int64))
+    return [generate_query(p["set_seed_base"] + q, int(n), *ref, ref_mut_frac=p["ref_mut_frac"])
+            for q, n in enumerate(sizes)]
+
+
 def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
     out = np.empty(count, dtype=np.float64)
     _load().cdr3_poisson_arrivals(seed, count, rate, _ptr(out))
