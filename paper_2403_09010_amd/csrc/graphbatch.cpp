@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -40,6 +41,21 @@
 namespace sd {
 
 constexpr int KEY_MAX_LEN_HOST = 24;  // the longest sequence a key holds
+
+namespace {
+// Host-side phases of a batch, printed to stderr when SD_DEBUG_BATCH is set.
+struct PhaseClock {
+  bool on = std::getenv("SD_DEBUG_BATCH") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void lap(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "graph batch: %-22s %8.3f ms\n", what,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+}  // namespace
 
 namespace {
 
@@ -261,6 +277,7 @@ std::string plan_key(const sd_ctx* c, const sd_index* idx, int k, uint64_t T,
 
 void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, int k,
                       sd_pairs* outs, hipStream_t s) {
+  PhaseClock clk;
   const uint64_t id_limit = (1ull << idx->idbits) - 2;
   const uint64_t T = std::min<uint64_t>(
       id_limit, c->batch_tile_seqs ? (uint64_t)c->batch_tile_seqs : (4ull << 20));
@@ -333,6 +350,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
       }
   }
   if (tiles.back().pieces.empty()) tiles.pop_back();
+  clk.lap("lengths and sizes");
   c->stats = sd_stats{};
   for (int x = 0; x < nsets; ++x) {
     outs[x].n = 0;
@@ -353,6 +371,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
   for (TileBufs& t : tiles)
     t.cap = std::min<uint64_t>(0xFFFFFFF0ull, (uint64_t)((double)t.nk * ratio * 1.1) + 65536);
   const std::string key = plan_key(c, idx, k, T, tiles);
+  clk.lap("plan key");
 
   GraphPlan* plan = nullptr;
   for (auto& p : c->graph_plans)
@@ -454,6 +473,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
     plan = c->graph_plans.back().get();
     c->stats.n_graph_captures += 1;
   }
+  clk.lap("plan");
 
   // inputs of this batch into the plan's tile buffers, then the replay
   if (all_dev) {
@@ -496,6 +516,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
     }
   }
   hipEvent_t ready = nullptr, done = nullptr;
+  clk.lap("inputs");
   hip_check(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "event");
   hip_check(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event");
   hip_check(hipEventRecord(ready, s), "record");
@@ -507,6 +528,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
   (void)hipEventDestroy(ready);
   (void)hipEventDestroy(done);
   c->stats.n_graph_launches += 1;
+  clk.lap("replay");
 
   // results: per tile its counters, join size and piece bounds; a tile that
   // overflowed its candidate capacity runs again eagerly
@@ -555,7 +577,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
       }
       // overflow: this tile again, eagerly, with room sized from the count
       c->stats.n_graph_retries += 1;
-      if (std::getenv("SD_DEBUG_GRAPH"))
+      if (std::getenv("SD_DEBUG_BATCH"))
         std::fprintf(stderr,
                      "graph batch: tile %zu runs again (candidates %llu, capacity %llu, spill %llu "
                      "of %llu, bucket over %d)\n",
@@ -583,6 +605,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
       c->graph_cand_ratio = cand_per_key;
     else if (2.0 * cand_per_key < c->graph_cand_ratio)
       c->graph_cand_ratio = std::max(1.2 * cand_per_key, kMinCandRatio);
+    clk.lap("read-backs");
     // per set: its pieces' slices in order, query ids made set-local
     std::vector<uint64_t> total(nsets, 0);
     for (size_t x = 0; x < plan->tiles.size(); ++x)
@@ -614,6 +637,7 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
     }
     for (int x = 0; x < nsets; ++x) finish_output(c, si[x], sj[x], sd[x], total[x], &outs[x], s);
     hip_check(hipStreamSynchronize(s), "synchronise");
+    clk.lap("per-set results");
     c->stats.n_pairs = (int64_t)npairs;
   } catch (...) {
     for (auto& r : res)

@@ -13,6 +13,10 @@
 //   batch of sets a split of the sorted result into per-set slices.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -341,6 +345,16 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
     return;
   }
   c->stats = sd_stats{};
+  // host-side phases, printed to stderr when SD_DEBUG_BATCH is set
+  const bool dbg = std::getenv("SD_DEBUG_BATCH") != nullptr;
+  auto t_last = std::chrono::steady_clock::now();
+  auto lap = [&](const char* what) {
+    if (!dbg) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "batch: %-22s %8.3f ms\n", what,
+                 std::chrono::duration<double, std::milli>(now - t_last).count());
+    t_last = now;
+  };
   const uint64_t id_limit = (1ull << idx->idbits) - 2;
   const uint64_t tile_limit =
       std::min<uint64_t>(id_limit, c->batch_tile_seqs ? (uint64_t)c->batch_tile_seqs : (4ull << 20));
@@ -446,7 +460,9 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
       hip_check(hipStreamSynchronize(s), "synchronise");  // host vectors go out of scope
       q = DevSeqs{codes, offs, tot};
     }
+    lap("tile inputs");
     TileOut r = query_tile(cl, idx, q, k, w);
+    lap("tile pipeline");
     c->stats.n_seqs += (int64_t)tot;
     c->stats.n_keys += (int64_t)r.nkeys;
     c->stats.n_cand_raw += (int64_t)r.ncand;
@@ -484,6 +500,7 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
       dfree(c, r.d);
     }
     tm.finish();
+    lap("tile results");
     first = last;
   }
 }
