@@ -58,7 +58,9 @@ typedef struct {
  * A result: n triplets (i[t], j[t], d[t]) in structure-of-arrays form.
  * The caller sets on_device before the call (1: leave the arrays in device
  * memory; 0: host memory). The library owns the arrays; release them with
- * sd_pairs_free() before sd_destroy().
+ * sd_pairs_free() before sd_destroy(). Host arrays are pinned memory, the
+ * three of one result in one block, which the context keeps after
+ * sd_pairs_free() for later results (up to 512 MiB of such blocks).
  */
 typedef struct {
   int64_t n;

@@ -9,6 +9,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <thread>
 #include <unordered_set>
 #include <vector>
 
@@ -193,6 +194,44 @@ void* readback(sd_ctx* c, const void* dptr, size_t bytes, hipStream_t s) {
   return c->pinned;
 }
 
+constexpr size_t kHostCacheBytes = 512ull << 20;  // released result blocks kept per context
+
+void* host_block(sd_ctx* c, size_t bytes) {
+  auto it = c->host_cache.lower_bound(bytes);
+  if (it != c->host_cache.end() && it->first <= 2 * bytes + 65536) {
+    void* p = it->second;
+    c->host_live[p] = it->first;
+    c->host_cache_bytes -= it->first;
+    c->host_cache.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  hip_check(hipHostMalloc(&p, bytes, hipHostMallocDefault), "hipHostMalloc");
+  c->host_live[p] = bytes;
+  return p;
+}
+
+void host_release(sd_ctx* c, void* p) {
+  auto h = c->host_live.find(p);
+  if (h == c->host_live.end()) return;
+  const size_t bytes = h->second;
+  c->host_live.erase(h);
+  // make room by dropping the largest kept blocks; a block larger than the
+  // whole budget is freed at once
+  while (!c->host_cache.empty() && c->host_cache_bytes + bytes > kHostCacheBytes) {
+    auto last = std::prev(c->host_cache.end());
+    (void)hipHostFree(last->second);
+    c->host_cache_bytes -= last->first;
+    c->host_cache.erase(last);
+  }
+  if (bytes > kHostCacheBytes) {
+    (void)hipHostFree(p);
+    return;
+  }
+  c->host_cache.emplace(bytes, p);
+  c->host_cache_bytes += bytes;
+}
+
 StageTimer::StageTimer(sd_ctx* ctx, hipStream_t st) : c(ctx), s(st), on(ctx->timing != 0) {
   if (!on) return;
   if (c->events.empty()) c->events.resize(SD_MAX_STAGES + 1, nullptr);
@@ -340,7 +379,10 @@ void sd_destroy(sd_ctx* c) {
   c->live.clear();
   sd::release_cache(c);
   for (auto& kv : c->host_live) (void)hipHostFree(kv.first);
+  for (auto& kv : c->host_cache) (void)hipHostFree(kv.second);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->stage_host) (void)hipHostFree(c->stage_host);
+  if (c->stage_event) (void)hipEventDestroy(c->stage_event);
   for (auto& e : c->events)
     if (e) (void)hipEventDestroy(e);
   delete c;
@@ -648,6 +690,19 @@ int sd_pairs_copy(sd_ctx* c, const sd_pairs* p, uint32_t* i, uint32_t* j, uint8_
     else
       kind = dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
     const size_t n = (size_t)p->n;
+    if (kind == hipMemcpyHostToHost) {
+      // a host result is complete when the search returns: plain copies, the
+      // i array on a second thread when the result is large
+      std::thread ti;
+      if (n >= (1u << 18))
+        ti = std::thread([&] { std::memcpy(i, p->i, n * 4); });
+      else
+        std::memcpy(i, p->i, n * 4);
+      std::memcpy(j, p->j, n * 4);
+      std::memcpy(d, p->d, n);
+      if (ti.joinable()) ti.join();
+      return;
+    }
     sd::hip_check(hipMemcpyAsync(i, p->i, n * 4, kind, s), "copy i");
     sd::hip_check(hipMemcpyAsync(j, p->j, n * 4, kind, s), "copy j");
     sd::hip_check(hipMemcpyAsync(d, p->d, n, kind, s), "copy d");
@@ -657,16 +712,12 @@ int sd_pairs_copy(sd_ctx* c, const sd_pairs* p, uint32_t* i, uint32_t* j, uint8_
 
 void sd_pairs_free(sd_ctx* c, sd_pairs* p) {
   if (!c || !p) return;
-  void* arrays[3] = {p->i, p->j, p->d};
-  for (void* a : arrays) {
-    if (!a) continue;
-    auto h = c->host_live.find(a);
-    if (h != c->host_live.end()) {
-      (void)hipHostFree(a);
-      c->host_live.erase(h);
-    } else {
-      sd::dfree(c, a);
-    }
+  if (p->i && c->host_live.count(p->i)) {
+    // a host result: i, j and d share the block that starts at i
+    sd::host_release(c, p->i);
+  } else {
+    for (void* a : {(void*)p->i, (void*)p->j, (void*)p->d})
+      if (a) sd::dfree(c, a);
   }
   p->i = nullptr;
   p->j = nullptr;

@@ -40,8 +40,6 @@
 
 namespace sd {
 
-constexpr int KEY_MAX_LEN_HOST = 24;  // the longest sequence a key holds
-
 namespace {
 // Host-side phases of a batch, printed to stderr when SD_DEBUG_BATCH is set.
 struct PhaseClock {
@@ -295,58 +293,28 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
       done += take;
     }
   }
-  // the variant counts and code sizes need every length: device sets in one
-  // pass on the device (length histograms), host sets on the host
-  bool all_dev = kDeviceStaging;
-  for (int x = 0; x < nsets; ++x) all_dev = all_dev && (sets[x].n == 0 || sets[x].on_device);
-  Scratch ssc(c);
-  std::vector<BatchPiece> staged;
-  std::vector<std::vector<int64_t>> hoff;  // host path: every set's offsets
-  if (all_dev) {
-    for (const TileBufs& t : tiles)
-      for (const Piece& pc : t.pieces) {
-        BatchPiece b;
-        b.set = pc.set;
-        b.first = pc.first;
-        b.count = pc.count;
-        staged.push_back(b);
-      }
-    stage_spans(c, ssc, sets, staged, true, s);
-    size_t at = 0;
-    for (TileBufs& t : tiles)
-      for (size_t p = 0; p < t.pieces.size(); ++p, ++at) {
-        const BatchPiece& b = staged[at];
-        for (int L = 1; L <= KEY_MAX_LEN_HOST; ++L)
-          t.nk += (uint64_t)b.hist[L] * variants_of_length(L, k);
-        t.ncodes += (uint64_t)(b.hi - b.lo);
-      }
-  } else {
-    hoff.resize(nsets);
-    for (int x = 0; x < nsets; ++x) {
-      const sd_seqs& st = sets[x];
-      hoff[x].assign(st.n + 1, 0);
-      if (!st.n) continue;
-      if (st.on_device)
-        hip_check(hipMemcpy(hoff[x].data(), st.offsets, (st.n + 1) * 8, hipMemcpyDeviceToHost),
-                  "read offsets");
-      else
-        std::memcpy(hoff[x].data(), st.offsets, (st.n + 1) * 8);
-      if (hoff[x][0] != 0) throw Error{SD_E_INVAL, "offsets must start at 0"};
-      // lengths decide every size of the graph, so they are checked here
-      for (int64_t y = 0; y < st.n; ++y) {
-        const int64_t L = hoff[x][y + 1] - hoff[x][y];
-        if (L < 0) throw Error{SD_E_INVAL, "offsets must not decrease"};
-        if (L < 1 || L > KEY_MAX_LEN_HOST)
-          throw Error{SD_E_LENGTH, "a sequence length is outside [1, 24]"};
-      }
-    }
+  // the variant counts and code sizes need every length: every set's offsets
+  // on the host (device sets read into pinned memory with one wait), checked
+  // and summed on host threads
+  size_t dev_words = 0, tile_words = 0;
+  for (int x = 0; x < nsets; ++x)
+    if (sets[x].n && sets[x].on_device) dev_words += (size_t)sets[x].n + 1;
+  for (const TileBufs& t : tiles) tile_words += t.n + 1;
+  int64_t* area = stage_area(c, (dev_words + tile_words) * 8);
+  const std::vector<const int64_t*> so = set_offsets(sets, 0, nsets, area, s);
+  std::vector<SetSpan> spans;
+  for (const TileBufs& t : tiles)
+    for (const Piece& pc : t.pieces) spans.push_back(SetSpan{pc.set, pc.first, pc.count});
+  {
     uint64_t vlen[KEY_MAX_LEN_HOST + 1];  // V(L, k) by length
     for (int L = 0; L <= KEY_MAX_LEN_HOST; ++L) vlen[L] = variants_of_length(L, k);
+    std::vector<uint64_t> sums(spans.size());
+    check_spans(so, spans, true, vlen, sums.data());
+    size_t at = 0;
     for (TileBufs& t : tiles)
       for (const Piece& pc : t.pieces) {
-        const std::vector<int64_t>& so = hoff[pc.set];
-        for (int64_t y = pc.first; y < pc.first + pc.count; ++y) t.nk += vlen[so[y + 1] - so[y]];
-        t.ncodes += (uint64_t)(so[pc.first + pc.count] - so[pc.first]);
+        t.nk += sums[at++];
+        t.ncodes += (uint64_t)(so[pc.set][pc.first + pc.count] - so[pc.set][pc.first]);
       }
   }
   if (tiles.back().pieces.empty()) tiles.pop_back();
@@ -475,45 +443,32 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
   }
   clk.lap("plan");
 
-  // inputs of this batch into the plan's tile buffers, then the replay
-  if (all_dev) {
+  // inputs of this batch into the plan's tile buffers (offsets rebased into
+  // pinned memory, one copy per tile; codes one copy per piece), then the
+  // replay
+  {
+    int64_t* dst = area + dev_words;
     size_t at = 0;
     for (TileBufs& t : plan->tiles) {
+      const std::vector<SetSpan> ts(spans.begin() + at, spans.begin() + at + t.pieces.size());
+      at += t.pieces.size();
+      rebase_spans(so, ts, dst);
       uint64_t q = 0;
-      int64_t cpos = 0;
-      for (size_t p = 0; p < t.pieces.size(); ++p, ++at) {
-        BatchPiece& b = staged[at];
-        b.dst_offs = t.offs + q;
-        b.dst_codes = t.codes + cpos;
-        b.cbase = cpos;
-        q += (uint64_t)b.count;
-        cpos += b.hi - b.lo;
-      }
-    }
-    stage_gather(c, ssc, sets, staged, s);
-  } else {
-    for (TileBufs& t : plan->tiles) {
-      std::vector<int64_t> hoffs(t.n + 1, 0);
-      uint64_t q = 0;
-      int64_t cpos = 0;
-      for (const Piece& p : t.pieces) {
-        const sd_seqs& st = sets[p.set];
-        const std::vector<int64_t>& so = hoff[p.set];
-        const int64_t a = so[p.first], b = so[p.first + p.count];
-        for (int64_t y = 0; y < p.count; ++y) hoffs[q + y] = cpos + (so[p.first + y] - a);
+      for (const SetSpan& sp : ts) {
+        const sd_seqs& st = sets[sp.set];
+        const int64_t a = so[sp.set][sp.first], b = so[sp.set][sp.first + sp.count];
         if (b > a)
-          hip_check(hipMemcpyAsync(t.codes + cpos, st.codes + a, (size_t)(b - a),
+          hip_check(hipMemcpyAsync(t.codes + dst[q], st.codes + a, (size_t)(b - a),
                                    st.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                    s),
                     "copy codes");
-        cpos += b - a;
-        q += (uint64_t)p.count;
+        q += (uint64_t)sp.count;
       }
-      hoffs[t.n] = cpos;
-      hip_check(hipMemcpyAsync(t.offs, hoffs.data(), (t.n + 1) * 8, hipMemcpyHostToDevice, s),
+      hip_check(hipMemcpyAsync(t.offs, dst, (t.n + 1) * 8, hipMemcpyHostToDevice, s),
                 "copy offsets");
-      hip_check(hipStreamSynchronize(s), "synchronise");  // hoffs goes out of scope
+      dst += t.n + 1;
     }
+    stage_done(c, s);
   }
   hipEvent_t ready = nullptr, done = nullptr;
   clk.lap("inputs");

@@ -778,28 +778,21 @@ void finish_output(sd_ctx* c, uint32_t* oi, uint32_t* oj, uint8_t* od, uint64_t 
     out->d = od;
     return;
   }
-  // host result: pinned arrays owned by the context until sd_pairs_free
-  void *hi = nullptr, *hj = nullptr, *hd = nullptr;
+  // host result: one pinned block (i, j, then d) owned by the context until
+  // sd_pairs_free
+  void* blk = nullptr;
+  const size_t m = npairs ? npairs : 1;
   try {
-    const size_t m = npairs ? npairs : 1;
-    hip_check(hipHostMalloc(&hi, m * 4, hipHostMallocDefault), "hipHostMalloc");
-    c->host_live[hi] = 1;
-    hip_check(hipHostMalloc(&hj, m * 4, hipHostMallocDefault), "hipHostMalloc");
-    c->host_live[hj] = 1;
-    hip_check(hipHostMalloc(&hd, m, hipHostMallocDefault), "hipHostMalloc");
-    c->host_live[hd] = 1;
+    blk = host_block(c, m * 9);
     if (npairs) {
-      hip_check(hipMemcpyAsync(hi, oi, npairs * 4, hipMemcpyDeviceToHost, s), "D2H");
-      hip_check(hipMemcpyAsync(hj, oj, npairs * 4, hipMemcpyDeviceToHost, s), "D2H");
-      hip_check(hipMemcpyAsync(hd, od, npairs, hipMemcpyDeviceToHost, s), "D2H");
+      uint8_t* h = static_cast<uint8_t*>(blk);
+      hip_check(hipMemcpyAsync(h, oi, npairs * 4, hipMemcpyDeviceToHost, s), "D2H");
+      hip_check(hipMemcpyAsync(h + m * 4, oj, npairs * 4, hipMemcpyDeviceToHost, s), "D2H");
+      hip_check(hipMemcpyAsync(h + m * 8, od, npairs, hipMemcpyDeviceToHost, s), "D2H");
     }
     hip_check(hipStreamSynchronize(s), "D2H synchronise");
   } catch (...) {
-    for (void* p : {hi, hj, hd})
-      if (p) {
-        (void)hipHostFree(p);
-        c->host_live.erase(p);
-      }
+    if (blk) host_release(c, blk);
     dfree(c, oi);
     dfree(c, oj);
     dfree(c, od);
@@ -809,9 +802,10 @@ void finish_output(sd_ctx* c, uint32_t* oi, uint32_t* oj, uint8_t* od, uint64_t 
   dfree(c, oi);
   dfree(c, oj);
   dfree(c, od);
-  out->i = static_cast<uint32_t*>(hi);
-  out->j = static_cast<uint32_t*>(hj);
-  out->d = static_cast<uint8_t*>(hd);
+  uint8_t* h = static_cast<uint8_t*>(blk);
+  out->i = reinterpret_cast<uint32_t*>(h);
+  out->j = reinterpret_cast<uint32_t*>(h + m * 4);
+  out->d = h + m * 8;
 }
 
 void pair_distance(sd_ctx* c, const sd_seqs* a, const sd_seqs* b, const uint32_t* ia,

@@ -363,13 +363,11 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
     // the tile: sets [first, last), whole sets while they fit
     uint64_t tot = 0;
     int last = first;
-    bool all_dev = true;
     while (last < nsets) {
       const sd_seqs& st = sets[last];
       if ((uint64_t)st.n > id_limit) throw Error{SD_E_TOO_MANY, "a query set exceeds the index id width"};
       if (last > first && tot + (uint64_t)st.n > tile_limit) break;
       tot += (uint64_t)st.n;
-      all_dev = all_dev && kDeviceStaging && (st.n == 0 || st.on_device);
       ++last;
     }
     Scratch sc(c);
@@ -388,76 +386,37 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
     }
     if (last - first == 1 && sets[first].on_device) {
       q = DevSeqs{sets[first].codes, sets[first].offsets, (uint64_t)sets[first].n};
-    } else if (all_dev) {
-      // device sets: their code spans in one pass, then one gather
-      std::vector<BatchPiece> pcs;
+    } else {
+      // the sets' offsets on the host (device sets read into pinned memory
+      // with one wait), checked and rebased on host threads into pinned
+      // memory, one copy of the tile's offsets; codes one copy per set
+      size_t dev_words = 0;
+      std::vector<SetSpan> spans;
       for (int x = first; x < last; ++x)
         if (sets[x].n) {
-          BatchPiece b;
-          b.set = x;
-          b.count = sets[x].n;
-          pcs.push_back(b);
+          if (sets[x].on_device) dev_words += (size_t)sets[x].n + 1;
+          spans.push_back(SetSpan{x, 0, sets[x].n});
         }
-      stage_spans(c, sc, sets, pcs, false, s);
-      int64_t codes_tot = 0;
-      for (const BatchPiece& b : pcs) codes_tot += b.hi - b.lo;
+      int64_t* area = stage_area(c, (dev_words + tot + 1) * 8);
+      const std::vector<const int64_t*> so = set_offsets(sets, first, last, area, s);
+      check_spans(so, spans, false, nullptr, nullptr);
+      int64_t* hoffs = area + dev_words;
+      const int64_t codes_tot = rebase_spans(so, spans, hoffs);
       uint8_t* codes = sc.get<uint8_t>((uint64_t)codes_tot + 1);
       int64_t* offs = sc.get<int64_t>(tot + 1);
-      launch_fill_u64(reinterpret_cast<uint64_t*>(offs), 0, 1, s);  // (all sets empty)
-      int64_t cpos = 0;
-      for (BatchPiece& b : pcs) {
-        b.dst_offs = offs + base[b.set - first];
-        b.dst_codes = codes + cpos;
-        b.cbase = cpos;
-        cpos += b.hi - b.lo;
+      uint64_t qpos = 0;
+      for (const SetSpan& sp : spans) {
+        const sd_seqs& st = sets[sp.set];
+        const int64_t ncd = so[sp.set][sp.count];
+        if (ncd)
+          hip_check(hipMemcpyAsync(codes + hoffs[qpos], st.codes, (size_t)ncd,
+                                   st.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
+                    "copy codes");
+        qpos += (uint64_t)sp.count;
       }
-      stage_gather(c, sc, sets, pcs, s);
-      q = DevSeqs{codes, offs, tot};
-    } else {
-      std::vector<int64_t> ncodes;
-      uint64_t codes_tot = 0;
-      for (int x = first; x < last; ++x) {
-        const sd_seqs& st = sets[x];
-        int64_t nc = 0;
-        if (st.n) {
-          if (st.on_device)
-            hip_check(hipMemcpy(&nc, st.offsets + st.n, 8, hipMemcpyDeviceToHost), "read offsets");
-          else
-            nc = st.offsets[st.n];
-        }
-        ncodes.push_back(nc);
-        codes_tot += (uint64_t)nc;
-      }
-      uint8_t* codes = sc.get<uint8_t>(codes_tot + 1);
-      int64_t* offs = sc.get<int64_t>(tot + 1);
-      std::vector<int64_t> hoffs(tot + 1);
-      uint64_t qpos = 0, cpos = 0;
-      for (int x = first; x < last; ++x) {
-        const sd_seqs& st = sets[x];
-        if (st.n) {
-          std::vector<int64_t> so(st.n + 1);
-          if (st.on_device)
-            hip_check(hipMemcpy(so.data(), st.offsets, (st.n + 1) * 8, hipMemcpyDeviceToHost), "offsets");
-          else
-            std::memcpy(so.data(), st.offsets, (st.n + 1) * 8);
-          if (so[0] != 0) throw Error{SD_E_INVAL, "offsets must start at 0"};
-          for (int64_t y = 0; y < st.n; ++y) {
-            if (so[y + 1] < so[y]) throw Error{SD_E_INVAL, "offsets must not decrease"};
-            hoffs[qpos + y] = (int64_t)cpos + so[y];
-          }
-          const int64_t ncd = so[st.n];
-          if (ncd)
-            hip_check(hipMemcpyAsync(codes + cpos, st.codes, (size_t)ncd,
-                                     st.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
-                      "copy codes");
-          qpos += (uint64_t)st.n;
-          cpos += (uint64_t)ncd;
-        }
-      }
-      hoffs[tot] = (int64_t)cpos;
-      hip_check(hipMemcpyAsync(offs, hoffs.data(), (tot + 1) * 8, hipMemcpyHostToDevice, s),
+      hip_check(hipMemcpyAsync(offs, hoffs, (tot + 1) * 8, hipMemcpyHostToDevice, s),
                 "copy offsets");
-      hip_check(hipStreamSynchronize(s), "synchronise");  // host vectors go out of scope
+      stage_done(c, s);
       q = DevSeqs{codes, offs, tot};
     }
     lap("tile inputs");

@@ -330,64 +330,6 @@ __global__ void k_slice_rebase(const uint32_t* __restrict__ qi, const uint32_t* 
   }
 }
 
-// ------------------------------------------------------------------ batch staging
-//
-// The sets of a batch arrive as separate device CSR arrays. Instead of one
-// synchronous read of every set's offsets, two kernels stage a whole batch:
-// k_stage_spans reads every piece's offsets once (the length histogram, the
-// code span, the offset checks) for one read-back, and k_stage_gather writes
-// the tiles' concatenated CSR.
-
-constexpr uint32_t STAGE_CHUNK = 8192;  // sequences per workgroup
-using sd::STAGE_BINS;
-using sd::StageChunk;
-using sd::StagePiece;
-
-__global__ __launch_bounds__(QNT) void k_stage_spans(const StagePiece* __restrict__ pieces,
-                                                     const StageChunk* __restrict__ chunks,
-                                                     uint32_t* __restrict__ hist,
-                                                     int64_t* __restrict__ spans,
-                                                     uint32_t* __restrict__ err) {
-  __shared__ uint32_t s_h[STAGE_BINS];
-  const StageChunk ch = chunks[blockIdx.x];
-  const StagePiece P = pieces[ch.piece];
-  if (hist)
-    for (uint32_t b = threadIdx.x; b < STAGE_BINS; b += QNT) s_h[b] = 0;
-  __syncthreads();
-  bool bad = false;
-  for (int64_t y = ch.first + threadIdx.x; y < ch.first + ch.count; y += QNT) {
-    const int64_t a = P.offs[y], b = P.offs[y + 1];
-    const int64_t L = b - a;
-    bad |= L < 0 || (y == 0 && a != 0);
-    if (hist) atomicAdd(&s_h[L >= 1 && L <= KEY_MAX_LEN ? (uint32_t)L : 0u], 1u);
-  }
-  if (bad) atomicOr(err, SD_ERRBIT_OFFSETS);
-  __syncthreads();
-  if (hist)
-    for (uint32_t b = threadIdx.x; b < STAGE_BINS; b += QNT)
-      if (s_h[b]) atomicAdd(&hist[(uint64_t)ch.piece * STAGE_BINS + b], s_h[b]);
-  if (threadIdx.x == 0) {
-    if (ch.first == P.first) spans[2 * (uint64_t)ch.piece] = P.offs[P.first];
-    if (ch.first + ch.count == P.first + P.count)
-      spans[2 * (uint64_t)ch.piece + 1] = P.offs[P.first + P.count];
-  }
-}
-
-// Tile offsets (each piece's rebased by its code base) and codes (the
-// chunk's contiguous code span, copied byte-coalesced).
-__global__ __launch_bounds__(QNT) void k_stage_gather(const StagePiece* __restrict__ pieces,
-                                                      const StageChunk* __restrict__ chunks) {
-  const StageChunk ch = chunks[blockIdx.x];
-  const StagePiece P = pieces[ch.piece];
-  const int64_t shift = P.cbase - P.lo;
-  for (int64_t y = ch.first + threadIdx.x; y < ch.first + ch.count; y += QNT)
-    P.dst_offs[y - P.first] = P.offs[y] + shift;
-  if (threadIdx.x == 0 && ch.first + ch.count == P.first + P.count)
-    P.dst_offs[P.count] = P.offs[P.first + P.count] + shift;
-  const int64_t c0 = P.offs[ch.first], c1 = P.offs[ch.first + ch.count];
-  for (int64_t b = c0 + threadIdx.x; b < c1; b += QNT) P.dst_codes[b - P.lo] = P.codes[b];
-}
-
 }  // namespace sdk
 
 namespace sd {
@@ -427,21 +369,6 @@ void launch_verify_weighted(const uint64_t* cand, uint64_t c, const u128* sa, co
                      dim3((unsigned)((c + weighted_tile() - 1) / weighted_tile())), dim3(sdk::QNT),
                      0, s, cand, c, sa, sb, k, subst, indel, max_score, oi, oj, od, status,
                      tile_counter, epoch, out_count, err);
-}
-
-uint32_t stage_chunk() { return sdk::STAGE_CHUNK; }
-
-void launch_stage_spans(const StagePiece* pieces, const StageChunk* chunks, uint32_t nchunks,
-                        uint32_t* hist, int64_t* spans, uint32_t* err, hipStream_t s) {
-  if (!nchunks) return;
-  hipLaunchKernelGGL(sdk::k_stage_spans, dim3(nchunks), dim3(sdk::QNT), 0, s, pieces, chunks, hist,
-                     spans, err);
-}
-
-void launch_stage_gather(const StagePiece* pieces, const StageChunk* chunks, uint32_t nchunks,
-                         hipStream_t s) {
-  if (!nchunks) return;
-  hipLaunchKernelGGL(sdk::k_stage_gather, dim3(nchunks), dim3(sdk::QNT), 0, s, pieces, chunks);
 }
 
 void launch_set_ranges(const uint32_t* qi, uint64_t n, const uint32_t* set_base, uint32_t nb,

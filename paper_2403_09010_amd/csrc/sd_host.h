@@ -25,23 +25,7 @@ inline void check_seqs(const sd_seqs* s) {
   if ((uint64_t)s->n >= 0xFFFFFFFFull) throw Error{SD_E_TOO_MANY, "at most 2^32 - 2 sequences"};
 }
 
-inline DevSeqs stage_seqs(sd_ctx* c, Scratch& sc, const sd_seqs* s, hipStream_t st) {
-  DevSeqs d{s->codes, s->offsets, (uint64_t)s->n};
-  if (s->on_device || s->n == 0) return d;
-  const int64_t total = s->offsets[s->n];
-  if (s->offsets[0] != 0) throw Error{SD_E_INVAL, "offsets must start at 0"};
-  for (int64_t x = 0; x < s->n; ++x)  // every sequence must lie inside codes[0, total)
-    if (s->offsets[x + 1] < s->offsets[x]) throw Error{SD_E_INVAL, "offsets must not decrease"};
-  uint8_t* codes = sc.get<uint8_t>((uint64_t)total + 1);
-  int64_t* offs = sc.get<int64_t>((uint64_t)s->n + 1);
-  if (total)
-    hip_check(hipMemcpyAsync(codes, s->codes, (size_t)total, hipMemcpyHostToDevice, st), "H2D codes");
-  hip_check(hipMemcpyAsync(offs, s->offsets, (size_t)(s->n + 1) * 8, hipMemcpyHostToDevice, st),
-            "H2D offsets");
-  d.codes = codes;
-  d.offs = offs;
-  return d;
-}
+DevSeqs stage_seqs(sd_ctx* c, Scratch& sc, const sd_seqs* s, hipStream_t st);
 
 inline void raise_validation(uint32_t err) {
   if (err & SD_ERRBIT_LENGTH) throw Error{SD_E_LENGTH, "a sequence length is outside [1, 24]"};
@@ -273,31 +257,40 @@ uint64_t bucket_sort_verify(Call& cl, const BucketPlan& p, uint64_t* cand, uint6
                             const char* sort_stage, const char* verify_stage,
                             const u128* a2 = nullptr, const u128* sb2 = nullptr);
 
-// A run of consecutive sequences of one set of a batch, and what staging
-// learns and needs of it.
-struct BatchPiece {
+constexpr int KEY_MAX_LEN_HOST = 24;  // the longest sequence a key holds
+
+// Host staging of batched query sets (stage.cpp). A span is a run of
+// consecutive sequences of one set.
+struct SetSpan {
   int set = 0;
   int64_t first = 0, count = 0;  // the set's sequences [first, first + count)
-  int64_t lo = 0, hi = 0;        // offs[first], offs[first + count] (stage_spans)
-  uint32_t hist[STAGE_BINS] = {};  // sequences per length (stage_spans with want_hist)
-  int64_t* dst_offs = nullptr;   // where stage_gather writes the piece's count + 1 offsets
-  uint8_t* dst_codes = nullptr;  // and its codes
-  int64_t cbase = 0;             // the code position dst_codes stands for
 };
-
-// Switched off until these kernels have run on the GPU: batches read set
-// offsets on the host as before.
-constexpr bool kDeviceStaging = false;
-
-// Device sets only: the spans (and, with want_hist, the length histograms)
-// of every piece after one pass and one read-back. Raises SD_E_INVAL for bad
-// offsets and SD_E_LENGTH for a length outside [1, 24] (with want_hist).
-void stage_spans(sd_ctx* c, Scratch& sc, const sd_seqs* sets, std::vector<BatchPiece>& pieces,
-                 bool want_hist, hipStream_t s);
-// Write every piece's rebased offsets and codes (one launch); returns after
-// the copies are done.
-void stage_gather(sd_ctx* c, Scratch& sc, const sd_seqs* sets,
-                  const std::vector<BatchPiece>& pieces, hipStream_t s);
+// Pinned host memory of the context for staging, at least `bytes` bytes,
+// kept until sd_destroy. Waits first for the copies the last stage_done()
+// recorded, so the area is free to overwrite.
+int64_t* stage_area(sd_ctx* c, size_t bytes);
+// Marks the end of the copies enqueued on s from the staging area.
+void stage_done(sd_ctx* c, hipStream_t s);
+// Host views of the offsets of the sets [first, last) (entries below first
+// are null): device sets are read into `area` (n + 1 words for each
+// non-empty device set, in set order) with one synchronisation of s, host
+// sets are used where they are. Raises SD_E_INVAL unless every non-empty
+// set's offsets start at 0.
+std::vector<const int64_t*> set_offsets(const sd_seqs* sets, int first, int last, int64_t* area,
+                                        hipStream_t s);
+// Checks every sequence of the spans on host threads: offsets must not
+// decrease (SD_E_INVAL) and, with check_len, lengths lie in [1, 24]
+// (SD_E_LENGTH); the first failing sequence in span order decides. With
+// vlen (indexed by length; lengths are then checked too), sums[x] = the sum
+// of vlen over span x.
+void check_spans(const std::vector<const int64_t*>& offs, const std::vector<SetSpan>& spans,
+                 bool check_len, const uint64_t* vlen, uint64_t* sums);
+// The spans' offsets laid end to end and rebased to their concatenated
+// codes, on host threads: dst[q + y] = (codes of the spans before) +
+// offs[first + y] - offs[first] for each span of q sequences before it, and
+// dst[total] = the codes of all spans, which is returned.
+int64_t rebase_spans(const std::vector<const int64_t*>& offs, const std::vector<SetSpan>& spans,
+                     int64_t* dst);
 
 struct Cands {
   uint64_t* p = nullptr;  // pool block owned by the caller

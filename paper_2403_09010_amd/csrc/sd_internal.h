@@ -249,34 +249,6 @@ void launch_verify_weighted(const uint64_t* cand, uint64_t c, const u128* sa, co
                             uint32_t* err, hipStream_t s);
 // bounds[s] = first position of qi[0, n) (n = min(n, *n_dev) with n_dev) whose
 // value is >= set_base[s]
-// Batch staging. A piece is a run of consecutive sequences of one device
-// set; a chunk is at most stage_chunk() sequences of one piece (one
-// workgroup each).
-struct StagePiece {
-  const int64_t* offs;   // the set's offsets (device)
-  const uint8_t* codes;  // the set's codes (device)
-  int64_t first, count;  // the piece's sequences in the set
-  int64_t* dst_offs;     // tile offsets at the piece's first tile-local id
-  uint8_t* dst_codes;    // tile codes at the piece's first code
-  int64_t lo;            // offs[first] (from the spans pass)
-  int64_t cbase;         // the piece's first code position in the tile
-};
-struct StageChunk {
-  uint32_t piece, pad;
-  int64_t first, count;
-};
-constexpr uint32_t STAGE_BINS = 26;  // length histogram: bin L for 1 <= L <= 24, bin 0 otherwise
-uint32_t stage_chunk();
-// Per piece: hist[piece * STAGE_BINS + L] += sequences of length L (hist may
-// be null), spans[2 piece] = offs[first], spans[2 piece + 1] =
-// offs[first + count]; SD_ERRBIT_OFFSETS in *err if a set's first offset is
-// not 0 or an offset decreases.
-void launch_stage_spans(const StagePiece* pieces, const StageChunk* chunks, uint32_t nchunks,
-                        uint32_t* hist, int64_t* spans, uint32_t* err, hipStream_t s);
-// Per piece: dst_offs[0..count] = offs[first..first + count] - lo + cbase
-// and the codes [lo, offs[first + count]) to dst_codes.
-void launch_stage_gather(const StagePiece* pieces, const StageChunk* chunks, uint32_t nchunks,
-                         hipStream_t s);
 void launch_set_ranges(const uint32_t* qi, uint64_t n, const uint32_t* set_base, uint32_t nb,
                        uint64_t* bounds, hipStream_t s, const unsigned long long* n_dev = nullptr);
 // oi[t] = qi[lo + t] + shift, oj[t] = rj[lo + t], od[t] = d[lo + t] for t < n
@@ -340,7 +312,11 @@ struct sd_ctx {
   // released one by one; the whole area is reused by the next such call
   unsigned char* arena = nullptr;
   size_t arena_size = 0, arena_used = 0;
-  std::unordered_map<void*, int> host_live;  // pinned host result arrays
+  // pinned host result blocks (i, j and d of one result in one block) by
+  // size, and released blocks kept for the next results
+  std::unordered_map<void*, size_t> host_live;
+  std::multimap<size_t, void*> host_cache;
+  size_t host_cache_bytes = 0;
   // look-back state
   uint64_t* status = nullptr;
   size_t status_words = 0;
@@ -350,6 +326,12 @@ struct sd_ctx {
   int tile_slot = 0;  // next tile-counter slot of the current call (0: none handed out yet)
   void* pinned = nullptr;  // pinned host staging for small read-backs
   size_t pinned_bytes = 0;
+  // pinned host staging of batched query sets (their offsets, the tiles'
+  // rebased offsets), and the event after the last copies out of it
+  int64_t* stage_host = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_event = nullptr;
+  bool stage_pending = false;
   sd_stats stats{};
   int timing = 0;
   int path = 0;        // 0 automatic, 1 full-key sort, 2 hashed
@@ -461,6 +443,11 @@ uint32_t next_epoch(sd_ctx* c, uint64_t words, hipStream_t s);
 uint32_t* fresh_counters(sd_ctx* c, size_t n, hipStream_t s);
 // copy `bytes` from device to the pinned staging area and wait for stream s
 void* readback(sd_ctx* c, const void* dptr, size_t bytes, hipStream_t s);
+// Pinned host memory for a host result (a released block of bytes to twice
+// that, else a new one); host_release keeps a block for reuse (up to a
+// bounded total per context) or frees it.
+void* host_block(sd_ctx* c, size_t bytes);
+void host_release(sd_ctx* c, void* p);
 
 // stage timing (HIP events on the call's stream; no host synchronisation
 // until the end of the call)

@@ -1,10 +1,14 @@
-// Staging of a batch of device query sets into tile CSR arrays: one pass
-// over every piece's offsets (lengths, code spans and checks) with a single
-// read-back, then one gather launch, instead of a synchronous read of every
-// set's offsets and a copy per set.
+// Host staging of sequence sets. A batch of query sets becomes tile CSR
+// arrays: the offsets of every device set come to pinned host memory with
+// one synchronisation, the checks and the rebasing onto the tile's
+// concatenated codes run on host threads into pinned memory, and each tile's
+// offsets go back with one copy. A single host set goes to the device as it
+// is, after the same checks.
 #include <hip/hip_runtime.h>
 
-#include <cstring>
+#include <algorithm>
+#include <atomic>
+#include <thread>
 #include <vector>
 
 #include "sd_host.h"
@@ -13,82 +17,165 @@ namespace sd {
 
 namespace {
 
-// chunks of at most stage_chunk() sequences, piece by piece
-std::vector<StageChunk> make_chunks(const std::vector<StagePiece>& pieces) {
-  std::vector<StageChunk> ch;
-  const int64_t step = stage_chunk();
-  for (size_t p = 0; p < pieces.size(); ++p)
-    for (int64_t y = pieces[p].first; y < pieces[p].first + pieces[p].count; y += step)
-      ch.push_back(StageChunk{(uint32_t)p, 0u, y,
-                              std::min<int64_t>(step, pieces[p].first + pieces[p].count - y)});
-  return ch;
+constexpr int64_t kGrain = 1 << 18;  // sequences per work item
+constexpr unsigned kMaxThreads = 16;
+
+// a piece of one span: its sequences [lo, hi) (set-local)
+struct Item {
+  size_t span;
+  int64_t lo, hi;
+};
+
+std::vector<Item> items_of(const std::vector<SetSpan>& spans) {
+  std::vector<Item> it;
+  for (size_t x = 0; x < spans.size(); ++x)
+    for (int64_t y = spans[x].first; y < spans[x].first + spans[x].count; y += kGrain)
+      it.push_back(Item{x, y, std::min(y + kGrain, spans[x].first + spans[x].count)});
+  return it;
 }
 
-template <typename T>
-T* upload(Scratch& sc, const std::vector<T>& v, hipStream_t s) {
-  T* d = sc.get<T>(v.size());
-  if (!v.empty())
-    hip_check(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s),
-              "upload staging table");
-  return d;
+// fn(item index) for every item, on up to kMaxThreads threads taking items
+// in turn (inline for one or two items)
+template <class F>
+void for_items(size_t n, F&& fn) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned nt = (unsigned)std::min<size_t>({n, (size_t)hw, (size_t)kMaxThreads});
+  if (nt <= 2) {
+    for (size_t x = 0; x < n; ++x) fn(x);
+    return;
+  }
+  std::atomic<size_t> next{0};
+  auto work = [&] {
+    for (size_t x = next.fetch_add(1); x < n; x = next.fetch_add(1)) fn(x);
+  };
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
 }
 
 }  // namespace
 
-void stage_spans(sd_ctx* c, Scratch& sc, const sd_seqs* sets, std::vector<BatchPiece>& pieces,
-                 bool want_hist, hipStream_t s) {
-  if (pieces.empty()) return;
-  std::vector<StagePiece> tab(pieces.size());
-  for (size_t p = 0; p < pieces.size(); ++p) {
-    const sd_seqs& st = sets[pieces[p].set];
-    if (!st.on_device) throw Error{SD_E_INVAL, "device staging takes device sets"};
-    tab[p] = StagePiece{st.offsets, st.codes, pieces[p].first, pieces[p].count,
-                        nullptr,    nullptr,  0,               0};
-  }
-  const std::vector<StageChunk> ch = make_chunks(tab);
-  const StagePiece* dtab = upload(sc, tab, s);
-  const StageChunk* dch = upload(sc, ch, s);
-  const uint64_t nh = want_hist ? pieces.size() * STAGE_BINS : 0;
-  // one block: the histogram, the spans and the error word
-  uint8_t* blk = sc.get<uint8_t>(nh * 4 + pieces.size() * 16 + 16);
-  uint32_t* hist = want_hist ? reinterpret_cast<uint32_t*>(blk) : nullptr;
-  int64_t* spans = reinterpret_cast<int64_t*>(blk + nh * 4);
-  uint32_t* err = reinterpret_cast<uint32_t*>(blk + nh * 4 + pieces.size() * 16);
-  launch_fill_u32(reinterpret_cast<uint32_t*>(blk), 0,
-                  (nh * 4 + pieces.size() * 16 + 16) / 4, s);
-  launch_stage_spans(dtab, dch, (uint32_t)ch.size(), hist, spans, err, s);
-  std::vector<uint8_t> h(nh * 4 + pieces.size() * 16 + 16);
-  hip_check(hipMemcpyAsync(h.data(), blk, h.size(), hipMemcpyDeviceToHost, s), "read spans");
-  hip_check(hipStreamSynchronize(s), "synchronise");
-  uint32_t e;
-  std::memcpy(&e, h.data() + nh * 4 + pieces.size() * 16, 4);
-  raise_validation(e);
-  for (size_t p = 0; p < pieces.size(); ++p) {
-    std::memcpy(&pieces[p].lo, h.data() + nh * 4 + p * 16, 8);
-    std::memcpy(&pieces[p].hi, h.data() + nh * 4 + p * 16 + 8, 8);
-    if (want_hist) {
-      std::memcpy(pieces[p].hist, h.data() + p * STAGE_BINS * 4, STAGE_BINS * 4);
-      if (pieces[p].hist[0]) throw Error{SD_E_LENGTH, "a sequence length is outside [1, 24]"};
-    }
-  }
+DevSeqs stage_seqs(sd_ctx* c, Scratch& sc, const sd_seqs* s, hipStream_t st) {
+  DevSeqs d{s->codes, s->offsets, (uint64_t)s->n};
+  if (s->on_device || s->n == 0) return d;
+  const int64_t total = s->offsets[s->n];
+  if (s->offsets[0] != 0) throw Error{SD_E_INVAL, "offsets must start at 0"};
+  // every sequence must lie inside codes[0, total) (checked on host threads)
+  check_spans({s->offsets}, {SetSpan{0, 0, s->n}}, false, nullptr, nullptr);
+  uint8_t* codes = sc.get<uint8_t>((uint64_t)total + 1);
+  int64_t* offs = sc.get<int64_t>((uint64_t)s->n + 1);
+  if (total)
+    hip_check(hipMemcpyAsync(codes, s->codes, (size_t)total, hipMemcpyHostToDevice, st), "H2D codes");
+  hip_check(hipMemcpyAsync(offs, s->offsets, (size_t)(s->n + 1) * 8, hipMemcpyHostToDevice, st),
+            "H2D offsets");
+  d.codes = codes;
+  d.offs = offs;
+  return d;
 }
 
-void stage_gather(sd_ctx* c, Scratch& sc, const sd_seqs* sets,
-                  const std::vector<BatchPiece>& pieces, hipStream_t s) {
-  (void)c;
-  if (pieces.empty()) return;
-  std::vector<StagePiece> tab(pieces.size());
-  for (size_t p = 0; p < pieces.size(); ++p) {
-    const BatchPiece& b = pieces[p];
-    tab[p] = StagePiece{sets[b.set].offsets, sets[b.set].codes, b.first, b.count,
-                        b.dst_offs,          b.dst_codes,       b.lo,    b.cbase};
+int64_t* stage_area(sd_ctx* c, size_t bytes) {
+  if (c->stage_pending) {
+    hip_check(hipEventSynchronize(c->stage_event), "wait for staging copies");
+    c->stage_pending = false;
   }
-  const std::vector<StageChunk> ch = make_chunks(tab);
-  const StagePiece* dtab = upload(sc, tab, s);
-  const StageChunk* dch = upload(sc, ch, s);
-  launch_stage_gather(dtab, dch, (uint32_t)ch.size(), s);
-  // the tables are host vectors of this scope
-  hip_check(hipStreamSynchronize(s), "synchronise");
+  if (bytes > c->stage_bytes) {
+    if (c->stage_host) (void)hipHostFree(c->stage_host);
+    c->stage_host = nullptr;
+    c->stage_bytes = 0;
+    const size_t want = std::max<size_t>(bytes + bytes / 4, 1 << 20);
+    hip_check(hipHostMalloc(reinterpret_cast<void**>(&c->stage_host), want, hipHostMallocDefault),
+              "hipHostMalloc");
+    c->stage_bytes = want;
+  }
+  return c->stage_host;
+}
+
+void stage_done(sd_ctx* c, hipStream_t s) {
+  if (!c->stage_event)
+    hip_check(hipEventCreateWithFlags(&c->stage_event, hipEventDisableTiming), "event");
+  hip_check(hipEventRecord(c->stage_event, s), "record");
+  c->stage_pending = true;
+}
+
+std::vector<const int64_t*> set_offsets(const sd_seqs* sets, int first, int last, int64_t* area,
+                                        hipStream_t s) {
+  std::vector<const int64_t*> of(last, nullptr);
+  bool copied = false;
+  for (int x = first; x < last; ++x) {
+    const sd_seqs& st = sets[x];
+    if (!st.n) continue;
+    if (!st.on_device) {
+      of[x] = st.offsets;
+      continue;
+    }
+    hip_check(hipMemcpyAsync(area, st.offsets, (size_t)(st.n + 1) * 8, hipMemcpyDeviceToHost, s),
+              "read offsets");
+    of[x] = area;
+    area += st.n + 1;
+    copied = true;
+  }
+  if (copied) hip_check(hipStreamSynchronize(s), "synchronise");
+  for (int x = first; x < last; ++x)
+    if (of[x] && of[x][0] != 0) throw Error{SD_E_INVAL, "offsets must start at 0"};
+  return of;
+}
+
+void check_spans(const std::vector<const int64_t*>& offs, const std::vector<SetSpan>& spans,
+                 bool check_len, const uint64_t* vlen, uint64_t* sums) {
+  const std::vector<Item> it = items_of(spans);
+  std::vector<int> err(it.size(), SD_OK);
+  std::vector<uint64_t> part(it.size(), 0);
+  for_items(it.size(), [&](size_t x) {
+    const int64_t* so = offs[spans[it[x].span].set];
+    uint64_t sum = 0;
+    for (int64_t y = it[x].lo; y < it[x].hi; ++y) {
+      const int64_t L = so[y + 1] - so[y];
+      if (L < 0) {
+        err[x] = SD_E_INVAL;
+        return;
+      }
+      if ((check_len || vlen) && (L < 1 || L > KEY_MAX_LEN_HOST)) {
+        err[x] = SD_E_LENGTH;
+        return;
+      }
+      if (vlen) sum += vlen[L];
+    }
+    part[x] = sum;
+  });
+  for (size_t x = 0; x < it.size(); ++x) {
+    if (err[x] == SD_E_INVAL) throw Error{SD_E_INVAL, "offsets must not decrease"};
+    if (err[x] == SD_E_LENGTH) throw Error{SD_E_LENGTH, "a sequence length is outside [1, 24]"};
+  }
+  if (!sums) return;
+  for (size_t x = 0; x < spans.size(); ++x) sums[x] = 0;
+  for (size_t x = 0; x < it.size(); ++x) sums[it[x].span] += part[x];
+}
+
+int64_t rebase_spans(const std::vector<const int64_t*>& offs, const std::vector<SetSpan>& spans,
+                     int64_t* dst) {
+  // where each span starts in dst, and its code base
+  std::vector<int64_t> q0(spans.size()), c0(spans.size());
+  int64_t q = 0, cpos = 0;
+  for (size_t x = 0; x < spans.size(); ++x) {
+    q0[x] = q;
+    c0[x] = cpos;
+    if (!spans[x].count) continue;
+    const int64_t* so = offs[spans[x].set];
+    q += spans[x].count;
+    cpos += so[spans[x].first + spans[x].count] - so[spans[x].first];
+  }
+  dst[q] = cpos;
+  const std::vector<Item> it = items_of(spans);
+  for_items(it.size(), [&](size_t x) {
+    const SetSpan& sp = spans[it[x].span];
+    const int64_t* so = offs[sp.set];
+    const int64_t shift = c0[it[x].span] - so[sp.first];
+    int64_t* d = dst + q0[it[x].span] - sp.first;
+    for (int64_t y = it[x].lo; y < it[x].hi; ++y) d[y] = so[y] + shift;
+  });
+  return cpos;
 }
 
 }  // namespace sd
