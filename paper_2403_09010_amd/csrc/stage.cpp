@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstring>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -60,16 +62,89 @@ void for_items(size_t n, F&& fn) {
 DevSeqs stage_seqs(sd_ctx* c, Scratch& sc, const sd_seqs* s, hipStream_t st) {
   DevSeqs d{s->codes, s->offsets, (uint64_t)s->n};
   if (s->on_device || s->n == 0) return d;
-  const int64_t total = s->offsets[s->n];
-  if (s->offsets[0] != 0) throw Error{SD_E_INVAL, "offsets must start at 0"};
-  // every sequence must lie inside codes[0, total) (checked on host threads)
-  check_spans({s->offsets}, {SetSpan{0, 0, s->n}}, false, nullptr, nullptr);
+  const int64_t n = s->n;
+  const int64_t* so = s->offsets;
+  if (so[0] != 0) throw Error{SD_E_INVAL, "offsets must start at 0"};
+  const int64_t total = so[n];
+  if (total < 0) throw Error{SD_E_INVAL, "offsets must not decrease"};
   uint8_t* codes = sc.get<uint8_t>((uint64_t)total + 1);
-  int64_t* offs = sc.get<int64_t>((uint64_t)s->n + 1);
-  if (total)
-    hip_check(hipMemcpyAsync(codes, s->codes, (size_t)total, hipMemcpyHostToDevice, st), "H2D codes");
-  hip_check(hipMemcpyAsync(offs, s->offsets, (size_t)(s->n + 1) * 8, hipMemcpyHostToDevice, st),
-            "H2D offsets");
+  int64_t* offs = sc.get<int64_t>((uint64_t)n + 1);
+  if (c->arena) {
+    // no-allocation calls: no pinned area, direct copies from the caller's memory
+    check_spans({so}, {SetSpan{0, 0, n}}, false, nullptr, nullptr);
+    if (total)
+      hip_check(hipMemcpyAsync(codes, s->codes, (size_t)total, hipMemcpyHostToDevice, st),
+                "H2D codes");
+    hip_check(hipMemcpyAsync(offs, so, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, st),
+              "H2D offsets");
+    d.codes = codes;
+    d.offs = offs;
+    return d;
+  }
+  // pieces of the codes (bytes) and of the offsets (words), copied into the
+  // pinned area by host threads, the offsets checked on the way (every
+  // sequence inside codes[0, total)); this thread sends each finished piece
+  // to the device in order, so the copies to the device overlap the copies
+  // into pinned memory
+  const size_t cpad = ((size_t)total + 255) & ~(size_t)255;
+  uint8_t* area = reinterpret_cast<uint8_t*>(stage_area(c, cpad + (size_t)(n + 1) * 8));
+  int64_t* aoff = reinterpret_cast<int64_t*>(area + cpad);
+  struct Part {
+    bool words;      // offsets (words) or codes (bytes)
+    int64_t lo, hi;  // [lo, hi) in its unit
+  };
+  std::vector<Part> parts;
+  constexpr int64_t kBytes = 2 << 20;
+  for (int64_t x = 0; x < total; x += kBytes) parts.push_back(Part{false, x, std::min(x + kBytes, total)});
+  for (int64_t x = 0; x <= n; x += kBytes / 8) parts.push_back(Part{true, x, std::min(x + kBytes / 8, n + 1)});
+  const size_t np = parts.size();
+  std::unique_ptr<std::atomic<int>[]> state(new std::atomic<int>[np]);  // 0 pending, 1 ready, 2 bad offsets
+  for (size_t x = 0; x < np; ++x) state[x].store(0);
+  auto fill = [&](size_t x) {
+    const Part& p = parts[x];
+    bool ok = true;
+    if (p.words) {
+      std::memcpy(aoff + p.lo, so + p.lo, (size_t)(p.hi - p.lo) * 8);
+      for (int64_t y = p.lo; y < p.hi && y < n; ++y) ok = ok && so[y + 1] >= so[y];
+    } else {
+      std::memcpy(area + p.lo, s->codes + p.lo, (size_t)(p.hi - p.lo));
+    }
+    state[x].store(ok ? 1 : 2, std::memory_order_release);
+  };
+  std::atomic<size_t> next{0};
+  std::vector<std::thread> th;
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned nt = (unsigned)std::min<size_t>({np / 2, (size_t)hw, (size_t)8});
+  bool bad = false;
+  try {
+    for (unsigned t = 0; t < nt; ++t)
+      th.emplace_back([&] {
+        for (size_t x = next.fetch_add(1); x < np; x = next.fetch_add(1)) fill(x);
+      });
+    for (size_t x = 0; x < np; ++x) {
+      if (th.empty()) fill(x);
+      int v;
+      while ((v = state[x].load(std::memory_order_acquire)) == 0) std::this_thread::yield();
+      if (v == 2) bad = true;
+      if (bad) continue;  // nothing more goes to the device; the threads finish their pieces
+      const Part& p = parts[x];
+      if (p.words)
+        hip_check(hipMemcpyAsync(offs + p.lo, aoff + p.lo, (size_t)(p.hi - p.lo) * 8,
+                                 hipMemcpyHostToDevice, st),
+                  "H2D offsets");
+      else
+        hip_check(hipMemcpyAsync(codes + p.lo, area + p.lo, (size_t)(p.hi - p.lo),
+                                 hipMemcpyHostToDevice, st),
+                  "H2D codes");
+    }
+  } catch (...) {
+    for (auto& t : th) t.join();
+    (void)hipStreamSynchronize(st);  // the area may be in use by copies already enqueued
+    throw;
+  }
+  for (auto& t : th) t.join();
+  stage_done(c, st);
+  if (bad) throw Error{SD_E_INVAL, "offsets must not decrease"};
   d.codes = codes;
   d.offs = offs;
   return d;
