@@ -567,31 +567,53 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
       for (size_t p = 0; p < plan->tiles[x].pieces.size(); ++p)
         total[plan->tiles[x].pieces[p].set] += res[x].bounds[p + 1] - res[x].bounds[p];
     std::vector<uint64_t> at(nsets, 0);
-    std::vector<uint32_t*> si(nsets), sj(nsets);
-    std::vector<uint8_t*> sd(nsets);
-    for (int x = 0; x < nsets; ++x) {
-      si[x] = dalloc_t<uint32_t>(c, total[x]);
-      sj[x] = dalloc_t<uint32_t>(c, total[x]);
-      sd[x] = dalloc_t<uint8_t>(c, total[x]);
-    }
+    bool host_out = true;
+    for (int x = 0; x < nsets; ++x) host_out = host_out && !outs[x].on_device;
     uint64_t npairs = 0;
-    for (size_t x = 0; x < plan->tiles.size(); ++x) {
-      const TileBufs& t = plan->tiles[x];
-      uint32_t q = 0;
-      for (size_t p = 0; p < t.pieces.size(); ++p) {
-        const Piece& pc = t.pieces[p];
-        const uint64_t lo = res[x].bounds[p], n = res[x].bounds[p + 1] - lo;
-        // tile-local id q + y is set-local id pc.first + y
-        launch_slice_rebase(res[x].i, res[x].j, res[x].d, lo, n, pc.first - (int64_t)q,
-                            si[pc.set] + at[pc.set], sj[pc.set] + at[pc.set],
-                            sd[pc.set] + at[pc.set], s);
-        at[pc.set] += n;
-        npairs += n;
-        q += (uint32_t)pc.count;
+    if (host_out) {
+      // host results: each tile's result comes over once and is cut on the
+      // host into the sets' pinned blocks
+      for (int x = 0; x < nsets; ++x) host_result(c, total[x], &outs[x]);
+      for (size_t x = 0; x < plan->tiles.size(); ++x) {
+        const TileBufs& t = plan->tiles[x];
+        std::vector<HostSlice> sl;
+        uint32_t q = 0;
+        for (size_t p = 0; p < t.pieces.size(); ++p) {
+          const Piece& pc = t.pieces[p];
+          const uint64_t lo = res[x].bounds[p], n = res[x].bounds[p + 1] - lo;
+          // tile-local id q + y is set-local id pc.first + y
+          sl.push_back(HostSlice{pc.set, lo, n, at[pc.set], pc.first - (int64_t)q});
+          at[pc.set] += n;
+          npairs += n;
+          q += (uint32_t)pc.count;
+        }
+        fill_host_slices(c, res[x].i, res[x].j, res[x].d, res[x].bounds.back(), sl, outs, s);
       }
+    } else {
+      std::vector<uint32_t*> si(nsets), sj(nsets);
+      std::vector<uint8_t*> sd(nsets);
+      for (int x = 0; x < nsets; ++x) {
+        si[x] = dalloc_t<uint32_t>(c, total[x]);
+        sj[x] = dalloc_t<uint32_t>(c, total[x]);
+        sd[x] = dalloc_t<uint8_t>(c, total[x]);
+      }
+      for (size_t x = 0; x < plan->tiles.size(); ++x) {
+        const TileBufs& t = plan->tiles[x];
+        uint32_t q = 0;
+        for (size_t p = 0; p < t.pieces.size(); ++p) {
+          const Piece& pc = t.pieces[p];
+          const uint64_t lo = res[x].bounds[p], n = res[x].bounds[p + 1] - lo;
+          launch_slice_rebase(res[x].i, res[x].j, res[x].d, lo, n, pc.first - (int64_t)q,
+                              si[pc.set] + at[pc.set], sj[pc.set] + at[pc.set],
+                              sd[pc.set] + at[pc.set], s);
+          at[pc.set] += n;
+          npairs += n;
+          q += (uint32_t)pc.count;
+        }
+      }
+      for (int x = 0; x < nsets; ++x) finish_output(c, si[x], sj[x], sd[x], total[x], &outs[x], s);
+      hip_check(hipStreamSynchronize(s), "synchronise");
     }
-    for (int x = 0; x < nsets; ++x) finish_output(c, si[x], sj[x], sd[x], total[x], &outs[x], s);
-    hip_check(hipStreamSynchronize(s), "synchronise");
     clk.lap("per-set results");
     c->stats.n_pairs = (int64_t)npairs;
   } catch (...) {

@@ -438,8 +438,20 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
       std::vector<uint64_t> hb(ns + 1);
       hip_check(hipMemcpyAsync(hb.data(), bounds, (ns + 1) * 8, hipMemcpyDeviceToHost, s), "bounds");
       hip_check(hipStreamSynchronize(s), "synchronise");
+      bool host_out = true;
+      for (int x = first; x < last; ++x) host_out = host_out && !outs[x].on_device;
       try {
-        for (int x = 0; x < ns; ++x) {
+        if (host_out) {
+          // host results: the tile's result comes over once and is cut on the
+          // host (ids made set-local on the way)
+          std::vector<HostSlice> sl;
+          for (int x = 0; x < ns; ++x) {
+            host_result(c, hb[x + 1] - hb[x], &outs[first + x]);
+            sl.push_back(HostSlice{first + x, hb[x], hb[x + 1] - hb[x], 0, -(int64_t)base[x]});
+          }
+          fill_host_slices(c, r.i, r.j, r.d, r.n, sl, outs, s);
+        }
+        for (int x = 0; x < ns && !host_out; ++x) {
           const uint64_t lo = hb[x], n = hb[x + 1] - hb[x];
           uint32_t* oi = dalloc_t<uint32_t>(c, n);
           uint32_t* oj = dalloc_t<uint32_t>(c, n);

@@ -292,6 +292,22 @@ void check_spans(const std::vector<const int64_t*>& offs, const std::vector<SetS
 int64_t rebase_spans(const std::vector<const int64_t*>& offs, const std::vector<SetSpan>& spans,
                      int64_t* dst);
 
+// Host results of batched sets cut from device results (stage.cpp): a
+// slice moves entries [lo, lo + n) of a (q, r)-sorted device result to
+// position `at` of the host result of set `set`, with q + shift as its id.
+struct HostSlice {
+  int set = 0;
+  uint64_t lo = 0, n = 0, at = 0;
+  int64_t shift = 0;
+};
+// A pinned host result of n pairs for out (one block: i, j, then d).
+void host_result(sd_ctx* c, uint64_t n, sd_pairs* out);
+// One copy of a device result of n pairs (di, dj, dd) into the pinned
+// staging area, then every slice into its set's host result on host threads.
+void fill_host_slices(sd_ctx* c, const uint32_t* di, const uint32_t* dj, const uint8_t* dd,
+                      uint64_t n, const std::vector<HostSlice>& slices, sd_pairs* outs,
+                      hipStream_t s);
+
 struct Cands {
   uint64_t* p = nullptr;  // pool block owned by the caller
   uint64_t n = 0;

@@ -253,4 +253,44 @@ int64_t rebase_spans(const std::vector<const int64_t*>& offs, const std::vector<
   return cpos;
 }
 
+void host_result(sd_ctx* c, uint64_t n, sd_pairs* out) {
+  const uint64_t m = n ? n : 1;
+  uint8_t* h = static_cast<uint8_t*>(host_block(c, m * 9));
+  out->n = (int64_t)n;
+  out->i = reinterpret_cast<uint32_t*>(h);
+  out->j = reinterpret_cast<uint32_t*>(h + m * 4);
+  out->d = h + m * 8;
+}
+
+void fill_host_slices(sd_ctx* c, const uint32_t* di, const uint32_t* dj, const uint8_t* dd,
+                      uint64_t n, const std::vector<HostSlice>& slices, sd_pairs* outs,
+                      hipStream_t s) {
+  if (!n) return;
+  uint8_t* h = reinterpret_cast<uint8_t*>(stage_area(c, n * 9));
+  uint32_t* hi = reinterpret_cast<uint32_t*>(h);
+  uint32_t* hj = hi + n;
+  uint8_t* hd = h + n * 8;
+  hip_check(hipMemcpyAsync(hi, di, n * 4, hipMemcpyDeviceToHost, s), "D2H");
+  hip_check(hipMemcpyAsync(hj, dj, n * 4, hipMemcpyDeviceToHost, s), "D2H");
+  hip_check(hipMemcpyAsync(hd, dd, n, hipMemcpyDeviceToHost, s), "D2H");
+  hip_check(hipStreamSynchronize(s), "D2H synchronise");
+  // pieces of at most kGrain pairs of one slice
+  struct Cut {
+    size_t slice;
+    uint64_t lo, hi;  // within the slice
+  };
+  std::vector<Cut> cuts;
+  for (size_t x = 0; x < slices.size(); ++x)
+    for (uint64_t y = 0; y < slices[x].n; y += kGrain)
+      cuts.push_back(Cut{x, y, std::min<uint64_t>(y + kGrain, slices[x].n)});
+  for_items(cuts.size(), [&](size_t x) {
+    const HostSlice& sl = slices[cuts[x].slice];
+    const sd_pairs& o = outs[sl.set];
+    const uint64_t a = cuts[x].lo, b = cuts[x].hi;
+    for (uint64_t t = a; t < b; ++t) o.i[sl.at + t] = (uint32_t)((int64_t)hi[sl.lo + t] + sl.shift);
+    std::memcpy(o.j + sl.at + a, hj + sl.lo + a, (b - a) * 4);
+    std::memcpy(o.d + sl.at + a, hd + sl.lo + a, b - a);
+  });
+}
+
 }  // namespace sd

@@ -3,8 +3,9 @@
 // stands in for device and pinned memory: the few HIP calls the staging
 // makes are defined below as plain copies, and device blocks come from
 // malloc. Checks the pieces of a large host set, the offset checks and their
-// order, the sums of a length table, and the rebased offsets of split spans
-// against plain loops. Exits 0 and prints "ok" when every check holds.
+// order, the sums of a length table, the rebased offsets of split spans and
+// host results cut from one device result against plain loops. Exits 0 and
+// prints "ok" when every check holds.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -20,6 +21,7 @@ void dfree(sd_ctx*, void* p) { std::free(p); }
 void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error{SD_E_HIP, what};
 }
+void* host_block(sd_ctx*, size_t bytes) { return std::malloc(bytes); }
 }  // namespace sd
 
 namespace {
@@ -188,6 +190,34 @@ int main() {
     bad[2].offsets = o.data();
     check(code_of([&] { sd::set_offsets(bad.data(), 0, 6, area, nullptr); }) == SD_E_INVAL,
           "set_offsets: a device set whose first offset is not 0");
+  }
+  // host results cut from one (q, r)-sorted "device" result: three sets,
+  // one split over two slices and one empty
+  {
+    const uint64_t n = 700000;
+    std::vector<uint32_t> di(n), dj(n);
+    std::vector<uint8_t> dd(n);
+    for (uint64_t t = 0; t < n; ++t) {
+      di[t] = (uint32_t)(1000 + t / 3);
+      dj[t] = draw(1u << 30);
+      dd[t] = (uint8_t)draw(3);
+    }
+    const std::vector<sd::HostSlice> sl = {
+        {0, 0, 300000, 0, -1000}, {2, 300000, 100000, 0, 5}, {0, 400000, 300000, 300000, -7}};
+    sd_pairs outs[3] = {};
+    sd::host_result(c, 600000, &outs[0]);
+    sd::host_result(c, 0, &outs[1]);
+    sd::host_result(c, 100000, &outs[2]);
+    sd::fill_host_slices(c, di.data(), dj.data(), dd.data(), n, sl, outs, nullptr);
+    bool ok = outs[0].n == 600000 && outs[1].n == 0 && outs[2].n == 100000;
+    for (const auto& x : sl)
+      for (uint64_t t = 0; ok && t < x.n; ++t) {
+        const sd_pairs& o = outs[x.set];
+        ok = o.i[x.at + t] == (uint32_t)((int64_t)di[x.lo + t] + x.shift) &&
+             o.j[x.at + t] == dj[x.lo + t] && o.d[x.at + t] == dd[x.lo + t];
+      }
+    check(ok, "fill_host_slices: every slice at its place, ids shifted");
+    for (auto& o : outs) std::free(o.i);
   }
   sd::stage_done(c, nullptr);
   (void)sd::stage_area(c, 16);
