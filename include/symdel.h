@@ -23,6 +23,10 @@
  *     aborts the process. After an error the context stays usable and
  *     sd_last_error() describes the failure.
  *   - Results are bit-deterministic: the same input gives the same bytes.
+ *   - A context serves one call at a time (calls on one context must not
+ *     overlap); separate contexts may run calls concurrently, also on one
+ *     device. Inside a call, host-side staging of inputs and results may use
+ *     up to 16 short-lived host threads.
  */
 #ifndef SYMDEL_H
 #define SYMDEL_H
