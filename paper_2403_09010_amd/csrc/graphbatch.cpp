@@ -300,11 +300,12 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
   for (int x = 0; x < nsets; ++x)
     if (sets[x].n && sets[x].on_device) dev_words += (size_t)sets[x].n + 1;
   for (const TileBufs& t : tiles) tile_words += t.n + 1;
-  int64_t* area = stage_area(c, (dev_words + tile_words) * 8);
-  const std::vector<const int64_t*> so = set_offsets(sets, 0, nsets, area, s);
   std::vector<SetSpan> spans;
   for (const TileBufs& t : tiles)
     for (const Piece& pc : t.pieces) spans.push_back(SetSpan{pc.set, pc.first, pc.count});
+  const uint64_t pin_bytes = host_code_bytes(sets, spans);
+  int64_t* area = stage_area(c, (dev_words + tile_words) * 8 + pin_bytes);
+  const std::vector<const int64_t*> so = set_offsets(sets, 0, nsets, area, s);
   {
     uint64_t vlen[KEY_MAX_LEN_HOST + 1];  // V(L, k) by length
     for (int L = 0; L <= KEY_MAX_LEN_HOST; ++L) vlen[L] = variants_of_length(L, k);
@@ -444,26 +445,18 @@ void query_sets_graph(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* 
   clk.lap("plan");
 
   // inputs of this batch into the plan's tile buffers (offsets rebased into
-  // pinned memory, one copy per tile; codes one copy per piece), then the
-  // replay
+  // pinned memory, one copy per tile; codes one copy per device piece and
+  // one per run of host pieces), then the replay
   {
     int64_t* dst = area + dev_words;
+    uint8_t* pin = reinterpret_cast<uint8_t*>(area + dev_words + tile_words);
     size_t at = 0;
     for (TileBufs& t : plan->tiles) {
       const std::vector<SetSpan> ts(spans.begin() + at, spans.begin() + at + t.pieces.size());
       at += t.pieces.size();
       rebase_spans(so, ts, dst);
-      uint64_t q = 0;
-      for (const SetSpan& sp : ts) {
-        const sd_seqs& st = sets[sp.set];
-        const int64_t a = so[sp.set][sp.first], b = so[sp.set][sp.first + sp.count];
-        if (b > a)
-          hip_check(hipMemcpyAsync(t.codes + dst[q], st.codes + a, (size_t)(b - a),
-                                   st.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                                   s),
-                    "copy codes");
-        q += (uint64_t)sp.count;
-      }
+      stage_codes(sets, so, ts, dst, t.codes, pin, s);
+      pin += host_code_bytes(sets, ts);
       hip_check(hipMemcpyAsync(t.offs, dst, (t.n + 1) * 8, hipMemcpyHostToDevice, s),
                 "copy offsets");
       dst += t.n + 1;

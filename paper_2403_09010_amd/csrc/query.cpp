@@ -389,7 +389,8 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
     } else {
       // the sets' offsets on the host (device sets read into pinned memory
       // with one wait), checked and rebased on host threads into pinned
-      // memory, one copy of the tile's offsets; codes one copy per set
+      // memory, one copy of the tile's offsets; codes one copy per device
+      // set and one per run of host sets (through pinned memory)
       size_t dev_words = 0;
       std::vector<SetSpan> spans;
       for (int x = first; x < last; ++x)
@@ -397,23 +398,15 @@ void query_sets(sd_ctx* c, const sd_index* idx, int nsets, const sd_seqs* sets, 
           if (sets[x].on_device) dev_words += (size_t)sets[x].n + 1;
           spans.push_back(SetSpan{x, 0, sets[x].n});
         }
-      int64_t* area = stage_area(c, (dev_words + tot + 1) * 8);
+      const uint64_t pin_bytes = host_code_bytes(sets, spans);
+      int64_t* area = stage_area(c, (dev_words + tot + 1) * 8 + pin_bytes);
       const std::vector<const int64_t*> so = set_offsets(sets, first, last, area, s);
       check_spans(so, spans, false, nullptr, nullptr);
       int64_t* hoffs = area + dev_words;
       const int64_t codes_tot = rebase_spans(so, spans, hoffs);
       uint8_t* codes = sc.get<uint8_t>((uint64_t)codes_tot + 1);
       int64_t* offs = sc.get<int64_t>(tot + 1);
-      uint64_t qpos = 0;
-      for (const SetSpan& sp : spans) {
-        const sd_seqs& st = sets[sp.set];
-        const int64_t ncd = so[sp.set][sp.count];
-        if (ncd)
-          hip_check(hipMemcpyAsync(codes + hoffs[qpos], st.codes, (size_t)ncd,
-                                   st.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
-                    "copy codes");
-        qpos += (uint64_t)sp.count;
-      }
+      stage_codes(sets, so, spans, hoffs, codes, reinterpret_cast<uint8_t*>(hoffs + tot + 1), s);
       hip_check(hipMemcpyAsync(offs, hoffs, (tot + 1) * 8, hipMemcpyHostToDevice, s),
                 "copy offsets");
       stage_done(c, s);

@@ -292,6 +292,17 @@ void check_spans(const std::vector<const int64_t*>& offs, const std::vector<SetS
 int64_t rebase_spans(const std::vector<const int64_t*>& offs, const std::vector<SetSpan>& spans,
                      int64_t* dst);
 
+// Bytes of codes of the host spans (the pinned room stage_codes needs).
+uint64_t host_code_bytes(const sd_seqs* sets, const std::vector<SetSpan>& spans);
+// The spans' codes into the tile's device codes, laid out as the rebased
+// offsets `dst` say (span x starts at dst[q] for the q sequences of the
+// spans before it): host spans are copied by host threads into `pin` (room
+// for host_code_bytes) and go over with one copy per run of consecutive host
+// spans; device spans are copied device to device, one copy each.
+void stage_codes(const sd_seqs* sets, const std::vector<const int64_t*>& offs,
+                 const std::vector<SetSpan>& spans, const int64_t* dst, uint8_t* codes,
+                 uint8_t* pin, hipStream_t s);
+
 // Host results of batched sets cut from device results (stage.cpp): a
 // slice moves entries [lo, lo + n) of a (q, r)-sorted device result to
 // position `at` of the host result of set `set`, with q + shift as its id.

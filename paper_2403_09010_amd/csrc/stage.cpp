@@ -253,6 +253,72 @@ int64_t rebase_spans(const std::vector<const int64_t*>& offs, const std::vector<
   return cpos;
 }
 
+uint64_t host_code_bytes(const sd_seqs* sets, const std::vector<SetSpan>& spans) {
+  uint64_t b = 0;
+  for (const SetSpan& sp : spans)
+    if (sp.count && !sets[sp.set].on_device)
+      b += (uint64_t)(sets[sp.set].offsets[sp.first + sp.count] - sets[sp.set].offsets[sp.first]);
+  return b;
+}
+
+void stage_codes(const sd_seqs* sets, const std::vector<const int64_t*>& offs,
+                 const std::vector<SetSpan>& spans, const int64_t* dst, uint8_t* codes,
+                 uint8_t* pin, hipStream_t s) {
+  // per span: its first tile sequence, its codes and, for host spans, its
+  // place in the pinned room
+  struct Part {
+    const uint8_t* src;
+    uint64_t bytes, pin_at;
+    int64_t tile_at;
+  };
+  std::vector<Part> parts(spans.size());
+  int64_t q = 0;
+  uint64_t pat = 0;
+  for (size_t x = 0; x < spans.size(); ++x) {
+    const SetSpan& sp = spans[x];
+    const int64_t a = sp.count ? offs[sp.set][sp.first] : 0;
+    const int64_t b = sp.count ? offs[sp.set][sp.first + sp.count] : 0;
+    parts[x] = Part{sets[sp.set].codes + a, (uint64_t)(b - a), pat, dst[q]};
+    if (!sets[sp.set].on_device) pat += (uint64_t)(b - a);
+    q += sp.count;
+  }
+  // host spans into pinned memory, in pieces of at most kGrain * 8 bytes
+  struct Cut {
+    size_t part;
+    uint64_t lo, hi;
+  };
+  std::vector<Cut> cuts;
+  constexpr uint64_t kBytes = (uint64_t)kGrain * 8;
+  for (size_t x = 0; x < spans.size(); ++x)
+    if (!sets[spans[x].set].on_device)
+      for (uint64_t y = 0; y < parts[x].bytes; y += kBytes)
+        cuts.push_back(Cut{x, y, std::min(y + kBytes, parts[x].bytes)});
+  for_items(cuts.size(), [&](size_t x) {
+    const Part& p = parts[cuts[x].part];
+    std::memcpy(pin + p.pin_at + cuts[x].lo, p.src + cuts[x].lo, cuts[x].hi - cuts[x].lo);
+  });
+  // one copy per run of consecutive host spans (contiguous on both sides),
+  // one per device span
+  for (size_t x = 0; x < spans.size();) {
+    if (sets[spans[x].set].on_device) {
+      if (parts[x].bytes)
+        hip_check(hipMemcpyAsync(codes + parts[x].tile_at, parts[x].src, parts[x].bytes,
+                                 hipMemcpyDeviceToDevice, s),
+                  "copy codes");
+      ++x;
+      continue;
+    }
+    size_t y = x;
+    uint64_t run = 0;
+    while (y < spans.size() && !sets[spans[y].set].on_device) run += parts[y++].bytes;
+    if (run)
+      hip_check(hipMemcpyAsync(codes + parts[x].tile_at, pin + parts[x].pin_at, run,
+                               hipMemcpyHostToDevice, s),
+                "copy codes");
+    x = y;
+  }
+}
+
 void host_result(sd_ctx* c, uint64_t n, sd_pairs* out) {
   const uint64_t m = n ? n : 1;
   uint8_t* h = static_cast<uint8_t*>(host_block(c, m * 9));

@@ -3,8 +3,8 @@
 // stands in for device and pinned memory: the few HIP calls the staging
 // makes are defined below as plain copies, and device blocks come from
 // malloc. Checks the pieces of a large host set, the offset checks and their
-// order, the sums of a length table, the rebased offsets of split spans and
-// host results cut from one device result against plain loops. Exits 0 and
+// order, the sums of a length table, the rebased offsets and codes of split
+// spans and host results cut from one device result against plain loops. Exits 0 and
 // prints "ok" when every check holds.
 #include <hip/hip_runtime.h>
 
@@ -164,6 +164,20 @@ int main() {
   check(ctot == want.back() && std::equal(want.begin(), want.end(), dst.begin()) &&
             dst[want.size()] == -7,
         "rebase_spans: offsets laid end to end, nothing written past");
+  // the spans' codes into one tile: device spans copied directly, host
+  // spans through the pinned room, runs of host spans in one copy
+  {
+    std::vector<uint8_t> tile((size_t)ctot + 1, 0xEE), pin(sd::host_code_bytes(views.data(), spans));
+    sd::stage_codes(views.data(), so, spans, dst.data(), tile.data(), pin.data(), nullptr);
+    std::vector<uint8_t> want_codes;
+    for (const auto& sp : spans)
+      if (sp.count)
+        want_codes.insert(want_codes.end(), sets[sp.set].codes.begin() + so[sp.set][sp.first],
+                          sets[sp.set].codes.begin() + so[sp.set][sp.first + sp.count]);
+    check(want_codes.size() == (size_t)ctot &&
+              std::equal(want_codes.begin(), want_codes.end(), tile.begin()) && tile[ctot] == 0xEE,
+          "stage_codes: the tile's codes in span order, nothing past");
+  }
   // the first failing sequence in span order decides the error
   {
     std::vector<int64_t> o = sets[4].offs;
