@@ -457,7 +457,7 @@ def main():
     ap.add_argument("--sets", type=int, default=512, help="batched: number of query sets")
     ap.add_argument("--set-scale", type=float, default=1.0, help="batched: scale of set sizes")
     ap.add_argument("--requests", type=int, default=2000, help="served: requests per rate")
-    ap.add_argument("--burst", type=int, default=400, help="served: requests for saturation")
+    ap.add_argument("--burst", type=int, default=2000, help="served: requests for saturation")
     ap.add_argument("--serial-requests", type=int, default=200, help="served: serial comparison")
     ap.add_argument("--ref-div", type=int, default=1, help="served/learned: reference size divisor")
     ap.add_argument("--learned-queries", type=int, default=200000, help="learned: query sequences")
