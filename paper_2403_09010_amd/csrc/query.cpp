@@ -65,6 +65,18 @@ int index_bits(uint64_t nkeys) {
   return b;
 }
 
+// Hash bits of a query tile's join segments: the index's own B, or fewer
+// for a small tile (about 128 query elements a segment, at least 2^4
+// segments). The join runs one workgroup per segment, so with the index's
+// 2^B segments a small query would launch mostly workgroups that find no
+// query element; a coarser segment is the union of 2^(B - bits) index
+// segments, searched in global memory.
+int join_bits(const sd_index* idx, uint64_t nk) {
+  int b = 4;
+  while (b < 24 && (nk >> (b + 1)) >= 128) ++b;
+  return std::min(b, idx->bits);
+}
+
 // One tile of queries: returns pool blocks (i = tile-local query id, j = ref
 // id, d) sorted by (i, j) and their count.
 TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const WeightedSpec* w) {
@@ -79,8 +91,8 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   const uint32_t nk = (uint32_t)p.nkeys;
   cl.tm.mark("q_pack_scan", (double)q.n * 56, 2);
 
-  // query elements, grouped by the index's top B hash bits
-  const int bits = idx->bits;
+  // query elements, grouped by the top hash bits of the join segments
+  const int bits = join_bits(idx, nk);
   const std::vector<Digit> digits = bits ? top_digits(64 - bits) : std::vector<Digit>();
   uint64_t* e1 = cl.sc.get<uint64_t>(nk);
   uint64_t* e2 = cl.sc.get<uint64_t>(nk);
@@ -119,14 +131,25 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   uint32_t* qs = cl.sc.get<uint32_t>(nseg);
   uint32_t* qe = cl.sc.get<uint32_t>(nseg);
   launch_seg_bounds(Eq, nk, 64u - (uint32_t)bits, qs, qe, s);
-  cl.tm.mark("q_vargen_passes", (double)nk * (8 + 16 * digits.size()), 2 + (int)digits.size());
+  // the index's segments at the same bits (its own directory, or coarser
+  // bounds found in its sorted array)
+  const uint32_t* rs = idx->seg_start;
+  const uint32_t* re = idx->seg_end;
+  if (bits < idx->bits) {
+    uint32_t* crs = cl.sc.get<uint32_t>(nseg);
+    uint32_t* cre = cl.sc.get<uint32_t>(nseg);
+    launch_seg_bounds(idx->E, idx->n_keys, 64u - (uint32_t)bits, crs, cre, s);
+    rs = crs;
+    re = cre;
+  }
+  cl.tm.mark("q_vargen_passes", (double)nk * (8 + 16 * digits.size()),
+             (bits < idx->bits ? 3 : 2) + (int)digits.size());
 
   // join against the index
   Cands cj = sharded_output(
       cl, nk / 4, "join",
       [&](const ShardArgs& out) {
-        launch_join_seg(idx->E, idx->seg_start, idx->seg_end, Eq, qs, qe, nseg, idx->idbits,
-                        JOIN_LDS_MIN_Q, out, s);
+        launch_join_seg(idx->E, rs, re, Eq, qs, qe, nseg, idx->idbits, JOIN_LDS_MIN_Q, out, s);
       },
       [&](uint64_t n) { return (double)nk * 8 + (double)n * 8; });
   cl.sc.blocks.push_back(cj.p);

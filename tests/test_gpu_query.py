@@ -193,3 +193,25 @@ def test_batch_of_24_sets_against_oracle(ctx, ref, index2):
         for x, (o, w) in enumerate(zip(outs, want)):
             assert triples(o) == w, f"set {x} (size {sizes[x]}) differs from the oracle"
     ctx.set_option(OPT_BATCH_TILE, 0)
+
+
+@pytest.mark.parametrize("n", [1, 10, 300, 3000])
+def test_small_queries_join_coarser_segments(ctx, n):
+    """A query tile with few variants joins over coarser segments than the
+    index's own (unions of index segments found in its sorted array): 1,
+    10 and 300 queries against a 20,000-sequence index take that path, 3,000
+    the index's own segments; each equals the oracle, plain and weighted."""
+    import oracle
+    big = cdr3gen.generate(19, 20_000)
+    qry = cdr3gen.generate_query(90 + n, n, *big, ref_mut_frac=0.5)
+    idx = ctx.build_index(*to_dev(*big), 2)
+    try:
+        log(f"{n} queries against 20K")
+        for k in (1, 2):
+            assert triples(ctx.query(idx, *qry, k)) == oracle_query(big, qry, k), f"k={k}"
+        subst = cdr3gen.cost_matrix(8, 3, 4)
+        got = triples(ctx.query_weighted(idx, *qry, subst, 8, 8))
+        a, b, d = oracle.query_weighted(big, qry, subst, 8, 8)
+        assert got == list(zip(a.tolist(), b.tolist(), d.tolist()))
+    finally:
+        idx.free()
