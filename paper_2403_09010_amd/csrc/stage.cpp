@@ -52,7 +52,11 @@ void for_items(size_t n, F&& fn) {
   };
   std::vector<std::thread> th;
   th.reserve(nt - 1);
-  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
+  try {
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
+  } catch (...) {
+    // no more threads: the items are shared by the ones that started
+  }
   work();
   for (auto& t : th) t.join();
 }
@@ -117,10 +121,14 @@ DevSeqs stage_seqs(sd_ctx* c, Scratch& sc, const sd_seqs* s, hipStream_t st) {
   const unsigned nt = (unsigned)std::min<size_t>({np / 2, (size_t)hw, (size_t)8});
   bool bad = false;
   try {
-    for (unsigned t = 0; t < nt; ++t)
-      th.emplace_back([&] {
-        for (size_t x = next.fetch_add(1); x < np; x = next.fetch_add(1)) fill(x);
-      });
+    try {
+      for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&] {
+          for (size_t x = next.fetch_add(1); x < np; x = next.fetch_add(1)) fill(x);
+        });
+    } catch (...) {
+      // no more threads: the ones that started (or this one) fill the pieces
+    }
     for (size_t x = 0; x < np; ++x) {
       if (th.empty()) fill(x);
       int v;
