@@ -426,6 +426,10 @@ int sd_set_option(sd_ctx* c, int option, int64_t value) {
       if (value < 0 || value > 2) return SD_E_INVAL;
       c->pair_sort = (int)value;
       return SD_OK;
+    case SD_OPT_JOIN_ELEMS:
+      if (value < 0 || value > (1 << 20)) return SD_E_INVAL;
+      c->join_elems = (int)value;
+      return SD_OK;
     case SD_OPT_BATCH_GRAPH:
       if (value < 0 || value > 1) return SD_E_INVAL;
       c->batch_graph = (int)value;

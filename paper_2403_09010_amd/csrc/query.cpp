@@ -66,14 +66,18 @@ int index_bits(uint64_t nkeys) {
 }
 
 // Hash bits of a query tile's join segments: the index's own B, or fewer
-// for a small tile (about 128 query elements a segment, at least 2^4
-// segments). The join runs one workgroup per segment, so with the index's
-// 2^B segments a small query would launch mostly workgroups that find no
-// query element; a coarser segment is the union of 2^(B - bits) index
+// for a small tile (about `per` query elements a segment, 256 unless
+// SD_OPT_JOIN_ELEMS says otherwise, at least 2^4 segments; 1 keeps the
+// index's own). The join runs one workgroup per segment, so with the
+// index's 2^B segments a small query would launch mostly workgroups that
+// find no query element, and each would stage its index segment in LDS for
+// a few lookups; a coarser segment is the union of 2^(B - bits) index
 // segments, searched in global memory.
-int join_bits(const sd_index* idx, uint64_t nk) {
+int join_bits(const sd_ctx* c, const sd_index* idx, uint64_t nk) {
+  if (c->join_elems == 1) return idx->bits;  // the index's own segments
+  const uint64_t per = c->join_elems ? (uint64_t)c->join_elems : 256;
   int b = 4;
-  while (b < 24 && (nk >> (b + 1)) >= 128) ++b;
+  while (b < 24 && (nk >> (b + 1)) >= per) ++b;
   return std::min(b, idx->bits);
 }
 
@@ -92,7 +96,7 @@ TileOut query_tile(Call& cl, const sd_index* idx, const DevSeqs& q, int k, const
   cl.tm.mark("q_pack_scan", (double)q.n * 56, 2);
 
   // query elements, grouped by the top hash bits of the join segments
-  const int bits = join_bits(idx, nk);
+  const int bits = join_bits(c, idx, nk);
   const std::vector<Digit> digits = bits ? top_digits(64 - bits) : std::vector<Digit>();
   uint64_t* e1 = cl.sc.get<uint64_t>(nk);
   uint64_t* e2 = cl.sc.get<uint64_t>(nk);

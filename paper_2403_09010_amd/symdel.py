@@ -38,6 +38,7 @@ OPT_STREAM = 11
 OPT_STREAM_ELEMS = 12
 OPT_GROUP_SHAPE = 13
 OPT_BATCH_GRAPH = 14
+OPT_JOIN_ELEMS = 15
 METRIC_LEVENSHTEIN = 0
 METRIC_HAMMING = 1
 MAX_STAGES = 16

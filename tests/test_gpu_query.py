@@ -198,20 +198,26 @@ def test_batch_of_24_sets_against_oracle(ctx, ref, index2):
 @pytest.mark.parametrize("n", [1, 10, 300, 3000])
 def test_small_queries_join_coarser_segments(ctx, n):
     """A query tile with few variants joins over coarser segments than the
-    index's own (unions of index segments found in its sorted array): 1,
-    10 and 300 queries against a 20,000-sequence index take that path, 3,000
-    the index's own segments; each equals the oracle, plain and weighted."""
+    index's own (unions of index segments found in its sorted array); with
+    SD_OPT_JOIN_ELEMS = 1 every tile keeps the index's own segments. Both
+    equal the oracle for 1 to 3,000 queries against a 20,000-sequence
+    index, plain and weighted."""
     import oracle
+    from paper_2403_09010_amd.symdel import OPT_JOIN_ELEMS
     big = cdr3gen.generate(19, 20_000)
     qry = cdr3gen.generate_query(90 + n, n, *big, ref_mut_frac=0.5)
+    subst = cdr3gen.cost_matrix(8, 3, 4)
+    a, b, d = oracle.query_weighted(big, qry, subst, 8, 8)
+    want_w = list(zip(a.tolist(), b.tolist(), d.tolist()))
+    want = {k: oracle_query(big, qry, k) for k in (1, 2)}
     idx = ctx.build_index(*to_dev(*big), 2)
     try:
-        log(f"{n} queries against 20K")
-        for k in (1, 2):
-            assert triples(ctx.query(idx, *qry, k)) == oracle_query(big, qry, k), f"k={k}"
-        subst = cdr3gen.cost_matrix(8, 3, 4)
-        got = triples(ctx.query_weighted(idx, *qry, subst, 8, 8))
-        a, b, d = oracle.query_weighted(big, qry, subst, 8, 8)
-        assert got == list(zip(a.tolist(), b.tolist(), d.tolist()))
+        for per in (0, 1):
+            ctx.set_option(OPT_JOIN_ELEMS, per)
+            log(f"{n} queries against 20K, join elements option {per}")
+            for k in (1, 2):
+                assert triples(ctx.query(idx, *qry, k)) == want[k], f"k={k}"
+            assert triples(ctx.query_weighted(idx, *qry, subst, 8, 8)) == want_w
     finally:
+        ctx.set_option(OPT_JOIN_ELEMS, 0)
         idx.free()
