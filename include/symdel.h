@@ -121,8 +121,9 @@ typedef struct {
                                in-memory path would exceed the budget), 1 never, 2 always */
 #define SD_OPT_JOIN_ELEMS 15 /* query tiles (eager): query elements a join segment aims at; a
                                 tile with fewer than that per index segment joins over coarser
-                                segments (unions of index segments); 0 = automatic (256), 1 keeps
-                                the index's own segments for any tile */
+                                segments (unions of index segments); 0 = automatic (the cube
+                                root of the tile's element count, at least 64), 1 keeps the
+                                index's own segments for any tile */
 #define SD_OPT_BATCH_GRAPH 14 /* sd_query_batch as one captured HIP graph: 0 off (tiles with host
                                  synchronisations), 1 on (capture once per batch shape, then replay) */
 #define SD_OPT_GROUP_SHAPE 13 /* hashed path grouping kernel at LDS capacity 2048: 0 (256 threads,

@@ -66,16 +66,17 @@ int index_bits(uint64_t nkeys) {
 }
 
 // Hash bits of a query tile's join segments: the index's own B, or fewer
-// for a small tile (about `per` query elements a segment, 256 unless
-// SD_OPT_JOIN_ELEMS says otherwise, at least 2^4 segments; 1 keeps the
-// index's own). The join runs one workgroup per segment, so with the
+// for a small tile (about `per` query elements a segment, at least 2^4
+// segments; `per` is the cube root of the tile's element count, at least
+// 64, unless SD_OPT_JOIN_ELEMS sets it; 1 keeps the index's own). The join runs one workgroup per segment, so with the
 // index's 2^B segments a small query would launch mostly workgroups that
 // find no query element, and each would stage its index segment in LDS for
 // a few lookups; a coarser segment is the union of 2^(B - bits) index
 // segments, searched in global memory.
 int join_bits(const sd_ctx* c, const sd_index* idx, uint64_t nk) {
   if (c->join_elems == 1) return idx->bits;  // the index's own segments
-  const uint64_t per = c->join_elems ? (uint64_t)c->join_elems : 256;
+  const uint64_t per =
+      c->join_elems ? (uint64_t)c->join_elems : std::max<uint64_t>(64, (uint64_t)std::cbrt((double)nk));
   int b = 4;
   while (b < 24 && (nk >> (b + 1)) >= per) ++b;
   return std::min(b, idx->bits);

@@ -345,7 +345,7 @@ struct sd_ctx {
   int stream = 0;              // streamed self search: 0 automatic, 1 never, 2 always
   uint64_t stream_elems = 0;   // elements per column group (0: from the budget)
   int64_t batch_tile_seqs = 0;  // query batches: sequences per tile (0 = automatic)
-  int join_elems = 0;           // query tiles: query elements a join segment aims at (0 = 256)
+  int join_elems = 0;           // query tiles: query elements a join segment aims at (0 = automatic)
   std::string tune_cache;       // autotuner cache file (empty: none)
   int probe = 0;                // learned indexes: 0 model window, 1 whole-array binary search
   std::map<std::string, uint64_t> out_hint;  // last output size of each sharded stage
